@@ -1,0 +1,191 @@
+/*
+ * jfnk.h -- C ABI of the MI355X JFNK solver for the implicit electron /
+ * electric-potential step of a low-Mach reacting flow under an applied field.
+ *
+ * One call of jfnk_step advances every column of a batch of independent 1D
+ * columns by one backward-Euler step of the coupled system of the paper's
+ * Section 3.2 (eq:pnp, discretised in time as eq:nls):
+ *
+ *   -n^{k+1} + f - dt k n^{k+1} - dt div Gamma(n^{k+1}, phi^{k+1})  = 0
+ *   -n^{k+1} + q + (eps0 eps_r / e) lap phi^{k+1}                   = 0
+ *
+ * with f = n^k + dt s, the electron flux Gamma = n (u + mu grad phi) - D grad n
+ * (electrons drift up the potential gradient; Scharfetter-Gummel face fluxes
+ * on a uniform cell-centred grid), net ion charge q (the provisional charged
+ * species of the paper's Algorithm 1, divided by e) and electrode potentials
+ * phi_left, phi_right applied at the column ends (the applied voltage of
+ * Section 4).  The root is reached by the paper's Algorithm 2: Newton with
+ * the diagonal scalings of eq:newton_sc, right-preconditioned GMRES with the
+ * finite-difference Jacobian-vector product eq:jf_dfapprox, an exact 2x2
+ * block preconditioner (eq:prec) and a backtracking line search.
+ *
+ * Units: SI throughout.  Unless marked HOST, pointers are DEVICE pointers
+ * (memory of the GPU the context was created on).  The caller owns every
+ * array passed in and keeps it alive until the call returns; the library
+ * owns its workspace, allocated once by jfnk_create.
+ *
+ * Errors: every entry point returns JFNK_OK (0) or a status.  Argument
+ * errors (< 0) are detected before any launch and leave outputs untouched.
+ * JFNK_EHIP reports a HIP runtime failure; the context must then be
+ * destroyed.  A column that does not converge is not an error: the call
+ * returns JFNK_NOT_CONVERGED and the column's status says why; its arrays
+ * hold the last accepted iterate.  jfnk_last_error gives a message.
+ *
+ * Threading: a context is used by one host thread at a time.  Calls on one
+ * context are serialised on the stream they are given.
+ */
+#ifndef JFNK_H
+#define JFNK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct jfnk_ctx jfnk_ctx;
+
+/* return codes */
+enum {
+    JFNK_OK = 0,
+    JFNK_NOT_CONVERGED = 1,   /* call completed, >= 1 column flagged */
+    JFNK_EINVAL = -1,         /* invalid argument (nothing launched) */
+    JFNK_ENOMEM = -2,         /* device allocation failed (create) */
+    JFNK_EHIP = -3,           /* HIP runtime error; destroy the context */
+    JFNK_ECAPACITY = -4,      /* problem exceeds the capacity given to create */
+    JFNK_EMODEL = -5          /* learned guess requested without a model */
+};
+
+/* electron condition at a column end */
+enum { JFNK_BC_DIRICHLET = 0, JFNK_BC_ZERO_FLUX = 1 };
+/* initial Newton guess.  PREV: X^n.  EXTRAP: the better (smaller scaled
+   residual, ties to the extrapolation) of X^n and 2X^n - X^{n-1}.  LEARNED:
+   the learned predictor, kept only if its scaled residual is strictly smaller
+   than that of the EXTRAP choice (the fallback). */
+enum { JFNK_GUESS_PREV = 0, JFNK_GUESS_EXTRAP = 1, JFNK_GUESS_LEARNED = 2 };
+/* storage and arithmetic of the per-cell preconditioner factors */
+enum { JFNK_PREC_FP64 = 0, JFNK_PREC_FP32 = 1 };
+/* PLAIN: one column at a time, every phase a launch, control on the host.
+   BATCHED: one launch per step solves all columns, control on the GPU. */
+enum { JFNK_SCHED_PLAIN = 0, JFNK_SCHED_BATCHED = 1 };
+/* per-column status */
+enum {
+    JFNK_COL_CONVERGED = 0,
+    JFNK_COL_MAX_NEWTON = 1,
+    JFNK_COL_NONFINITE = 2,
+    JFNK_COL_LINESEARCH = 3,
+    JFNK_COL_BAD_INPUT = 4
+};
+
+typedef struct {
+    int32_t max_cols;            /* capacity: columns per step */
+    int64_t max_total_cells;     /* capacity: cells over all columns */
+    int32_t max_cells_per_col;   /* capacity: cells of the longest column */
+    int32_t gmres_restart;       /* Krylov space size m before restart (<= 30) */
+    int32_t max_restarts;        /* GMRES restarts per Newton iteration */
+    int32_t max_newton;          /* Newton iterations per step */
+    int32_t max_backtracks;      /* halvings of the line-search step */
+    double tol_f;                /* converged when ||S_F^-1 F||_inf <= tol_f */
+    double tol_x;                /* 0: off; else also requires the error estimate
+                                    ||P^-1 S_F^-1 F||_inf (the scaled Newton step
+                                    from the current iterate) <= tol_x */
+    double gamma;                /* GMRES forcing: ||J d + F|| <= gamma ||F|| */
+    double armijo_alpha;         /* sufficient-decrease constant */
+    int32_t prec_precision;      /* JFNK_PREC_* */
+    int32_t guess;               /* JFNK_GUESS_* */
+    int32_t schedule;            /* JFNK_SCHED_* */
+    int32_t threads_override;    /* 0: autotuned; else workgroup size per column */
+} jfnk_config;
+
+/* One step's problem: ncols columns packed back to back. */
+typedef struct {
+    int32_t ncols;
+    const int64_t *col_offset;   /* HOST [ncols+1]: column c owns cells
+                                    [col_offset[c], col_offset[c+1]), >= 3 cells */
+    const double *length;        /* HOST [ncols] column length, m */
+    const double *dt;            /* HOST [ncols] time step, s (> 0) */
+    const double *phi_left;      /* HOST [ncols] electrode potential at x = 0, V */
+    const double *phi_right;     /* HOST [ncols] electrode potential at x = L, V */
+    const double *eps_over_e;    /* HOST [ncols] eps0 eps_r / e, 1/(V m) */
+    const int32_t *bc_left;      /* HOST [ncols] JFNK_BC_* */
+    const int32_t *bc_right;     /* HOST [ncols] */
+    const double *ne_left;       /* HOST [ncols] wall density (Dirichlet), m^-3 */
+    const double *ne_right;      /* HOST [ncols] */
+    const double *mu;            /* [total] electron mobility >= 0, m^2/(V s) */
+    const double *diff;          /* [total] electron diffusivity > 0, m^2/s */
+    const double *src;           /* [total] explicit electron source, m^-3 s^-1 */
+    const double *k_loss;        /* [total] implicit loss rate >= 0, 1/s (NULL: 0) */
+    const double *q_ion;         /* [total] net ion charge / e, m^-3 */
+    const double *u_face;        /* [total + ncols] face velocities (column c's
+                                    n+1 faces start at col_offset[c] + c), m/s
+                                    (NULL: 0) */
+    const double *temp;          /* [total] gas temperature, K (learned guess) */
+} jfnk_problem;
+
+typedef struct {
+    double *ne;                  /* [total] in: n^k, out: n^{k+1} */
+    double *phi;                 /* [total] in: phi^k, out: phi^{k+1} */
+    const double *ne_prev;       /* [total] n^{k-1} for the guesses (NULL: none) */
+    const double *phi_prev;      /* [total] */
+} jfnk_state;
+
+/* HOST arrays [ncols]; any pointer may be NULL */
+typedef struct {
+    int32_t *status;             /* JFNK_COL_* */
+    int32_t *newton_iters;
+    int32_t *gmres_iters;
+    int32_t *backtracks;
+    int32_t *guess_used;         /* JFNK_GUESS_* actually taken */
+    double *res_scaled;          /* final ||S_F^-1 F||_inf */
+} jfnk_stats;
+
+/* Fill cfg with the defaults: restart 30, 5 restarts, 50 Newton iterations,
+   10 backtracks, tol_f 1e-10, tol_x 1e-10, gamma 1e-4, alpha 1e-4, FP32
+   preconditioner, extrapolated guess, batched schedule. */
+void jfnk_config_default(jfnk_config *cfg);
+
+/* Allocate a context and its workspace on the current HIP device for the
+   capacity in cfg.  *out receives the context (NULL on error).
+   Errors: JFNK_EINVAL (bad config), JFNK_ENOMEM, JFNK_EHIP. */
+int jfnk_create(const jfnk_config *cfg, jfnk_ctx **out);
+
+/* Advance every column one step (Algorithm 2 per column).  Work is queued on
+   `stream` (a hipStream_t; NULL = default stream) and the call returns once
+   the results and stats are complete.  Allocates nothing.
+   Returns JFNK_OK, JFNK_NOT_CONVERGED, or an error code. */
+int jfnk_step(jfnk_ctx *ctx, const jfnk_problem *p, jfnk_state *x, jfnk_stats *st,
+              void *stream);
+
+/* Release the context and its workspace.  NULL-safe. */
+void jfnk_destroy(jfnk_ctx *ctx);
+
+/* Message of the last error on this context (never NULL). */
+const char *jfnk_last_error(const jfnk_ctx *ctx);
+
+/* ---- test exports: single phases of the step, same kernels ----------- */
+
+/* F(X) (unscaled, per cell: fe, fp) with X = (x_ne, x_phi) and the step's
+   X^n = (x->ne, x->phi) giving f = n^n + dt s; scal (HOST [4*ncols], may be
+   NULL) receives s_Fn, s_Fphi, s_Xn, s_Xphi per column. */
+int jfnk_eval_residual(jfnk_ctx *ctx, const jfnk_problem *p, const jfnk_state *x,
+                       const double *x_ne, const double *x_phi, double *fe, double *fp,
+                       double *scal, void *stream);
+
+/* w = S_F^-1 [F(X + eps S_X v) - F(X)] / eps with the step of
+   eq:jf_dfapprox; v and w in scaled units, layout as fe/fp. */
+int jfnk_eval_jv(jfnk_ctx *ctx, const jfnk_problem *p, const jfnk_state *x,
+                 const double *x_ne, const double *x_phi, const double *v_ne,
+                 const double *v_phi, double *w_ne, double *w_phi, void *stream);
+
+/* z = P^-1 r for the scaled analytic Jacobian P = S_F^-1 J(X) S_X, factored
+   as in a step (precision of the context). */
+int jfnk_block_solve(jfnk_ctx *ctx, const jfnk_problem *p, const jfnk_state *x,
+                     const double *x_ne, const double *x_phi, const double *r_ne,
+                     const double *r_phi, double *z_ne, double *z_phi, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JFNK_H */

@@ -1,0 +1,859 @@
+// Per-column phases of the JFNK electron/potential solve, executed by one
+// workgroup of T threads that owns the column (layout in jfnk_types.h).
+//
+// Method (paper Section 3.2, Algorithm 2): Newton on the backward-Euler
+// residual F(X) = 0 of the electron transport and Poisson equations
+// (eq:nls), scaled by S_F, S_X (eq:newton_sc); each Newton system is solved
+// by right-preconditioned GMRES from dX_0 = 0, with the finite-difference
+// product J v ~ [F(X + eps v) - F(X)] / eps (eq:jf_dfapprox) and the
+// step eps = lambda (lambda + |X| / |v|), lambda = eps_mach^(1/3); the
+// preconditioner is the exact inverse of the 2x2 block Jacobian (the
+// paper's eq:prec is exact too), obtained here by a direct block-tridiagonal
+// factorisation instead of the paper's Schur complement + multigrid, since in
+// 1D the Jacobian of the scheme is exactly 2x2 block tridiagonal.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "jfnk_types.h"
+
+namespace jfnk {
+
+// ---------------------------------------------------------------------------
+// 2x2 blocks
+// ---------------------------------------------------------------------------
+template <class R>
+struct Blk { R a, b, c, d; };   // [[a b] [c d]]
+template <class R>
+struct Vec2 { R x, y; };
+
+template <class R> __device__ __forceinline__ Blk<R> bmul(const Blk<R>& p, const Blk<R>& q) {
+    return {p.a * q.a + p.b * q.c, p.a * q.b + p.b * q.d, p.c * q.a + p.d * q.c, p.c * q.b + p.d * q.d};
+}
+template <class R> __device__ __forceinline__ Vec2<R> bmv(const Blk<R>& p, const Vec2<R>& v) {
+    return {p.a * v.x + p.b * v.y, p.c * v.x + p.d * v.y};
+}
+template <class R> __device__ __forceinline__ Blk<R> bsub(const Blk<R>& p, const Blk<R>& q) {
+    return {p.a - q.a, p.b - q.b, p.c - q.c, p.d - q.d};
+}
+template <class R> __device__ __forceinline__ Blk<R> bneg(const Blk<R>& p) { return {-p.a, -p.b, -p.c, -p.d}; }
+template <class R> __device__ __forceinline__ Blk<R> binv(const Blk<R>& p) {
+    const R id = R(1) / (p.a * p.d - p.b * p.c);
+    return {p.d * id, -p.b * id, -p.c * id, p.a * id};
+}
+__device__ __forceinline__ Blk<double> bzero() { return {0.0, 0.0, 0.0, 0.0}; }
+__device__ __forceinline__ Blk<double> beye() { return {1.0, 0.0, 0.0, 1.0}; }
+
+// ---------------------------------------------------------------------------
+// Bernoulli function B(x) = x / (e^x - 1) for the Scharfetter-Gummel flux.
+// One expm1 per face gives both B(x) and B(-x): with a = |x|,
+// B(-a) = B(a) + a, a sum of two non-negative terms (no cancellation).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void bernoulli_pair(double x, double& bx, double& bmx) {
+    const double a = fabs(x);
+    double ba;
+    if (a < 1e-3) {
+        // 1 / (expm1(a)/a), Taylor series of expm1(a)/a to a^4
+        ba = 1.0 / (1.0 + a * (0.5 + a * (1.0 / 6.0 + a * (1.0 / 24.0 + a * (1.0 / 120.0)))));
+    } else {
+        ba = a / expm1(a);
+    }
+    const double bna = ba + a;
+    if (x >= 0.0) { bx = ba; bmx = bna; } else { bx = bna; bmx = ba; }
+}
+
+// dB/dx at x and at -x: B'(x) = (B(x)/x)(1 - B(-x)), -1/2 + x/6 - x^3/180 near 0.
+__device__ __forceinline__ void bernoulli_dpair(double x, double bx, double bmx, double& dbx,
+                                                double& dbmx) {
+    if (fabs(x) < 1e-3) {
+        const double x3 = x * x * x;
+        dbx = -0.5 + x * (1.0 / 6.0) - x3 * (1.0 / 180.0);
+        dbmx = -0.5 - x * (1.0 / 6.0) + x3 * (1.0 / 180.0);
+    } else {
+        dbx = (bx / x) * (1.0 - bmx);
+        dbmx = -(bmx / x) * (1.0 - bx);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup reductions (wave64 butterflies + LDS across waves).  Fixed order:
+// bitwise reproducible from run to run.
+// ---------------------------------------------------------------------------
+template <int T, int K>
+__device__ __forceinline__ void wg_sum(double (&v)[K], double* scr) {
+    constexpr int NW = T / 64;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) scr[k * NW + w] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) s += scr[k * NW + i];
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
+template <int T, int K>
+__device__ __forceinline__ void wg_max(double (&v)[K], double* scr) {
+    constexpr int NW = T / 64;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] = fmax(v[k], __shfl_xor(v[k], off, 64));
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) scr[k * NW + w] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = scr[k * NW];
+#pragma unroll
+        for (int i = 1; i < NW; ++i) s = fmax(s, scr[k * NW + i]);
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
+// A two-component vector of one column with a scale per component:
+// value(s) = (p0[s] * s0, p1[s] * s1).
+struct VecRef {
+    const double* p0;
+    const double* p1;
+    double s0, s1;
+};
+
+struct Norms {
+    double rinf;    // ||S_F^-1 F||_inf
+    double r2;      // ||S_F^-1 F||_2
+    double xn2;     // ||S_X^-1 X||_2^2
+    double step;    // ||S_X^-1 dX||_inf of the step that produced X
+};
+
+// LDS layout of a column workgroup (doubles):
+//   [0, 12T)            PCR rows / exchange buffers
+//   [12T, 12T + 16*NW)  reduction scratch
+//   then the GMRES small dense state.
+template <int T>
+struct Lds {
+    static constexpr int NW = T / 64;
+    static constexpr int kPcr = 0;
+    static constexpr int kScr = 12 * T;
+    static constexpr int kH = kScr + 16 * NW;                   // (m+1) x m, column major
+    static constexpr int kCs = kH + (kMaxRestart + 1) * kMaxRestart;
+    static constexpr int kSn = kCs + kMaxRestart;
+    static constexpr int kG = kSn + kMaxRestart;
+    static constexpr int kY = kG + kMaxRestart + 1;
+    static constexpr int kMisc = kY + kMaxRestart;               // 16 scalar slots
+    static constexpr int kBasis = kMisc + 16;                    // (m+1) VecRefs (4 words each)
+    static constexpr int kTotal = kBasis + 4 * (kMaxRestart + 1);
+    static constexpr size_t bytes() { return sizeof(double) * kTotal; }
+};
+
+// ---------------------------------------------------------------------------
+// The column object: phases over the column owned by this workgroup.
+// ---------------------------------------------------------------------------
+template <int T, class FT>
+struct Column {
+    ColDesc cd;
+    Work W;
+    SolverParams prm;
+    double* lds;
+    int t;
+    double ih, dth, epsh;            // 1/h, dt/h, (eps/e)/h
+    double rR, gR, wR;               // right-wall face coefficients
+    double sfn, sfp, sxn, sxp, isfn, isfp;
+
+    __device__ void init(const ColDesc& d, const Work& w, const SolverParams& p, double* l) {
+        cd = d; W = w; prm = p; lds = l;
+        t = threadIdx.x;
+        ih = 1.0 / cd.h;
+        dth = cd.dt / cd.h;
+        epsh = cd.eps / cd.h;
+    }
+
+    __device__ __forceinline__ int64_t sidx(int tt, int j) const {
+        return cd.ws + (int64_t)j * T + tt;
+    }
+    __device__ __forceinline__ double* xb(int b, int comp) const { return W.x + (2 * b + comp) * W.P; }
+    __device__ __forceinline__ double* Fb(int b, int comp) const { return W.F + (2 * b + comp) * W.P; }
+    __device__ __forceinline__ double* Vb(int k, int comp) const { return W.V + (2 * (int64_t)k + comp) * W.P; }
+    __device__ __forceinline__ double* Zb(int k, int comp) const { return W.Z + (2 * (int64_t)k + comp) * W.P; }
+    __device__ __forceinline__ double* dXb(int comp) const { return W.dX + comp * W.P; }
+    __device__ __forceinline__ FT* fac(int slot) const { return (FT*)W.fac + slot * W.P; }
+    __device__ __forceinline__ FT* tmpv(int comp) const { return (FT*)W.tmp + comp * W.P; }
+    __device__ __forceinline__ double* ftmp(int slot) const { return W.ftmp + slot * W.P; }
+    // this thread's chunk entry of per-chunk slot k (SoA over the chunks)
+    __device__ __forceinline__ double* red(int k) const { return W.red + cd.red + (int64_t)k * T + t; }
+
+    // ------------------------------------------------------------------
+    // Generic stencil sweep.  Thread t walks cells c = t*M + j, j = 0..M-1,
+    // carrying the left face; faces see (left state, right state).
+    // getx(s, n, phi) returns the state at a storage index; the cell functor
+    // receives both faces of each real cell; pad(s) is called for padding.
+    // ------------------------------------------------------------------
+    template <class FaceRec, class GetX, class FaceFn, class CellFn, class PadFn>
+    __device__ __forceinline__ void sweep(GetX getx, FaceFn face, CellFn cell, PadFn pad) {
+        const int M = cd.M, n = cd.n;
+        const int c0 = t * M;
+        if (c0 >= n) {
+            for (int j = 0; j < M; ++j) pad(sidx(t, j));
+            return;
+        }
+        const int64_t s0 = sidx(t, 0);
+        double nC, pC, nL, pL, ihL;
+        getx(s0, nC, pC);
+        if (c0 == 0) { nL = cd.nel; pL = cd.phil; ihL = 2.0 * ih; }
+        else { getx(sidx(t - 1, M - 1), nL, pL); ihL = ih; }
+        FaceRec FL = face(W.fa[s0], W.fg[s0], prm.has_u ? W.fw[s0] : 0.0, ihL, nL, pL, nC, pC);
+        for (int j = 0; j < M; ++j) {
+            const int c = c0 + j;
+            const int64_t s = sidx(t, j);
+            if (c >= n) { pad(s); continue; }
+            double nR, pR;
+            FaceRec FR;
+            if (c == n - 1) {
+                nR = cd.ner; pR = cd.phir;
+                FR = face(rR, gR, wR, 2.0 * ih, nC, pC, nR, pR);
+            } else {
+                const int64_t sn = (j + 1 < M) ? s + T : sidx(t + 1, 0);
+                getx(sn, nR, pR);
+                FR = face(W.fa[sn], W.fg[sn], prm.has_u ? W.fw[sn] : 0.0, ih, nC, pC, nR, pR);
+            }
+            cell(s, c, nC, pC, FL, FR);
+            nC = nR; pC = pR; FL = FR;
+        }
+    }
+
+    struct FluxRec { double gam, grd; };
+
+    // electron flux and potential gradient of one face
+    struct FluxFace {
+        __device__ __forceinline__ FluxRec operator()(double r, double g, double w, double ihf,
+                                                      double nA, double pA, double nB, double pB) const {
+            const double pe = w + r * (pB - pA);
+            double bx, bmx;
+            bernoulli_pair(pe, bx, bmx);
+            return {g * (bmx * nA - bx * nB), (pB - pA) * ihf};
+        }
+    };
+
+    // ------------------------------------------------------------------
+    // Residual F(X) at the state returned by getx; writes F (unscaled) and,
+    // optionally, the state itself; returns the scaled norms.
+    // ------------------------------------------------------------------
+    template <class GetX>
+    __device__ Norms residual(GetX getx, double* oF0, double* oF1, double* oX0, double* oX1,
+                              VecRef stepdir, double steplam) {
+        double mx[3] = {0.0, 0.0, 0.0};       // max|Fe|, max|Fp|, max|step|
+        double sm[4] = {0.0, 0.0, 0.0, 0.0};  // sum Fe^2, sum Fp^2, sum n^2, sum phi^2
+        const double dt_h = dth, eps_h = epsh;
+        const double* fv = W.f;
+        const double* kv = W.kd;
+        const double* qv = W.q;
+        const bool wantstep = stepdir.p0 != nullptr;
+        sweep<FluxRec>(getx, FluxFace{},
+            [&](int64_t s, int c, double nC, double pC, const FluxRec& L, const FluxRec& R) {
+                const double fe = -nC + fv[s] - kv[s] * nC - dt_h * (R.gam - L.gam);
+                const double fp = -nC + qv[s] + eps_h * (R.grd - L.grd);
+                oF0[s] = fe;
+                oF1[s] = fp;
+                if (oX0) { oX0[s] = nC; oX1[s] = pC; }
+                mx[0] = fmax(mx[0], fabs(fe));
+                mx[1] = fmax(mx[1], fabs(fp));
+                sm[0] += fe * fe;
+                sm[1] += fp * fp;
+                sm[2] += nC * nC;
+                sm[3] += pC * pC;
+                if (wantstep) {
+                    mx[2] = fmax(mx[2], fmax(fabs(steplam * stepdir.p0[s] * stepdir.s0),
+                                             fabs(steplam * stepdir.p1[s] * stepdir.s1)));
+                }
+            },
+            [&](int64_t s) {
+                oF0[s] = 0.0; oF1[s] = 0.0;
+                if (oX0) { oX0[s] = 0.0; oX1[s] = 0.0; }
+            });
+        double* scr = lds + Lds<T>::kScr;
+        wg_max<T, 3>(mx, scr);
+        wg_sum<T, 4>(sm, scr);
+        Norms r;
+        r.rinf = fmax(mx[0] * isfn, mx[1] * isfp);
+        r.r2 = sqrt(sm[0] * isfn * isfn + sm[1] * isfp * isfp);
+        r.xn2 = sm[2] / (sxn * sxn) + sm[3] / (sxp * sxp);
+        r.step = mx[2];
+        if (isnan(sm[0]) || isnan(sm[1])) r.r2 = NAN;
+        return r;
+    }
+
+    // ------------------------------------------------------------------
+    // Step setup: caller arrays -> workspace, scalings from X^n, initial
+    // guess candidates and the choice between them.  Returns the norms of
+    // the chosen guess; *cur receives its buffer.
+    // ------------------------------------------------------------------
+    __device__ Norms setup(const UserArrays& U, int* cur, int* guess_used) {
+        const int M = cd.M, n = cd.n;
+        const int c0 = t * M;
+        const double dt = cd.dt, hb = 0.5 * cd.h;
+        const int64_t fo = cd.uoff + cd.index;   // faces of column: n + 1 per column
+        double* X00 = xb(0, 0); double* X01 = xb(0, 1);
+        double* X10 = xb(1, 0); double* X11 = xb(1, 1);
+        double* X20 = xb(2, 0); double* X21 = xb(2, 1);
+        const bool extrap = prm.guess >= 1 && prm.has_prev;
+        const bool learn = prm.guess == 2 && prm.has_learned;
+        for (int j = 0; j < M; ++j) {
+            const int c = c0 + j;
+            const int64_t s = sidx(t, j);
+            if (c >= n) {
+                W.fa[s] = 0.0; W.fg[s] = 0.0;
+                if (prm.has_u) W.fw[s] = 0.0;
+                W.f[s] = 0.0; W.kd[s] = 0.0; W.q[s] = 0.0;
+                X00[s] = X01[s] = X10[s] = X11[s] = X20[s] = X21[s] = 0.0;
+                continue;
+            }
+            const int64_t u = cd.uoff + c;
+            const double mu = U.mu[u], D = U.diff[u];
+            double r, g, w = 0.0;
+            if (c == 0) {
+                r = mu / D;
+                g = (cd.bcl == 1) ? 0.0 : D / hb;
+                if (prm.has_u) w = U.uface[fo + c] * hb / D;
+            } else {
+                const double muf = 0.5 * (U.mu[u - 1] + mu);
+                const double Df = 0.5 * (U.diff[u - 1] + D);
+                r = muf / Df;
+                g = Df / cd.h;
+                if (prm.has_u) w = U.uface[fo + c] * cd.h / Df;
+            }
+            W.fa[s] = r; W.fg[s] = g;
+            if (prm.has_u) W.fw[s] = w;
+            const double ne = U.ne[u], ph = U.phi[u];
+            W.f[s] = ne + dt * U.src[u];
+            W.kd[s] = U.kloss ? dt * U.kloss[u] : 0.0;
+            W.q[s] = U.q[u];
+            X00[s] = ne; X01[s] = ph;
+            if (extrap) { X10[s] = 2.0 * ne - U.ne_prev[u]; X11[s] = 2.0 * ph - U.phi_prev[u]; }
+            if (learn) { X20[s] = U.ne_learn[u]; X21[s] = U.phi_learn[u]; }
+            if (c == n - 1) {
+                // right wall face: the last cell's mu and D at distance h/2
+                double* misc = lds + Lds<T>::kMisc;
+                misc[0] = mu / D;
+                misc[1] = (cd.bcr == 1) ? 0.0 : D / hb;
+                misc[2] = prm.has_u ? U.uface[fo + n] * hb / D : 0.0;
+            }
+        }
+        __syncthreads();
+        {
+            const double* misc = lds + Lds<T>::kMisc;
+            rR = misc[0]; gR = misc[1]; wR = misc[2];
+        }
+        __syncthreads();
+
+        // Sweep A: scalings from X^n (term magnitudes) + residual at X^n.
+        struct ScRec { double gam, grd, mag; };
+        double mx[5] = {0.0, 0.0, 0.0, 0.0, 0.0};     // te, tp, |n|, |q|, |phi|
+        double mr[2] = {0.0, 0.0};                    // max|Fe|, max|Fp|
+        double sm[4] = {0.0, 0.0, 0.0, 0.0};
+        {
+            const double dt_h = dth, eps_h = epsh;
+            double* F0 = Fb(0, 0); double* F1 = Fb(0, 1);
+            sweep<ScRec>(
+                [&](int64_t s, double& a, double& b) { a = X00[s]; b = X01[s]; },
+                [](double r, double g, double w, double ihf, double nA, double pA, double nB, double pB) {
+                    const double pe = w + r * (pB - pA);
+                    double bx, bmx;
+                    bernoulli_pair(pe, bx, bmx);
+                    ScRec o;
+                    o.gam = g * (bmx * nA - bx * nB);
+                    o.grd = (pB - pA) * ihf;
+                    o.mag = g * (bmx * fabs(nA) + bx * fabs(nB));
+                    return o;
+                },
+                [&](int64_t s, int c, double nC, double pC, const ScRec& L, const ScRec& R) {
+                    const double fv = W.f[s], kv = W.kd[s], qv = W.q[s];
+                    const double fe = -nC + fv - kv * nC - dt_h * (R.gam - L.gam);
+                    const double fp = -nC + qv + eps_h * (R.grd - L.grd);
+                    F0[s] = fe; F1[s] = fp;
+                    const double te = fabs(fv) + kv * fabs(nC) + dt_h * (L.mag + R.mag);
+                    const double tp = fabs(nC) + fabs(qv) + eps_h * (fabs(L.grd) + fabs(R.grd));
+                    mx[0] = fmax(mx[0], te);
+                    mx[1] = fmax(mx[1], tp);
+                    mx[2] = fmax(mx[2], fabs(nC));
+                    mx[3] = fmax(mx[3], fabs(qv));
+                    mx[4] = fmax(mx[4], fabs(pC));
+                    mr[0] = fmax(mr[0], fabs(fe));
+                    mr[1] = fmax(mr[1], fabs(fp));
+                    sm[0] += fe * fe; sm[1] += fp * fp;
+                    sm[2] += nC * nC; sm[3] += pC * pC;
+                },
+                [&](int64_t s) { F0[s] = 0.0; F1[s] = 0.0; });
+        }
+        double* scr = lds + Lds<T>::kScr;
+        wg_max<T, 5>(mx, scr);
+        wg_max<T, 2>(mr, scr);
+        wg_sum<T, 4>(sm, scr);
+        sfn = mx[0];
+        sfp = mx[1];
+        sxn = fmax(1.0, fmax(mx[2], mx[3]));
+        sxp = fmax(1.0, fmax(mx[4], fmax(fabs(cd.phil), fabs(cd.phir))));
+        // an all-zero column (no terms at all) keeps unit scales
+        if (!(sfn > 0.0)) sfn = 1.0;
+        if (!(sfp > 0.0)) sfp = 1.0;
+        isfn = 1.0 / sfn;
+        isfp = 1.0 / sfp;
+        Norms best;
+        best.rinf = fmax(mr[0] * isfn, mr[1] * isfp);
+        best.r2 = sqrt(sm[0] * isfn * isfn + sm[1] * isfp * isfp);
+        best.xn2 = sm[2] / (sxn * sxn) + sm[3] / (sxp * sxp);
+        best.step = INFINITY;
+        if (isnan(sm[0]) || isnan(sm[1])) best.r2 = NAN;
+        *cur = 0;
+        *guess_used = 0;
+        const VecRef none{nullptr, nullptr, 0.0, 0.0};
+        if (extrap) {
+            Norms e = residual([&](int64_t s, double& a, double& b) { a = X10[s]; b = X11[s]; },
+                               Fb(1, 0), Fb(1, 1), nullptr, nullptr, none, 0.0);
+            e.step = INFINITY;
+            // X^n or the extrapolation, whichever has the smaller scaled
+            // residual (ties to the extrapolation): after a sharp transient the
+            // extrapolated state can lie outside Newton's basin
+            if (!isnan(e.r2) && (isnan(best.r2) || e.rinf <= best.rinf)) {
+                best = e; *cur = 1; *guess_used = 1;
+            }
+        }
+        if (learn) {
+            Norms l = residual([&](int64_t s, double& a, double& b) { a = X20[s]; b = X21[s]; },
+                               Fb(2, 0), Fb(2, 1), nullptr, nullptr, none, 0.0);
+            l.step = INFINITY;
+            // fallback rule: the learned guess must beat the plain one strictly
+            if (!isnan(l.r2) && (isnan(best.r2) || l.rinf < best.rinf)) {
+                best = l; *cur = 2; *guess_used = 2;
+            }
+        }
+        if (t == 0) {
+            ColState* cs = W.cst + cd.index;
+            cs->sfn = sfn; cs->sfp = sfp; cs->sxn = sxn; cs->sxp = sxp;
+            cs->rR = rR; cs->gR = gR; cs->wR = wR;
+        }
+        return best;
+    }
+
+    // restore scalars kept in ColState (host-driven mode re-enters per phase)
+    __device__ void load_state() {
+        const ColState* cs = W.cst + cd.index;
+        sfn = cs->sfn; sfp = cs->sfp; sxn = cs->sxn; sxp = cs->sxp;
+        isfn = 1.0 / sfn; isfp = 1.0 / sfp;
+        rR = cs->rR; gR = cs->gR; wR = cs->wR;
+    }
+
+    // ------------------------------------------------------------------
+    // Jacobian assembly + factorisation (FP64 arithmetic; per-cell factors
+    // stored in FT; reduced per-chunk system kept and factored in FP64).
+    // Rows of chunk t: row 0 is the chunk's interface unknown x0(t); rows
+    // j >= 1 are eliminated into  x_j = d''_j - a''_j x0(t) - g''_j x0(t+1).
+    // ------------------------------------------------------------------
+    struct JacRec { double dnA, dnB, dpB, ihf; };
+
+    // derivatives of the face flux w.r.t. the left (A) and right (B) states
+    struct JacFace {
+        __device__ __forceinline__ JacRec operator()(double r, double g, double w, double ihf,
+                                                     double nA, double pA, double nB, double pB) const {
+            const double pe = w + r * (pB - pA);
+            double bx, bmx, dbx, dbmx;
+            bernoulli_pair(pe, bx, bmx);
+            bernoulli_dpair(pe, bx, bmx, dbx, dbmx);
+            JacRec o;
+            o.dnA = g * bmx;
+            o.dnB = -g * bx;
+            o.dpB = g * r * (-dbmx * nA - dbx * nB);
+            o.ihf = ihf;
+            return o;
+        }
+    };
+
+    __device__ void store_blk(int slot, int64_t s, const Blk<double>& m) {
+        fac(slot + 0)[s] = (FT)m.a; fac(slot + 1)[s] = (FT)m.b;
+        fac(slot + 2)[s] = (FT)m.c; fac(slot + 3)[s] = (FT)m.d;
+    }
+    __device__ Blk<FT> load_blk(int slot, int64_t s) const {
+        return {fac(slot + 0)[s], fac(slot + 1)[s], fac(slot + 2)[s], fac(slot + 3)[s]};
+    }
+
+    __device__ void factor(int cur) {
+        const int M = cd.M, n = cd.n;
+        const int c0 = t * M;
+        const double* X0 = xb(cur, 0);
+        const double* X1 = xb(cur, 1);
+        const double dt_h = dth, eps_h = epsh;
+        // scale factors of the four block entries
+        const double s_en = isfn * sxn, s_ep = isfn * sxp, s_pn = isfp * sxn, s_pp = isfp * sxp;
+        Blk<double> A0 = bzero(), B0 = beye(), C0 = bzero();
+        Blk<double> gprev = bzero(), aprev = bzero();
+        double* T0 = ftmp(0); double* T1 = ftmp(1); double* T2 = ftmp(2); double* T3 = ftmp(3);
+        double* T4 = ftmp(4); double* T5 = ftmp(5); double* T6 = ftmp(6); double* T7 = ftmp(7);
+
+        auto rowproc = [&](int j, int64_t s, const Blk<double>& A, const Blk<double>& B,
+                           const Blk<double>& C) {
+            if (j == 0) { A0 = A; B0 = B; C0 = C; return; }
+            Blk<double> m, al;
+            if (j == 1) {
+                m = binv(B);
+                al = bmul(m, A);
+            } else {
+                m = binv(bsub(B, bmul(A, gprev)));
+                al = bneg(bmul(m, bmul(A, aprev)));
+            }
+            const Blk<double> ga = bmul(m, C);
+            store_blk(0, s, m);
+            store_blk(4, s, bmul(m, A));
+            store_blk(8, s, ga);
+            T0[s] = al.a; T1[s] = al.b; T2[s] = al.c; T3[s] = al.d;
+            T4[s] = ga.a; T5[s] = ga.b; T6[s] = ga.c; T7[s] = ga.d;
+            gprev = ga; aprev = al;
+        };
+
+        sweep<JacRec>(
+            [&](int64_t s, double& a, double& b) { a = X0[s]; b = X1[s]; },
+            JacFace{},
+            [&](int64_t s, int c, double nC, double pC, const JacRec& L, const JacRec& R) {
+                const int j = c - c0;
+                const double kv = W.kd[s];
+                Blk<double> A, B, C;
+                B.a = (-1.0 - kv - dt_h * (R.dnA - L.dnB)) * s_en;
+                B.b = (dt_h * (R.dpB + L.dpB)) * s_ep;
+                B.c = -1.0 * s_pn;
+                B.d = (-eps_h * (R.ihf + L.ihf)) * s_pp;
+                if (c > 0) {
+                    A.a = dt_h * L.dnA * s_en;
+                    A.b = -dt_h * L.dpB * s_ep;
+                    A.c = 0.0;
+                    A.d = eps_h * L.ihf * s_pp;
+                } else {
+                    A = bzero();
+                }
+                if (c < n - 1) {
+                    C.a = -dt_h * R.dnB * s_en;
+                    C.b = -dt_h * R.dpB * s_ep;
+                    C.c = 0.0;
+                    C.d = eps_h * R.ihf * s_pp;
+                } else {
+                    C = bzero();
+                }
+                rowproc(j, s, A, B, C);
+            },
+            [&](int64_t s) {
+                const int j = (int)((s - cd.ws) / T);
+                rowproc(j, s, bzero(), beye(), bzero());
+            });
+
+        // up sweep: spikes a''_j, g''_j (FP64 recurrences from FP64 temps)
+        Blk<double> a1 = bzero(), g1 = bneg(beye()), aL = bneg(beye()), gL = bzero();
+        if (M >= 2) {
+            Blk<double> an = aprev, gn = gprev;   // row M-1
+            aL = an; gL = gn;
+            store_blk(12, sidx(t, M - 1), an);
+            store_blk(16, sidx(t, M - 1), gn);
+            for (int j = M - 2; j >= 1; --j) {
+                const int64_t s = sidx(t, j);
+                const Blk<double> al{T0[s], T1[s], T2[s], T3[s]};
+                const Blk<double> ga{T4[s], T5[s], T6[s], T7[s]};
+                an = bsub(al, bmul(ga, an));
+                gn = bneg(bmul(ga, gn));
+                store_blk(12, s, an);
+                store_blk(16, s, gn);
+            }
+            a1 = an; g1 = gn;
+        }
+        // reduced system row of chunk t
+        double* P = lds + Lds<T>::kPcr;
+        __syncthreads();
+        P[8 * t + 0] = aL.a; P[8 * t + 1] = aL.b; P[8 * t + 2] = aL.c; P[8 * t + 3] = aL.d;
+        P[8 * t + 4] = gL.a; P[8 * t + 5] = gL.b; P[8 * t + 6] = gL.c; P[8 * t + 7] = gL.d;
+        __syncthreads();
+        Blk<double> aLp = bzero(), gLp = bzero();
+        if (t > 0) {
+            aLp = {P[8 * (t - 1) + 0], P[8 * (t - 1) + 1], P[8 * (t - 1) + 2], P[8 * (t - 1) + 3]};
+            gLp = {P[8 * (t - 1) + 4], P[8 * (t - 1) + 5], P[8 * (t - 1) + 6], P[8 * (t - 1) + 7]};
+        }
+        Blk<double> Lr = bneg(bmul(A0, aLp));
+        Blk<double> Dr = bsub(bsub(B0, bmul(A0, gLp)), bmul(C0, a1));
+        Blk<double> Ur = bneg(bmul(C0, g1));
+        red(0)[0] = A0.a; red(1)[0] = A0.b; red(2)[0] = A0.c; red(3)[0] = A0.d;
+        red(4)[0] = C0.a; red(5)[0] = C0.b; red(6)[0] = C0.c; red(7)[0] = C0.d;
+        // parallel cyclic reduction (FP64)
+        int k = 8;
+        for (int st = 1; st < T; st <<= 1, k += 8) {
+            __syncthreads();
+            double* row = P + 12 * t;
+            row[0] = Lr.a; row[1] = Lr.b; row[2] = Lr.c; row[3] = Lr.d;
+            row[4] = Dr.a; row[5] = Dr.b; row[6] = Dr.c; row[7] = Dr.d;
+            row[8] = Ur.a; row[9] = Ur.b; row[10] = Ur.c; row[11] = Ur.d;
+            __syncthreads();
+            Blk<double> k1 = bzero(), k2 = bzero(), Lm = bzero(), Um = bzero(), Lp = bzero(), Up = bzero();
+            if (t >= st) {
+                const double* o = P + 12 * (t - st);
+                Lm = {o[0], o[1], o[2], o[3]};
+                const Blk<double> Dm{o[4], o[5], o[6], o[7]};
+                Um = {o[8], o[9], o[10], o[11]};
+                k1 = bmul(Lr, binv(Dm));
+            }
+            if (t + st < T) {
+                const double* o = P + 12 * (t + st);
+                Lp = {o[0], o[1], o[2], o[3]};
+                const Blk<double> Dp{o[4], o[5], o[6], o[7]};
+                Up = {o[8], o[9], o[10], o[11]};
+                k2 = bmul(Ur, binv(Dp));
+            }
+            Dr = bsub(bsub(Dr, bmul(k1, Um)), bmul(k2, Lp));
+            Lr = bneg(bmul(k1, Lm));
+            Ur = bneg(bmul(k2, Up));
+            red(k + 0)[0] = k1.a; red(k + 1)[0] = k1.b; red(k + 2)[0] = k1.c; red(k + 3)[0] = k1.d;
+            red(k + 4)[0] = k2.a; red(k + 5)[0] = k2.b; red(k + 6)[0] = k2.c; red(k + 7)[0] = k2.d;
+        }
+        const Blk<double> Di = binv(Dr);
+        red(k + 0)[0] = Di.a; red(k + 1)[0] = Di.b; red(k + 2)[0] = Di.c; red(k + 3)[0] = Di.d;
+        __syncthreads();
+    }
+
+    // ------------------------------------------------------------------
+    // Preconditioner apply z = P^-1 v (chunk sweeps in FT, reduced system
+    // in FP64).  Returns (||z||_2^2, ||z||_inf).  v and z must not alias.
+    // ------------------------------------------------------------------
+    __device__ Vec2<double> apply(const VecRef& v, double* z0, double* z1) {
+        const int M = cd.M;
+        FT* D0 = tmpv(0);
+        FT* D1 = tmpv(1);
+        Vec2<double> d0{v.p0[sidx(t, 0)] * v.s0, v.p1[sidx(t, 0)] * v.s1};
+        Vec2<FT> dprev{FT(0), FT(0)};
+        for (int j = 1; j < M; ++j) {
+            const int64_t s = sidx(t, j);
+            const Vec2<FT> d{(FT)(v.p0[s] * v.s0), (FT)(v.p1[s] * v.s1)};
+            const Blk<FT> m = load_blk(0, s);
+            Vec2<FT> de = bmv(m, d);
+            if (j >= 2) {
+                const Blk<FT> at = load_blk(4, s);
+                const Vec2<FT> q = bmv(at, dprev);
+                de.x -= q.x; de.y -= q.y;
+            }
+            D0[s] = de.x; D1[s] = de.y;
+            dprev = de;
+        }
+        // up sweep: d''_j = d_j - g_j d''_{j+1}
+        Vec2<FT> dn = dprev;      // row M-1 (d'' = d)
+        Vec2<double> dLast{0.0, 0.0}, dFirst{0.0, 0.0};
+        if (M >= 2) {
+            dLast = {(double)dn.x, (double)dn.y};
+            for (int j = M - 2; j >= 1; --j) {
+                const int64_t s = sidx(t, j);
+                const Blk<FT> g = load_blk(8, s);
+                const Vec2<FT> q = bmv(g, dn);
+                dn = {D0[s] - q.x, D1[s] - q.y};
+                D0[s] = dn.x; D1[s] = dn.y;
+            }
+            dFirst = {(double)dn.x, (double)dn.y};
+        }
+        double* P = lds + Lds<T>::kPcr;
+        __syncthreads();
+        P[2 * t] = dLast.x; P[2 * t + 1] = dLast.y;
+        __syncthreads();
+        Vec2<double> dLp{0.0, 0.0};
+        if (t > 0) dLp = {P[2 * (t - 1)], P[2 * (t - 1) + 1]};
+        const Blk<double> A0{red(0)[0], red(1)[0], red(2)[0], red(3)[0]};
+        const Blk<double> C0{red(4)[0], red(5)[0], red(6)[0], red(7)[0]};
+        const Vec2<double> qa = bmv(A0, dLp), qc = bmv(C0, dFirst);
+        Vec2<double> r{d0.x - qa.x - qc.x, d0.y - qa.y - qc.y};
+        int k = 8;
+        for (int st = 1; st < T; st <<= 1, k += 8) {
+            __syncthreads();
+            P[2 * t] = r.x; P[2 * t + 1] = r.y;
+            __syncthreads();
+            if (t >= st) {
+                const Blk<double> k1{red(k)[0], red(k + 1)[0], red(k + 2)[0], red(k + 3)[0]};
+                const Vec2<double> q = bmv(k1, Vec2<double>{P[2 * (t - st)], P[2 * (t - st) + 1]});
+                r.x -= q.x; r.y -= q.y;
+            }
+            if (t + st < T) {
+                const Blk<double> k2{red(k + 4)[0], red(k + 5)[0], red(k + 6)[0], red(k + 7)[0]};
+                const Vec2<double> q = bmv(k2, Vec2<double>{P[2 * (t + st)], P[2 * (t + st) + 1]});
+                r.x -= q.x; r.y -= q.y;
+            }
+        }
+        const Blk<double> Di{red(k)[0], red(k + 1)[0], red(k + 2)[0], red(k + 3)[0]};
+        const Vec2<double> x0 = bmv(Di, r);
+        __syncthreads();
+        P[2 * t] = x0.x; P[2 * t + 1] = x0.y;
+        __syncthreads();
+        Vec2<double> xn{0.0, 0.0};
+        if (t + 1 < T) xn = {P[2 * (t + 1)], P[2 * (t + 1) + 1]};
+        double zz = 0.0, zm = 0.0;
+        {
+            const int64_t s = sidx(t, 0);
+            z0[s] = x0.x; z1[s] = x0.y;
+            zz += x0.x * x0.x + x0.y * x0.y;
+            zm = fmax(fabs(x0.x), fabs(x0.y));
+        }
+        for (int j = 1; j < M; ++j) {
+            const int64_t s = sidx(t, j);
+            const Blk<FT> a = load_blk(12, s);
+            const Blk<FT> g = load_blk(16, s);
+            const double zx = (double)D0[s] - ((double)a.a * x0.x + (double)a.b * x0.y) -
+                              ((double)g.a * xn.x + (double)g.b * xn.y);
+            const double zy = (double)D1[s] - ((double)a.c * x0.x + (double)a.d * x0.y) -
+                              ((double)g.c * xn.x + (double)g.d * xn.y);
+            z0[s] = zx; z1[s] = zy;
+            zz += zx * zx + zy * zy;
+            zm = fmax(zm, fmax(fabs(zx), fabs(zy)));
+        }
+        double sm[1] = {zz};
+        double mm[1] = {zm};
+        wg_sum<T, 1>(sm, lds + Lds<T>::kScr);
+        wg_max<T, 1>(mm, lds + Lds<T>::kScr);
+        return Vec2<double>{sm[0], mm[0]};
+    }
+
+    // ------------------------------------------------------------------
+    // Finite-difference product w = S_F^-1 [F(X + eps S_X z) - F(X)] / eps,
+    // written to (w0, w1), fused with up to 8 dot products against basis
+    // vectors and ||w||^2 (dots[nb] on return).
+    // ------------------------------------------------------------------
+    __device__ void jv(int cur, const VecRef& z, double eps, double* w0, double* w1,
+                       const VecRef* basis, int nb, double* dots) {
+        const double* X0 = xb(cur, 0);
+        const double* X1 = xb(cur, 1);
+        const double* F0 = Fb(cur, 0);
+        const double* F1 = Fb(cur, 1);
+        const double e0 = eps * sxn * z.s0, e1 = eps * sxp * z.s1;
+        const double c0 = isfn / eps, c1 = isfp / eps;
+        const double dt_h = dth, eps_h = epsh;
+        double acc[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) acc[i] = 0.0;
+        const int nbf = nb < 8 ? nb : 8;
+        sweep<FluxRec>(
+            [&](int64_t s, double& a, double& b) { a = X0[s] + e0 * z.p0[s]; b = X1[s] + e1 * z.p1[s]; },
+            FluxFace{},
+            [&](int64_t s, int c, double nC, double pC, const FluxRec& L, const FluxRec& R) {
+                const double fe = -nC + W.f[s] - W.kd[s] * nC - dt_h * (R.gam - L.gam);
+                const double fp = -nC + W.q[s] + eps_h * (R.grd - L.grd);
+                const double a = (fe - F0[s]) * c0;
+                const double b = (fp - F1[s]) * c1;
+                w0[s] = a; w1[s] = b;
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (i < nbf) acc[i] += basis[i].p0[s] * basis[i].s0 * a + basis[i].p1[s] * basis[i].s1 * b;
+                acc[8] += a * a + b * b;
+            },
+            [&](int64_t s) { w0[s] = 0.0; w1[s] = 0.0; });
+        wg_sum<T, 9>(acc, lds + Lds<T>::kScr);
+        for (int i = 0; i < nbf; ++i) dots[i] = acc[i];
+        if (nb > 8) dots_more(w0, w1, basis, 8, nb, dots);
+        dots[nb] = acc[8];
+    }
+
+    // dots[i] = basis[i] . w for i in [i0, nb)
+    __device__ void dots_more(const double* w0, const double* w1, const VecRef* basis, int i0, int nb,
+                              double* dots) {
+        const int M = cd.M;
+        for (int g = i0; g < nb; g += 8) {
+            double acc[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) acc[i] = 0.0;
+            for (int j = 0; j < M; ++j) {
+                const int64_t s = sidx(t, j);
+                const double a = w0[s], b = w1[s];
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (g + i < nb) acc[i] += basis[g + i].p0[s] * basis[g + i].s0 * a + basis[g + i].p1[s] * basis[g + i].s1 * b;
+            }
+            wg_sum<T, 8>(acc, lds + Lds<T>::kScr);
+            for (int i = 0; i < 8 && g + i < nb; ++i) dots[g + i] = acc[i];
+        }
+    }
+
+    // One classical Gram-Schmidt pass: w -= sum_i h[i] basis[i]; then
+    // dots[i] = basis[i] . w (i < nb) and dots[nb] = ||w||^2.
+    __device__ void cgs_pass(double* w0, double* w1, const VecRef* basis, int nb, const double* h,
+                             double* dots) {
+        const int M = cd.M;
+        double acc[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) acc[i] = 0.0;
+        const int nbf = nb < 8 ? nb : 8;
+        for (int j = 0; j < M; ++j) {
+            const int64_t s = sidx(t, j);
+            double a = w0[s], b = w1[s];
+            for (int i = 0; i < nb; ++i) {
+                a -= h[i] * basis[i].p0[s] * basis[i].s0;
+                b -= h[i] * basis[i].p1[s] * basis[i].s1;
+            }
+            w0[s] = a; w1[s] = b;
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (i < nbf) acc[i] += basis[i].p0[s] * basis[i].s0 * a + basis[i].p1[s] * basis[i].s1 * b;
+            acc[8] += a * a + b * b;
+        }
+        wg_sum<T, 9>(acc, lds + Lds<T>::kScr);
+        for (int i = 0; i < nbf; ++i) dots[i] = acc[i];
+        if (nb > 8) dots_more(w0, w1, basis, 8, nb, dots);
+        dots[nb] = acc[8];
+    }
+
+    // out = (accumulate ? out : 0) + sum_i c[i] vecs[i]
+    __device__ void lincomb(double* o0, double* o1, const VecRef* vecs, const double* c, int nv,
+                            bool accumulate) {
+        const int M = cd.M;
+        for (int j = 0; j < M; ++j) {
+            const int64_t s = sidx(t, j);
+            double a = accumulate ? o0[s] : 0.0, b = accumulate ? o1[s] : 0.0;
+            for (int i = 0; i < nv; ++i) {
+                a += c[i] * vecs[i].p0[s] * vecs[i].s0;
+                b += c[i] * vecs[i].p1[s] * vecs[i].s1;
+            }
+            o0[s] = a; o1[s] = b;
+        }
+        __syncthreads();
+    }
+
+    // Line-search trial X_t = X + lam S_X d, its residual and norms.
+    __device__ Norms trial(int cur, int out, const VecRef& d, double lam) {
+        const double* X0 = xb(cur, 0);
+        const double* X1 = xb(cur, 1);
+        const double a0 = lam * sxn * d.s0, a1 = lam * sxp * d.s1;
+        return residual(
+            [&](int64_t s, double& a, double& b) { a = X0[s] + a0 * d.p0[s]; b = X1[s] + a1 * d.p1[s]; },
+            Fb(out, 0), Fb(out, 1), xb(out, 0), xb(out, 1), d, lam);
+    }
+
+    // Residual of buffer b (test export / re-evaluation)
+    __device__ Norms eval(int b) {
+        const double* X0 = xb(b, 0);
+        const double* X1 = xb(b, 1);
+        const VecRef none{nullptr, nullptr, 0.0, 0.0};
+        return residual([&](int64_t s, double& a, double& c) { a = X0[s]; c = X1[s]; },
+                        Fb(b, 0), Fb(b, 1), nullptr, nullptr, none, 0.0);
+    }
+
+    // Workspace buffer -> caller arrays (natural layout)
+    __device__ void write_back(const double* s0p, const double* s1p, double* o0, double* o1) {
+        const int M = cd.M, n = cd.n;
+        for (int j = 0; j < M; ++j) {
+            const int c = t * M + j;
+            if (c >= n) break;
+            const int64_t s = sidx(t, j);
+            o0[cd.uoff + c] = s0p[s];
+            o1[cd.uoff + c] = s1p[s];
+        }
+    }
+};
+
+}  // namespace jfnk

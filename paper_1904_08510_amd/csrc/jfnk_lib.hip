@@ -1,0 +1,829 @@
+// libjfnk: kernels and host runtime of the C ABI declared in include/jfnk.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/jfnk.h"
+#include "jfnk_solver.h"
+
+using namespace jfnk;
+
+namespace {
+
+constexpr int kTmax = 512;          // largest workgroup that owns a column
+constexpr int kScalSlots = 64;      // doubles of scalar exchange per column
+
+// ---------------------------------------------------------------------------
+// Batched schedule: one workgroup per column, whole step in one launch.
+// ---------------------------------------------------------------------------
+struct SolveArgs {
+    Work W;
+    SolverParams prm;
+    UserArrays U;
+    const int* order;   // blockIdx -> column
+};
+
+template <int T, class FT>
+__global__ __launch_bounds__(T) void k_solve(SolveArgs a) {
+    extern __shared__ double lds[];
+    const int ci = a.order[blockIdx.x];
+    DevExec<T, FT> ex;
+    ex.col.init(a.W.cols[ci], a.W, a.prm, lds);
+    ex.U = a.U;
+    ColOutcome o;
+    jfnk_solve(ex, a.prm, o);
+}
+
+// ---------------------------------------------------------------------------
+// Plain schedule: one kernel per phase of one column; scalars go back to the
+// host through W.scal.
+// ---------------------------------------------------------------------------
+enum Phase {
+    PH_SETUP, PH_FACTOR, PH_APPLY, PH_JV, PH_CGS, PH_LINCOMB, PH_NORM_DX, PH_RES0, PH_TRIAL,
+    PH_FINAL, PH_EVAL, PH_LOAD_X, PH_LOAD_V, PH_STORE_V, PH_STORE_W, PH_STORE_F
+};
+
+struct PhaseArgs {
+    Work W;
+    SolverParams prm;
+    UserArrays U;
+    int ci;
+    int phase;
+    int cur, out, zslot, wslot, nb, acc;
+    double eps, lam;
+    VecRef v;
+    VecRef basis[kMaxRestart + 1];
+    double h[kMaxRestart + 2];
+    ColOutcome o;
+    const double* in0;
+    const double* in1;
+    double* out0;
+    double* out1;
+};
+
+template <int T, class FT>
+__global__ __launch_bounds__(T) void k_phase(PhaseArgs a) {
+    extern __shared__ double lds[];
+    Column<T, FT> col;
+    col.init(a.W.cols[a.ci], a.W, a.prm, lds);
+    double* scal = a.W.scal + (int64_t)a.ci * kScalSlots;
+    VecRef* bl = (VecRef*)(lds + Lds<T>::kBasis);
+    if (a.phase != PH_SETUP) col.load_state();
+    if (a.phase == PH_JV || a.phase == PH_CGS) {
+        if (threadIdx.x == 0)
+            for (int i = 0; i < a.nb; ++i) bl[i] = a.basis[i];
+        __syncthreads();
+    }
+    switch (a.phase) {
+    case PH_SETUP: {
+        int cur, g;
+        const Norms n = col.setup(a.U, &cur, &g);
+        if (threadIdx.x == 0) {
+            scal[0] = cur; scal[1] = g; scal[2] = n.rinf; scal[3] = n.r2; scal[4] = n.xn2;
+            scal[5] = n.step; scal[6] = col.sfn; scal[7] = col.sfp; scal[8] = col.sxn; scal[9] = col.sxp;
+        }
+        break;
+    }
+    case PH_FACTOR:
+        col.factor(a.cur);
+        break;
+    case PH_APPLY: {
+        const Vec2<double> z = col.apply(a.v, col.Zb(a.zslot, 0), col.Zb(a.zslot, 1));
+        if (threadIdx.x == 0) { scal[0] = z.x; scal[1] = z.y; }
+        break;
+    }
+    case PH_JV: {
+        double dots[kMaxRestart + 2];
+        const VecRef z = (a.zslot >= 0) ? VecRef{col.Zb(a.zslot, 0), col.Zb(a.zslot, 1), 1.0, 1.0}
+                                        : a.v;
+        col.jv(a.cur, z, a.eps, col.Vb(a.wslot, 0), col.Vb(a.wslot, 1), bl, a.nb, dots);
+        if (threadIdx.x == 0)
+            for (int i = 0; i <= a.nb; ++i) scal[i] = dots[i];
+        break;
+    }
+    case PH_CGS: {
+        double dots[kMaxRestart + 2];
+        col.cgs_pass(col.Vb(a.wslot, 0), col.Vb(a.wslot, 1), bl, a.nb, a.h, dots);
+        if (threadIdx.x == 0)
+            for (int i = 0; i <= a.nb; ++i) scal[i] = dots[i];
+        break;
+    }
+    case PH_LINCOMB: {
+        VecRef zs[kMaxRestart];
+        for (int i = 0; i < a.nb; ++i) zs[i] = VecRef{col.Zb(i, 0), col.Zb(i, 1), 1.0, 1.0};
+        col.lincomb(col.dXb(0), col.dXb(1), zs, a.h, a.nb, a.acc != 0);
+        break;
+    }
+    case PH_NORM_DX: {
+        double dd[1] = {0.0};
+        const double* d0 = col.dXb(0);
+        const double* d1 = col.dXb(1);
+        for (int j = 0; j < col.cd.M; ++j) {
+            const int64_t s = col.sidx(col.t, j);
+            dd[0] += d0[s] * d0[s] + d1[s] * d1[s];
+        }
+        wg_sum<T, 1>(dd, lds + Lds<T>::kScr);
+        if (threadIdx.x == 0) scal[0] = dd[0];
+        break;
+    }
+    case PH_RES0: {
+        double* v0 = col.Vb(0, 0);
+        double* v1 = col.Vb(0, 1);
+        const double* F0 = col.Fb(a.cur, 0);
+        const double* F1 = col.Fb(a.cur, 1);
+        double acc[1] = {0.0};
+        for (int j = 0; j < col.cd.M; ++j) {
+            const int64_t s = col.sidx(col.t, j);
+            const double x = -F0[s] * col.isfn - v0[s];
+            const double y = -F1[s] * col.isfp - v1[s];
+            v0[s] = x; v1[s] = y;
+            acc[0] += x * x + y * y;
+        }
+        wg_sum<T, 1>(acc, lds + Lds<T>::kScr);
+        if (threadIdx.x == 0) scal[0] = acc[0];
+        break;
+    }
+    case PH_TRIAL: {
+        const Norms n = col.trial(a.cur, a.out, a.v, a.lam);
+        if (threadIdx.x == 0) { scal[0] = n.rinf; scal[1] = n.r2; scal[2] = n.xn2; scal[3] = n.step; }
+        break;
+    }
+    case PH_FINAL: {
+        col.write_back(col.xb(a.o.cur, 0), col.xb(a.o.cur, 1), a.U.ne, a.U.phi);
+        if (threadIdx.x == 0) {
+            ColState* cs = a.W.cst + col.cd.index;
+            cs->res_inf = a.o.rinf; cs->res2 = a.o.r2; cs->status = a.o.status;
+            cs->newton = a.o.newton; cs->gmres = a.o.gmres; cs->backtracks = a.o.backtracks;
+            cs->guess = a.o.guess; cs->restarts = a.o.restarts;
+        }
+        break;
+    }
+    case PH_EVAL: {
+        const Norms n = col.eval(a.cur);
+        if (threadIdx.x == 0) { scal[0] = n.rinf; scal[1] = n.r2; scal[2] = n.xn2; }
+        break;
+    }
+    case PH_LOAD_X:
+    case PH_LOAD_V: {
+        // natural-layout caller arrays -> buffer (x[cur] or Z[zslot])
+        double* o0 = (a.phase == PH_LOAD_X) ? col.xb(a.cur, 0) : col.Zb(a.zslot, 0);
+        double* o1 = (a.phase == PH_LOAD_X) ? col.xb(a.cur, 1) : col.Zb(a.zslot, 1);
+        for (int j = 0; j < col.cd.M; ++j) {
+            const int c = col.t * col.cd.M + j;
+            const int64_t s = col.sidx(col.t, j);
+            if (c < col.cd.n) { o0[s] = a.in0[col.cd.uoff + c]; o1[s] = a.in1[col.cd.uoff + c]; }
+            else { o0[s] = 0.0; o1[s] = 0.0; }
+        }
+        __syncthreads();
+        break;
+    }
+    case PH_STORE_V:
+        col.write_back(col.Zb(a.zslot, 0), col.Zb(a.zslot, 1), a.out0, a.out1);
+        break;
+    case PH_STORE_W:
+        col.write_back(col.Vb(a.wslot, 0), col.Vb(a.wslot, 1), a.out0, a.out1);
+        break;
+    case PH_STORE_F:
+        col.write_back(col.Fb(a.cur, 0), col.Fb(a.cur, 1), a.out0, a.out1);
+        break;
+    default:
+        break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host context
+// ---------------------------------------------------------------------------
+}  // namespace
+
+struct jfnk_ctx {
+    jfnk_config cfg{};
+    int device = 0;
+    int64_t capP = 0;
+    int64_t capRed = 0;
+    char* base = nullptr;        // single workspace allocation
+    Work W{};
+    int* d_order = nullptr;
+    ColDesc* h_cols = nullptr;   // pinned
+    ColState* h_cst = nullptr;   // pinned
+    double* h_scal = nullptr;    // pinned
+    int* h_order = nullptr;      // pinned
+    std::string err;
+    bool poisoned = false;
+    int Tsel = 0;                // workgroup size of the last schedule
+};
+
+namespace {
+
+int fail(jfnk_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIP_OK(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            ctx->poisoned = true;                                                        \
+            return fail(ctx, JFNK_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+        }                                                                                \
+    } while (0)
+
+int choose_T(const jfnk_config& cfg, int nmax) {
+    if (cfg.threads_override > 0) return cfg.threads_override;
+    // chunk of <= 16 cells per thread where possible
+    int T = 64;
+    while (T < kTmax && (nmax + T - 1) / T > 16) T <<= 1;
+    return T;
+}
+
+int64_t work_doubles_per_cell(int m) {
+    // fa fg fw f kd q (6) x (6) F (6) V (2(m+1)) Z (2m) dX (2) ftmp (8)
+    // fac (20, sized for FP64) tmp (2, sized for FP64)
+    return 6 + 6 + 6 + 2 * (m + 1) + 2 * m + 2 + kTempSlots + kFactorSlots + 2;
+}
+
+void carve(jfnk_ctx* c) {
+    const int64_t P = c->capP;
+    const int m = c->cfg.gmres_restart;
+    double* p = (double*)c->base;
+    auto take = [&](int64_t n) { double* r = p; p += n; return r; };
+    Work& W = c->W;
+    W.P = P;
+    W.fa = take(P); W.fg = take(P); W.fw = take(P);
+    W.f = take(P); W.kd = take(P); W.q = take(P);
+    W.x = take(6 * P); W.F = take(6 * P);
+    W.V = take(2 * (int64_t)(m + 1) * P);
+    W.Z = take(2 * (int64_t)m * P);
+    W.dX = take(2 * P);
+    W.ftmp = take((int64_t)kTempSlots * P);
+    W.fac = (void*)take((int64_t)kFactorSlots * P);
+    W.tmp = (void*)take(2 * P);
+    W.red = take(c->capRed);
+    W.cols = (ColDesc*)take((c->cfg.max_cols * (int64_t)sizeof(ColDesc) + 7) / 8);
+    W.cst = (ColState*)take((c->cfg.max_cols * (int64_t)sizeof(ColState) + 7) / 8);
+    W.scal = take((int64_t)c->cfg.max_cols * kScalSlots);
+}
+
+// validation of the problem; fills the schedule on success
+int validate(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x) {
+    if (!p || !x) return fail(ctx, JFNK_EINVAL, "null problem or state");
+    if (p->ncols < 1) return fail(ctx, JFNK_EINVAL, "ncols < 1");
+    if (p->ncols > ctx->cfg.max_cols) return fail(ctx, JFNK_ECAPACITY, "ncols exceeds capacity");
+    if (!p->col_offset || !p->length || !p->dt || !p->phi_left || !p->phi_right || !p->eps_over_e ||
+        !p->bc_left || !p->bc_right || !p->ne_left || !p->ne_right)
+        return fail(ctx, JFNK_EINVAL, "null per-column array");
+    if (!p->mu || !p->diff || !p->src || !p->q_ion || !x->ne || !x->phi)
+        return fail(ctx, JFNK_EINVAL, "null per-cell array");
+    if ((x->ne_prev == nullptr) != (x->phi_prev == nullptr))
+        return fail(ctx, JFNK_EINVAL, "ne_prev and phi_prev must both be given or both NULL");
+    if (p->col_offset[0] != 0) return fail(ctx, JFNK_EINVAL, "col_offset[0] != 0");
+    int nmax = 0;
+    for (int c = 0; c < p->ncols; ++c) {
+        const int64_t n = p->col_offset[c + 1] - p->col_offset[c];
+        if (n < 3) return fail(ctx, JFNK_EINVAL, "column with fewer than 3 cells");
+        if (n > ctx->cfg.max_cells_per_col) return fail(ctx, JFNK_ECAPACITY, "column longer than capacity");
+        nmax = std::max<int>(nmax, (int)n);
+        const double v[7] = {p->length[c], p->dt[c], p->phi_left[c], p->phi_right[c], p->eps_over_e[c],
+                             p->ne_left[c], p->ne_right[c]};
+        for (double d : v)
+            if (!std::isfinite(d)) return fail(ctx, JFNK_EINVAL, "non-finite per-column scalar");
+        if (!(p->length[c] > 0.0) || !(p->dt[c] > 0.0) || !(p->eps_over_e[c] > 0.0))
+            return fail(ctx, JFNK_EINVAL, "length, dt and eps_over_e must be > 0");
+        if ((p->bc_left[c] != 0 && p->bc_left[c] != 1) || (p->bc_right[c] != 0 && p->bc_right[c] != 1))
+            return fail(ctx, JFNK_EINVAL, "bad boundary condition code");
+    }
+    if (p->col_offset[p->ncols] > ctx->cfg.max_total_cells)
+        return fail(ctx, JFNK_ECAPACITY, "total cells exceed capacity");
+    const int T = choose_T(ctx->cfg, nmax);
+    int64_t ws = 0, red = 0;
+    for (int c = 0; c < p->ncols; ++c) {
+        const int n = (int)(p->col_offset[c + 1] - p->col_offset[c]);
+        const int M = (n + T - 1) / T;
+        ColDesc& d = ctx->h_cols[c];
+        d.n = n; d.M = M; d.bcl = p->bc_left[c]; d.bcr = p->bc_right[c];
+        d.index = c; d.T = T;
+        d.uoff = p->col_offset[c]; d.ws = ws; d.red = red;
+        d.h = p->length[c] / n; d.dt = p->dt[c];
+        d.phil = p->phi_left[c]; d.phir = p->phi_right[c];
+        d.eps = p->eps_over_e[c]; d.nel = p->ne_left[c]; d.ner = p->ne_right[c];
+        ws += (int64_t)T * M;
+        red += (int64_t)T * kRedPerChunk;
+    }
+    if (ws > ctx->capP || red > ctx->capRed) return fail(ctx, JFNK_ECAPACITY, "padded workspace exceeds capacity");
+    // longest columns first: the dispatcher then balances the tail (LPT)
+    std::vector<int> ord(p->ncols);
+    for (int c = 0; c < p->ncols; ++c) ord[c] = c;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return ctx->h_cols[a].n > ctx->h_cols[b].n; });
+    for (int c = 0; c < p->ncols; ++c) ctx->h_order[c] = ord[c];
+    ctx->Tsel = T;
+    return JFNK_OK;
+}
+
+SolverParams make_params(const jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x) {
+    SolverParams s{};
+    s.m = ctx->cfg.gmres_restart;
+    s.max_restarts = ctx->cfg.max_restarts;
+    s.max_newton = ctx->cfg.max_newton;
+    s.max_backtracks = ctx->cfg.max_backtracks;
+    s.guess = ctx->cfg.guess;
+    s.has_prev = x->ne_prev != nullptr;
+    s.has_learned = 0;
+    s.has_u = p->u_face != nullptr;
+    s.tol_f = ctx->cfg.tol_f;
+    s.tol_x = ctx->cfg.tol_x;
+    s.gamma = ctx->cfg.gamma;
+    s.alpha = ctx->cfg.armijo_alpha;
+    return s;
+}
+
+UserArrays make_user(const jfnk_problem* p, jfnk_state* x) {
+    UserArrays U{};
+    U.mu = p->mu; U.diff = p->diff; U.src = p->src; U.kloss = p->k_loss; U.q = p->q_ion;
+    U.uface = p->u_face;
+    U.ne = x->ne; U.phi = x->phi;
+    U.ne_prev = x->ne_prev; U.phi_prev = x->phi_prev;
+    U.ne_learn = nullptr; U.phi_learn = nullptr;
+    return U;
+}
+
+// ---------------------------------------------------------------------------
+// Host-driven executor of the control logic (plain schedule).
+// ---------------------------------------------------------------------------
+template <int T, class FT>
+struct HostExecT {
+    jfnk_ctx* ctx;
+    hipStream_t st;
+    PhaseArgs a;
+    hipError_t herr = hipSuccess;
+    double sfn = 1, sfp = 1, isfn = 1, isfp = 1;
+    VecRef bas[kMaxRestart + 1];
+    double H[(kMaxRestart + 1) * kMaxRestart];
+    double cs[kMaxRestart], sn[kMaxRestart], g[kMaxRestart + 1];
+    bool implicit_dir = false;
+    double implicit_y = 0.0;
+
+    const ColDesc& cd() const { return ctx->h_cols[a.ci]; }
+    double* xb(int b, int comp) const { return ctx->W.x + (2 * b + comp) * ctx->W.P; }
+    double* Fb(int b, int comp) const { return ctx->W.F + (2 * b + comp) * ctx->W.P; }
+    double* Vb(int k, int comp) const { return ctx->W.V + (2 * (int64_t)k + comp) * ctx->W.P; }
+    double* Zb(int k, int comp) const { return ctx->W.Z + (2 * (int64_t)k + comp) * ctx->W.P; }
+    double* dXb(int comp) const { return ctx->W.dX + comp * ctx->W.P; }
+
+    void launch(int phase) {
+        a.phase = phase;
+        if (herr != hipSuccess) return;
+        hipLaunchKernelGGL((k_phase<T, FT>), dim3(1), dim3(T), Lds<T>::bytes(), st, a);
+        herr = hipGetLastError();
+    }
+    const double* fetch(int n) {
+        double* hs = ctx->h_scal;
+        if (herr != hipSuccess) { for (int i = 0; i < n; ++i) hs[i] = NAN; return hs; }
+        herr = hipMemcpyAsync(hs, ctx->W.scal + (int64_t)a.ci * kScalSlots, sizeof(double) * n,
+                              hipMemcpyDeviceToHost, st);
+        if (herr == hipSuccess) herr = hipStreamSynchronize(st);
+        if (herr != hipSuccess) for (int i = 0; i < n; ++i) hs[i] = NAN;
+        return hs;
+    }
+
+    Norms setup(int* cur, int* guess) {
+        launch(PH_SETUP);
+        const double* s = fetch(10);
+        *cur = (int)s[0]; *guess = (int)s[1];
+        Norms n{s[2], s[3], s[4], s[5]};
+        sfn = s[6]; sfp = s[7];
+        isfn = 1.0 / sfn; isfp = 1.0 / sfp;
+        if (herr != hipSuccess) n.r2 = NAN;
+        return n;
+    }
+    void factor(int cur) { a.cur = cur; launch(PH_FACTOR); }
+    VecRef fref(int cur, double sc) { return VecRef{Fb(cur, 0), Fb(cur, 1), sc * isfn, sc * isfp}; }
+    VecRef vslot(int k, double sc) { return VecRef{Vb(k, 0), Vb(k, 1), sc, sc}; }
+    void set_basis(int i, VecRef r) { bas[i] = r; }
+    VecRef basis(int i) { return bas[i]; }
+    Vec2<double> apply(const VecRef& v, int zslot) {
+        a.v = v; a.zslot = zslot;
+        launch(PH_APPLY);
+        const double* s = fetch(2);
+        return Vec2<double>{s[0], s[1]};
+    }
+    void jv(int cur, int zslot, double eps, int wslot, double* dots) {
+        a.cur = cur; a.zslot = zslot; a.eps = eps; a.wslot = wslot; a.nb = wslot;
+        for (int i = 0; i < wslot; ++i) a.basis[i] = bas[i];
+        launch(PH_JV);
+        const double* s = fetch(wslot + 1);
+        for (int i = 0; i <= wslot; ++i) dots[i] = s[i];
+    }
+    void cgs(int wslot, int nb, const double* h, double* dots) {
+        a.wslot = wslot; a.nb = nb;
+        for (int i = 0; i < nb; ++i) { a.basis[i] = bas[i]; a.h[i] = h[i]; }
+        launch(PH_CGS);
+        const double* s = fetch(nb + 1);
+        for (int i = 0; i <= nb; ++i) dots[i] = s[i];
+    }
+    void gm_begin(double beta) {
+        g[0] = beta;
+        for (int i = 1; i <= kMaxRestart; ++i) g[i] = 0.0;
+    }
+    double gm_probe(int j, const double* h, double hn) {
+        return givens_column(H, kMaxRestart + 1, cs, sn, g, j, h, hn, false);
+    }
+    double gm_commit(int j, const double* h, double hn) {
+        return givens_column(H, kMaxRestart + 1, cs, sn, g, j, h, hn, true);
+    }
+    void gm_solve(int k, double* y) { givens_solve(H, kMaxRestart + 1, g, k, y); }
+    int direction(int k, const double* y, bool have_dx) {
+        if (k == 1 && !have_dx) { implicit_dir = true; implicit_y = y[0]; return k; }
+        a.nb = k; a.acc = have_dx ? 1 : 0;
+        for (int i = 0; i < k; ++i) a.h[i] = y[i];
+        launch(PH_LINCOMB);
+        implicit_dir = false;
+        return k;
+    }
+    VecRef dir_ref() {
+        if (implicit_dir) return VecRef{Zb(0, 0), Zb(0, 1), implicit_y, implicit_y};
+        return VecRef{dXb(0), dXb(1), 1.0, 1.0};
+    }
+    double restart_residual(int cur, double xnorm) {
+        if (implicit_dir) {
+            a.nb = 1; a.acc = 0; a.h[0] = implicit_y;
+            launch(PH_LINCOMB);
+            implicit_dir = false;
+        }
+        launch(PH_NORM_DX);
+        const double dd = fetch(1)[0];
+        if (!(dd > 0.0)) return 0.0;
+        const double lam_fd = 6.0554544523933395e-06;
+        a.cur = cur; a.zslot = -1; a.v = VecRef{dXb(0), dXb(1), 1.0, 1.0};
+        a.eps = lam_fd * (lam_fd + xnorm / std::sqrt(dd));
+        a.wslot = 0; a.nb = 0;
+        launch(PH_JV);
+        fetch(1);
+        a.cur = cur;
+        launch(PH_RES0);
+        return std::sqrt(fetch(1)[0]);
+    }
+    Norms trial(int cur, int out, double lam) {
+        a.cur = cur; a.out = out; a.lam = lam; a.v = dir_ref();
+        launch(PH_TRIAL);
+        const double* s = fetch(4);
+        return Norms{s[0], s[1], s[2], s[3]};
+    }
+    void finalize(const ColOutcome& o) {
+        a.o = o;
+        launch(PH_FINAL);
+    }
+};
+
+template <int T, class FT>
+int run_plain(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t st) {
+    const SolverParams prm = make_params(ctx, p, x);
+    const UserArrays U = make_user(p, x);
+    for (int c = 0; c < p->ncols; ++c) {
+        HostExecT<T, FT> ex;
+        ex.ctx = ctx;
+        ex.st = st;
+        memset(&ex.a, 0, sizeof(ex.a));
+        ex.a.W = ctx->W;
+        ex.a.prm = prm;
+        ex.a.U = U;
+        ex.a.ci = c;
+        ColOutcome o;
+        jfnk_solve(ex, prm, o);
+        if (ex.herr != hipSuccess) {
+            ctx->poisoned = true;
+            return fail(ctx, JFNK_EHIP, std::string("plain schedule: ") + hipGetErrorString(ex.herr));
+        }
+    }
+    return JFNK_OK;
+}
+
+template <int T, class FT>
+int run_batched(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t st) {
+    SolveArgs a;
+    a.W = ctx->W;
+    a.prm = make_params(ctx, p, x);
+    a.U = make_user(p, x);
+    a.order = ctx->d_order;
+    hipLaunchKernelGGL((k_solve<T, FT>), dim3(p->ncols), dim3(T), Lds<T>::bytes(), st, a);
+    HIP_OK(hipGetLastError());
+    return JFNK_OK;
+}
+
+template <class FT>
+int dispatch_run(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t st) {
+    const bool plain = ctx->cfg.schedule == JFNK_SCHED_PLAIN;
+    switch (ctx->Tsel) {
+#define CASE_T(TT) \
+    case TT: return plain ? run_plain<TT, FT>(ctx, p, x, st) : run_batched<TT, FT>(ctx, p, x, st);
+        CASE_T(64) CASE_T(128) CASE_T(256) CASE_T(512)
+#undef CASE_T
+    default:
+        return fail(ctx, JFNK_EINVAL, "unsupported workgroup size");
+    }
+}
+
+// single-column phase runner for the test exports
+template <int T, class FT>
+int run_phases(jfnk_ctx* ctx, hipStream_t st, PhaseArgs& a, const std::vector<int>& phases) {
+    for (int ph : phases) {
+        a.phase = ph;
+        hipLaunchKernelGGL((k_phase<T, FT>), dim3(1), dim3(T), Lds<T>::bytes(), st, a);
+        HIP_OK(hipGetLastError());
+    }
+    return JFNK_OK;
+}
+
+template <class FT>
+int dispatch_phases(jfnk_ctx* ctx, hipStream_t st, PhaseArgs& a, const std::vector<int>& ph) {
+    switch (ctx->Tsel) {
+#define CASE_T(TT) case TT: return run_phases<TT, FT>(ctx, st, a, ph);
+        CASE_T(64) CASE_T(128) CASE_T(256) CASE_T(512)
+#undef CASE_T
+    default:
+        return fail(ctx, JFNK_EINVAL, "unsupported workgroup size");
+    }
+}
+
+int upload_schedule(jfnk_ctx* ctx, int ncols, hipStream_t st) {
+    HIP_OK(hipMemcpyAsync(ctx->W.cols, ctx->h_cols, sizeof(ColDesc) * ncols, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(ctx->d_order, ctx->h_order, sizeof(int) * ncols, hipMemcpyHostToDevice, st));
+    return JFNK_OK;
+}
+
+int gather_stats(jfnk_ctx* ctx, int ncols, jfnk_stats* stt, hipStream_t st, int* nfail) {
+    HIP_OK(hipMemcpyAsync(ctx->h_cst, ctx->W.cst, sizeof(ColState) * ncols, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    int bad = 0;
+    for (int c = 0; c < ncols; ++c) {
+        const ColState& s = ctx->h_cst[c];
+        if (s.status != COL_CONVERGED) ++bad;
+        if (stt) {
+            if (stt->status) stt->status[c] = s.status;
+            if (stt->newton_iters) stt->newton_iters[c] = s.newton;
+            if (stt->gmres_iters) stt->gmres_iters[c] = s.gmres;
+            if (stt->backtracks) stt->backtracks[c] = s.backtracks;
+            if (stt->guess_used) stt->guess_used[c] = s.guess;
+            if (stt->res_scaled) stt->res_scaled[c] = s.res_inf;
+        }
+    }
+    *nfail = bad;
+    return JFNK_OK;
+}
+
+int check_ctx(jfnk_ctx* ctx) {
+    if (!ctx) return JFNK_EINVAL;
+    if (ctx->poisoned) return fail(ctx, JFNK_EHIP, "context poisoned by an earlier HIP error");
+    return JFNK_OK;
+}
+
+// common set-up of the single-phase test exports
+int prepare_test(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, hipStream_t st,
+                 PhaseArgs& a) {
+    int rc = validate(ctx, p, x);
+    if (rc) return rc;
+    rc = upload_schedule(ctx, p->ncols, st);
+    if (rc) return rc;
+    memset(&a, 0, sizeof(a));
+    a.W = ctx->W;
+    jfnk_state xs = *x;
+    xs.ne_prev = nullptr; xs.phi_prev = nullptr;
+    a.prm = make_params(ctx, p, &xs);
+    a.prm.guess = JFNK_GUESS_PREV;
+    a.U = make_user(p, &xs);
+    return JFNK_OK;
+}
+
+template <class Fn>
+int for_each_column(jfnk_ctx* ctx, const jfnk_problem* p, hipStream_t st, PhaseArgs& a, Fn fn) {
+    for (int c = 0; c < p->ncols; ++c) {
+        a.ci = c;
+        std::vector<int> ph = fn(c);
+        const int rc = ctx->cfg.prec_precision == JFNK_PREC_FP32 ? dispatch_phases<float>(ctx, st, a, ph)
+                                                                : dispatch_phases<double>(ctx, st, a, ph);
+        if (rc) return rc;
+    }
+    return JFNK_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void jfnk_config_default(jfnk_config* cfg) {
+    if (!cfg) return;
+    memset(cfg, 0, sizeof(*cfg));
+    cfg->max_cols = 1;
+    cfg->max_total_cells = 4096;
+    cfg->max_cells_per_col = 4096;
+    cfg->gmres_restart = 30;
+    cfg->max_restarts = 5;
+    cfg->max_newton = 50;
+    cfg->max_backtracks = 10;
+    cfg->tol_f = 1e-10;
+    cfg->tol_x = 1e-10;
+    cfg->gamma = 1e-4;
+    cfg->armijo_alpha = 1e-4;
+    cfg->prec_precision = JFNK_PREC_FP32;
+    cfg->guess = JFNK_GUESS_EXTRAP;
+    cfg->schedule = JFNK_SCHED_BATCHED;
+    cfg->threads_override = 0;
+}
+
+int jfnk_create(const jfnk_config* cfg, jfnk_ctx** out) {
+    if (!out) return JFNK_EINVAL;
+    *out = nullptr;
+    if (!cfg) return JFNK_EINVAL;
+    if (cfg->max_cols < 1 || cfg->max_total_cells < 3 || cfg->max_cells_per_col < 3 ||
+        cfg->gmres_restart < 1 || cfg->gmres_restart > kMaxRestart || cfg->max_restarts < 0 ||
+        cfg->max_newton < 0 || cfg->max_backtracks < 0 || !(cfg->tol_f > 0.0) || !(cfg->tol_x >= 0.0) ||
+        !(cfg->gamma > 0.0 && cfg->gamma < 1.0) || !(cfg->armijo_alpha >= 0.0 && cfg->armijo_alpha < 1.0) ||
+        (cfg->prec_precision != JFNK_PREC_FP64 && cfg->prec_precision != JFNK_PREC_FP32) ||
+        cfg->guess < 0 || cfg->guess > 2 ||
+        (cfg->schedule != JFNK_SCHED_PLAIN && cfg->schedule != JFNK_SCHED_BATCHED))
+        return JFNK_EINVAL;
+    if (cfg->threads_override != 0) {
+        const int t = cfg->threads_override;
+        if (t != 64 && t != 128 && t != 256 && t != 512) return JFNK_EINVAL;
+    }
+    jfnk_ctx* ctx = new (std::nothrow) jfnk_ctx();
+    if (!ctx) return JFNK_ENOMEM;
+    ctx->cfg = *cfg;
+    if (hipGetDevice(&ctx->device) != hipSuccess) { delete ctx; return JFNK_EHIP; }
+    const int Tcap = cfg->threads_override > 0 ? cfg->threads_override : kTmax;
+    ctx->capP = cfg->max_total_cells + (int64_t)cfg->max_cols * Tcap;
+    ctx->capRed = (int64_t)cfg->max_cols * Tcap * kRedPerChunk;
+    const int64_t per = work_doubles_per_cell(cfg->gmres_restart);
+    const int64_t words = per * ctx->capP + ctx->capRed +
+                          (cfg->max_cols * (int64_t)(sizeof(ColDesc) + sizeof(ColState)) + 16) / 8 + 4 +
+                          (int64_t)cfg->max_cols * kScalSlots;
+    hipError_t e = hipMalloc((void**)&ctx->base, sizeof(double) * words);
+    if (e != hipSuccess) { (void)hipGetLastError(); delete ctx; return JFNK_ENOMEM; }
+    carve(ctx);
+    e = hipMalloc((void**)&ctx->d_order, sizeof(int) * cfg->max_cols);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_cols, sizeof(ColDesc) * cfg->max_cols, 0);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_cst, sizeof(ColState) * cfg->max_cols, 0);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_scal, sizeof(double) * kScalSlots * 2, 0);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_order, sizeof(int) * cfg->max_cols, 0);
+    if (e != hipSuccess) { (void)hipGetLastError(); jfnk_destroy(ctx); return JFNK_ENOMEM; }
+    // zero the whole workspace once: padding cells must read as zero
+    e = hipMemset(ctx->base, 0, sizeof(double) * words);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) { jfnk_destroy(ctx); return JFNK_EHIP; }
+    *out = ctx;
+    return JFNK_OK;
+}
+
+void jfnk_destroy(jfnk_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->base) (void)hipFree(ctx->base);
+    if (ctx->d_order) (void)hipFree(ctx->d_order);
+    if (ctx->h_cols) (void)hipHostFree(ctx->h_cols);
+    if (ctx->h_cst) (void)hipHostFree(ctx->h_cst);
+    if (ctx->h_scal) (void)hipHostFree(ctx->h_scal);
+    if (ctx->h_order) (void)hipHostFree(ctx->h_order);
+    delete ctx;
+}
+
+const char* jfnk_last_error(const jfnk_ctx* ctx) {
+    if (!ctx) return "null context";
+    return ctx->err.c_str();
+}
+
+int jfnk_step(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, jfnk_stats* stt, void* stream) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (ctx->cfg.guess == JFNK_GUESS_LEARNED)
+        return fail(ctx, JFNK_EMODEL, "learned guess requested but no model is loaded");
+    rc = validate(ctx, p, x);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    rc = upload_schedule(ctx, p->ncols, st);
+    if (rc) return rc;
+    rc = ctx->cfg.prec_precision == JFNK_PREC_FP32 ? dispatch_run<float>(ctx, p, x, st)
+                                                   : dispatch_run<double>(ctx, p, x, st);
+    if (rc) return rc;
+    int nfail = 0;
+    rc = gather_stats(ctx, p->ncols, stt, st, &nfail);
+    if (rc) return rc;
+    return nfail ? JFNK_NOT_CONVERGED : JFNK_OK;
+}
+
+int jfnk_eval_residual(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, const double* x_ne,
+                       const double* x_phi, double* fe, double* fp, double* scal, void* stream) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!x_ne || !x_phi || !fe || !fp) return fail(ctx, JFNK_EINVAL, "null array");
+    hipStream_t st = (hipStream_t)stream;
+    PhaseArgs a;
+    rc = prepare_test(ctx, p, x, st, a);
+    if (rc) return rc;
+    a.in0 = x_ne; a.in1 = x_phi; a.out0 = fe; a.out1 = fp; a.cur = 1;
+    rc = for_each_column(ctx, p, st, a, [](int) {
+        return std::vector<int>{PH_SETUP, PH_LOAD_X, PH_EVAL, PH_STORE_F};
+    });
+    if (rc) return rc;
+    if (scal) {
+        HIP_OK(hipMemcpyAsync(ctx->h_cst, ctx->W.cst, sizeof(ColState) * p->ncols, hipMemcpyDeviceToHost, st));
+    }
+    HIP_OK(hipStreamSynchronize(st));
+    if (scal)
+        for (int c = 0; c < p->ncols; ++c) {
+            scal[4 * c + 0] = ctx->h_cst[c].sfn; scal[4 * c + 1] = ctx->h_cst[c].sfp;
+            scal[4 * c + 2] = ctx->h_cst[c].sxn; scal[4 * c + 3] = ctx->h_cst[c].sxp;
+        }
+    return JFNK_OK;
+}
+
+int jfnk_eval_jv(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, const double* x_ne,
+                 const double* x_phi, const double* v_ne, const double* v_phi, double* w_ne,
+                 double* w_phi, void* stream) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!x_ne || !x_phi || !v_ne || !v_phi || !w_ne || !w_phi) return fail(ctx, JFNK_EINVAL, "null array");
+    hipStream_t st = (hipStream_t)stream;
+    PhaseArgs a;
+    rc = prepare_test(ctx, p, x, st, a);
+    if (rc) return rc;
+    // per column: set up, load X into buffer 1, F(X), load v into Z[0], norms
+    for (int c = 0; c < p->ncols; ++c) {
+        a.ci = c;
+        a.cur = 1; a.in0 = x_ne; a.in1 = x_phi;
+        auto run = [&](std::vector<int> ph) {
+            return ctx->cfg.prec_precision == JFNK_PREC_FP32 ? dispatch_phases<float>(ctx, st, a, ph)
+                                                            : dispatch_phases<double>(ctx, st, a, ph);
+        };
+        rc = run({PH_SETUP, PH_LOAD_X, PH_EVAL});
+        if (rc) return rc;
+        HIP_OK(hipMemcpyAsync(ctx->h_scal, ctx->W.scal + (int64_t)c * kScalSlots, sizeof(double) * 4,
+                              hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        const double xn2 = ctx->h_scal[2];
+        a.zslot = 0; a.in0 = v_ne; a.in1 = v_phi;
+        rc = run({PH_LOAD_V});
+        if (rc) return rc;
+        // ||v||^2 through the dX norm phase: copy v into dX via a one-term lincomb
+        a.nb = 1; a.acc = 0; a.h[0] = 1.0;
+        rc = run({PH_LINCOMB, PH_NORM_DX});
+        if (rc) return rc;
+        HIP_OK(hipMemcpyAsync(ctx->h_scal, ctx->W.scal + (int64_t)c * kScalSlots, sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        const double vn2 = ctx->h_scal[0];
+        const double lam_fd = 6.0554544523933395e-06;
+        a.eps = (vn2 > 0.0) ? lam_fd * (lam_fd + std::sqrt(xn2) / std::sqrt(vn2)) : 1.0;
+        a.cur = 1; a.zslot = 0; a.wslot = 1; a.nb = 0;
+        a.out0 = w_ne; a.out1 = w_phi;
+        rc = run({PH_JV});
+        if (rc) return rc;
+        rc = run({PH_STORE_W});
+        if (rc) return rc;
+    }
+    HIP_OK(hipStreamSynchronize(st));
+    return JFNK_OK;
+}
+
+int jfnk_block_solve(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, const double* x_ne,
+                     const double* x_phi, const double* r_ne, const double* r_phi, double* z_ne,
+                     double* z_phi, void* stream) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!x_ne || !x_phi || !r_ne || !r_phi || !z_ne || !z_phi) return fail(ctx, JFNK_EINVAL, "null array");
+    hipStream_t st = (hipStream_t)stream;
+    PhaseArgs a;
+    rc = prepare_test(ctx, p, x, st, a);
+    if (rc) return rc;
+    for (int c = 0; c < p->ncols; ++c) {
+        a.ci = c;
+        auto run = [&](std::vector<int> ph) {
+            return ctx->cfg.prec_precision == JFNK_PREC_FP32 ? dispatch_phases<float>(ctx, st, a, ph)
+                                                            : dispatch_phases<double>(ctx, st, a, ph);
+        };
+        a.cur = 1; a.in0 = x_ne; a.in1 = x_phi;
+        rc = run({PH_SETUP, PH_LOAD_X, PH_FACTOR});
+        if (rc) return rc;
+        a.zslot = 0; a.in0 = r_ne; a.in1 = r_phi;
+        rc = run({PH_LOAD_V});
+        if (rc) return rc;
+        a.v = VecRef{ctx->W.Z, ctx->W.Z + ctx->W.P, 1.0, 1.0};
+        a.zslot = 1;
+        rc = run({PH_APPLY});
+        if (rc) return rc;
+        a.out0 = z_ne; a.out1 = z_phi;
+        rc = run({PH_STORE_V});
+        if (rc) return rc;
+    }
+    HIP_OK(hipStreamSynchronize(st));
+    return JFNK_OK;
+}
+
+}  // extern "C"

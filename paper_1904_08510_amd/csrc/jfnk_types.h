@@ -1,0 +1,90 @@
+// Shared host/device types of the JFNK electron/potential solver.
+//
+// Data layout (HBM): every per-cell workspace field is a flat array over all
+// columns, columns back to back, each padded to Np = T * M cells, where T is
+// the workgroup size that solves the column and M = ceil(n / T) the chunk of
+// consecutive cells one thread owns.  Inside a column, cell c = t * M + j
+// (thread t, row j of its chunk) is stored at offset j * T + t, so that the
+// threads of a workgroup sweeping their chunks in step touch consecutive
+// addresses (coalesced 64-lane accesses) while each thread still walks its
+// own contiguous run of cells, as the block-tridiagonal recursions require.
+// Padding cells carry zero residuals and identity Jacobian rows.
+#pragma once
+#include <stdint.h>
+
+#ifndef __HIPCC__
+#define __host__
+#define __device__
+#endif
+
+namespace jfnk {
+
+constexpr int kMaxRestart = 30;      // largest GMRES restart length supported
+constexpr int kRedPerChunk = 96;     // doubles of reduced-system data per chunk (T <= 1024)
+constexpr int kFactorSlots = 20;     // FT values per cell stored by the factorisation
+constexpr int kTempSlots = 8;        // FP64 values per cell kept between factor sweeps
+
+// Column status codes (also in include/jfnk.h).
+enum { COL_CONVERGED = 0, COL_MAX_NEWTON = 1, COL_NONFINITE = 2, COL_LINESEARCH = 3,
+       COL_BAD_INPUT = 4 };
+
+struct ColDesc {
+    int32_t n;          // cells
+    int32_t M;          // chunk length (cells per thread)
+    int32_t bcl, bcr;   // 0 Dirichlet, 1 zero flux
+    int32_t index;      // caller's column index
+    int32_t T;          // workgroup size that owns this column
+    int64_t uoff;       // first cell in the caller's packed arrays
+    int64_t ws;         // first padded cell in the workspace
+    int64_t red;        // first double of the per-chunk data
+    double h, dt, phil, phir, eps, nel, ner;
+};
+
+// Per-column results and solver scalars (device resident).
+struct ColState {
+    double sfn, sfp, sxn, sxp;      // S_F and S_X block scalars
+    double rR, gR, wR;              // right-wall face coefficients
+    double res_inf, res2;
+    int32_t status, newton, gmres, backtracks, guess, restarts;
+};
+
+struct SolverParams {
+    int32_t m;              // GMRES restart length
+    int32_t max_restarts;
+    int32_t max_newton;
+    int32_t max_backtracks;
+    int32_t guess;          // 0 prev, 1 extrap, 2 learned
+    int32_t has_prev;       // X^{n-1} supplied
+    int32_t has_learned;    // learned candidate supplied
+    int32_t has_u;          // advective face velocities supplied
+    double tol_f, tol_x, gamma, alpha;
+};
+
+// Caller arrays (natural layout, device pointers).
+struct UserArrays {
+    const double *mu, *diff, *src, *kloss, *q, *uface;
+    double *ne, *phi;
+    const double *ne_prev, *phi_prev;
+    const double *ne_learn, *phi_learn;
+};
+
+// Workspace (device pointers).
+struct Work {
+    int64_t P;                       // padded cells over all columns
+    double *fa, *fg, *fw;            // left-face mu_f/D_f, D_f/h_f, u_f h_f/D_f
+    double *f, *kd, *q;              // n^n + dt s, dt k, q
+    double *x;                       // 3 buffers x 2 components
+    double *F;                       // unscaled residuals, 3 x 2
+    double *V;                       // Krylov basis (m+1) x 2
+    double *Z;                       // preconditioned basis m x 2
+    double *dX;                      // Newton direction (scaled), 2
+    void *fac;                       // kFactorSlots x P values of the factor type
+    void *tmp;                       // 2 x P values of the factor type (apply)
+    double *ftmp;                    // kTempSlots x P doubles (factorisation)
+    double *red;                     // per-chunk reduced-system data
+    ColDesc *cols;
+    ColState *cst;
+    double *scal;                    // per-column scalar exchange (host-driven mode)
+};
+
+}  // namespace jfnk

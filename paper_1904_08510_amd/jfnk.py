@@ -1,0 +1,295 @@
+"""Python binding of libjfnk (include/jfnk.h): argument marshalling only.
+
+Every step of the solve runs in the HIP library; this module converts torch
+device tensors and numpy host arrays into the C structs of the ABI.  It
+raises if the built library is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjfnk.so")
+
+JFNK_OK, JFNK_NOT_CONVERGED = 0, 1
+JFNK_EINVAL, JFNK_ENOMEM, JFNK_EHIP, JFNK_ECAPACITY, JFNK_EMODEL = -1, -2, -3, -4, -5
+BC_DIRICHLET, BC_ZERO_FLUX = 0, 1
+GUESS_PREV, GUESS_EXTRAP, GUESS_LEARNED = 0, 1, 2
+PREC_FP64, PREC_FP32 = 0, 1
+SCHED_PLAIN, SCHED_BATCHED = 0, 1
+COL_CONVERGED, COL_MAX_NEWTON, COL_NONFINITE, COL_LINESEARCH, COL_BAD_INPUT = 0, 1, 2, 3, 4
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_lp = C.POINTER(C.c_int64)
+
+
+class jfnk_config(C.Structure):
+    _fields_ = [("max_cols", C.c_int32), ("max_total_cells", C.c_int64),
+                ("max_cells_per_col", C.c_int32), ("gmres_restart", C.c_int32),
+                ("max_restarts", C.c_int32), ("max_newton", C.c_int32),
+                ("max_backtracks", C.c_int32), ("tol_f", C.c_double), ("tol_x", C.c_double),
+                ("gamma", C.c_double), ("armijo_alpha", C.c_double),
+                ("prec_precision", C.c_int32), ("guess", C.c_int32), ("schedule", C.c_int32),
+                ("threads_override", C.c_int32)]
+
+
+class jfnk_problem(C.Structure):
+    _fields_ = [("ncols", C.c_int32), ("col_offset", _lp), ("length", _dp), ("dt", _dp),
+                ("phi_left", _dp), ("phi_right", _dp), ("eps_over_e", _dp),
+                ("bc_left", _ip), ("bc_right", _ip), ("ne_left", _dp), ("ne_right", _dp),
+                ("mu", C.c_void_p), ("diff", C.c_void_p), ("src", C.c_void_p),
+                ("k_loss", C.c_void_p), ("q_ion", C.c_void_p), ("u_face", C.c_void_p),
+                ("temp", C.c_void_p)]
+
+
+class jfnk_state(C.Structure):
+    _fields_ = [("ne", C.c_void_p), ("phi", C.c_void_p), ("ne_prev", C.c_void_p),
+                ("phi_prev", C.c_void_p)]
+
+
+class jfnk_stats(C.Structure):
+    _fields_ = [("status", _ip), ("newton_iters", _ip), ("gmres_iters", _ip),
+                ("backtracks", _ip), ("guess_used", _ip), ("res_scaled", _dp)]
+
+
+_LIB = None
+
+
+def lib():
+    """The loaded libjfnk.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libjfnk.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        L.jfnk_config_default.argtypes = [C.POINTER(jfnk_config)]
+        L.jfnk_config_default.restype = None
+        L.jfnk_create.argtypes = [C.POINTER(jfnk_config), C.POINTER(C.c_void_p)]
+        L.jfnk_create.restype = C.c_int
+        L.jfnk_step.argtypes = [C.c_void_p, C.POINTER(jfnk_problem), C.POINTER(jfnk_state),
+                                C.POINTER(jfnk_stats), C.c_void_p]
+        L.jfnk_step.restype = C.c_int
+        L.jfnk_destroy.argtypes = [C.c_void_p]
+        L.jfnk_destroy.restype = None
+        L.jfnk_last_error.argtypes = [C.c_void_p]
+        L.jfnk_last_error.restype = C.c_char_p
+        L.jfnk_eval_residual.argtypes = [C.c_void_p, C.POINTER(jfnk_problem), C.POINTER(jfnk_state),
+                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, _dp, C.c_void_p]
+        L.jfnk_eval_residual.restype = C.c_int
+        L.jfnk_eval_jv.argtypes = [C.c_void_p, C.POINTER(jfnk_problem), C.POINTER(jfnk_state),
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p]
+        L.jfnk_eval_jv.restype = C.c_int
+        L.jfnk_block_solve.argtypes = [C.c_void_p, C.POINTER(jfnk_problem), C.POINTER(jfnk_state),
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p]
+        L.jfnk_block_solve.restype = C.c_int
+        _LIB = L
+    return _LIB
+
+
+EXPORTED_SYMBOLS = ("jfnk_config_default", "jfnk_create", "jfnk_step", "jfnk_destroy",
+                    "jfnk_last_error", "jfnk_eval_residual", "jfnk_eval_jv", "jfnk_block_solve")
+
+
+class JfnkError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"jfnk error {code}: {msg}")
+        self.code = code
+
+
+def default_config(**kw) -> jfnk_config:
+    cfg = jfnk_config()
+    lib().jfnk_config_default(C.byref(cfg))
+    for k, v in kw.items():
+        if not hasattr(cfg, k):
+            raise AttributeError(k)
+        setattr(cfg, k, v)
+    return cfg
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+    return t.data_ptr()
+
+
+@dataclass
+class DeviceProblem:
+    """Host per-column arrays + device per-cell tensors of one batch."""
+    ncols: int
+    col_offset: np.ndarray
+    length: np.ndarray
+    dt: np.ndarray
+    phi_left: np.ndarray
+    phi_right: np.ndarray
+    eps_over_e: np.ndarray
+    bc_left: np.ndarray
+    bc_right: np.ndarray
+    ne_left: np.ndarray
+    ne_right: np.ndarray
+    mu: object
+    diff: object
+    src: object
+    kloss: object
+    q: object
+    temp: object
+    uface: object = None
+
+    def cstruct(self) -> jfnk_problem:
+        p = jfnk_problem()
+        p.ncols = self.ncols
+        self._keep = [np.ascontiguousarray(self.col_offset, dtype=np.int64)]
+        p.col_offset = self._keep[0].ctypes.data_as(_lp)
+        for name in ("length", "dt", "phi_left", "phi_right", "eps_over_e", "ne_left", "ne_right"):
+            a = np.ascontiguousarray(getattr(self, name), dtype=np.float64)
+            self._keep.append(a)
+            setattr(p, name, a.ctypes.data_as(_dp))
+        for name in ("bc_left", "bc_right"):
+            a = np.ascontiguousarray(getattr(self, name), dtype=np.int32)
+            self._keep.append(a)
+            setattr(p, name, a.ctypes.data_as(_ip))
+        p.mu, p.diff, p.src = _ptr(self.mu), _ptr(self.diff), _ptr(self.src)
+        p.k_loss, p.q_ion = _ptr(self.kloss), _ptr(self.q)
+        p.u_face, p.temp = _ptr(self.uface), _ptr(self.temp)
+        return p
+
+
+def device_problem(packed, device="cuda") -> tuple:
+    """(DeviceProblem, ne, phi, ne_prev, phi_prev) on the GPU from a workloads.Packed."""
+    import torch
+
+    def dev(a):
+        return None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+
+    dp = DeviceProblem(packed.ncols, packed.col_offset, packed.length, packed.dt, packed.phi_left,
+                       packed.phi_right, packed.eps_over_e, packed.bc_left, packed.bc_right,
+                       packed.ne_left, packed.ne_right, dev(packed.mu), dev(packed.diff),
+                       dev(packed.src), dev(packed.kloss), dev(packed.q), dev(packed.temp))
+    return dp, dev(packed.ne), dev(packed.phi), dev(packed.ne_prev), dev(packed.phi_prev)
+
+
+class Stats:
+    def __init__(self, n):
+        self.status = np.zeros(n, np.int32)
+        self.newton_iters = np.zeros(n, np.int32)
+        self.gmres_iters = np.zeros(n, np.int32)
+        self.backtracks = np.zeros(n, np.int32)
+        self.guess_used = np.zeros(n, np.int32)
+        self.res_scaled = np.zeros(n, np.float64)
+
+    def cstruct(self) -> jfnk_stats:
+        s = jfnk_stats()
+        for name in ("status", "newton_iters", "gmres_iters", "backtracks", "guess_used"):
+            setattr(s, name, getattr(self, name).ctypes.data_as(_ip))
+        s.res_scaled = self.res_scaled.ctypes.data_as(_dp)
+        return s
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return int(stream)
+
+
+class Solver:
+    """Owns one jfnk_ctx."""
+
+    def __init__(self, config: jfnk_config):
+        self.config = config
+        h = C.c_void_p()
+        rc = lib().jfnk_create(C.byref(config), C.byref(h))
+        if rc != JFNK_OK:
+            raise JfnkError(rc, "jfnk_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().jfnk_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return lib().jfnk_last_error(self.h).decode()
+
+    def _check(self, rc, allow=(JFNK_OK, JFNK_NOT_CONVERGED)):
+        if rc not in allow:
+            raise JfnkError(rc, self.last_error())
+        return rc
+
+    @staticmethod
+    def _state(ne, phi, ne_prev=None, phi_prev=None) -> jfnk_state:
+        s = jfnk_state()
+        s.ne, s.phi = _ptr(ne), _ptr(phi)
+        s.ne_prev, s.phi_prev = _ptr(ne_prev), _ptr(phi_prev)
+        return s
+
+    def step(self, prob: DeviceProblem, ne, phi, ne_prev=None, phi_prev=None, stream=None,
+             stats: Optional[Stats] = None, raw: bool = False):
+        """One backward-Euler step of all columns, in place on ne/phi."""
+        p = prob.cstruct()
+        s = self._state(ne, phi, ne_prev, phi_prev)
+        st = stats if stats is not None else Stats(prob.ncols)
+        rc = lib().jfnk_step(self.h, C.byref(p), C.byref(s), C.byref(st.cstruct()), _stream_ptr(stream))
+        if raw:
+            return rc, st
+        self._check(rc)
+        return rc, st
+
+    def eval_residual(self, prob: DeviceProblem, ne_old, phi_old, x_ne, x_phi, stream=None):
+        import torch
+        fe = torch.empty_like(x_ne)
+        fp = torch.empty_like(x_phi)
+        scal = np.zeros(4 * prob.ncols)
+        p = prob.cstruct()
+        s = self._state(ne_old, phi_old)
+        rc = lib().jfnk_eval_residual(self.h, C.byref(p), C.byref(s), _ptr(x_ne), _ptr(x_phi),
+                                      _ptr(fe), _ptr(fp), scal.ctypes.data_as(_dp), _stream_ptr(stream))
+        self._check(rc, (JFNK_OK,))
+        return fe, fp, scal.reshape(-1, 4)
+
+    def eval_jv(self, prob, ne_old, phi_old, x_ne, x_phi, v_ne, v_phi, stream=None):
+        import torch
+        w_ne = torch.empty_like(x_ne)
+        w_phi = torch.empty_like(x_phi)
+        p = prob.cstruct()
+        s = self._state(ne_old, phi_old)
+        rc = lib().jfnk_eval_jv(self.h, C.byref(p), C.byref(s), _ptr(x_ne), _ptr(x_phi), _ptr(v_ne),
+                                _ptr(v_phi), _ptr(w_ne), _ptr(w_phi), _stream_ptr(stream))
+        self._check(rc, (JFNK_OK,))
+        return w_ne, w_phi
+
+    def block_solve(self, prob, ne_old, phi_old, x_ne, x_phi, r_ne, r_phi, stream=None):
+        import torch
+        z_ne = torch.empty_like(x_ne)
+        z_phi = torch.empty_like(x_phi)
+        p = prob.cstruct()
+        s = self._state(ne_old, phi_old)
+        rc = lib().jfnk_block_solve(self.h, C.byref(p), C.byref(s), _ptr(x_ne), _ptr(x_phi),
+                                    _ptr(r_ne), _ptr(r_phi), _ptr(z_ne), _ptr(z_phi),
+                                    _stream_ptr(stream))
+        self._check(rc, (JFNK_OK,))
+        return z_ne, z_phi
+
+
+def config_for(packed, **kw) -> jfnk_config:
+    """Config with capacity sized for a packed batch."""
+    ns = np.diff(packed.col_offset)
+    base = dict(max_cols=int(packed.ncols), max_total_cells=int(packed.col_offset[-1]),
+                max_cells_per_col=int(ns.max()))
+    base.update(kw)
+    return default_config(**base)

@@ -1,0 +1,58 @@
+"""The C-ABI library loads and exports every symbol the header declares (no
+GPU needed: nothing here launches work)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    with open(os.path.join(ROOT, "include", "jfnk.h")) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(jfnk_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def libjfnk():
+    from paper_1904_08510_amd import jfnk
+    if not os.path.exists(jfnk.LIB_PATH):
+        from paper_1904_08510_amd import build_ext
+        build_ext.build()
+    return jfnk
+
+
+def test_library_exports_every_declared_symbol(libjfnk):
+    names = header_functions()
+    assert "jfnk_step" in names and "jfnk_create" in names
+    L = ctypes.CDLL(libjfnk.LIB_PATH)
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(libjfnk.EXPORTED_SYMBOLS) == set(names)
+
+
+def test_config_defaults(libjfnk):
+    cfg = libjfnk.default_config()
+    assert cfg.gmres_restart == 30 and cfg.max_newton == 50 and cfg.tol_f == 1e-10
+    assert cfg.gamma == 1e-4 and cfg.prec_precision == libjfnk.PREC_FP32
+
+
+def test_create_rejects_bad_config_without_touching_a_device(libjfnk):
+    L = libjfnk.lib()
+    h = ctypes.c_void_p()
+    for kw in (dict(gmres_restart=31), dict(gmres_restart=0), dict(tol_f=0.0), dict(gamma=1.5),
+               dict(max_cols=0), dict(threads_override=100), dict(schedule=7)):
+        cfg = libjfnk.default_config(**kw)
+        assert L.jfnk_create(ctypes.byref(cfg), ctypes.byref(h)) == libjfnk.JFNK_EINVAL
+        assert not h.value
+    assert L.jfnk_create(None, ctypes.byref(h)) == libjfnk.JFNK_EINVAL
+
+
+def test_null_safety(libjfnk):
+    L = libjfnk.lib()
+    L.jfnk_destroy(None)
+    assert L.jfnk_last_error(None) == b"null context"
+    assert L.jfnk_step(None, None, None, None, None) == libjfnk.JFNK_EINVAL

@@ -1,0 +1,265 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Every comparison runs the same seeded inputs through libjfnk (device) and the
+oracle (host) and compares element by element.
+"""
+import numpy as np
+import pytest
+
+from paper_1904_08510_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def J():
+    _need_gpu()
+    from paper_1904_08510_amd import jfnk
+    jfnk.lib()
+    return jfnk
+
+
+def ragged_batch(seed=7):
+    """Uneven columns covering tiny, ragged (not a multiple of the
+    workgroup) and multi-chunk sizes, both wall conditions."""
+    rng = np.random.default_rng(seed)
+    sizes = [3, 5, 64, 65, 127, 300, 1000, 1500, 2049]
+    cols = []
+    for i, n in enumerate(sizes):
+        c = W.flame_column(n, float(rng.uniform(-900, 900)), a_ion=float(10 ** rng.uniform(15, 16.5)),
+                           x_f=float(rng.uniform(0.006, 0.014)))
+        if i % 3 == 1:
+            c.bc_right = W.BC_ZERO_FLUX
+        if i % 4 == 2:
+            c.ne_left = 1e12
+        cols.append(c)
+    return cols
+
+
+def oracle_scaled_jacobian(orc, col, ne, phi):
+    oc = orc.OracleColumn(col)
+    s = orc.scalings(oc)
+    Jd = orc.jacobian_dense(oc, ne, phi)
+    n = col.n
+    sf = np.tile([1 / s[0], 1 / s[1]], n)
+    sx = np.tile([s[2], s[3]], n)
+    return (Jd * sf[:, None]) * sx[None, :], s
+
+
+def test_residual_matches_oracle(J, orc):
+    cols = ragged_batch()
+    packed = W.pack(cols)
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    rng = np.random.default_rng(1)
+    xn = packed.ne * rng.uniform(0.5, 1.5, packed.total) + 1e10
+    xp = packed.phi + rng.uniform(-5, 5, packed.total)
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64))
+    fe, fp, scal = solver.eval_residual(prob, ne, phi, torch.from_numpy(xn).cuda(),
+                                        torch.from_numpy(xp).cuda())
+    fe, fp = fe.cpu().numpy(), fp.cpu().numpy()
+    for i, col in enumerate(cols):
+        sl = slice(packed.col_offset[i], packed.col_offset[i + 1])
+        oc = orc.OracleColumn(col)
+        s = orc.scalings(oc)
+        np.testing.assert_allclose(scal[i], s, rtol=1e-14, atol=0)
+        ofe, ofp = orc.residual(oc, xn[sl], xp[sl])
+        assert np.max(np.abs(fe[sl] - ofe)) / s[0] < 1e-13, i
+        assert np.max(np.abs(fp[sl] - ofp)) / s[1] < 1e-13, i
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_block_solve_backward_error(J, orc, prec):
+    cols = ragged_batch(seed=3)
+    packed = W.pack(cols)
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    rng = np.random.default_rng(2)
+    xn = packed.ne * rng.uniform(0.7, 1.3, packed.total)
+    xp = packed.phi + rng.uniform(-2, 2, packed.total)
+    r = rng.standard_normal((2, packed.total))
+    p = J.PREC_FP64 if prec == "fp64" else J.PREC_FP32
+    solver = J.Solver(J.config_for(packed, prec_precision=p))
+    zn, zp = solver.block_solve(prob, ne, phi, torch.from_numpy(xn).cuda(), torch.from_numpy(xp).cuda(),
+                                torch.from_numpy(r[0].copy()).cuda(), torch.from_numpy(r[1].copy()).cuda())
+    zn, zp = zn.cpu().numpy(), zp.cpu().numpy()
+    for i, col in enumerate(cols):
+        sl = slice(packed.col_offset[i], packed.col_offset[i + 1])
+        Js, _ = oracle_scaled_jacobian(orc, col, xn[sl], xp[sl])
+        z = np.empty(2 * col.n)
+        z[0::2], z[1::2] = zn[sl], zp[sl]
+        b = np.empty(2 * col.n)
+        b[0::2], b[1::2] = r[0][sl], r[1][sl]
+        be = np.linalg.norm(Js @ z - b) / (np.linalg.norm(Js, np.inf) * np.linalg.norm(z) + np.linalg.norm(b))
+        zt = orc.dense_solve(Js, b) if col.n <= 300 else np.linalg.solve(Js, b)
+        fe = np.linalg.norm(z - zt) / np.linalg.norm(zt)
+        if prec == "fp64":
+            assert be < 1e-11 and fe < 1e-6, (i, col.n, be, fe)
+        else:
+            assert be < 1e-6 and fe < 1e-4, (i, col.n, be, fe)
+
+
+def test_jv_matches_analytic_jacobian(J, orc):
+    cols = ragged_batch(seed=4)
+    packed = W.pack(cols)
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    rng = np.random.default_rng(5)
+    xn = packed.ne * rng.uniform(0.7, 1.3, packed.total) + 1e12
+    xp = packed.phi + rng.uniform(-2, 2, packed.total)
+    v = rng.standard_normal((2, packed.total))
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64))
+    wn, wp = solver.eval_jv(prob, ne, phi, torch.from_numpy(xn).cuda(), torch.from_numpy(xp).cuda(),
+                            torch.from_numpy(v[0].copy()).cuda(), torch.from_numpy(v[1].copy()).cuda())
+    wn, wp = wn.cpu().numpy(), wp.cpu().numpy()
+    for i, col in enumerate(cols):
+        sl = slice(packed.col_offset[i], packed.col_offset[i + 1])
+        Js, _ = oracle_scaled_jacobian(orc, col, xn[sl], xp[sl])
+        vv = np.empty(2 * col.n)
+        vv[0::2], vv[1::2] = v[0][sl], v[1][sl]
+        ref = Js @ vv
+        got = np.empty(2 * col.n)
+        got[0::2], got[1::2] = wn[sl], wp[sl]
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert err < 1e-4, (i, col.n, err)
+
+
+def _check_roots(orc, cols, packed, got_n, got_p, tol):
+    worst = 0.0
+    for i, col in enumerate(cols):
+        sl = slice(packed.col_offset[i], packed.col_offset[i + 1])
+        r = orc.newton(orc.OracleColumn(col), reference=True)
+        assert r.status == orc.CONVERGED
+        en = np.linalg.norm(got_n[sl] - r.ne) / np.linalg.norm(r.ne)
+        ep = np.linalg.norm(got_p[sl] - r.phi) / max(np.linalg.norm(r.phi), 1e-300)
+        worst = max(worst, en, ep)
+        assert en <= tol and ep <= tol, (i, col.n, en, ep)
+        # the GPU answer itself satisfies the stopping test in the oracle's arithmetic
+        assert orc.scaled_residual_inf(orc.OracleColumn(col), got_n[sl], got_p[sl]) < 2e-10
+    return worst
+
+
+@pytest.mark.parametrize("sched", ["batched", "plain"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_step_matches_oracle_root(J, orc, sched, prec):
+    cols = ragged_batch(seed=11)
+    packed = W.pack(cols)
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    cfg = J.config_for(packed, prec_precision=J.PREC_FP64 if prec == "fp64" else J.PREC_FP32,
+                       schedule=J.SCHED_BATCHED if sched == "batched" else J.SCHED_PLAIN)
+    solver = J.Solver(cfg)
+    rc, st = solver.step(prob, ne, phi)
+    assert rc == J.JFNK_OK, (st.status, st.res_scaled)
+    assert np.all(st.res_scaled <= 1e-10)
+    tol = 1e-9 if prec == "fp64" else 1e-5
+    _check_roots(orc, cols, packed, ne.cpu().numpy(), phi.cpu().numpy(), tol)
+
+
+def test_plain_and_batched_agree(J):
+    cols = ragged_batch(seed=12)
+    packed = W.pack(cols)
+    out = {}
+    for sched in (J.SCHED_PLAIN, J.SCHED_BATCHED):
+        prob, ne, phi, _, _ = J.device_problem(packed)
+        solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64, schedule=sched))
+        rc, st = solver.step(prob, ne, phi)
+        assert rc == J.JFNK_OK
+        out[sched] = (ne.cpu().numpy(), phi.cpu().numpy(), st.newton_iters.copy(), st.gmres_iters.copy())
+    a, b = out[J.SCHED_PLAIN], out[J.SCHED_BATCHED]
+    # same iterations; the host and device scalar arithmetic (sqrt, hypot)
+    # may differ in the last bit, so the roots agree to rounding level
+    np.testing.assert_allclose(a[0], b[0], rtol=1e-11, atol=1e-11 * np.abs(a[0]).max())
+    np.testing.assert_allclose(a[1], b[1], rtol=1e-11, atol=1e-11 * np.abs(a[1]).max())
+    assert np.array_equal(a[2], b[2])
+
+
+def test_config0_single_column(J, orc):
+    cols = W.config0()
+    packed = W.pack(cols)
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64, schedule=J.SCHED_PLAIN))
+    rc, st = solver.step(prob, ne, phi)
+    assert rc == J.JFNK_OK
+    _check_roots(orc, cols, packed, ne.cpu().numpy(), phi.cpu().numpy(), 1e-9)
+
+
+def test_config1_march_with_extrapolation(J, orc):
+    """The 4096-cell column at 1000 V marched 10 steps with the extrapolated
+    guess, each step compared with the oracle's root from the same X^n."""
+    col = W.config1()[0]
+    packed = W.pack([col])
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64, guess=J.GUESS_EXTRAP))
+    ne_prev = phi_prev = None
+    for k in range(10):
+        xn_n, xn_p = ne.cpu().numpy().copy(), phi.cpu().numpy().copy()
+        old_n, old_p = ne.clone(), phi.clone()
+        rc, st = solver.step(prob, ne, phi, ne_prev, phi_prev)
+        assert rc == J.JFNK_OK
+        if k == 1:
+            # right after the initial transient X^n beats the extrapolation
+            assert st.guess_used[0] == J.GUESS_PREV
+        r = orc.newton(orc.OracleColumn(col, xn_n, xn_p), reference=True)
+        got_n, got_p = ne.cpu().numpy(), phi.cpu().numpy()
+        assert np.linalg.norm(got_n - r.ne) / np.linalg.norm(r.ne) < 1e-9
+        assert np.linalg.norm(got_p - r.phi) / np.linalg.norm(r.phi) < 1e-9
+        ne_prev, phi_prev = old_n, old_p
+
+
+def test_advection_velocity(J, orc):
+    """Face velocities enter the Scharfetter-Gummel Peclet number."""
+    col = W.flame_column(333, 150.0)
+    uf = np.linspace(-40.0, 60.0, col.n + 1)
+    col.uface = uf
+    packed = W.pack([col])
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    prob.uface = torch.from_numpy(uf.copy()).cuda()
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64))
+    rc, st = solver.step(prob, ne, phi)
+    assert rc == J.JFNK_OK
+    r = orc.newton(orc.OracleColumn(col), reference=True)
+    assert np.linalg.norm(ne.cpu().numpy() - r.ne) / np.linalg.norm(r.ne) < 1e-9
+    assert np.linalg.norm(phi.cpu().numpy() - r.phi) / np.linalg.norm(r.phi) < 1e-9
+
+
+def test_invalid_arguments_leave_outputs_untouched(J):
+    cols = [W.flame_column(100, 50.0)]
+    packed = W.pack(cols)
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    solver = J.Solver(J.config_for(packed))
+    before = ne.clone()
+    prob.dt = np.array([-1.0])
+    rc, _ = solver.step(prob, ne, phi, raw=True)
+    assert rc == J.JFNK_EINVAL
+    assert torch.equal(ne, before)
+    prob.dt = np.array([1e-5])
+    big = W.pack([W.flame_column(200, 50.0)])
+    prob2, ne2, phi2, _, _ = J.device_problem(big)
+    rc, _ = solver.step(prob2, ne2, phi2, raw=True)
+    assert rc == J.JFNK_ECAPACITY
+
+
+def test_nonfinite_column_is_isolated(J):
+    cols = [W.flame_column(200, 100.0), W.flame_column(300, -200.0)]
+    packed = W.pack(cols)
+    packed.src[packed.col_offset[1] + 17] = np.nan
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64))
+    rc, st = solver.step(prob, ne, phi)
+    assert rc == J.JFNK_NOT_CONVERGED
+    assert st.status[0] == J.COL_CONVERGED
+    assert st.status[1] == J.COL_NONFINITE
+
+
+def test_newton_cap_flags_columns(J):
+    cols = [W.flame_column(400, 700.0)]
+    packed = W.pack(cols)
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    solver = J.Solver(J.config_for(packed, max_newton=1))
+    rc, st = solver.step(prob, ne, phi)
+    assert rc == J.JFNK_NOT_CONVERGED
+    assert st.status[0] == J.COL_MAX_NEWTON and st.newton_iters[0] == 1
