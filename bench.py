@@ -1,0 +1,267 @@
+"""Throughput of the batched JFNK electron/potential step on one MI355X.
+
+Workload: 1024 independent flame columns of U{512..8192} cells, applied
+voltage U[-1000, 1000] V, ion peak log-U[1e15, 1e17] m^-3, flame position
+U[0.5, 1.5] cm (seed 2026), dt = 1e-5 s, marched in episodes of 20 steps
+from n_e = n_ion (each episode restarts from the initial state).  One bench
+step = one jfnk_step over the whole batch (1024 column-steps).
+
+Prints one JSON line: whole-job column-steps/s of the batched solver at
+||S_F^-1 F||_inf < 1e-10, with the plain (host-driven, one column at a time)
+solver and the CPU oracle measured beside it, and the roofline of the solve
+kernel from HIP events and the algorithmic byte model of the design doc.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "column-steps/s at ||F||<1e-10, plain vs batched+learned JFNK, 1 MI355X"
+EPISODE = 20
+HBM_PEAK_GBS = 8000.0
+
+
+def bytes_per_cell(newton, gmres, backtracks, has_prev, fb):
+    """Algorithmic HBM bytes per cell of one column-step (each phase of the
+    method reads its operands from and writes its results to HBM once)."""
+    R = 72.0                                   # residual: X + 5 coefficients -> F
+    b = 112.0 + R                              # set-up: 7 inputs -> 5 coeffs + X, F(X^n)
+    if has_prev:
+        b += 32.0 + R                          # extrapolated candidate and its residual
+    fac = 40.0 + 20.0 * fb                     # X + 3 coefficients -> per-cell factors
+    app = 32.0 + 20.0 * fb                     # v + factors -> z
+    b += app                                   # stopping-test error estimate
+    if newton == 0:
+        b += fac
+    b += 32.0                                  # result back to the caller
+    if newton > 0:
+        k = gmres / newton                     # GMRES iterations per Newton iteration
+        extra = max(gmres - newton, 0)         # iterations that needed the CGS2 passes
+        per_newton = fac + k * (app + 104.0) + (16.0 * k * (k - 1) / 2.0) + 104.0
+        b += newton * per_newton
+        b += extra * 2 * (32.0 + 16.0 * (k + 1) / 2.0 + 16.0)
+        b += backtracks * 104.0
+        if k > 1:
+            b += newton * 16.0 * (k + 1)
+    return b
+
+
+def run_gpu(args):
+    import torch
+    from paper_1904_08510_amd import jfnk as J
+    from paper_1904_08510_amd import workloads as W
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    cols = W.config2(seed=2026, ncols=args.ncols)
+    packed = W.pack(cols)
+    prob, ne, phi, _, _ = J.device_problem(packed, dev)
+    ne0, phi0 = ne.clone(), phi.clone()
+    prev_n, prev_p = torch.empty_like(ne), torch.empty_like(phi)
+    ns = np.diff(packed.col_offset)
+    prec = J.PREC_FP32 if args.prec == "fp32" else J.PREC_FP64
+    guess = J.GUESS_EXTRAP
+    cfg = J.config_for(packed, prec_precision=prec, guess=guess, schedule=J.SCHED_BATCHED)
+    solver = J.Solver(cfg)
+    fb = 4.0 if prec == J.PREC_FP32 else 8.0
+    stream = torch.cuda.current_stream()
+    state = {"e": 0}
+
+    def one_step(record):
+        e = state["e"]
+        if e == 0:
+            ne.copy_(ne0)
+            phi.copy_(phi0)
+            has_prev = False
+        else:
+            has_prev = True
+        cur_n, cur_p = ne.clone(), phi.clone()
+        rc, st = solver.step(prob, ne, phi, prev_n if has_prev else None,
+                             prev_p if has_prev else None, stream=stream)
+        prev_n.copy_(cur_n)
+        prev_p.copy_(cur_p)
+        state["e"] = (e + 1) % EPISODE
+        if record is not None:
+            ms, _ = solver.last_timing()
+            nbytes = float(np.sum(ns * np.array([
+                bytes_per_cell(st.newton_iters[i], st.gmres_iters[i], st.backtracks[i], has_prev, fb)
+                for i in range(len(ns))])))
+            record.append(dict(rc=rc, ms=ms, bytes=nbytes, newton=st.newton_iters.copy(),
+                               gmres=st.gmres_iters.copy(), bt=st.backtracks.copy(),
+                               res=float(st.res_scaled.max()), conv=int(np.sum(st.status == 0))))
+        return rc
+
+    for _ in range(args.warmup):
+        one_step(None)
+    state["e"] = 0
+    torch.cuda.synchronize()
+    rec = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step(rec)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    converged = sum(r["conv"] for r in rec)
+    total_cs = args.ncols * args.steps
+    kern_ms = sum(r["ms"] for r in rec)
+    kern_bytes = sum(r["bytes"] for r in rec)
+    achieved = kern_bytes / (kern_ms * 1e-3) / 1e9
+    newton = np.concatenate([r["newton"] for r in rec])
+    gmres = np.concatenate([r["gmres"] for r in rec])
+    out = dict(
+        value=converged / wall, wall=wall, ms_per_step=1e3 * wall / args.steps,
+        converged=converged, total=total_cs, max_res=max(r["res"] for r in rec),
+        kernel_ms_avg=kern_ms / len(rec), achieved_gbs=achieved, bytes_per_launch=kern_bytes / len(rec),
+        newton_mean=float(newton.mean()), newton_max=int(newton.max()),
+        gmres_per_newton=float(gmres.sum() / max(newton.sum(), 1)),
+        cells=int(packed.col_offset[-1]),
+    )
+    solver.close()
+
+    # plain schedule on a bounded sample of the same batch (one column per call)
+    if not args.skip_plain:
+        idx = list(range(0, args.ncols, max(1, args.ncols // args.plain_cols)))[: args.plain_cols]
+        sub = W.pack([cols[i] for i in idx])
+        sprob, sne, sphi, _, _ = J.device_problem(sub, dev)
+        s0n, s0p = sne.clone(), sphi.clone()
+        pn, pp = torch.empty_like(sne), torch.empty_like(sphi)
+        psolver = J.Solver(J.config_for(sub, prec_precision=J.PREC_FP64, guess=J.GUESS_EXTRAP,
+                                        schedule=J.SCHED_PLAIN))
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        conv_p = 0
+        for e in range(args.plain_steps):
+            cn, cp = sne.clone(), sphi.clone()
+            rc, st = psolver.step(sprob, sne, sphi, pn if e else None, pp if e else None, stream=stream)
+            conv_p += int(np.sum(st.status == 0))
+            pn.copy_(cn)
+            pp.copy_(cp)
+        torch.cuda.synchronize()
+        tplain = time.perf_counter() - tp
+        out["plain"] = dict(value=conv_p / tplain, columns=len(idx), steps=args.plain_steps,
+                            sample=f"{len(idx)} columns (every {args.ncols // len(idx)}th) x "
+                                   f"episode steps 0..{args.plain_steps - 1}, FP64 factors, extrapolated guess")
+        psolver.close()
+        del s0n, s0p
+    return out
+
+
+def _cpu_column_episode(args):
+    """Oracle timed mode over the first `steps` steps of a column's episode."""
+    ci, steps = args
+    from oracle import oracle as O
+    from paper_1904_08510_amd import workloads as W
+    col = W.config2(seed=2026)[ci]
+    t0 = time.process_time()
+    ne, phi = col.ne.copy(), col.phi.copy()
+    pne = pphi = None
+    for k in range(steps):
+        oc = O.OracleColumn(col, ne, phi)
+        g_n, g_p = ne, phi
+        if pne is not None:
+            e_n, e_p = 2 * ne - pne, 2 * phi - pphi
+            if O.scaled_residual_inf(oc, e_n, e_p) <= O.scaled_residual_inf(oc, ne, phi):
+                g_n, g_p = e_n, e_p
+        r = O.newton(oc, g_n, g_p, tol=1e-10)
+        pne, pphi = ne, phi
+        ne, phi = r.ne, r.phi
+    return time.process_time() - t0
+
+
+def run_cpu(args):
+    import multiprocessing as mp
+    ncores = min(len(os.sched_getaffinity(0)), 16)
+    idx = list(range(0, 1024, 1024 // args.cpu_cols))[: args.cpu_cols]
+    tasks = [(i, args.cpu_steps) for i in idx]
+    from oracle import oracle as O
+    O.lib()
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(ncores) as pool:
+        cpu_times = pool.map(_cpu_column_episode, tasks, chunksize=1)
+    wall = time.perf_counter() - t0
+    n = len(tasks) * args.cpu_steps
+    return dict(value=n / wall, unit="column-steps/s", cores=ncores, kind="oracle",
+                sample=f"{len(tasks)} columns (every {1024 // len(tasks)}th of the batch) x episode steps "
+                       f"0..{args.cpu_steps - 1}, timed mode (1e-10), one process per core; "
+                       f"{sum(cpu_times):.1f} CPU-s",
+                single_core_value=n / sum(cpu_times))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--ncols", type=int, default=1024)
+    ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--skip-plain", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--plain-cols", type=int, default=16)
+    ap.add_argument("--plain-steps", type=int, default=EPISODE)
+    ap.add_argument("--cpu-cols", type=int, default=1024)
+    ap.add_argument("--cpu-steps", type=int, default=EPISODE)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the columns are independent and this build runs "
+              f"on a single MI355X (asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+    # the CPU leg forks its worker processes before this process touches the GPU
+    cpu = None if args.skip_cpu else run_cpu(args)
+    g = run_gpu(args)
+    line = {
+        "metric": METRIC,
+        "value": g["value"],
+        "unit": "column-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": g["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else "f64+f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.ncols} flame columns x U{{512..8192}} cells (seed 2026), V~U[-1000,1000], "
+                        f"ion peak logU[1e15,1e17], dt=1e-5 s, 20-step episodes; batched, "
+                        f"{args.prec.upper()} preconditioner factors, extrapolated guess",
+            "columns": args.ncols,
+            "cells": g["cells"],
+            "episode_steps": EPISODE,
+            "prec": args.prec,
+            "guess": "extrap",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": g["achieved_gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": g["achieved_gbs"] / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "k_solve",
+            "kernel_ms_avg": g["kernel_ms_avg"],
+            "bytes_per_launch": g["bytes_per_launch"],
+        },
+        "cpu_baseline": cpu,
+        "plain": g.get("plain"),
+        "speedup_vs_plain": (g["value"] / g["plain"]["value"]) if g.get("plain") else None,
+        "solver": {
+            "converged": g["converged"], "column_steps": g["total"], "max_res": g["max_res"],
+            "newton_mean": g["newton_mean"], "newton_max": g["newton_max"],
+            "gmres_per_newton": g["gmres_per_newton"],
+        },
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

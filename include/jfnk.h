@@ -91,7 +91,9 @@ typedef struct {
                                     ||P^-1 S_F^-1 F||_inf (the scaled Newton step
                                     from the current iterate) <= tol_x */
     double gamma;                /* GMRES forcing: ||J d + F|| <= gamma ||F|| */
-    double armijo_alpha;         /* sufficient-decrease constant */
+    double ls_theta;             /* backtracking accepts X + lam d when the
+                                    simplified Newton correction there satisfies
+                                    ||P^-1 S_F^-1 F||_inf <= (1 - ls_theta lam) ||d||_inf */
     int32_t prec_precision;      /* JFNK_PREC_* */
     int32_t guess;               /* JFNK_GUESS_* */
     int32_t schedule;            /* JFNK_SCHED_* */
@@ -141,7 +143,7 @@ typedef struct {
 } jfnk_stats;
 
 /* Fill cfg with the defaults: restart 30, 5 restarts, 50 Newton iterations,
-   10 backtracks, tol_f 1e-10, tol_x 1e-10, gamma 1e-4, alpha 1e-4, FP32
+   10 backtracks, tol_f 1e-10, tol_x 1e-10, gamma 1e-4, ls_theta 0.25, FP32
    preconditioner, extrapolated guess, batched schedule. */
 void jfnk_config_default(jfnk_config *cfg);
 
@@ -162,6 +164,12 @@ void jfnk_destroy(jfnk_ctx *ctx);
 
 /* Message of the last error on this context (never NULL). */
 const char *jfnk_last_error(const jfnk_ctx *ctx);
+
+/* Device time of the last jfnk_step's solve (ms, HIP events recorded on the
+   step's stream right before and after the solve launches; for the plain
+   schedule the span of all its phase launches) and the number of launches
+   it spans (-1: host-driven).  Returns JFNK_EINVAL on NULL arguments. */
+int jfnk_last_timing(const jfnk_ctx *ctx, double *solve_ms, int32_t *launches);
 
 /* ---- test exports: single phases of the step, same kernels ----------- */
 

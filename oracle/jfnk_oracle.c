@@ -307,14 +307,13 @@ void orc_jacobian_band(const orc_column *c, const double *ne, const double *phi,
 /* Direct solvers (textbook Gaussian elimination with partial pivoting).  */
 /* ---------------------------------------------------------------------- */
 
-/* Band LU with partial pivoting, then forward/back substitution.
-   ab is overwritten by the factors; b by the solution.  Returns 0, or
-   k+1 if the k-th pivot is exactly zero. */
-int orc_band_solve(int n, double *ab, double *b)
+/* Band LU with partial pivoting (row exchanges recorded in piv[n]).  ab is
+   overwritten by the factors.  Returns 0, or k+1 if the k-th pivot is
+   exactly zero. */
+int orc_band_factor(int n, double *ab, int *piv)
 {
     const int kl = ORC_KL, ku = ORC_KU, w = ORC_BAND_W;
 #define AB(i, j) ab[(size_t)(i) * w + ((j) - (i) + kl)]
-    int *piv = (int *)malloc(sizeof(int) * n);
     int info = 0;
     for (int k = 0; k < n; ++k) {
         int last = k + kl < n - 1 ? k + kl : n - 1;
@@ -337,23 +336,38 @@ int orc_band_solve(int n, double *ab, double *b)
                 for (int j = k + 1; j <= jend; ++j) AB(i, j) -= l * AB(k, j);
         }
     }
-    if (!info) {
-        /* L y = P b */
-        for (int k = 0; k < n; ++k) {
-            int p = piv[k];
-            if (p != k) { double t = b[k]; b[k] = b[p]; b[p] = t; }
-            int last = k + kl < n - 1 ? k + kl : n - 1;
-            for (int i = k + 1; i <= last; ++i) b[i] -= AB(i, k) * b[k];
-        }
-        /* U x = y */
-        for (int k = n - 1; k >= 0; --k) {
-            int jend = k + kl + ku < n - 1 ? k + kl + ku : n - 1;
-            double s = b[k];
-            for (int j = k + 1; j <= jend; ++j) s -= AB(k, j) * b[j];
-            b[k] = s / AB(k, k);
-        }
+#undef AB
+    return info;
+}
+
+/* Solve with the factors of orc_band_factor; b is overwritten. */
+void orc_band_factored_solve(int n, const double *ab, const int *piv, double *b)
+{
+    const int kl = ORC_KL, ku = ORC_KU, w = ORC_BAND_W;
+#define AB(i, j) ab[(size_t)(i) * w + ((j) - (i) + kl)]
+    /* L y = P b */
+    for (int k = 0; k < n; ++k) {
+        int p = piv[k];
+        if (p != k) { double t = b[k]; b[k] = b[p]; b[p] = t; }
+        int last = k + kl < n - 1 ? k + kl : n - 1;
+        for (int i = k + 1; i <= last; ++i) b[i] -= AB(i, k) * b[k];
+    }
+    /* U x = y */
+    for (int k = n - 1; k >= 0; --k) {
+        int jend = k + kl + ku < n - 1 ? k + kl + ku : n - 1;
+        double s = b[k];
+        for (int j = k + 1; j <= jend; ++j) s -= AB(k, j) * b[j];
+        b[k] = s / AB(k, k);
     }
 #undef AB
+}
+
+/* Factor and solve one right-hand side (ab and b overwritten). */
+int orc_band_solve(int n, double *ab, double *b)
+{
+    int *piv = (int *)malloc(sizeof(int) * n);
+    int info = orc_band_factor(n, ab, piv);
+    if (!info) orc_band_factored_solve(n, ab, piv, b);
     free(piv);
     return info;
 }
@@ -406,6 +420,18 @@ static void scaled_norms(int N, const double *fe, const double *fp, const double
     if (n2) *n2 = sqrt(s2);
 }
 
+/* ||S_X^-1 d||_inf of an interleaved (n, phi) vector */
+static double scaled_step_inf(int N, const double *d, const double s[4])
+{
+    double m = 0.0;
+    for (int i = 0; i < N; ++i) {
+        double a = fabs(d[2 * i] / s[2]), b = fabs(d[2 * i + 1] / s[3]);
+        if (a > m) m = a;
+        if (b > m) m = b;
+    }
+    return m;
+}
+
 int orc_newton(const orc_column *c, const orc_newton_opts *o, double *ne, double *phi,
                orc_newton_stats *st)
 {
@@ -420,7 +446,9 @@ int orc_newton(const orc_column *c, const orc_newton_opts *o, double *ne, double
     double *xn = (double *)malloc(sizeof(double) * N);
     double *xp = (double *)malloc(sizeof(double) * N);
     double *rhs = (double *)malloc(sizeof(double) * n2);
+    double *cor = (double *)malloc(sizeof(double) * n2);
     double *ab = (double *)malloc(sizeof(double) * (size_t)n2 * ORC_BAND_W);
+    int *piv = (int *)malloc(sizeof(int) * n2);
     double *best_n = (double *)malloc(sizeof(double) * N);
     double *best_p = (double *)malloc(sizeof(double) * N);
     orc_source_term(c, f);
@@ -454,10 +482,18 @@ int orc_newton(const orc_column *c, const orc_newton_opts *o, double *ne, double
         prev = rinf;
         /* Newton direction: J d = -F */
         orc_jacobian_band(c, ne, phi, ab);
+        if (orc_band_factor(n2, ab, piv) != 0) { status = ORC_SINGULAR; break; }
         for (int i = 0; i < N; ++i) { rhs[2 * i] = -fe[i]; rhs[2 * i + 1] = -fp[i]; }
-        if (orc_band_solve(n2, ab, rhs) != 0) { status = ORC_SINGULAR; break; }
-        /* Armijo backtracking on the scaled 2-norm */
+        orc_band_factored_solve(n2, ab, piv, rhs);
+        const double dinf = scaled_step_inf(N, rhs, s);
+        /* Backtracking (Section 3.2: line search for globalisation).  A trial
+           step X + lam d is taken when the simplified Newton correction there,
+           J(X)^-1 F(X + lam d), has shrunk against the step d in the scaled
+           max norm: ||S_X^-1 J^-1 F(X + lam d)||_inf <= (1 - theta lam) ||S_X^-1 d||_inf
+           with theta = ls_theta (the natural monotonicity test, invariant to
+           the scaling of F).  If no halving passes, the full step is taken. */
         double lam = 1.0, rt2 = 0.0, rtinf = 0.0;
+        int accepted = 0, finite_seen = 0;
         for (;;) {
             for (int i = 0; i < N; ++i) {
                 xn[i] = ne[i] + lam * rhs[2 * i];
@@ -465,10 +501,30 @@ int orc_newton(const orc_column *c, const orc_newton_opts *o, double *ne, double
             }
             orc_residual(c, f, xn, xp, te, tp);
             scaled_norms(N, te, tp, s, &rtinf, &rt2);
-            if (!isnan(rt2) && rt2 <= (1.0 - o->armijo_alpha * lam) * r2) break;
+            if (!isnan(rt2)) {
+                finite_seen = 1;
+                for (int i = 0; i < N; ++i) { cor[2 * i] = -te[i]; cor[2 * i + 1] = -tp[i]; }
+                orc_band_factored_solve(n2, ab, piv, cor);
+                if (scaled_step_inf(N, cor, s) <= (1.0 - o->ls_theta * lam) * dinf) { accepted = 1; break; }
+            }
             if (lam * 0.5 < o->lambda_min) break;
             lam *= 0.5;
             ++backtracks;
+        }
+        if (!accepted) {
+            /* full step unless it is not finite (then the last finite trial) */
+            for (int i = 0; i < N; ++i) { cor[2 * i] = ne[i] + rhs[2 * i]; cor[2 * i + 1] = phi[i] + rhs[2 * i + 1]; }
+            for (int i = 0; i < N; ++i) { xn[i] = cor[2 * i]; xp[i] = cor[2 * i + 1]; }
+            orc_residual(c, f, xn, xp, te, tp);
+            scaled_norms(N, te, tp, s, &rtinf, &rt2);
+            if (isnan(rt2) && finite_seen) {
+                for (int i = 0; i < N; ++i) {
+                    xn[i] = ne[i] + lam * rhs[2 * i];
+                    xp[i] = phi[i] + lam * rhs[2 * i + 1];
+                }
+                orc_residual(c, f, xn, xp, te, tp);
+                scaled_norms(N, te, tp, s, &rtinf, &rt2);
+            }
         }
         memcpy(ne, xn, sizeof(double) * N);
         memcpy(phi, xp, sizeof(double) * N);
@@ -492,6 +548,6 @@ int orc_newton(const orc_column *c, const orc_newton_opts *o, double *ne, double
         for (int k = 0; k < 4; ++k) st->scal[k] = s[k];
     }
     free(f); free(fe); free(fp); free(te); free(tp); free(xn); free(xp);
-    free(rhs); free(ab); free(best_n); free(best_p);
+    free(rhs); free(cor); free(ab); free(piv); free(best_n); free(best_p);
     return status;
 }

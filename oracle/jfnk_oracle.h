@@ -41,7 +41,7 @@ typedef struct {
     double tol;                  /* stop at ||S_F^-1 F||_inf <= tol (timed mode) */
     int reference_mode;          /* 1: iterate to the rounding floor */
     double floor_tol;            /* reference mode stops here at the latest */
-    double armijo_alpha;
+    double ls_theta;             /* restricted natural monotonicity factor */
     double lambda_min;
 } orc_newton_opts;
 
@@ -60,6 +60,8 @@ void orc_residual(const orc_column *c, const double *f, const double *ne, const 
 void orc_scalings(const orc_column *c, double s[4]);
 void orc_jacobian_dense(const orc_column *c, const double *ne, const double *phi, double *a);
 void orc_jacobian_band(const orc_column *c, const double *ne, const double *phi, double *ab);
+int orc_band_factor(int n, double *ab, int *piv);
+void orc_band_factored_solve(int n, const double *ab, const int *piv, double *b);
 int orc_band_solve(int n, double *ab, double *b);
 int orc_dense_solve(int n, double *a, double *b);
 int orc_newton(const orc_column *c, const orc_newton_opts *o, double *ne, double *phi,

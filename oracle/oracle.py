@@ -33,7 +33,7 @@ class _Column(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("max_iters", C.c_int), ("tol", C.c_double), ("reference_mode", C.c_int),
-                ("floor_tol", C.c_double), ("armijo_alpha", C.c_double),
+                ("floor_tol", C.c_double), ("ls_theta", C.c_double),
                 ("lambda_min", C.c_double)]
 
 
@@ -210,12 +210,12 @@ class NewtonResult:
 
 
 def newton(oc: OracleColumn, ne0=None, phi0=None, *, tol=1e-10, reference=False,
-           max_iters=100, floor_tol=1e-15, armijo_alpha=1e-4,
+           max_iters=100, floor_tol=1e-15, ls_theta=0.25,
            lambda_min=2.0 ** -10) -> NewtonResult:
     """Root of the backward-Euler system from the guess (ne0, phi0) (default X^n)."""
     ne = np.array(oc.ne_old if ne0 is None else ne0, dtype=np.float64, copy=True)
     phi = np.array(oc.phi_old if phi0 is None else phi0, dtype=np.float64, copy=True)
-    o = _Opts(max_iters, tol, 1 if reference else 0, floor_tol, armijo_alpha, lambda_min)
+    o = _Opts(max_iters, tol, 1 if reference else 0, floor_tol, ls_theta, lambda_min)
     st = _Stats()
     lib().orc_newton(C.byref(oc.s), C.byref(o), _p(ne), _p(phi), C.byref(st))
     return NewtonResult(ne, phi, st.iters, st.backtracks, st.status, st.res_scaled,
@@ -233,16 +233,19 @@ def march(col, steps: int, *, reference=True, tol=1e-10, guess="prev", on_step=N
     """Advance a column ``steps`` backward-Euler steps with the oracle.
 
     Returns the list of (ne, phi) after each step.  ``guess`` is "prev"
-    (X^n) or "extrap" (2 X^n - X^{n-1}, X^n on the first step)."""
+    (X^n) or "extrap" (the better of X^n and 2 X^n - X^{n-1} by scaled
+    residual, ties to the extrapolation)."""
     ne, phi = col.ne.copy(), col.phi.copy()
     pne, pphi = None, None
     out = []
     for k in range(steps):
         oc = OracleColumn(col, ne, phi)
+        g0, g1 = ne, phi
         if guess == "extrap" and pne is not None:
-            g0, g1 = 2 * ne - pne, 2 * phi - pphi
-        else:
-            g0, g1 = ne, phi
+            # the extrapolation if its scaled residual is not larger than X^n's
+            e0, e1 = 2 * ne - pne, 2 * phi - pphi
+            if scaled_residual_inf(oc, e0, e1) <= scaled_residual_inf(oc, ne, phi):
+                g0, g1 = e0, e1
         r = newton(oc, g0, g1, tol=tol, reference=reference)
         if on_step is not None:
             on_step(k, r)

@@ -45,7 +45,7 @@ __global__ __launch_bounds__(T) void k_solve(SolveArgs a) {
 // host through W.scal.
 // ---------------------------------------------------------------------------
 enum Phase {
-    PH_SETUP, PH_FACTOR, PH_APPLY, PH_JV, PH_CGS, PH_LINCOMB, PH_NORM_DX, PH_RES0, PH_TRIAL,
+    PH_SETUP, PH_FACTOR, PH_APPLY, PH_CORR, PH_JV, PH_CGS, PH_LINCOMB, PH_NORM_DX, PH_RES0, PH_TRIAL,
     PH_FINAL, PH_EVAL, PH_LOAD_X, PH_LOAD_V, PH_STORE_V, PH_STORE_W, PH_STORE_F
 };
 
@@ -95,6 +95,11 @@ __global__ __launch_bounds__(T) void k_phase(PhaseArgs a) {
         break;
     case PH_APPLY: {
         const Vec2<double> z = col.apply(a.v, col.Zb(a.zslot, 0), col.Zb(a.zslot, 1));
+        if (threadIdx.x == 0) { scal[0] = z.x; scal[1] = z.y; }
+        break;
+    }
+    case PH_CORR: {
+        const Vec2<double> z = col.apply(a.v, col.Vb(a.prm.m, 0), col.Vb(a.prm.m, 1));
         if (threadIdx.x == 0) { scal[0] = z.x; scal[1] = z.y; }
         break;
     }
@@ -217,6 +222,10 @@ struct jfnk_ctx {
     std::string err;
     bool poisoned = false;
     int Tsel = 0;                // workgroup size of the last schedule
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // around the solve launches
+    bool timed = false;
+    double last_ms = 0.0;
+    int last_launches = 0;
 };
 
 namespace {
@@ -339,7 +348,7 @@ SolverParams make_params(const jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_
     s.tol_f = ctx->cfg.tol_f;
     s.tol_x = ctx->cfg.tol_x;
     s.gamma = ctx->cfg.gamma;
-    s.alpha = ctx->cfg.armijo_alpha;
+    s.theta = ctx->cfg.ls_theta;
     return s;
 }
 
@@ -403,6 +412,12 @@ struct HostExecT {
         return n;
     }
     void factor(int cur) { a.cur = cur; launch(PH_FACTOR); }
+    Vec2<double> correction(int b) {
+        a.v = fref(b, -1.0);
+        launch(PH_CORR);
+        const double* s = fetch(2);
+        return Vec2<double>{s[0], s[1]};
+    }
     VecRef fref(int cur, double sc) { return VecRef{Fb(cur, 0), Fb(cur, 1), sc * isfn, sc * isfp}; }
     VecRef vslot(int k, double sc) { return VecRef{Vb(k, 0), Vb(k, 1), sc, sc}; }
     void set_basis(int i, VecRef r) { bas[i] = r; }
@@ -485,6 +500,7 @@ template <int T, class FT>
 int run_plain(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t st) {
     const SolverParams prm = make_params(ctx, p, x);
     const UserArrays U = make_user(p, x);
+    HIP_OK(hipEventRecord(ctx->ev0, st));
     for (int c = 0; c < p->ncols; ++c) {
         HostExecT<T, FT> ex;
         ex.ctx = ctx;
@@ -501,6 +517,9 @@ int run_plain(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t s
             return fail(ctx, JFNK_EHIP, std::string("plain schedule: ") + hipGetErrorString(ex.herr));
         }
     }
+    HIP_OK(hipEventRecord(ctx->ev1, st));
+    ctx->timed = true;
+    ctx->last_launches = -1;   // host-driven: many launches, span measured
     return JFNK_OK;
 }
 
@@ -511,8 +530,12 @@ int run_batched(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t
     a.prm = make_params(ctx, p, x);
     a.U = make_user(p, x);
     a.order = ctx->d_order;
+    HIP_OK(hipEventRecord(ctx->ev0, st));
     hipLaunchKernelGGL((k_solve<T, FT>), dim3(p->ncols), dim3(T), Lds<T>::bytes(), st, a);
     HIP_OK(hipGetLastError());
+    HIP_OK(hipEventRecord(ctx->ev1, st));
+    ctx->timed = true;
+    ctx->last_launches = 1;
     return JFNK_OK;
 }
 
@@ -560,6 +583,12 @@ int upload_schedule(jfnk_ctx* ctx, int ncols, hipStream_t st) {
 int gather_stats(jfnk_ctx* ctx, int ncols, jfnk_stats* stt, hipStream_t st, int* nfail) {
     HIP_OK(hipMemcpyAsync(ctx->h_cst, ctx->W.cst, sizeof(ColState) * ncols, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
+    if (ctx->timed) {
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        ctx->last_ms = ms;
+        ctx->timed = false;
+    }
     int bad = 0;
     for (int c = 0; c < ncols; ++c) {
         const ColState& s = ctx->h_cst[c];
@@ -632,7 +661,7 @@ void jfnk_config_default(jfnk_config* cfg) {
     cfg->tol_f = 1e-10;
     cfg->tol_x = 1e-10;
     cfg->gamma = 1e-4;
-    cfg->armijo_alpha = 1e-4;
+    cfg->ls_theta = 0.25;
     cfg->prec_precision = JFNK_PREC_FP32;
     cfg->guess = JFNK_GUESS_EXTRAP;
     cfg->schedule = JFNK_SCHED_BATCHED;
@@ -646,7 +675,7 @@ int jfnk_create(const jfnk_config* cfg, jfnk_ctx** out) {
     if (cfg->max_cols < 1 || cfg->max_total_cells < 3 || cfg->max_cells_per_col < 3 ||
         cfg->gmres_restart < 1 || cfg->gmres_restart > kMaxRestart || cfg->max_restarts < 0 ||
         cfg->max_newton < 0 || cfg->max_backtracks < 0 || !(cfg->tol_f > 0.0) || !(cfg->tol_x >= 0.0) ||
-        !(cfg->gamma > 0.0 && cfg->gamma < 1.0) || !(cfg->armijo_alpha >= 0.0 && cfg->armijo_alpha < 1.0) ||
+        !(cfg->gamma > 0.0 && cfg->gamma < 1.0) || !(cfg->ls_theta >= 0.0 && cfg->ls_theta < 1.0) ||
         (cfg->prec_precision != JFNK_PREC_FP64 && cfg->prec_precision != JFNK_PREC_FP32) ||
         cfg->guess < 0 || cfg->guess > 2 ||
         (cfg->schedule != JFNK_SCHED_PLAIN && cfg->schedule != JFNK_SCHED_BATCHED))
@@ -674,6 +703,8 @@ int jfnk_create(const jfnk_config* cfg, jfnk_ctx** out) {
     if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_cst, sizeof(ColState) * cfg->max_cols, 0);
     if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_scal, sizeof(double) * kScalSlots * 2, 0);
     if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_order, sizeof(int) * cfg->max_cols, 0);
+    if (e == hipSuccess) e = hipEventCreate(&ctx->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ctx->ev1);
     if (e != hipSuccess) { (void)hipGetLastError(); jfnk_destroy(ctx); return JFNK_ENOMEM; }
     // zero the whole workspace once: padding cells must read as zero
     e = hipMemset(ctx->base, 0, sizeof(double) * words);
@@ -691,7 +722,16 @@ void jfnk_destroy(jfnk_ctx* ctx) {
     if (ctx->h_cst) (void)hipHostFree(ctx->h_cst);
     if (ctx->h_scal) (void)hipHostFree(ctx->h_scal);
     if (ctx->h_order) (void)hipHostFree(ctx->h_order);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     delete ctx;
+}
+
+int jfnk_last_timing(const jfnk_ctx* ctx, double* solve_ms, int32_t* launches) {
+    if (!ctx || !solve_ms) return JFNK_EINVAL;
+    *solve_ms = ctx->last_ms;
+    if (launches) *launches = ctx->last_launches;
+    return JFNK_OK;
 }
 
 const char* jfnk_last_error(const jfnk_ctx* ctx) {

@@ -68,15 +68,18 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
     double hcol[kMaxRestart + 2];
     double y[kMaxRestart];
     int factored = -1;   // buffer whose state the current factorisation was built at
+    double est = -1.0;   // ||S_X^-1 P^-1 S_F^-1 F(X)||_inf of the current iterate (-1: unknown)
     for (;;) {
         if (isnan(nr.r2)) { status = COL_NONFINITE; break; }
         if (nr.rinf <= p.tol_f) {
             if (p.tol_x <= 0.0) { status = COL_CONVERGED; break; }
-            // error estimate ||S_X^-1 (X - X*)||_inf ~ ||P^-1 S_F^-1 F(X)||_inf with
-            // the latest factorisation (the stopping test on the Newton step)
-            if (factored < 0) { ex.factor(cur); factored = cur; }
-            const double e = ex.apply(ex.fref(cur, 1.0), 0).y;
-            if (e <= p.tol_x) { status = COL_CONVERGED; break; }
+            // stopping test on the Newton correction: the error estimate
+            // ||S_X^-1 (X - X*)||_inf ~ ||P^-1 S_F^-1 F(X)||_inf with the latest factorisation
+            if (est < 0.0) {
+                if (factored < 0) { ex.factor(cur); factored = cur; }
+                est = ex.correction(cur).y;
+            }
+            if (est <= p.tol_x) { status = COL_CONVERGED; break; }
         }
         if (it >= p.max_newton) break;
         if (factored != cur) ex.factor(cur);
@@ -86,7 +89,6 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
         const double xnorm = sqrt(nr.xn2);
         double beta = beta0;
         bool have_dx = false;
-        int kdir = 0;
         bool lucky = false;
         for (int cyc = 0;; ++cyc) {
             if (cyc == 0) {
@@ -132,29 +134,42 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
             const int k = j;
             if (k > 0) {
                 ex.gm_solve(k, y);
-                kdir = ex.direction(k, y, have_dx);
+                ex.direction(k, y, have_dx);
                 have_dx = true;
             }
             if (conv || lucky || cyc >= p.max_restarts) break;
             ++rtot;
         }
         if (!have_dx) { status = COL_LINESEARCH; break; }
-        // backtracking line search (Armijo on ||S_F^-1 F||_2)
-        const int nxt = (cur + 1) % 3;
-        double lam = 1.0;
-        int bt = 0;
-        Norms tn;
+        // Backtracking: the trial X + lam S_X d is taken when the simplified
+        // Newton correction there, P^-1 S_F^-1 F(X + lam S_X d), has shrunk
+        // against the step: ||.||_inf <= (1 - theta lam) ||d||_inf (natural
+        // monotonicity test).  If no halving passes, the full step is taken.
+        const int ba = (cur + 1) % 3, bb = (cur + 2) % 3;
+        double lam = 1.0, dinf = 0.0, e_full = -1.0, e_acc = -1.0;
+        int bt = 0, outb = ba;
+        bool accepted = false;
+        Norms tn, tfull;
         for (;;) {
-            tn = ex.trial(cur, nxt, lam);
-            if (!isnan(tn.r2) && tn.r2 <= (1.0 - p.alpha * lam) * nr.r2) break;
+            outb = (bt == 0) ? ba : bb;
+            tn = ex.trial(cur, outb, lam);
+            if (bt == 0) { tfull = tn; dinf = tn.step; }
+            if (!isnan(tn.r2)) {
+                const double e = ex.correction(outb).y;
+                if (bt == 0) e_full = e;
+                if (e <= (1.0 - p.theta * lam) * dinf) { accepted = true; e_acc = e; break; }
+            }
             if (bt >= p.max_backtracks) break;
             lam *= 0.5;
             ++bt;
         }
         btot += bt;
-        (void)kdir;
-        if (isnan(tn.r2)) { status = COL_NONFINITE; break; }
-        cur = nxt;
+        if (!accepted) {
+            if (!isnan(tfull.r2)) { outb = ba; tn = tfull; e_acc = e_full; }
+            else if (isnan(tn.r2)) { status = COL_NONFINITE; break; }
+        }
+        est = e_acc;
+        cur = outb;
         nr = tn;
         ++it;
     }
@@ -199,6 +214,10 @@ struct DevExec {
 
     __device__ Vec2<double> apply(const VecRef& v, int zslot) {
         return col.apply(v, col.Zb(zslot, 0), col.Zb(zslot, 1));
+    }
+    // P^-1 (-S_F^-1 F) of buffer b, into the last Krylov slot (free after GMRES)
+    __device__ Vec2<double> correction(int b) {
+        return col.apply(fref(b, -1.0), col.Vb(col.prm.m, 0), col.Vb(col.prm.m, 1));
     }
     __device__ void jv(int cur, int zslot, double eps, int wslot, double* dots) {
         const VecRef z{col.Zb(zslot, 0), col.Zb(zslot, 1), 1.0, 1.0};

@@ -57,7 +57,7 @@ struct SolverParams {
     int32_t has_prev;       // X^{n-1} supplied
     int32_t has_learned;    // learned candidate supplied
     int32_t has_u;          // advective face velocities supplied
-    double tol_f, tol_x, gamma, alpha;
+    double tol_f, tol_x, gamma, theta;
 };
 
 // Caller arrays (natural layout, device pointers).

@@ -34,7 +34,7 @@ class jfnk_config(C.Structure):
                 ("max_cells_per_col", C.c_int32), ("gmres_restart", C.c_int32),
                 ("max_restarts", C.c_int32), ("max_newton", C.c_int32),
                 ("max_backtracks", C.c_int32), ("tol_f", C.c_double), ("tol_x", C.c_double),
-                ("gamma", C.c_double), ("armijo_alpha", C.c_double),
+                ("gamma", C.c_double), ("ls_theta", C.c_double),
                 ("prec_precision", C.c_int32), ("guess", C.c_int32), ("schedule", C.c_int32),
                 ("threads_override", C.c_int32)]
 
@@ -79,6 +79,8 @@ def lib():
         L.jfnk_destroy.restype = None
         L.jfnk_last_error.argtypes = [C.c_void_p]
         L.jfnk_last_error.restype = C.c_char_p
+        L.jfnk_last_timing.argtypes = [C.c_void_p, _dp, _ip]
+        L.jfnk_last_timing.restype = C.c_int
         L.jfnk_eval_residual.argtypes = [C.c_void_p, C.POINTER(jfnk_problem), C.POINTER(jfnk_state),
                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, _dp, C.c_void_p]
         L.jfnk_eval_residual.restype = C.c_int
@@ -95,7 +97,7 @@ def lib():
 
 
 EXPORTED_SYMBOLS = ("jfnk_config_default", "jfnk_create", "jfnk_step", "jfnk_destroy",
-                    "jfnk_last_error", "jfnk_eval_residual", "jfnk_eval_jv", "jfnk_block_solve")
+                    "jfnk_last_error", "jfnk_last_timing", "jfnk_eval_residual", "jfnk_eval_jv", "jfnk_block_solve")
 
 
 class JfnkError(RuntimeError):
@@ -195,9 +197,12 @@ class Stats:
 
 
 def _stream_ptr(stream):
+    """hipStream_t of a torch stream (None: torch's current stream)."""
     if stream is None:
         import torch
         return torch.cuda.current_stream().cuda_stream
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
     return int(stream)
 
 
@@ -225,6 +230,13 @@ class Solver:
 
     def last_error(self) -> str:
         return lib().jfnk_last_error(self.h).decode()
+
+    def last_timing(self):
+        """(solve ms, launches) of the last step, from HIP events."""
+        ms = C.c_double()
+        n = C.c_int32()
+        self._check(lib().jfnk_last_timing(self.h, C.byref(ms), C.byref(n)), (JFNK_OK,))
+        return ms.value, n.value
 
     def _check(self, rc, allow=(JFNK_OK, JFNK_NOT_CONVERGED)):
         if rc not in allow:
