@@ -31,27 +31,28 @@ HBM_PEAK_GBS = 8000.0
 
 
 def bytes_per_cell(newton, gmres, backtracks, has_prev, fb):
-    """Algorithmic HBM bytes per cell of one column-step (each phase of the
-    method reads its operands from and writes its results to HBM once)."""
+    """Algorithmic HBM bytes per cell of one column-step: each phase of the
+    method reads its operands from HBM and writes its results to HBM once
+    (fb = bytes per stored preconditioner value)."""
     R = 72.0                                   # residual: X + 5 coefficients -> F
-    b = 112.0 + R                              # set-up: 7 inputs -> 5 coeffs + X, F(X^n)
+    fac = 40.0 + 20.0 * fb                     # X + 3 coefficients -> 20 factor values
+    app = 32.0 + 20.0 * fb                     # v + factors -> z
+    trial = 104.0                              # X + direction + 5 coefficients -> X_t, F_t
+    b = 112.0 + R                              # set-up: 7 inputs -> 5 coefficients + X; F(X^n)
     if has_prev:
         b += 32.0 + R                          # extrapolated candidate and its residual
-    fac = 40.0 + 20.0 * fb                     # X + 3 coefficients -> per-cell factors
-    app = 32.0 + 20.0 * fb                     # v + factors -> z
-    b += app                                   # stopping-test error estimate
     if newton == 0:
-        b += fac
-    b += 32.0                                  # result back to the caller
-    if newton > 0:
+        b += fac + app                         # stopping-test error estimate
+    else:
         k = gmres / newton                     # GMRES iterations per Newton iteration
-        extra = max(gmres - newton, 0)         # iterations that needed the CGS2 passes
-        per_newton = fac + k * (app + 104.0) + (16.0 * k * (k - 1) / 2.0) + 104.0
-        b += newton * per_newton
-        b += extra * 2 * (32.0 + 16.0 * (k + 1) / 2.0 + 16.0)
-        b += backtracks * 104.0
+        extra = max(gmres - newton, 0)         # iterations that needed the two CGS passes
+        # factor, k x (apply + J.v with fused dots), trial + its simplified correction
+        b += newton * (fac + k * (app + 104.0) + 16.0 * k * (k - 1) / 2.0 + trial + app)
+        b += extra * 2 * (32.0 + 16.0 * (k + 1) / 2.0)
+        b += backtracks * (trial + app)
         if k > 1:
-            b += newton * 16.0 * (k + 1)
+            b += newton * 16.0 * (k + 1)       # direction from k Krylov vectors
+    b += 32.0                                  # result back to the caller
     return b
 
 
@@ -62,6 +63,14 @@ def run_gpu(args):
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        # one device-to-device copy of known size, to calibrate HBM counters
+        from paper_1904_08510_amd.profiling import CALIB_BYTES
+        src = torch.empty(CALIB_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cols = W.config2(seed=2026, ncols=args.ncols)
     packed = W.pack(cols)
     prob, ne, phi, _, _ = J.device_problem(packed, dev)
@@ -196,6 +205,20 @@ def run_cpu(args):
                 single_core_value=n / sum(cpu_times))
 
 
+def measured_traffic():
+    """HBM bytes per solve launch from the committed FETCH_SIZE/WRITE_SIZE
+    counter runs, if they were taken with the current kernel sources."""
+    from paper_1904_08510_amd.profiling import source_hash
+    path = os.path.join(ROOT, "profiles", "k_solve_c2_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,6 +232,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=EPISODE)
     ap.add_argument("--cpu-cols", type=int, default=1024)
     ap.add_argument("--cpu-steps", type=int, default=EPISODE)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="one 256 MiB device copy first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the columns are independent and this build runs "
@@ -217,6 +242,7 @@ def main():
     # the CPU leg forks its worker processes before this process touches the GPU
     cpu = None if args.skip_cpu else run_cpu(args)
     g = run_gpu(args)
+    traffic = measured_traffic()
     line = {
         "metric": METRIC,
         "value": g["value"],
@@ -246,7 +272,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": g["achieved_gbs"] / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "kernel": "k_solve",
             "kernel_ms_avg": g["kernel_ms_avg"],
             "bytes_per_launch": g["bytes_per_launch"],

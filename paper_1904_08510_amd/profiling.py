@@ -1,0 +1,99 @@
+"""Summaries of rocprofv3 output for the solve kernel.
+
+    python -m paper_1904_08510_amd.profiling stats <dir>            # --kernel-trace --stats run
+    python -m paper_1904_08510_amd.profiling pmc <fetch_dir> <write_dir> <out.json>
+
+`stats` prints the per-kernel time table of a kernel-trace run.  `pmc`
+combines a FETCH_SIZE run and a WRITE_SIZE run (counters in KiB per
+dispatch) into HBM bytes per launch of the solve kernel, each counter scaled
+by what it reads for the calibration copy (a device-to-device copy of known
+size that bench.py --calib-copy performs), and records the hash of the
+kernel sources the counters were taken with.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOLVE_KERNEL = "k_solve"
+COPY_KERNEL = "copyBuffer"
+CALIB_BYTES = 256 * 1024 * 1024   # bench.py --calib-copy: one copy of this many bytes
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        with open(path, "rb") as fh:
+            h.update(os.path.basename(path).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _find(d: str, suffix: str) -> str:
+    hits = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[-1]
+
+
+def stats(d: str) -> str:
+    rows = list(csv.DictReader(open(_find(d, "kernel_stats.csv"))))
+    out = ["kernel | calls | total ms | avg ms | min ms | max ms | pct"]
+    for r in rows:
+        name = r["Name"]
+        m = re.search(r"(k_\w+<[^>]*>|__amd_\w+|\w+::\w+<[^(]{0,40})", name)
+        short = m.group(1) if m else name[:60]
+        out.append(f"{short} | {r['Calls']} | {float(r['TotalDurationNs'])/1e6:.3f} | "
+                   f"{float(r['AverageNs'])/1e6:.4f} | {float(r['MinNs'])/1e6:.4f} | "
+                   f"{float(r['MaxNs'])/1e6:.4f} | {float(r['Percentage']):.2f}")
+    return "\n".join(out)
+
+
+def _counter_per_dispatch(d: str, counter: str):
+    rows = list(csv.DictReader(open(_find(d, "counter_collection.csv"))))
+    solve, copy = [], []
+    for r in rows:
+        if r.get("Counter_Name") != counter:
+            continue
+        name = r.get("Kernel_Name", "")
+        v = float(r["Counter_Value"])
+        if SOLVE_KERNEL in name:
+            solve.append(v)
+        elif COPY_KERNEL in name:
+            copy.append(v)
+    return solve, copy
+
+
+def pmc(fetch_dir: str, write_dir: str, out_path: str) -> dict:
+    fs, fc = _counter_per_dispatch(fetch_dir, "FETCH_SIZE")
+    ws, wc = _counter_per_dispatch(write_dir, "WRITE_SIZE")
+    if not fs or not ws or not fc or not wc:
+        raise RuntimeError("missing solve or calibration-copy dispatches in the counter runs")
+    # the calibration copy is the largest copy dispatch (it reads and writes CALIB_BYTES)
+    f_scale = CALIB_BYTES / (max(fc) * 1024.0)
+    w_scale = CALIB_BYTES / (max(wc) * 1024.0)
+    fetch = sum(fs) / len(fs) * 1024.0 * f_scale
+    write = sum(ws) / len(ws) * 1024.0 * w_scale
+    res = dict(source_hash=source_hash(), kernel=SOLVE_KERNEL, dispatches=len(fs),
+               fetch_kib_per_dispatch=sum(fs) / len(fs), write_kib_per_dispatch=sum(ws) / len(ws),
+               copy_fetch_kib=max(fc), copy_write_kib=max(wc), fetch_scale=f_scale,
+               write_scale=w_scale, fetch_bytes=fetch, write_bytes=write,
+               traffic_bytes_per_launch=fetch + write)
+    with open(out_path, "w") as fh:
+        json.dump(res, fh, indent=1)
+    return res
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        print(stats(sys.argv[2]))
+    elif sys.argv[1] == "pmc":
+        print(json.dumps(pmc(sys.argv[2], sys.argv[3], sys.argv[4]), indent=1))
+    else:
+        raise SystemExit(__doc__)
