@@ -79,7 +79,8 @@ def run_gpu(args):
     ns = np.diff(packed.col_offset)
     prec = J.PREC_FP32 if args.prec == "fp32" else J.PREC_FP64
     guess = J.GUESS_EXTRAP
-    cfg = J.config_for(packed, prec_precision=prec, guess=guess, schedule=J.SCHED_BATCHED)
+    cfg = J.config_for(packed, prec_precision=prec, guess=guess, schedule=J.SCHED_BATCHED,
+                       threads_override=args.threads)
     solver = J.Solver(cfg)
     fb = 4.0 if prec == J.PREC_FP32 else 8.0
     stream = torch.cuda.current_stream()
@@ -101,12 +102,9 @@ def run_gpu(args):
         state["e"] = (e + 1) % EPISODE
         if record is not None:
             ms, _ = solver.last_timing()
-            nbytes = float(np.sum(ns * np.array([
-                bytes_per_cell(st.newton_iters[i], st.gmres_iters[i], st.backtracks[i], has_prev, fb)
-                for i in range(len(ns))])))
-            record.append(dict(rc=rc, ms=ms, bytes=nbytes, newton=st.newton_iters.copy(),
+            record.append(dict(rc=rc, ms=ms, has_prev=has_prev, newton=st.newton_iters.copy(),
                                gmres=st.gmres_iters.copy(), bt=st.backtracks.copy(),
-                               res=float(st.res_scaled.max()), conv=int(np.sum(st.status == 0))))
+                               res=st.res_scaled.copy(), status=st.status.copy()))
         return rc
 
     for _ in range(args.warmup):
@@ -119,6 +117,12 @@ def run_gpu(args):
         one_step(rec)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    for r in rec:   # outside the timed region
+        r["conv"] = int(np.sum(r["status"] == 0))
+        r["res"] = float(r["res"].max())
+        r["bytes"] = float(np.sum(ns * np.array([
+            bytes_per_cell(r["newton"][i], r["gmres"][i], r["bt"][i], r["has_prev"], fb)
+            for i in range(len(ns))])))
     converged = sum(r["conv"] for r in rec)
     total_cs = args.ncols * args.steps
     kern_ms = sum(r["ms"] for r in rec)
@@ -226,6 +230,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--ncols", type=int, default=1024)
     ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--threads", type=int, default=0, help="workgroup size per column (0: autotuned)")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--plain-cols", type=int, default=16)

@@ -198,41 +198,71 @@ struct Column {
 
     // ------------------------------------------------------------------
     // Generic stencil sweep.  Thread t walks cells c = t*M + j, j = 0..M-1,
-    // carrying the left face; faces see (left state, right state).
-    // getx(s, n, phi) returns the state at a storage index; the cell functor
-    // receives both faces of each real cell; pad(s) is called for padding.
+    // carrying the left face; faces see (left state, right state).  The cells
+    // are taken in groups of U: all loads of a group (right-neighbour state,
+    // face coefficients, and the cell's own operands from own(s)) are issued
+    // before any cell of the group is computed, so the global-load latencies
+    // of U cells overlap instead of serialising along the recursion.
+    // getx(s, n, phi) returns the state at a storage index; cell(...) receives
+    // both faces and the own operands of each real cell; pad(s) is called for
+    // padding cells (always after the real cells of a chunk).
     // ------------------------------------------------------------------
-    template <class FaceRec, class GetX, class FaceFn, class CellFn, class PadFn>
-    __device__ __forceinline__ void sweep(GetX getx, FaceFn face, CellFn cell, PadFn pad) {
+    template <int U, class FaceRec, class GetX, class FaceFn, class OwnFn, class CellFn, class PadFn>
+    __device__ __forceinline__ void sweep(GetX getx, FaceFn face, OwnFn own, CellFn cell, PadFn pad) {
+        using Own = decltype(own(int64_t(0)));
         const int M = cd.M, n = cd.n;
         const int c0 = t * M;
         if (c0 >= n) {
             for (int j = 0; j < M; ++j) pad(sidx(t, j));
             return;
         }
+        const int jr = (n - c0 < M) ? (n - c0) : M;   // real rows of this chunk
         const int64_t s0 = sidx(t, 0);
         double nC, pC, nL, pL, ihL;
         getx(s0, nC, pC);
         if (c0 == 0) { nL = cd.nel; pL = cd.phil; ihL = 2.0 * ih; }
         else { getx(sidx(t - 1, M - 1), nL, pL); ihL = ih; }
         FaceRec FL = face(W.fa[s0], W.fg[s0], prm.has_u ? W.fw[s0] : 0.0, ihL, nL, pL, nC, pC);
-        for (int j = 0; j < M; ++j) {
-            const int c = c0 + j;
-            const int64_t s = sidx(t, j);
-            if (c >= n) { pad(s); continue; }
-            double nR, pR;
-            FaceRec FR;
-            if (c == n - 1) {
-                nR = cd.ner; pR = cd.phir;
-                FR = face(rR, gR, wR, 2.0 * ih, nC, pC, nR, pR);
-            } else {
-                const int64_t sn = (j + 1 < M) ? s + T : sidx(t + 1, 0);
-                getx(sn, nR, pR);
-                FR = face(W.fa[sn], W.fg[sn], prm.has_u ? W.fw[sn] : 0.0, ih, nC, pC, nR, pR);
+        for (int j0 = 0; j0 < jr; j0 += U) {
+            double xn[U], xp[U], fa[U], fg[U], fw[U];
+            Own ow[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u;
+                xn[u] = xp[u] = fa[u] = fg[u] = fw[u] = 0.0;
+                if (j < jr) {
+                    const int64_t s = sidx(t, j);
+                    ow[u] = own(s);
+                    if (c0 + j < n - 1) {
+                        const int64_t sn = (j + 1 < M) ? s + T : sidx(t + 1, 0);
+                        getx(sn, xn[u], xp[u]);
+                        fa[u] = W.fa[sn];
+                        fg[u] = W.fg[sn];
+                        if (prm.has_u) fw[u] = W.fw[sn];
+                    }
+                }
             }
-            cell(s, c, nC, pC, FL, FR);
-            nC = nR; pC = pR; FL = FR;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u;
+                if (j < jr) {
+                    const int c = c0 + j;
+                    const int64_t s = sidx(t, j);
+                    double nR, pR;
+                    FaceRec FR;
+                    if (c == n - 1) {
+                        nR = cd.ner; pR = cd.phir;
+                        FR = face(rR, gR, wR, 2.0 * ih, nC, pC, nR, pR);
+                    } else {
+                        nR = xn[u]; pR = xp[u];
+                        FR = face(fa[u], fg[u], fw[u], ih, nC, pC, nR, pR);
+                    }
+                    cell(s, c, nC, pC, FL, FR, ow[u]);
+                    nC = nR; pC = pR; FL = FR;
+                }
+            }
         }
+        for (int j = jr; j < M; ++j) pad(sidx(t, j));
     }
 
     struct FluxRec { double gam, grd; };
@@ -262,10 +292,18 @@ struct Column {
         const double* kv = W.kd;
         const double* qv = W.q;
         const bool wantstep = stepdir.p0 != nullptr;
-        sweep<FluxRec>(getx, FluxFace{},
-            [&](int64_t s, int c, double nC, double pC, const FluxRec& L, const FluxRec& R) {
-                const double fe = -nC + fv[s] - kv[s] * nC - dt_h * (R.gam - L.gam);
-                const double fp = -nC + qv[s] + eps_h * (R.grd - L.grd);
+        struct Own { double f, k, q, d0, d1; };
+        sweep<2, FluxRec>(getx, FluxFace{},
+            [&](int64_t s) {
+                Own o;
+                o.f = fv[s]; o.k = kv[s]; o.q = qv[s];
+                o.d0 = wantstep ? stepdir.p0[s] : 0.0;
+                o.d1 = wantstep ? stepdir.p1[s] : 0.0;
+                return o;
+            },
+            [&](int64_t s, int c, double nC, double pC, const FluxRec& L, const FluxRec& R, const Own& o) {
+                const double fe = -nC + o.f - o.k * nC - dt_h * (R.gam - L.gam);
+                const double fp = -nC + o.q + eps_h * (R.grd - L.grd);
                 oF0[s] = fe;
                 oF1[s] = fp;
                 if (oX0) { oX0[s] = nC; oX1[s] = pC; }
@@ -276,8 +314,8 @@ struct Column {
                 sm[2] += nC * nC;
                 sm[3] += pC * pC;
                 if (wantstep) {
-                    mx[2] = fmax(mx[2], fmax(fabs(steplam * stepdir.p0[s] * stepdir.s0),
-                                             fabs(steplam * stepdir.p1[s] * stepdir.s1)));
+                    mx[2] = fmax(mx[2], fmax(fabs(steplam * o.d0 * stepdir.s0),
+                                             fabs(steplam * o.d1 * stepdir.s1)));
                 }
             },
             [&](int64_t s) {
@@ -311,45 +349,70 @@ struct Column {
         double* X20 = xb(2, 0); double* X21 = xb(2, 1);
         const bool extrap = prm.guess >= 1 && prm.has_prev;
         const bool learn = prm.guess == 2 && prm.has_learned;
-        for (int j = 0; j < M; ++j) {
-            const int c = c0 + j;
-            const int64_t s = sidx(t, j);
-            if (c >= n) {
-                W.fa[s] = 0.0; W.fg[s] = 0.0;
-                if (prm.has_u) W.fw[s] = 0.0;
-                W.f[s] = 0.0; W.kd[s] = 0.0; W.q[s] = 0.0;
-                X00[s] = X01[s] = X10[s] = X11[s] = X20[s] = X21[s] = 0.0;
-                continue;
+        // Natural-order pass: thread t takes cells c = k T + t, so the reads of
+        // the caller's arrays are coalesced and independent; each cell is
+        // written to its chunk-interleaved slot.  Loads of U cells go first.
+        constexpr int UC = 2;
+        (void)c0;
+        for (int k0 = 0; k0 < M; k0 += UC) {
+            double mu[UC], D[UC], mum[UC], Dm[UC], ne[UC], ph[UC], sr[UC], kl[UC], qq[UC];
+            double pn[UC], pp[UC], ln[UC], lp[UC], uf[UC];
+#pragma unroll
+            for (int v = 0; v < UC; ++v) {
+                const int c = (k0 + v) * T + t;
+                mu[v] = D[v] = mum[v] = Dm[v] = ne[v] = ph[v] = sr[v] = kl[v] = qq[v] = 0.0;
+                pn[v] = pp[v] = ln[v] = lp[v] = uf[v] = 0.0;
+                if (k0 + v < M && c < n) {
+                    const int64_t u = cd.uoff + c;
+                    mu[v] = U.mu[u]; D[v] = U.diff[u];
+                    if (c > 0) { mum[v] = U.mu[u - 1]; Dm[v] = U.diff[u - 1]; }
+                    ne[v] = U.ne[u]; ph[v] = U.phi[u]; sr[v] = U.src[u];
+                    if (U.kloss) kl[v] = U.kloss[u];
+                    qq[v] = U.q[u];
+                    if (extrap) { pn[v] = U.ne_prev[u]; pp[v] = U.phi_prev[u]; }
+                    if (learn) { ln[v] = U.ne_learn[u]; lp[v] = U.phi_learn[u]; }
+                    if (prm.has_u) uf[v] = U.uface[fo + c];
+                }
             }
-            const int64_t u = cd.uoff + c;
-            const double mu = U.mu[u], D = U.diff[u];
-            double r, g, w = 0.0;
-            if (c == 0) {
-                r = mu / D;
-                g = (cd.bcl == 1) ? 0.0 : D / hb;
-                if (prm.has_u) w = U.uface[fo + c] * hb / D;
-            } else {
-                const double muf = 0.5 * (U.mu[u - 1] + mu);
-                const double Df = 0.5 * (U.diff[u - 1] + D);
-                r = muf / Df;
-                g = Df / cd.h;
-                if (prm.has_u) w = U.uface[fo + c] * cd.h / Df;
-            }
-            W.fa[s] = r; W.fg[s] = g;
-            if (prm.has_u) W.fw[s] = w;
-            const double ne = U.ne[u], ph = U.phi[u];
-            W.f[s] = ne + dt * U.src[u];
-            W.kd[s] = U.kloss ? dt * U.kloss[u] : 0.0;
-            W.q[s] = U.q[u];
-            X00[s] = ne; X01[s] = ph;
-            if (extrap) { X10[s] = 2.0 * ne - U.ne_prev[u]; X11[s] = 2.0 * ph - U.phi_prev[u]; }
-            if (learn) { X20[s] = U.ne_learn[u]; X21[s] = U.phi_learn[u]; }
-            if (c == n - 1) {
-                // right wall face: the last cell's mu and D at distance h/2
-                double* misc = lds + Lds<T>::kMisc;
-                misc[0] = mu / D;
-                misc[1] = (cd.bcr == 1) ? 0.0 : D / hb;
-                misc[2] = prm.has_u ? U.uface[fo + n] * hb / D : 0.0;
+#pragma unroll
+            for (int v = 0; v < UC; ++v) {
+                const int c = (k0 + v) * T + t;
+                if (k0 + v >= M) continue;
+                const int64_t s = cd.ws + (int64_t)(c % M) * T + c / M;
+                if (c >= n) {
+                    W.fa[s] = 0.0; W.fg[s] = 0.0;
+                    if (prm.has_u) W.fw[s] = 0.0;
+                    W.f[s] = 0.0; W.kd[s] = 0.0; W.q[s] = 0.0;
+                    X00[s] = X01[s] = X10[s] = X11[s] = X20[s] = X21[s] = 0.0;
+                    continue;
+                }
+                double r, g, w = 0.0;
+                if (c == 0) {
+                    r = mu[v] / D[v];
+                    g = (cd.bcl == 1) ? 0.0 : D[v] / hb;
+                    if (prm.has_u) w = uf[v] * hb / D[v];
+                } else {
+                    const double muf = 0.5 * (mum[v] + mu[v]);
+                    const double Df = 0.5 * (Dm[v] + D[v]);
+                    r = muf / Df;
+                    g = Df / cd.h;
+                    if (prm.has_u) w = uf[v] * cd.h / Df;
+                }
+                W.fa[s] = r; W.fg[s] = g;
+                if (prm.has_u) W.fw[s] = w;
+                W.f[s] = ne[v] + dt * sr[v];
+                W.kd[s] = dt * kl[v];
+                W.q[s] = qq[v];
+                X00[s] = ne[v]; X01[s] = ph[v];
+                if (extrap) { X10[s] = 2.0 * ne[v] - pn[v]; X11[s] = 2.0 * ph[v] - pp[v]; }
+                if (learn) { X20[s] = ln[v]; X21[s] = lp[v]; }
+                if (c == n - 1) {
+                    // right wall face: the last cell's mu and D at distance h/2
+                    double* misc = lds + Lds<T>::kMisc;
+                    misc[0] = mu[v] / D[v];
+                    misc[1] = (cd.bcr == 1) ? 0.0 : D[v] / hb;
+                    misc[2] = prm.has_u ? U.uface[fo + n] * hb / D[v] : 0.0;
+                }
             }
         }
         __syncthreads();
@@ -367,7 +430,8 @@ struct Column {
         {
             const double dt_h = dth, eps_h = epsh;
             double* F0 = Fb(0, 0); double* F1 = Fb(0, 1);
-            sweep<ScRec>(
+            struct Own { double f, k, q; };
+            sweep<2, ScRec>(
                 [&](int64_t s, double& a, double& b) { a = X00[s]; b = X01[s]; },
                 [](double r, double g, double w, double ihf, double nA, double pA, double nB, double pB) {
                     const double pe = w + r * (pB - pA);
@@ -379,8 +443,9 @@ struct Column {
                     o.mag = g * (bmx * fabs(nA) + bx * fabs(nB));
                     return o;
                 },
-                [&](int64_t s, int c, double nC, double pC, const ScRec& L, const ScRec& R) {
-                    const double fv = W.f[s], kv = W.kd[s], qv = W.q[s];
+                [&](int64_t s) { return Own{W.f[s], W.kd[s], W.q[s]}; },
+                [&](int64_t s, int c, double nC, double pC, const ScRec& L, const ScRec& R, const Own& o) {
+                    const double fv = o.f, kv = o.k, qv = o.q;
                     const double fe = -nC + fv - kv * nC - dt_h * (R.gam - L.gam);
                     const double fp = -nC + qv + eps_h * (R.grd - L.grd);
                     F0[s] = fe; F1[s] = fp;
@@ -522,12 +587,12 @@ struct Column {
             gprev = ga; aprev = al;
         };
 
-        sweep<JacRec>(
+        sweep<2, JacRec>(
             [&](int64_t s, double& a, double& b) { a = X0[s]; b = X1[s]; },
             JacFace{},
-            [&](int64_t s, int c, double nC, double pC, const JacRec& L, const JacRec& R) {
+            [&](int64_t s) { return W.kd[s]; },
+            [&](int64_t s, int c, double nC, double pC, const JacRec& L, const JacRec& R, const double& kv) {
                 const int j = c - c0;
-                const double kv = W.kd[s];
                 Blk<double> A, B, C;
                 B.a = (-1.0 - kv - dt_h * (R.dnA - L.dnB)) * s_en;
                 B.b = (dt_h * (R.dpB + L.dpB)) * s_ep;
@@ -563,14 +628,29 @@ struct Column {
             aL = an; gL = gn;
             store_blk(12, sidx(t, M - 1), an);
             store_blk(16, sidx(t, M - 1), gn);
-            for (int j = M - 2; j >= 1; --j) {
-                const int64_t s = sidx(t, j);
-                const Blk<double> al{T0[s], T1[s], T2[s], T3[s]};
-                const Blk<double> ga{T4[s], T5[s], T6[s], T7[s]};
-                an = bsub(al, bmul(ga, an));
-                gn = bneg(bmul(ga, gn));
-                store_blk(12, s, an);
-                store_blk(16, s, gn);
+            constexpr int U = 2;
+            for (int j0 = M - 2; j0 >= 1; j0 -= U) {
+                Blk<double> aa[U], gg[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = j0 - u;
+                    if (j >= 1) {
+                        const int64_t s = sidx(t, j);
+                        aa[u] = Blk<double>{T0[s], T1[s], T2[s], T3[s]};
+                        gg[u] = Blk<double>{T4[s], T5[s], T6[s], T7[s]};
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = j0 - u;
+                    if (j >= 1) {
+                        const int64_t s = sidx(t, j);
+                        an = bsub(aa[u], bmul(gg[u], an));
+                        gn = bneg(bmul(gg[u], gn));
+                        store_blk(12, s, an);
+                        store_blk(16, s, gn);
+                    }
+                }
             }
             a1 = an; g1 = gn;
         }
@@ -630,35 +710,68 @@ struct Column {
     // in FP64).  Returns (||z||_2^2, ||z||_inf).  v and z must not alias.
     // ------------------------------------------------------------------
     __device__ Vec2<double> apply(const VecRef& v, double* z0, double* z1) {
+        constexpr int U = 4;
         const int M = cd.M;
         FT* D0 = tmpv(0);
         FT* D1 = tmpv(1);
         Vec2<double> d0{v.p0[sidx(t, 0)] * v.s0, v.p1[sidx(t, 0)] * v.s1};
+        // down sweep: d_j = m_j v_j - At_j d_{j-1}, loads of U rows issued first
         Vec2<FT> dprev{FT(0), FT(0)};
-        for (int j = 1; j < M; ++j) {
-            const int64_t s = sidx(t, j);
-            const Vec2<FT> d{(FT)(v.p0[s] * v.s0), (FT)(v.p1[s] * v.s1)};
-            const Blk<FT> m = load_blk(0, s);
-            Vec2<FT> de = bmv(m, d);
-            if (j >= 2) {
-                const Blk<FT> at = load_blk(4, s);
-                const Vec2<FT> q = bmv(at, dprev);
-                de.x -= q.x; de.y -= q.y;
+        for (int j0 = 1; j0 < M; j0 += U) {
+            Blk<FT> mm[U], aa[U];
+            Vec2<FT> vv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u;
+                if (j < M) {
+                    const int64_t s = sidx(t, j);
+                    mm[u] = load_blk(0, s);
+                    aa[u] = load_blk(4, s);
+                    vv[u] = Vec2<FT>{(FT)(v.p0[s] * v.s0), (FT)(v.p1[s] * v.s1)};
+                }
             }
-            D0[s] = de.x; D1[s] = de.y;
-            dprev = de;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u;
+                if (j < M) {
+                    const int64_t s = sidx(t, j);
+                    Vec2<FT> de = bmv(mm[u], vv[u]);
+                    if (j >= 2) {
+                        const Vec2<FT> q = bmv(aa[u], dprev);
+                        de.x -= q.x; de.y -= q.y;
+                    }
+                    D0[s] = de.x; D1[s] = de.y;
+                    dprev = de;
+                }
+            }
         }
         // up sweep: d''_j = d_j - g_j d''_{j+1}
         Vec2<FT> dn = dprev;      // row M-1 (d'' = d)
         Vec2<double> dLast{0.0, 0.0}, dFirst{0.0, 0.0};
         if (M >= 2) {
             dLast = {(double)dn.x, (double)dn.y};
-            for (int j = M - 2; j >= 1; --j) {
-                const int64_t s = sidx(t, j);
-                const Blk<FT> g = load_blk(8, s);
-                const Vec2<FT> q = bmv(g, dn);
-                dn = {D0[s] - q.x, D1[s] - q.y};
-                D0[s] = dn.x; D1[s] = dn.y;
+            for (int j0 = M - 2; j0 >= 1; j0 -= U) {
+                Blk<FT> gg[U];
+                Vec2<FT> dd[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = j0 - u;
+                    if (j >= 1) {
+                        const int64_t s = sidx(t, j);
+                        gg[u] = load_blk(8, s);
+                        dd[u] = Vec2<FT>{D0[s], D1[s]};
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = j0 - u;
+                    if (j >= 1) {
+                        const int64_t s = sidx(t, j);
+                        const Vec2<FT> q = bmv(gg[u], dn);
+                        dn = {dd[u].x - q.x, dd[u].y - q.y};
+                        D0[s] = dn.x; D1[s] = dn.y;
+                    }
+                }
             }
             dFirst = {(double)dn.x, (double)dn.y};
         }
@@ -702,17 +815,34 @@ struct Column {
             zz += x0.x * x0.x + x0.y * x0.y;
             zm = fmax(fabs(x0.x), fabs(x0.y));
         }
-        for (int j = 1; j < M; ++j) {
-            const int64_t s = sidx(t, j);
-            const Blk<FT> a = load_blk(12, s);
-            const Blk<FT> g = load_blk(16, s);
-            const double zx = (double)D0[s] - ((double)a.a * x0.x + (double)a.b * x0.y) -
-                              ((double)g.a * xn.x + (double)g.b * xn.y);
-            const double zy = (double)D1[s] - ((double)a.c * x0.x + (double)a.d * x0.y) -
-                              ((double)g.c * xn.x + (double)g.d * xn.y);
-            z0[s] = zx; z1[s] = zy;
-            zz += zx * zx + zy * zy;
-            zm = fmax(zm, fmax(fabs(zx), fabs(zy)));
+        for (int j0 = 1; j0 < M; j0 += U) {
+            Blk<FT> aa[U], gg[U];
+            Vec2<FT> dd[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u;
+                if (j < M) {
+                    const int64_t s = sidx(t, j);
+                    aa[u] = load_blk(12, s);
+                    gg[u] = load_blk(16, s);
+                    dd[u] = Vec2<FT>{D0[s], D1[s]};
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u;
+                if (j < M) {
+                    const int64_t s = sidx(t, j);
+                    const Blk<FT> a = aa[u], g = gg[u];
+                    const double zx = (double)dd[u].x - ((double)a.a * x0.x + (double)a.b * x0.y) -
+                                      ((double)g.a * xn.x + (double)g.b * xn.y);
+                    const double zy = (double)dd[u].y - ((double)a.c * x0.x + (double)a.d * x0.y) -
+                                      ((double)g.c * xn.x + (double)g.d * xn.y);
+                    z0[s] = zx; z1[s] = zy;
+                    zz += zx * zx + zy * zy;
+                    zm = fmax(zm, fmax(fabs(zx), fabs(zy)));
+                }
+            }
         }
         double sm[1] = {zz};
         double mm[1] = {zm};
@@ -735,29 +865,37 @@ struct Column {
         const double e0 = eps * sxn * z.s0, e1 = eps * sxp * z.s1;
         const double c0 = isfn / eps, c1 = isfp / eps;
         const double dt_h = dth, eps_h = epsh;
-        double acc[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) acc[i] = 0.0;
-        const int nbf = nb < 8 ? nb : 8;
-        sweep<FluxRec>(
+        double acc[3] = {0.0, 0.0, 0.0};
+        const int nbf = nb < 2 ? nb : 2;
+        const VecRef b0 = nbf > 0 ? basis[0] : VecRef{F0, F1, 0.0, 0.0};
+        const VecRef b1 = nbf > 1 ? basis[1] : VecRef{F0, F1, 0.0, 0.0};
+        struct Own { double f, k, q, F0, F1, v00, v01, v10, v11; };
+        sweep<2, FluxRec>(
             [&](int64_t s, double& a, double& b) { a = X0[s] + e0 * z.p0[s]; b = X1[s] + e1 * z.p1[s]; },
             FluxFace{},
-            [&](int64_t s, int c, double nC, double pC, const FluxRec& L, const FluxRec& R) {
-                const double fe = -nC + W.f[s] - W.kd[s] * nC - dt_h * (R.gam - L.gam);
-                const double fp = -nC + W.q[s] + eps_h * (R.grd - L.grd);
-                const double a = (fe - F0[s]) * c0;
-                const double b = (fp - F1[s]) * c1;
+            [&](int64_t s) {
+                Own o;
+                o.f = W.f[s]; o.k = W.kd[s]; o.q = W.q[s]; o.F0 = F0[s]; o.F1 = F1[s];
+                o.v00 = b0.p0[s]; o.v01 = b0.p1[s];
+                o.v10 = nbf > 1 ? b1.p0[s] : 0.0;
+                o.v11 = nbf > 1 ? b1.p1[s] : 0.0;
+                return o;
+            },
+            [&](int64_t s, int c, double nC, double pC, const FluxRec& L, const FluxRec& R, const Own& o) {
+                const double fe = -nC + o.f - o.k * nC - dt_h * (R.gam - L.gam);
+                const double fp = -nC + o.q + eps_h * (R.grd - L.grd);
+                const double a = (fe - o.F0) * c0;
+                const double b = (fp - o.F1) * c1;
                 w0[s] = a; w1[s] = b;
-#pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    if (i < nbf) acc[i] += basis[i].p0[s] * basis[i].s0 * a + basis[i].p1[s] * basis[i].s1 * b;
-                acc[8] += a * a + b * b;
+                acc[0] += o.v00 * b0.s0 * a + o.v01 * b0.s1 * b;
+                acc[1] += o.v10 * b1.s0 * a + o.v11 * b1.s1 * b;
+                acc[2] += a * a + b * b;
             },
             [&](int64_t s) { w0[s] = 0.0; w1[s] = 0.0; });
-        wg_sum<T, 9>(acc, lds + Lds<T>::kScr);
+        wg_sum<T, 3>(acc, lds + Lds<T>::kScr);
         for (int i = 0; i < nbf; ++i) dots[i] = acc[i];
-        if (nb > 8) dots_more(w0, w1, basis, 8, nb, dots);
-        dots[nb] = acc[8];
+        if (nb > 2) dots_more(w0, w1, basis, 2, nb, dots);
+        dots[nb] = acc[2];
     }
 
     // dots[i] = basis[i] . w for i in [i0, nb)
@@ -784,23 +922,47 @@ struct Column {
     // dots[i] = basis[i] . w (i < nb) and dots[nb] = ||w||^2.
     __device__ void cgs_pass(double* w0, double* w1, const VecRef* basis, int nb, const double* h,
                              double* dots) {
+        constexpr int U = 4;
         const int M = cd.M;
         double acc[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) acc[i] = 0.0;
         const int nbf = nb < 8 ? nb : 8;
-        for (int j = 0; j < M; ++j) {
-            const int64_t s = sidx(t, j);
-            double a = w0[s], b = w1[s];
-            for (int i = 0; i < nb; ++i) {
-                a -= h[i] * basis[i].p0[s] * basis[i].s0;
-                b -= h[i] * basis[i].p1[s] * basis[i].s1;
-            }
-            w0[s] = a; w1[s] = b;
+        for (int j0 = 0; j0 < M; j0 += U) {
+            double a[U], b[U];
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                if (i < nbf) acc[i] += basis[i].p0[s] * basis[i].s0 * a + basis[i].p1[s] * basis[i].s1 * b;
-            acc[8] += a * a + b * b;
+            for (int u = 0; u < U; ++u) {
+                a[u] = b[u] = 0.0;
+                if (j0 + u < M) { const int64_t s = sidx(t, j0 + u); a[u] = w0[s]; b[u] = w1[s]; }
+            }
+            for (int i = 0; i < nb; ++i) {
+                const VecRef bi = basis[i];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (j0 + u < M) {
+                        const int64_t s = sidx(t, j0 + u);
+                        a[u] -= h[i] * bi.p0[s] * bi.s0;
+                        b[u] -= h[i] * bi.p1[s] * bi.s1;
+                    }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (j0 + u < M) {
+                    const int64_t s = sidx(t, j0 + u);
+                    w0[s] = a[u]; w1[s] = b[u];
+                    acc[8] += a[u] * a[u] + b[u] * b[u];
+                }
+            for (int i = 0; i < nbf; ++i) {
+                const VecRef bi = basis[i];
+                double sacc = 0.0;
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (j0 + u < M) {
+                        const int64_t s = sidx(t, j0 + u);
+                        sacc += bi.p0[s] * bi.s0 * a[u] + bi.p1[s] * bi.s1 * b[u];
+                    }
+                acc[i] += sacc;
+            }
         }
         wg_sum<T, 9>(acc, lds + Lds<T>::kScr);
         for (int i = 0; i < nbf; ++i) dots[i] = acc[i];
@@ -811,15 +973,28 @@ struct Column {
     // out = (accumulate ? out : 0) + sum_i c[i] vecs[i]
     __device__ void lincomb(double* o0, double* o1, const VecRef* vecs, const double* c, int nv,
                             bool accumulate) {
+        constexpr int U = 4;
         const int M = cd.M;
-        for (int j = 0; j < M; ++j) {
-            const int64_t s = sidx(t, j);
-            double a = accumulate ? o0[s] : 0.0, b = accumulate ? o1[s] : 0.0;
-            for (int i = 0; i < nv; ++i) {
-                a += c[i] * vecs[i].p0[s] * vecs[i].s0;
-                b += c[i] * vecs[i].p1[s] * vecs[i].s1;
+        for (int j0 = 0; j0 < M; j0 += U) {
+            double a[U], b[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                a[u] = b[u] = 0.0;
+                if (accumulate && j0 + u < M) { const int64_t s = sidx(t, j0 + u); a[u] = o0[s]; b[u] = o1[s]; }
             }
-            o0[s] = a; o1[s] = b;
+            for (int i = 0; i < nv; ++i) {
+                const VecRef vi = vecs[i];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (j0 + u < M) {
+                        const int64_t s = sidx(t, j0 + u);
+                        a[u] += c[i] * vi.p0[s] * vi.s0;
+                        b[u] += c[i] * vi.p1[s] * vi.s1;
+                    }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (j0 + u < M) { const int64_t s = sidx(t, j0 + u); o0[s] = a[u]; o1[s] = b[u]; }
         }
         __syncthreads();
     }
