@@ -171,6 +171,90 @@ const char *jfnk_last_error(const jfnk_ctx *ctx);
    it spans (-1: host-driven).  Returns JFNK_EINVAL on NULL arguments. */
 int jfnk_last_timing(const jfnk_ctx *ctx, double *solve_ms, int32_t *launches);
 
+/* ---- learned Newton initial guess --------------------------------------
+ *
+ * Not part of the paper's method: a small 1D convolutional network that
+ * predicts X^{n+1} of every column from X^n (and X^{n-1}), the ion charge
+ * q, the gas temperature and the applied voltage.  Its prediction is only a
+ * Newton initial guess (JFNK_GUESS_LEARNED): the step keeps it only if its
+ * scaled residual ||S_F^-1 F||_inf is strictly smaller than that of the
+ * EXTRAP choice, so the root and the convergence test are those of the
+ * method without it.
+ *
+ * Network: six convolutions along the column, kernel 5, zero padding at
+ * the column ends, channels 8 -> 64 -> 64 -> 64 -> 64 -> 64 -> 2, ReLU after
+ * the first five; BF16 weights and activations, FP32 accumulation (matrix
+ * cores).  Input channels per cell, with n0 = 1e8 m^-3, a(n) = asinh(n/n0)/20
+ * and phi_s = max(|phi_left|, |phi_right|, 1 V):
+ *   a(n^n), phi^n/phi_s, a(q), (T - 1150 K)/850 K, log10(h / 1e-5 m),
+ *   (phi_right - phi_left)/1000 V, a(n^n) - a(n^{n-1}), (phi^n - phi^{n-1})/phi_s
+ * (the last two are 0 without X^{n-1}).  Outputs (o0, o1) give the guess
+ *   n = n0 sinh(20 (a(n^n) + s0 o0)),  phi = phi^n + phi_s s1 o1
+ * with the output scales s0, s1 of the configuration.  Loss of a batch:
+ *   (1/N) sum over its N cells of (o0 - t0)^2 + (o1 - t1)^2,
+ *   t0 = (a(n^{n+1}) - a(n^n))/s0,  t1 = (phi^{n+1} - phi^n)/(phi_s s1).
+ * Parameters, as one flat FP32 array (jfnk_net_param_count() values): for
+ * each layer in order, W[c_out][5][c_in] (tap j multiplies the input of cell
+ * i + j - 2 for output cell i) followed by b[c_out].
+ */
+typedef struct jfnk_net jfnk_net;
+
+typedef struct {
+    int32_t max_cols;            /* capacity of a training batch: columns */
+    int64_t max_total_cells;     /* capacity of a training batch: cells */
+    float out_scale_ne;          /* s0 */
+    float out_scale_phi;         /* s1 */
+    float beta1, beta2, adam_eps;/* Adam moments and epsilon */
+} jfnk_net_config;
+
+/* Defaults: capacity 0 (prediction only), s0 = 0.1, s1 = 0.3, Adam 0.9,
+   0.999, 1e-8. */
+void jfnk_net_config_default(jfnk_net_config *cfg);
+
+/* Number of parameters of the network. */
+int64_t jfnk_net_param_count(void);
+
+/* Allocate a network (parameters, Adam state, training workspace for the
+   capacity) on the current HIP device.  Parameters start at zero: set them
+   with jfnk_net_set_params.  Errors: JFNK_EINVAL, JFNK_ENOMEM, JFNK_EHIP. */
+int jfnk_net_create(const jfnk_net_config *cfg, jfnk_net **out);
+void jfnk_net_destroy(jfnk_net *net);                 /* NULL-safe */
+const char *jfnk_net_last_error(const jfnk_net *net); /* never NULL */
+
+/* HOST [n] parameters in the flat order above; n must equal
+   jfnk_net_param_count().  set also clears the Adam moments and step count.
+   Both synchronise the device. */
+int jfnk_net_set_params(jfnk_net *net, const float *params, int64_t n);
+int jfnk_net_get_params(jfnk_net *net, float *params, int64_t n);
+
+/* The guess for every column of p: ne_out, phi_out DEVICE [total], layout
+   of x->ne.  Uses p's col_offset, length, phi_left/right, q_ion, temp and
+   x's ne, phi, ne_prev, phi_prev.  Queued on stream; returns when queued. */
+int jfnk_net_predict(jfnk_net *net, const jfnk_problem *p, const jfnk_state *x,
+                     double *ne_out, double *phi_out, void *stream);
+
+/* Loss of one batch (inputs as for predict, targets X^{n+1} = (ne_next,
+   phi_next) DEVICE [total]) and its gradient: grad HOST [param_count] (may be
+   NULL), loss HOST (may be NULL).  Synchronises the stream. */
+int jfnk_net_grad(jfnk_net *net, const jfnk_problem *p, const jfnk_state *x,
+                  const double *ne_next, const double *phi_next, float *grad,
+                  double *loss, void *stream);
+
+/* One Adam step with learning rate lr on the batch's gradient (FP32 master
+   weights, BF16 copies for the matrix cores).  loss HOST (may be NULL: then
+   the call does not wait for the device) receives the batch loss before the
+   update. */
+int jfnk_net_train_step(jfnk_net *net, const jfnk_problem *p, const jfnk_state *x,
+                        const double *ne_next, const double *phi_next, float lr,
+                        double *loss, void *stream);
+
+/* Attach a network to a solver context for JFNK_GUESS_LEARNED (NULL
+   detaches).  The context does not own the network, which must outlive its
+   use.  The network is evaluated before the solve for the columns whose
+   previous step on this context needed at least one Newton iteration (all
+   columns on the first step and whenever the column layout changes). */
+int jfnk_set_model(jfnk_ctx *ctx, jfnk_net *net);
+
 /* ---- test exports: single phases of the step, same kernels ----------- */
 
 /* F(X) (unscaled, per cell: fe, fp) with X = (x_ne, x_phi) and the step's

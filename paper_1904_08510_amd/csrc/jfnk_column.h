@@ -348,7 +348,7 @@ struct Column {
         double* X10 = xb(1, 0); double* X11 = xb(1, 1);
         double* X20 = xb(2, 0); double* X21 = xb(2, 1);
         const bool extrap = prm.guess >= 1 && prm.has_prev;
-        const bool learn = prm.guess == 2 && prm.has_learned;
+        const bool learn = prm.guess == 2 && prm.has_learned && W.lmask[cd.index] != 0;
         // Natural-order pass: thread t takes cells c = k T + t, so the reads of
         // the caller's arrays are coalesced and independent; each cell is
         // written to its chunk-interleaved slot.  Loads of U cells go first.

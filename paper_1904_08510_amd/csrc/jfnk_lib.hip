@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "jfnk.h"
+#include "jfnk_net.h"
 #include "jfnk_solver.h"
 
 using namespace jfnk;
@@ -229,8 +230,17 @@ struct jfnk_ctx {
     std::vector<int32_t> last_bc;
     bool sched_valid = false;
     bool timed = false;
+    bool pre_recorded = false;   // ev0 already recorded (before the learned guess)
     double last_ms = 0.0;
     int last_launches = 0;
+    // learned guess
+    jfnk_net* model = nullptr;
+    double* d_learn = nullptr;   // [2][max_total_cells]: guess n, phi
+    int32_t* d_lmask = nullptr;  // [max_cols]
+    int32_t* h_lmask = nullptr;  // pinned
+    bool learn_active = false;
+    bool hist_valid = false;     // last_newton / last_status describe the current layout
+    std::vector<int32_t> last_newton, last_status;
 };
 
 namespace {
@@ -348,7 +358,7 @@ SolverParams make_params(const jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_
     s.max_backtracks = ctx->cfg.max_backtracks;
     s.guess = ctx->cfg.guess;
     s.has_prev = x->ne_prev != nullptr;
-    s.has_learned = 0;
+    s.has_learned = ctx->learn_active ? 1 : 0;
     s.has_u = p->u_face != nullptr;
     s.tol_f = ctx->cfg.tol_f;
     s.tol_x = ctx->cfg.tol_x;
@@ -357,13 +367,17 @@ SolverParams make_params(const jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_
     return s;
 }
 
-UserArrays make_user(const jfnk_problem* p, jfnk_state* x) {
+UserArrays make_user(const jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x) {
     UserArrays U{};
     U.mu = p->mu; U.diff = p->diff; U.src = p->src; U.kloss = p->k_loss; U.q = p->q_ion;
     U.uface = p->u_face;
     U.ne = x->ne; U.phi = x->phi;
     U.ne_prev = x->ne_prev; U.phi_prev = x->phi_prev;
     U.ne_learn = nullptr; U.phi_learn = nullptr;
+    if (ctx->learn_active) {
+        U.ne_learn = ctx->d_learn;
+        U.phi_learn = ctx->d_learn + ctx->cfg.max_total_cells;
+    }
     return U;
 }
 
@@ -504,8 +518,8 @@ struct HostExecT {
 template <int T, class FT>
 int run_plain(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t st) {
     const SolverParams prm = make_params(ctx, p, x);
-    const UserArrays U = make_user(p, x);
-    HIP_OK(hipEventRecord(ctx->ev0, st));
+    const UserArrays U = make_user(ctx, p, x);
+    if (!ctx->pre_recorded) HIP_OK(hipEventRecord(ctx->ev0, st));
     for (int c = 0; c < p->ncols; ++c) {
         HostExecT<T, FT> ex;
         ex.ctx = ctx;
@@ -533,14 +547,14 @@ int run_batched(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t
     SolveArgs a;
     a.W = ctx->W;
     a.prm = make_params(ctx, p, x);
-    a.U = make_user(p, x);
+    a.U = make_user(ctx, p, x);
     a.order = ctx->d_order;
-    HIP_OK(hipEventRecord(ctx->ev0, st));
+    if (!ctx->pre_recorded) HIP_OK(hipEventRecord(ctx->ev0, st));
     hipLaunchKernelGGL((k_solve<T, FT>), dim3(p->ncols), dim3(T), Lds<T>::bytes(), st, a);
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(ctx->ev1, st));
     ctx->timed = true;
-    ctx->last_launches = 1;
+    ctx->last_launches = ctx->pre_recorded ? 2 : 1;
     return JFNK_OK;
 }
 
@@ -609,6 +623,7 @@ int schedule_cached(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, h
         }
     }
     ctx->sched_valid = false;
+    ctx->hist_valid = false;
     int rc = validate(ctx, p, x);
     if (rc) return rc;
     rc = upload_schedule(ctx, p->ncols, st);
@@ -659,6 +674,8 @@ int check_ctx(jfnk_ctx* ctx) {
 int prepare_test(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, hipStream_t st,
                  PhaseArgs& a) {
     ctx->sched_valid = false;
+    ctx->hist_valid = false;
+    ctx->learn_active = false;
     int rc = validate(ctx, p, x);
     if (rc) return rc;
     rc = upload_schedule(ctx, p->ncols, st);
@@ -669,7 +686,7 @@ int prepare_test(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, hipS
     xs.ne_prev = nullptr; xs.phi_prev = nullptr;
     a.prm = make_params(ctx, p, &xs);
     a.prm.guess = JFNK_GUESS_PREV;
-    a.U = make_user(p, &xs);
+    a.U = make_user(ctx, p, &xs);
     return JFNK_OK;
 }
 
@@ -682,6 +699,32 @@ int for_each_column(jfnk_ctx* ctx, const jfnk_problem* p, hipStream_t st, PhaseA
                                                                 : dispatch_phases<double>(ctx, st, a, ph);
         if (rc) return rc;
     }
+    return JFNK_OK;
+}
+
+// Learned candidate for the columns whose previous step on this layout
+// needed Newton iterations (all columns without such a record).
+int learned_guess(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t st) {
+    if (!p->temp) return fail(ctx, JFNK_EINVAL, "the learned guess needs the temperature field");
+    const int nc = p->ncols;
+    std::vector<uint8_t> use(nc, 1);
+    int nuse = nc;
+    if (ctx->hist_valid && (int)ctx->last_newton.size() == nc) {
+        nuse = 0;
+        for (int c = 0; c < nc; ++c) {
+            use[c] = !(ctx->last_status[c] == COL_CONVERGED && ctx->last_newton[c] == 0);
+            nuse += use[c];
+        }
+    }
+    HIP_OK(hipEventRecord(ctx->ev0, st));
+    ctx->pre_recorded = true;
+    if (nuse == 0) return JFNK_OK;
+    for (int c = 0; c < nc; ++c) ctx->h_lmask[c] = use[c];
+    HIP_OK(hipMemcpyAsync(ctx->d_lmask, ctx->h_lmask, sizeof(int32_t) * nc, hipMemcpyHostToDevice, st));
+    const int rc = net_predict_masked(ctx->model, p, x, use.data(), ctx->d_learn,
+                                      ctx->d_learn + ctx->cfg.max_total_cells, st);
+    if (rc) return fail(ctx, rc, std::string("learned guess: ") + jfnk_net_last_error(ctx->model));
+    ctx->learn_active = true;
     return JFNK_OK;
 }
 
@@ -768,6 +811,9 @@ void jfnk_destroy(jfnk_ctx* ctx) {
     if (ctx->h_order) (void)hipHostFree(ctx->h_order);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->d_learn) (void)hipFree(ctx->d_learn);
+    if (ctx->d_lmask) (void)hipFree(ctx->d_lmask);
+    if (ctx->h_lmask) (void)hipHostFree(ctx->h_lmask);
     delete ctx;
 }
 
@@ -786,18 +832,57 @@ const char* jfnk_last_error(const jfnk_ctx* ctx) {
 int jfnk_step(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, jfnk_stats* stt, void* stream) {
     int rc = check_ctx(ctx);
     if (rc) return rc;
-    if (ctx->cfg.guess == JFNK_GUESS_LEARNED)
+    if (ctx->cfg.guess == JFNK_GUESS_LEARNED && !ctx->model)
         return fail(ctx, JFNK_EMODEL, "learned guess requested but no model is loaded");
     hipStream_t st = (hipStream_t)stream;
     rc = schedule_cached(ctx, p, x, st);
     if (rc) return rc;
+    ctx->learn_active = false;
+    ctx->pre_recorded = false;
+    if (ctx->cfg.guess == JFNK_GUESS_LEARNED) {
+        rc = learned_guess(ctx, p, x, st);
+        if (rc) return rc;
+    }
     rc = ctx->cfg.prec_precision == JFNK_PREC_FP32 ? dispatch_run<float>(ctx, p, x, st)
                                                    : dispatch_run<double>(ctx, p, x, st);
+    ctx->pre_recorded = false;
+    ctx->learn_active = false;
     if (rc) return rc;
     int nfail = 0;
     rc = gather_stats(ctx, p->ncols, stt, st, &nfail);
     if (rc) return rc;
+    // which columns needed Newton iterations (the learned guess is evaluated for those)
+    ctx->last_newton.resize(p->ncols);
+    ctx->last_status.resize(p->ncols);
+    for (int c = 0; c < p->ncols; ++c) {
+        ctx->last_newton[c] = ctx->h_cst[c].newton;
+        ctx->last_status[c] = ctx->h_cst[c].status;
+    }
+    ctx->hist_valid = true;
     return nfail ? JFNK_NOT_CONVERGED : JFNK_OK;
+}
+
+int jfnk_set_model(jfnk_ctx* ctx, jfnk_net* net) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!net) {
+        ctx->model = nullptr;
+        return JFNK_OK;
+    }
+    HIP_OK(hipSetDevice(ctx->device));
+    rc = net_ensure_predict_capacity(net, ctx->cfg.max_cols, ctx->cfg.max_total_cells);
+    if (rc) return fail(ctx, rc, std::string("model: ") + jfnk_net_last_error(net));
+    if (!ctx->d_learn) {
+        HIP_OK(hipMalloc((void**)&ctx->d_learn, sizeof(double) * 2 * ctx->cfg.max_total_cells));
+        HIP_OK(hipMalloc((void**)&ctx->d_lmask, sizeof(int32_t) * ctx->cfg.max_cols));
+        HIP_OK(hipHostMalloc((void**)&ctx->h_lmask, sizeof(int32_t) * ctx->cfg.max_cols, 0));
+        HIP_OK(hipMemset(ctx->d_lmask, 0, sizeof(int32_t) * ctx->cfg.max_cols));
+        HIP_OK(hipDeviceSynchronize());
+        ctx->W.lmask = ctx->d_lmask;
+    }
+    ctx->model = net;
+    ctx->hist_valid = false;
+    return JFNK_OK;
 }
 
 int jfnk_eval_residual(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, const double* x_ne,

@@ -85,6 +85,7 @@ struct Work {
     ColDesc *cols;
     ColState *cst;
     double *scal;                    // per-column scalar exchange (host-driven mode)
+    const int32_t *lmask;            // per column: learned candidate present (guess 2)
 };
 
 }  // namespace jfnk

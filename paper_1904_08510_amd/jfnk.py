@@ -53,6 +53,12 @@ class jfnk_state(C.Structure):
                 ("phi_prev", C.c_void_p)]
 
 
+class jfnk_net_config(C.Structure):
+    _fields_ = [("max_cols", C.c_int32), ("max_total_cells", C.c_int64),
+                ("out_scale_ne", C.c_float), ("out_scale_phi", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("adam_eps", C.c_float)]
+
+
 class jfnk_stats(C.Structure):
     _fields_ = [("status", _ip), ("newton_iters", _ip), ("gmres_iters", _ip),
                 ("backtracks", _ip), ("guess_used", _ip), ("res_scaled", _dp)]
@@ -92,12 +98,41 @@ def lib():
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p]
         L.jfnk_block_solve.restype = C.c_int
+        _fp = C.POINTER(C.c_float)
+        P, S = C.POINTER(jfnk_problem), C.POINTER(jfnk_state)
+        L.jfnk_net_config_default.argtypes = [C.POINTER(jfnk_net_config)]
+        L.jfnk_net_config_default.restype = None
+        L.jfnk_net_param_count.argtypes = []
+        L.jfnk_net_param_count.restype = C.c_int64
+        L.jfnk_net_create.argtypes = [C.POINTER(jfnk_net_config), C.POINTER(C.c_void_p)]
+        L.jfnk_net_create.restype = C.c_int
+        L.jfnk_net_destroy.argtypes = [C.c_void_p]
+        L.jfnk_net_destroy.restype = None
+        L.jfnk_net_last_error.argtypes = [C.c_void_p]
+        L.jfnk_net_last_error.restype = C.c_char_p
+        L.jfnk_net_set_params.argtypes = [C.c_void_p, _fp, C.c_int64]
+        L.jfnk_net_set_params.restype = C.c_int
+        L.jfnk_net_get_params.argtypes = [C.c_void_p, _fp, C.c_int64]
+        L.jfnk_net_get_params.restype = C.c_int
+        L.jfnk_net_predict.argtypes = [C.c_void_p, P, S, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.jfnk_net_predict.restype = C.c_int
+        L.jfnk_net_grad.argtypes = [C.c_void_p, P, S, C.c_void_p, C.c_void_p, _fp, _dp, C.c_void_p]
+        L.jfnk_net_grad.restype = C.c_int
+        L.jfnk_net_train_step.argtypes = [C.c_void_p, P, S, C.c_void_p, C.c_void_p, C.c_float, _dp,
+                                          C.c_void_p]
+        L.jfnk_net_train_step.restype = C.c_int
+        L.jfnk_set_model.argtypes = [C.c_void_p, C.c_void_p]
+        L.jfnk_set_model.restype = C.c_int
         _LIB = L
     return _LIB
 
 
 EXPORTED_SYMBOLS = ("jfnk_config_default", "jfnk_create", "jfnk_step", "jfnk_destroy",
-                    "jfnk_last_error", "jfnk_last_timing", "jfnk_eval_residual", "jfnk_eval_jv", "jfnk_block_solve")
+                    "jfnk_last_error", "jfnk_last_timing", "jfnk_eval_residual", "jfnk_eval_jv",
+                    "jfnk_block_solve", "jfnk_net_config_default", "jfnk_net_param_count",
+                    "jfnk_net_create", "jfnk_net_destroy", "jfnk_net_last_error",
+                    "jfnk_net_set_params", "jfnk_net_get_params", "jfnk_net_predict",
+                    "jfnk_net_grad", "jfnk_net_train_step", "jfnk_set_model")
 
 
 class JfnkError(RuntimeError):
@@ -262,6 +297,11 @@ class Solver:
         self._check(rc)
         return rc, st
 
+    def set_model(self, net: Optional["Net"]):
+        """Attach a learned-guess network (None detaches)."""
+        self._model = net
+        self._check(lib().jfnk_set_model(self.h, net.h if net is not None else None), (JFNK_OK,))
+
     def eval_residual(self, prob: DeviceProblem, ne_old, phi_old, x_ne, x_phi, stream=None):
         import torch
         fe = torch.empty_like(x_ne)
@@ -305,3 +345,87 @@ def config_for(packed, **kw) -> jfnk_config:
                 max_cells_per_col=int(ns.max()))
     base.update(kw)
     return default_config(**base)
+
+
+def net_param_count() -> int:
+    return int(lib().jfnk_net_param_count())
+
+
+def net_default_config(**kw) -> jfnk_net_config:
+    cfg = jfnk_net_config()
+    lib().jfnk_net_config_default(C.byref(cfg))
+    for k, v in kw.items():
+        if not hasattr(cfg, k):
+            raise AttributeError(k)
+        setattr(cfg, k, v)
+    return cfg
+
+
+class Net:
+    """Owns one jfnk_net (learned Newton initial guess)."""
+
+    def __init__(self, config: Optional[jfnk_net_config] = None, **kw):
+        self.config = config if config is not None else net_default_config(**kw)
+        h = C.c_void_p()
+        rc = lib().jfnk_net_create(C.byref(self.config), C.byref(h))
+        if rc != JFNK_OK:
+            raise JfnkError(rc, "jfnk_net_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().jfnk_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return lib().jfnk_net_last_error(self.h).decode()
+
+    def _check(self, rc):
+        if rc != JFNK_OK:
+            raise JfnkError(rc, self.last_error())
+
+    def set_params(self, params: np.ndarray):
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(lib().jfnk_net_set_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+
+    def get_params(self) -> np.ndarray:
+        a = np.zeros(net_param_count(), np.float32)
+        self._check(lib().jfnk_net_get_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+        return a
+
+    def predict(self, prob: DeviceProblem, ne, phi, ne_prev=None, phi_prev=None, stream=None):
+        import torch
+        ne_out = torch.empty_like(ne)
+        phi_out = torch.empty_like(phi)
+        p = prob.cstruct()
+        s = Solver._state(ne, phi, ne_prev, phi_prev)
+        self._check(lib().jfnk_net_predict(self.h, C.byref(p), C.byref(s), _ptr(ne_out), _ptr(phi_out),
+                                           _stream_ptr(stream)))
+        return ne_out, phi_out
+
+    def grad(self, prob: DeviceProblem, ne, phi, ne_prev, phi_prev, ne_next, phi_next, stream=None):
+        """(loss, gradient) of one batch."""
+        g = np.zeros(net_param_count(), np.float32)
+        loss = C.c_double()
+        p = prob.cstruct()
+        s = Solver._state(ne, phi, ne_prev, phi_prev)
+        self._check(lib().jfnk_net_grad(self.h, C.byref(p), C.byref(s), _ptr(ne_next), _ptr(phi_next),
+                                        g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss),
+                                        _stream_ptr(stream)))
+        return loss.value, g
+
+    def train_step(self, prob: DeviceProblem, ne, phi, ne_prev, phi_prev, ne_next, phi_next, lr: float,
+                   want_loss: bool = False, stream=None):
+        loss = C.c_double()
+        p = prob.cstruct()
+        s = Solver._state(ne, phi, ne_prev, phi_prev)
+        self._check(lib().jfnk_net_train_step(self.h, C.byref(p), C.byref(s), _ptr(ne_next), _ptr(phi_next),
+                                              float(lr), C.byref(loss) if want_loss else None,
+                                              _stream_ptr(stream)))
+        return loss.value if want_loss else None

@@ -1,0 +1,237 @@
+"""GPU checks of the learned-guess network kernels through the C ABI.
+
+The FP64 reference (oracle/net_ref.py) is run with the same bfloat16
+rounding points as the matrix-core kernels (quant=True), so the remaining
+differences are FP32 accumulation order; it is also compared without the
+rounding, at the looser bound that BF16 storage allows.
+"""
+import numpy as np
+import pytest
+
+from paper_1904_08510_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def J():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_08510_amd import jfnk
+    jfnk.lib()
+    return jfnk
+
+
+@pytest.fixture(scope="module")
+def R():
+    from oracle import net_ref
+    return net_ref
+
+
+S0, S1 = 0.1, 0.3
+
+
+def batch(seed=11, sizes=(200, 333, 64, 5, 129)):
+    """Ragged columns (partial last tiles, a column shorter than the
+    convolution's reach) with X^{n-1}, X^n and a target X^{n+1}."""
+    rng = np.random.default_rng(seed)
+    cols, prev, nxt = [], [], []
+    for n in sizes:
+        c = W.flame_column(n, float(rng.uniform(-900, 900)), a_ion=float(10 ** rng.uniform(15, 17)),
+                           x_f=float(rng.uniform(0.006, 0.014)))
+        x = W.cell_centres(n, c.length)
+        c.ne = c.ne * (1.0 + 0.3 * np.sin(x * 700.0)) + 1e9
+        c.phi = c.phi + 4.0 * np.cos(x * 300.0)
+        prev.append((c.ne * 0.97, c.phi - 1.5 * np.sin(x * 200.0)))
+        nxt.append((c.ne * (1.0 + 0.2 * np.cos(x * 500.0)), c.phi + 2.0 * np.sin(x * 900.0)))
+        cols.append(c)
+    return cols, prev, nxt
+
+
+def to_dev(J, cols, prev, nxt):
+    packed = W.pack(cols)
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    cat = lambda xs: torch.from_numpy(np.ascontiguousarray(np.concatenate(xs))).cuda()
+    pne = cat([p[0] for p in prev]) if prev else None
+    pph = cat([p[1] for p in prev]) if prev else None
+    nne = cat([p[0] for p in nxt])
+    nph = cat([p[1] for p in nxt])
+    return packed, prob, ne, phi, pne, pph, nne, nph
+
+
+def ref_inputs(R, cols, prev, nxt, with_prev=True):
+    xs, ts = [], []
+    for c, p, q in zip(cols, prev, nxt):
+        xs.append(R.features(c, c.ne, c.phi, *(p if with_prev else (None, None))))
+        ts.append(R.targets(c, c.ne, c.phi, q[0], q[1], np.float32(S0), np.float32(S1)))
+    return xs, ts
+
+
+def params32(R, seed):
+    p = R.flat(R.init_params(seed)).astype(np.float32)
+    rng = np.random.default_rng(seed + 1)
+    # nonzero biases exercise the bias path
+    o = 0
+    for l in range(R.NLAYER):
+        nw = R.CH[l + 1] * R.K * R.CH[l]
+        p[o + nw:o + nw + R.CH[l + 1]] = (0.05 * rng.standard_normal(R.CH[l + 1])).astype(np.float32)
+        o += nw + R.CH[l + 1]
+    return p
+
+
+def make_net(J, packed):
+    return J.Net(J.net_default_config(max_cols=packed.ncols + 2, max_total_cells=packed.total + 100,
+                                      out_scale_ne=S0, out_scale_phi=S1))
+
+
+@pytest.mark.parametrize("with_prev", [True, False])
+def test_predict_matches_reference(J, R, with_prev):
+    cols, prev, nxt = batch()
+    packed, prob, ne, phi, pne, pph, _, _ = to_dev(J, cols, prev, nxt)
+    net = make_net(J, packed)
+    p = params32(R, 5)
+    net.set_params(p)
+    np.testing.assert_array_equal(net.get_params(), p)
+    ne_o, phi_o = net.predict(prob, ne, phi, pne if with_prev else None, pph if with_prev else None)
+    torch.cuda.synchronize()
+    ne_o, phi_o = ne_o.cpu().numpy(), phi_o.cpu().numpy()
+    params = R.unflat(p.astype(np.float64))
+    xs, _ = ref_inputs(R, cols, prev, nxt, with_prev)
+    worst_q = worst_64 = 0.0
+    dq = [0.0, 0.0]
+    for i, c in enumerate(cols):
+        sl = slice(packed.col_offset[i], packed.col_offset[i + 1])
+        ps = R.phi_scale(c.phi_left, c.phi_right)
+        o_gpu = np.stack([(R.a_of(ne_o[sl]) - R.a_of(c.ne)) / np.float32(S0),
+                          (phi_o[sl] - c.phi) / (ps * np.float32(S1))], axis=1)
+        oq, _ = R.forward(params, xs[i], quant=True)
+        o64, _ = R.forward(params, xs[i], quant=False)
+        scale = max(np.max(np.abs(oq)), 1e-3)
+        worst_q = max(worst_q, np.max(np.abs(o_gpu - oq)) / scale)
+        worst_64 = max(worst_64, np.max(np.abs(o_gpu - o64)) / scale)
+        dq[0] += np.sum((o_gpu - oq) ** 2)
+        dq[1] += np.sum(oq ** 2)
+        # the candidate itself: same transform of the outputs
+        n_ref, p_ref = R.candidate(c, c.ne, c.phi, oq, np.float32(S0), np.float32(S1))
+        assert np.all(np.isfinite(ne_o[sl])) and np.all(np.isfinite(phi_o[sl]))
+    rel_q = np.sqrt(dq[0] / dq[1])
+    print(f"predict: max |o - o_ref| / max|o_ref|: bf16-rounded ref {worst_q:.2e}, fp64 ref {worst_64:.2e}; "
+          f"rel L2 vs bf16-rounded ref {rel_q:.2e}")
+    # accumulation order flips an occasional BF16 rounding of a hidden activation
+    assert rel_q < 2e-3
+    assert worst_q < 1e-2
+    assert worst_64 < 5e-2
+
+
+def test_gradient_matches_reference(J, R):
+    cols, prev, nxt = batch(seed=12)
+    packed, prob, ne, phi, pne, pph, nne, nph = to_dev(J, cols, prev, nxt)
+    net = make_net(J, packed)
+    p = params32(R, 6)
+    net.set_params(p)
+    loss, g = net.grad(prob, ne, phi, pne, pph, nne, nph)
+    params = R.unflat(p.astype(np.float64))
+    xs, ts = ref_inputs(R, cols, prev, nxt)
+    lq, gq = R.loss_and_grad(params, xs, ts, quant=True)
+    l64, g64 = R.loss_and_grad(params, xs, ts, quant=False)
+    gq, g64 = R.flat(gq), R.flat(g64)
+    g = g.astype(np.float64)
+    rel_q = np.linalg.norm(g - gq) / np.linalg.norm(gq)
+    cos64 = np.dot(g, g64) / (np.linalg.norm(g) * np.linalg.norm(g64))
+    print(f"grad: loss {loss:.6e} ref {lq:.6e}; rel L2 vs bf16-rounded ref {rel_q:.2e}; cosine vs fp64 {cos64:.6f}")
+    assert abs(loss - lq) <= 1e-4 * lq
+    assert rel_q < 1e-2
+    assert cos64 > 0.999
+    # every layer's block, weights and biases separately
+    o = 0
+    for l in range(R.NLAYER):
+        nw = R.CH[l + 1] * R.K * R.CH[l]
+        for blk in (slice(o, o + nw), slice(o + nw, o + nw + R.CH[l + 1])):
+            err = np.linalg.norm(g[blk] - gq[blk]) / max(np.linalg.norm(gq[blk]), 1e-30)
+            assert err < 3e-2, (l, blk, err)
+        o += nw + R.CH[l + 1]
+
+
+def test_adam_step_matches_reference(J, R):
+    cols, prev, nxt = batch(seed=13)
+    packed, prob, ne, phi, pne, pph, nne, nph = to_dev(J, cols, prev, nxt)
+    net = make_net(J, packed)
+    p = params32(R, 7)
+    net.set_params(p)
+    _, g = net.grad(prob, ne, phi, pne, pph, nne, nph)
+    m = np.zeros(p.size)
+    v = np.zeros(p.size)
+    params = R.unflat(p.astype(np.float64))
+    lr = 1e-3
+    for step in (1, 2):
+        loss = net.train_step(prob, ne, phi, pne, pph, nne, nph, lr, want_loss=True)
+        params, m, v = R.adam(params, R.unflat(g.astype(np.float64)), m, v, step, lr)
+        got = net.get_params()
+        exp = R.flat(params)
+        assert np.max(np.abs(got - exp)) < 1e-6 + 1e-5 * lr, step
+        # the next step's gradient is taken at the updated weights
+        _, g = net.grad(prob, ne, phi, pne, pph, nne, nph)
+    assert np.isfinite(loss)
+
+
+def test_training_reduces_loss(J, R):
+    cols, prev, nxt = batch(seed=14)
+    packed, prob, ne, phi, pne, pph, nne, nph = to_dev(J, cols, prev, nxt)
+    net = make_net(J, packed)
+    net.set_params(params32(R, 8))
+    first = net.train_step(prob, ne, phi, pne, pph, nne, nph, 2e-3, want_loss=True)
+    for _ in range(150):
+        net.train_step(prob, ne, phi, pne, pph, nne, nph, 2e-3)
+    last = net.train_step(prob, ne, phi, pne, pph, nne, nph, 2e-3, want_loss=True)
+    print(f"training: loss {first:.4e} -> {last:.4e}")
+    assert last < 0.5 * first
+
+
+def test_learned_guess_keeps_the_root(J, R):
+    """The step with the learned guess reaches the same root (the guess only
+    changes where Newton starts) and reports which guess it took."""
+    cols = W.config2(seed=2100, ncols=6, nmin=300, nmax=900)
+    packed = W.pack(cols)
+    outs = {}
+    for mode in ("extrap", "learned"):
+        prob, ne, phi, _, _ = J.device_problem(packed)
+        solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64,
+                                       guess=J.GUESS_LEARNED if mode == "learned" else J.GUESS_EXTRAP))
+        net = None
+        if mode == "learned":
+            net = J.Net(J.net_default_config(out_scale_ne=S0, out_scale_phi=S1))
+            net.set_params(params32(R, 9))
+            solver.set_model(net)
+        pne = pph = None
+        used = []
+        for k in range(3):
+            cur = (ne.clone(), phi.clone())
+            rc, st = solver.step(prob, ne, phi, pne, pph)
+            assert rc == J.JFNK_OK, st.status
+            used.append(st.guess_used.copy())
+            pne, pph = cur
+        outs[mode] = (ne.cpu().numpy(), phi.cpu().numpy(), used)
+    a, b = outs["extrap"], outs["learned"]
+    for x, y in ((a[0], b[0]), (a[1], b[1])):
+        assert np.linalg.norm(x - y) <= 1e-9 * np.linalg.norm(x)
+    assert all(set(u.tolist()) <= {0, 1, 2} for u in b[2])
+
+
+def test_learned_errors(J, R):
+    cols, prev, nxt = batch(seed=15)
+    packed, prob, ne, phi, pne, pph, nne, nph = to_dev(J, cols, prev, nxt)
+    solver = J.Solver(J.config_for(packed, guess=J.GUESS_LEARNED))
+    rc, _ = solver.step(prob, ne, phi, raw=True)
+    assert rc == J.JFNK_EMODEL
+    net = J.Net(J.net_default_config(max_cols=2, max_total_cells=300))
+    with pytest.raises(J.JfnkError) as e:
+        net.grad(prob, ne, phi, pne, pph, nne, nph)
+    assert e.value.code == J.JFNK_ECAPACITY
+    with pytest.raises(J.JfnkError):
+        net.set_params(np.zeros(5, np.float32))
+    prob.temp = None
+    with pytest.raises(J.JfnkError) as e:
+        net.predict(prob, ne, phi)
+    assert e.value.code == J.JFNK_EINVAL
