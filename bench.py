@@ -56,6 +56,96 @@ def bytes_per_cell(newton, gmres, backtracks, has_prev, fb):
     return b
 
 
+def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None, stream=None):
+    """Warm-up then timed episodes of the batched solver; per-step records."""
+    import torch
+    cfg = J.config_for_dims(len(ns), int(ns.sum()), int(ns.max()), prec_precision=prec, guess=guess,
+                            schedule=J.SCHED_BATCHED, threads_override=args.threads)
+    solver = J.Solver(cfg)
+    if net is not None:
+        solver.set_model(net)
+    fb = 4.0 if prec == J.PREC_FP32 else 8.0
+    prev_n, prev_p = torch.empty_like(ne), torch.empty_like(phi)
+    state = {"e": 0}
+
+    def one_step(record):
+        e = state["e"]
+        if e == 0:
+            ne.copy_(ne0)
+            phi.copy_(phi0)
+        has_prev = e > 0
+        cur_n, cur_p = ne.clone(), phi.clone()
+        rc, st = solver.step(prob, ne, phi, prev_n if has_prev else None,
+                             prev_p if has_prev else None, stream=stream)
+        prev_n.copy_(cur_n)
+        prev_p.copy_(cur_p)
+        state["e"] = (e + 1) % EPISODE
+        if record is not None:
+            ms, _ = solver.last_timing()
+            record.append(dict(rc=rc, ms=ms, has_prev=has_prev, newton=st.newton_iters.copy(),
+                               gmres=st.gmres_iters.copy(), bt=st.backtracks.copy(),
+                               res=st.res_scaled.copy(), status=st.status.copy(),
+                               guess=st.guess_used.copy()))
+        return rc
+
+    for _ in range(args.warmup):
+        one_step(None)
+    state["e"] = 0
+    torch.cuda.synchronize()
+    rec = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step(rec)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    solver.close()
+    for r in rec:   # outside the timed region
+        r["conv"] = int(np.sum(r["status"] == 0))
+        r["res"] = float(r["res"].max())
+        r["bytes"] = float(np.sum(ns * np.array([
+            bytes_per_cell(r["newton"][i], r["gmres"][i], r["bt"][i], r["has_prev"], fb)
+            for i in range(len(ns))])))
+    converged = sum(r["conv"] for r in rec)
+    kern_ms = sum(r["ms"] for r in rec)
+    kern_bytes = sum(r["bytes"] for r in rec)
+    newton = np.concatenate([r["newton"] for r in rec])
+    gmres = np.concatenate([r["gmres"] for r in rec])
+    used = np.concatenate([r["guess"] for r in rec])
+    return dict(
+        value=converged / wall, wall=wall, ms_per_step=1e3 * wall / args.steps,
+        converged=converged, total=len(ns) * args.steps, max_res=max(r["res"] for r in rec),
+        kernel_ms_avg=kern_ms / len(rec), achieved_gbs=kern_bytes / (kern_ms * 1e-3) / 1e9,
+        bytes_per_launch=kern_bytes / len(rec),
+        newton_mean=float(newton.mean()), newton_max=int(newton.max()),
+        gmres_per_newton=float(gmres.sum() / max(newton.sum(), 1)),
+        guess_used={"prev": int(np.sum(used == 0)), "extrap": int(np.sum(used == 1)),
+                    "learned": int(np.sum(used == 2))},
+    )
+
+
+def train_guess_net(J, args):
+    """Train the learned-guess network on solver-generated episodes of the
+    training seeds (disjoint from the benchmark batch's seed)."""
+    import torch
+    from paper_1904_08510_amd import train_guess as TG
+    from paper_1904_08510_amd import workloads as W
+    t0 = time.perf_counter()
+    data = TG.generate(list(W.training_seeds())[:args.train_seeds], ncols=args.train_cols,
+                       steps=EPISODE, log=lambda *a: None)
+    t1 = time.perf_counter()
+    net = TG.make_net(data)
+    net.set_params(TG.init_params(0))
+    hist = TG.train(net, data, epochs=args.train_epochs, log=lambda *a: None)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    info = dict(episodes=len(data), columns_per_episode=args.train_cols, steps=EPISODE,
+                column_steps=len(data) * args.train_cols * EPISODE, epochs=args.train_epochs,
+                data_s=t1 - t0, train_s=t2 - t1, loss_per_epoch=hist)
+    del data
+    torch.cuda.empty_cache()
+    return net, info
+
+
 def run_gpu(args):
     import torch
     from paper_1904_08510_amd import jfnk as J
@@ -71,81 +161,38 @@ def run_gpu(args):
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    net, train_info = (None, None)
+    if args.guess == "learned":
+        net, train_info = train_guess_net(J, args)
     cols = W.config2(seed=2026, ncols=args.ncols)
     packed = W.pack(cols)
     prob, ne, phi, _, _ = J.device_problem(packed, dev)
     ne0, phi0 = ne.clone(), phi.clone()
-    prev_n, prev_p = torch.empty_like(ne), torch.empty_like(phi)
     ns = np.diff(packed.col_offset)
-    prec = J.PREC_FP32 if args.prec == "fp32" else J.PREC_FP64
-    guess = J.GUESS_EXTRAP
-    cfg = J.config_for(packed, prec_precision=prec, guess=guess, schedule=J.SCHED_BATCHED,
-                       threads_override=args.threads)
-    solver = J.Solver(cfg)
-    fb = 4.0 if prec == J.PREC_FP32 else 8.0
     stream = torch.cuda.current_stream()
-    state = {"e": 0}
-
-    def one_step(record):
-        e = state["e"]
-        if e == 0:
-            ne.copy_(ne0)
-            phi.copy_(phi0)
-            has_prev = False
-        else:
-            has_prev = True
-        cur_n, cur_p = ne.clone(), phi.clone()
-        rc, st = solver.step(prob, ne, phi, prev_n if has_prev else None,
-                             prev_p if has_prev else None, stream=stream)
-        prev_n.copy_(cur_n)
-        prev_p.copy_(cur_p)
-        state["e"] = (e + 1) % EPISODE
-        if record is not None:
-            ms, _ = solver.last_timing()
-            record.append(dict(rc=rc, ms=ms, has_prev=has_prev, newton=st.newton_iters.copy(),
-                               gmres=st.gmres_iters.copy(), bt=st.backtracks.copy(),
-                               res=st.res_scaled.copy(), status=st.status.copy()))
-        return rc
-
-    for _ in range(args.warmup):
-        one_step(None)
-    state["e"] = 0
-    torch.cuda.synchronize()
-    rec = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        one_step(rec)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    for r in rec:   # outside the timed region
-        r["conv"] = int(np.sum(r["status"] == 0))
-        r["res"] = float(r["res"].max())
-        r["bytes"] = float(np.sum(ns * np.array([
-            bytes_per_cell(r["newton"][i], r["gmres"][i], r["bt"][i], r["has_prev"], fb)
-            for i in range(len(ns))])))
-    converged = sum(r["conv"] for r in rec)
-    total_cs = args.ncols * args.steps
-    kern_ms = sum(r["ms"] for r in rec)
-    kern_bytes = sum(r["bytes"] for r in rec)
-    achieved = kern_bytes / (kern_ms * 1e-3) / 1e9
-    newton = np.concatenate([r["newton"] for r in rec])
-    gmres = np.concatenate([r["gmres"] for r in rec])
-    out = dict(
-        value=converged / wall, wall=wall, ms_per_step=1e3 * wall / args.steps,
-        converged=converged, total=total_cs, max_res=max(r["res"] for r in rec),
-        kernel_ms_avg=kern_ms / len(rec), achieved_gbs=achieved, bytes_per_launch=kern_bytes / len(rec),
-        newton_mean=float(newton.mean()), newton_max=int(newton.max()),
-        gmres_per_newton=float(gmres.sum() / max(newton.sum(), 1)),
-        cells=int(packed.col_offset[-1]),
-    )
-    solver.close()
+    prec = J.PREC_FP32 if args.prec == "fp32" else J.PREC_FP64
+    guess = J.GUESS_LEARNED if args.guess == "learned" else J.GUESS_EXTRAP
+    out = measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net, stream)
+    out["cells"] = int(packed.col_offset[-1])
+    out["train"] = train_info
+    if not args.skip_ablations:
+        abl = {}
+        for name, pr, gs in (("batched_fp32_extrap", J.PREC_FP32, J.GUESS_EXTRAP),
+                             ("batched_fp64_extrap", J.PREC_FP64, J.GUESS_EXTRAP)):
+            if pr == prec and gs == guess:
+                continue
+            r = measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, pr, gs, None, stream)
+            abl[name] = dict(value=r["value"], ms_per_step=r["ms_per_step"], converged=r["converged"],
+                             max_res=r["max_res"], kernel_ms_avg=r["kernel_ms_avg"])
+        out["ablations"] = abl
+    if net is not None:
+        net.close()
 
     # plain schedule on a bounded sample of the same batch (one column per call)
     if not args.skip_plain:
         idx = list(range(0, args.ncols, max(1, args.ncols // args.plain_cols)))[: args.plain_cols]
         sub = W.pack([cols[i] for i in idx])
         sprob, sne, sphi, _, _ = J.device_problem(sub, dev)
-        s0n, s0p = sne.clone(), sphi.clone()
         pn, pp = torch.empty_like(sne), torch.empty_like(sphi)
         psolver = J.Solver(J.config_for(sub, prec_precision=J.PREC_FP64, guess=J.GUESS_EXTRAP,
                                         schedule=J.SCHED_PLAIN))
@@ -164,7 +211,6 @@ def run_gpu(args):
                             sample=f"{len(idx)} columns (every {args.ncols // len(idx)}th) x "
                                    f"episode steps 0..{args.plain_steps - 1}, FP64 factors, extrapolated guess")
         psolver.close()
-        del s0n, s0p
     return out
 
 
@@ -231,6 +277,11 @@ def main():
     ap.add_argument("--ncols", type=int, default=1024)
     ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--threads", type=int, default=0, help="workgroup size per column (0: autotuned)")
+    ap.add_argument("--guess", choices=["learned", "extrap"], default="learned")
+    ap.add_argument("--train-seeds", type=int, default=100)
+    ap.add_argument("--train-cols", type=int, default=50)
+    ap.add_argument("--train-epochs", type=int, default=4)
+    ap.add_argument("--skip-ablations", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--plain-cols", type=int, default=16)
@@ -264,12 +315,14 @@ def main():
         "config": {
             "workload": f"{args.ncols} flame columns x U{{512..8192}} cells (seed 2026), V~U[-1000,1000], "
                         f"ion peak logU[1e15,1e17], dt=1e-5 s, 20-step episodes; batched, "
-                        f"{args.prec.upper()} preconditioner factors, extrapolated guess",
+                        f"{args.prec.upper()} preconditioner factors, "
+                        + ("learned guess (BF16 conv net) with extrapolated fallback" if args.guess == "learned"
+                           else "extrapolated guess"),
             "columns": args.ncols,
             "cells": g["cells"],
             "episode_steps": EPISODE,
             "prec": args.prec,
-            "guess": "extrap",
+            "guess": args.guess,
         },
         "roofline": {
             "bound": "hbm",
@@ -284,11 +337,13 @@ def main():
         },
         "cpu_baseline": cpu,
         "plain": g.get("plain"),
+        "ablations": g.get("ablations"),
+        "learned": None if g.get("train") is None else dict(g["train"], guess_used=g["guess_used"]),
         "speedup_vs_plain": (g["value"] / g["plain"]["value"]) if g.get("plain") else None,
         "solver": {
             "converged": g["converged"], "column_steps": g["total"], "max_res": g["max_res"],
             "newton_mean": g["newton_mean"], "newton_max": g["newton_max"],
-            "gmres_per_newton": g["gmres_per_newton"],
+            "gmres_per_newton": g["gmres_per_newton"], "guess_used": g["guess_used"],
         },
     }
     print(json.dumps(line), flush=True)

@@ -167,8 +167,9 @@ const char *jfnk_last_error(const jfnk_ctx *ctx);
 
 /* Device time of the last jfnk_step's solve (ms, HIP events recorded on the
    step's stream right before and after the solve launches; for the plain
-   schedule the span of all its phase launches) and the number of launches
-   it spans (-1: host-driven).  Returns JFNK_EINVAL on NULL arguments. */
+   schedule the span of all its phase launches; the learned guess, evaluated
+   before, is not included) and the number of launches it spans (-1:
+   host-driven).  Returns JFNK_EINVAL on NULL arguments. */
 int jfnk_last_timing(const jfnk_ctx *ctx, double *solve_ms, int32_t *launches);
 
 /* ---- learned Newton initial guess --------------------------------------
@@ -252,7 +253,9 @@ int jfnk_net_train_step(jfnk_net *net, const jfnk_problem *p, const jfnk_state *
    detaches).  The context does not own the network, which must outlive its
    use.  The network is evaluated before the solve for the columns whose
    previous step on this context needed at least one Newton iteration (all
-   columns on the first step and whenever the column layout changes). */
+   columns on the first step and whenever the column layout changes); after
+   r consecutive evaluations whose candidate lost to the fallback, a column
+   skips the network for the next 2^min(r,5) - 1 steps. */
 int jfnk_set_model(jfnk_ctx *ctx, jfnk_net *net);
 
 /* ---- test exports: single phases of the step, same kernels ----------- */

@@ -19,6 +19,7 @@ namespace {
 
 constexpr int kTmax = 512;          // largest workgroup that owns a column
 constexpr int kScalSlots = 64;      // doubles of scalar exchange per column
+constexpr int kMaxBackoff = 5;      // a losing learned guess is skipped up to 2^5 - 1 steps
 
 // ---------------------------------------------------------------------------
 // Batched schedule: one workgroup per column, whole step in one launch.
@@ -230,7 +231,6 @@ struct jfnk_ctx {
     std::vector<int32_t> last_bc;
     bool sched_valid = false;
     bool timed = false;
-    bool pre_recorded = false;   // ev0 already recorded (before the learned guess)
     double last_ms = 0.0;
     int last_launches = 0;
     // learned guess
@@ -239,8 +239,11 @@ struct jfnk_ctx {
     int32_t* d_lmask = nullptr;  // [max_cols]
     int32_t* h_lmask = nullptr;  // pinned
     bool learn_active = false;
-    bool hist_valid = false;     // last_newton / last_status describe the current layout
+    bool hist_valid = false;     // the per-column records below describe the current layout
     std::vector<int32_t> last_newton, last_status;
+    std::vector<uint8_t> evaluated;       // network evaluated for the column this step
+    std::vector<int32_t> reject_streak;   // consecutive steps its candidate lost
+    std::vector<int32_t> skip_left;       // steps to skip before evaluating it again
 };
 
 namespace {
@@ -519,7 +522,7 @@ template <int T, class FT>
 int run_plain(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t st) {
     const SolverParams prm = make_params(ctx, p, x);
     const UserArrays U = make_user(ctx, p, x);
-    if (!ctx->pre_recorded) HIP_OK(hipEventRecord(ctx->ev0, st));
+    HIP_OK(hipEventRecord(ctx->ev0, st));
     for (int c = 0; c < p->ncols; ++c) {
         HostExecT<T, FT> ex;
         ex.ctx = ctx;
@@ -549,12 +552,12 @@ int run_batched(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t
     a.prm = make_params(ctx, p, x);
     a.U = make_user(ctx, p, x);
     a.order = ctx->d_order;
-    if (!ctx->pre_recorded) HIP_OK(hipEventRecord(ctx->ev0, st));
+    HIP_OK(hipEventRecord(ctx->ev0, st));
     hipLaunchKernelGGL((k_solve<T, FT>), dim3(p->ncols), dim3(T), Lds<T>::bytes(), st, a);
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(ctx->ev1, st));
     ctx->timed = true;
-    ctx->last_launches = ctx->pre_recorded ? 2 : 1;
+    ctx->last_launches = 1;
     return JFNK_OK;
 }
 
@@ -707,17 +710,27 @@ int for_each_column(jfnk_ctx* ctx, const jfnk_problem* p, hipStream_t st, PhaseA
 int learned_guess(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t st) {
     if (!p->temp) return fail(ctx, JFNK_EINVAL, "the learned guess needs the temperature field");
     const int nc = p->ncols;
-    std::vector<uint8_t> use(nc, 1);
+    std::vector<uint8_t>& use = ctx->evaluated;
+    use.assign(nc, 1);
     int nuse = nc;
     if (ctx->hist_valid && (int)ctx->last_newton.size() == nc) {
+        // skip columns that converged at their initial guess last step, and
+        // back off exponentially from columns whose learned candidate keeps losing
         nuse = 0;
         for (int c = 0; c < nc; ++c) {
-            use[c] = !(ctx->last_status[c] == COL_CONVERGED && ctx->last_newton[c] == 0);
+            const bool settled = ctx->last_status[c] == COL_CONVERGED && ctx->last_newton[c] == 0;
+            if (ctx->skip_left[c] > 0) {
+                --ctx->skip_left[c];
+                use[c] = 0;
+            } else {
+                use[c] = !settled;
+            }
             nuse += use[c];
         }
+    } else {
+        ctx->reject_streak.assign(nc, 0);
+        ctx->skip_left.assign(nc, 0);
     }
-    HIP_OK(hipEventRecord(ctx->ev0, st));
-    ctx->pre_recorded = true;
     if (nuse == 0) return JFNK_OK;
     for (int c = 0; c < nc; ++c) ctx->h_lmask[c] = use[c];
     HIP_OK(hipMemcpyAsync(ctx->d_lmask, ctx->h_lmask, sizeof(int32_t) * nc, hipMemcpyHostToDevice, st));
@@ -838,14 +851,12 @@ int jfnk_step(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, jfnk_stats* s
     rc = schedule_cached(ctx, p, x, st);
     if (rc) return rc;
     ctx->learn_active = false;
-    ctx->pre_recorded = false;
     if (ctx->cfg.guess == JFNK_GUESS_LEARNED) {
         rc = learned_guess(ctx, p, x, st);
         if (rc) return rc;
     }
     rc = ctx->cfg.prec_precision == JFNK_PREC_FP32 ? dispatch_run<float>(ctx, p, x, st)
                                                    : dispatch_run<double>(ctx, p, x, st);
-    ctx->pre_recorded = false;
     ctx->learn_active = false;
     if (rc) return rc;
     int nfail = 0;
@@ -854,9 +865,19 @@ int jfnk_step(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, jfnk_stats* s
     // which columns needed Newton iterations (the learned guess is evaluated for those)
     ctx->last_newton.resize(p->ncols);
     ctx->last_status.resize(p->ncols);
+    const bool learned = ctx->cfg.guess == JFNK_GUESS_LEARNED && (int)ctx->evaluated.size() == p->ncols &&
+                         (int)ctx->reject_streak.size() == p->ncols;
     for (int c = 0; c < p->ncols; ++c) {
         ctx->last_newton[c] = ctx->h_cst[c].newton;
         ctx->last_status[c] = ctx->h_cst[c].status;
+        if (learned && ctx->evaluated[c]) {
+            if (ctx->h_cst[c].guess == JFNK_GUESS_LEARNED) {
+                ctx->reject_streak[c] = 0;
+            } else {
+                ctx->reject_streak[c] = std::min(ctx->reject_streak[c] + 1, kMaxBackoff);
+                ctx->skip_left[c] = (1 << ctx->reject_streak[c]) - 1;
+            }
+        }
     }
     ctx->hist_valid = true;
     return nfail ? JFNK_NOT_CONVERGED : JFNK_OK;

@@ -347,6 +347,13 @@ def config_for(packed, **kw) -> jfnk_config:
     return default_config(**base)
 
 
+def config_for_dims(ncols: int, total_cells: int, max_cells: int, **kw) -> jfnk_config:
+    """Config with the given capacity."""
+    base = dict(max_cols=int(ncols), max_total_cells=int(total_cells), max_cells_per_col=int(max_cells))
+    base.update(kw)
+    return default_config(**base)
+
+
 def net_param_count() -> int:
     return int(lib().jfnk_net_param_count())
 
