@@ -454,38 +454,49 @@ int orc_newton(const orc_column *c, const orc_newton_opts *o, double *ne, double
     orc_source_term(c, f);
 
     int status = ORC_MAX_ITERS, it = 0, backtracks = 0, stagn = 0;
-    double rinf, r2, best = INFINITY;
+    double rinf, r2, best = INFINITY, best_r = INFINITY, prev_d = INFINITY;
     orc_residual(c, f, ne, phi, fe, fp);
     scaled_norms(N, fe, fp, s, &rinf, &r2);
-    double prev = rinf;
-    int extra = 0;
     for (;;) {
         if (isnan(rinf)) { status = ORC_NONFINITE; break; }
-        if (rinf < best) {
-            best = rinf;
-            memcpy(best_n, ne, sizeof(double) * N);
-            memcpy(best_p, phi, sizeof(double) * N);
-        }
-        if (o->reference_mode) {
-            if (rinf <= o->floor_tol) { status = ORC_CONVERGED; break; }
-            if (extra) { status = ORC_CONVERGED; break; }
-            if (it > 0 && rinf > 0.5 * prev) {
-                if (++stagn >= 2 && best <= o->tol) extra = 1;
-            } else {
-                stagn = 0;
+        if (!o->reference_mode) {
+            if (rinf < best) {
+                best = rinf;
+                best_r = rinf;
+                memcpy(best_n, ne, sizeof(double) * N);
+                memcpy(best_p, phi, sizeof(double) * N);
             }
-        } else if (rinf <= o->tol) {
-            status = ORC_CONVERGED;
-            break;
+            if (rinf <= o->tol) { status = ORC_CONVERGED; break; }
         }
-        if (it >= o->max_iters) break;
-        prev = rinf;
+        if (it >= o->max_iters && !o->reference_mode) break;
         /* Newton direction: J d = -F */
         orc_jacobian_band(c, ne, phi, ab);
         if (orc_band_factor(n2, ab, piv) != 0) { status = ORC_SINGULAR; break; }
         for (int i = 0; i < N; ++i) { rhs[2 * i] = -fe[i]; rhs[2 * i + 1] = -fp[i]; }
         orc_band_factored_solve(n2, ab, piv, rhs);
         const double dinf = scaled_step_inf(N, rhs, s);
+        if (o->reference_mode) {
+            /* Reference root: Newton runs on until its correction ||S_X^-1 d||_inf
+               (the distance of the iterate to the root it converges to) reaches
+               floor_tol or stops halving; the iterate with the smallest
+               correction is returned.  In the stiff cases the residual reaches
+               its FP64 rounding floor while the iterate is still measurably away
+               from the root, so the residual cannot rank iterates there. */
+            if (dinf < best) {
+                best = dinf;
+                best_r = rinf;
+                memcpy(best_n, ne, sizeof(double) * N);
+                memcpy(best_p, phi, sizeof(double) * N);
+            }
+            if (dinf <= o->floor_tol) { status = ORC_CONVERGED; break; }
+            if (it > 0 && dinf > 0.5 * prev_d) {
+                if (++stagn >= 2 && best_r <= o->tol) { status = ORC_CONVERGED; break; }
+            } else {
+                stagn = 0;
+            }
+            if (it >= o->max_iters) break;
+            prev_d = dinf;
+        }
         /* Backtracking (Section 3.2: line search for globalisation).  A trial
            step X + lam d is taken when the simplified Newton correction there,
            J(X)^-1 F(X + lam d), has shrunk against the step d in the scaled
@@ -534,11 +545,12 @@ int orc_newton(const orc_column *c, const orc_newton_opts *o, double *ne, double
         r2 = rt2;
         ++it;
     }
-    /* hand back the lowest-residual iterate met on the way */
-    if (best < rinf || isnan(rinf)) {
+    /* hand back the best iterate met on the way: smallest residual (timed
+       mode) or smallest Newton correction (reference mode) */
+    if (best_r < INFINITY && (o->reference_mode || best_r < rinf || isnan(rinf))) {
         memcpy(ne, best_n, sizeof(double) * N);
         memcpy(phi, best_p, sizeof(double) * N);
-        rinf = best;
+        rinf = best_r;
     }
     if (st) {
         st->iters = it;

@@ -39,8 +39,10 @@ typedef struct {
 typedef struct {
     int max_iters;
     double tol;                  /* stop at ||S_F^-1 F||_inf <= tol (timed mode) */
-    int reference_mode;          /* 1: iterate to the rounding floor */
-    double floor_tol;            /* reference mode stops here at the latest */
+    int reference_mode;          /* 1: iterate to the rounding floor and return
+                                    the iterate with the smallest Newton correction */
+    double floor_tol;            /* reference mode: stop once the scaled Newton
+                                    correction ||S_X^-1 d||_inf is this small */
     double ls_theta;             /* restricted natural monotonicity factor */
     double lambda_min;
 } orc_newton_opts;
