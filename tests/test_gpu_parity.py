@@ -210,6 +210,47 @@ def test_config1_march_with_extrapolation(J, orc):
         ne_prev, phi_prev = old_n, old_p
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_stiff_batch_sampled_columns(J, orc, prec):
+    """The stiff batch (256 columns x 65536 cells, 5-10 kV, dt = 1e-4 s, dt
+    over the dielectric relaxation time ~1e6) marched 5 steps in one batch;
+    sampled columns are compared, step by step, with the oracle's root from
+    the same X^n (the GPU's) and the final states must be roots in the
+    oracle's arithmetic."""
+    cols = W.config4()
+    packed = W.pack(cols)
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    p = J.PREC_FP64 if prec == "fp64" else J.PREC_FP32
+    solver = J.Solver(J.config_for(packed, prec_precision=p, guess=J.GUESS_EXTRAP))
+    sample = [0, 97, 170, 255]
+    tol = 1e-9 if prec == "fp64" else 1e-5
+    pne = pph = None
+    for k in range(5):
+        off = packed.col_offset
+        xn = {c: (ne[off[c]:off[c + 1]].cpu().numpy(), phi[off[c]:off[c + 1]].cpu().numpy()) for c in sample}
+        xp = None if pne is None else {c: (pne[off[c]:off[c + 1]].cpu().numpy(), pph[off[c]:off[c + 1]].cpu().numpy())
+                                       for c in sample}
+        cur = (ne.clone(), phi.clone())
+        rc, st = solver.step(prob, ne, phi, pne, pph)
+        assert rc == J.JFNK_OK, (k, np.bincount(st.status))
+        assert st.res_scaled.max() <= 1e-10
+        for c in sample:
+            oc = orc.OracleColumn(cols[c], *xn[c])
+            g = xn[c]
+            if xp is not None:
+                e = (2 * xn[c][0] - xp[c][0], 2 * xn[c][1] - xp[c][1])
+                if orc.scaled_residual_inf(oc, *e) <= orc.scaled_residual_inf(oc, *g):
+                    g = e
+            r = orc.newton(oc, g[0].copy(), g[1].copy(), reference=True)
+            got_n = ne[off[c]:off[c + 1]].cpu().numpy()
+            got_p = phi[off[c]:off[c + 1]].cpu().numpy()
+            en = np.linalg.norm(got_n - r.ne) / np.linalg.norm(r.ne)
+            ep = np.linalg.norm(got_p - r.phi) / np.linalg.norm(r.phi)
+            assert en < tol and ep < tol, (k, c, en, ep)
+            assert orc.scaled_residual_inf(oc, got_n, got_p) <= 2e-10, (k, c)
+        pne, pph = cur
+
+
 def test_advection_velocity(J, orc):
     """Face velocities enter the Scharfetter-Gummel Peclet number."""
     col = W.flame_column(333, 150.0)
