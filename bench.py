@@ -30,7 +30,7 @@ EPISODE = 20
 HBM_PEAK_GBS = 8000.0
 
 
-def bytes_per_cell(newton, gmres, backtracks, has_prev, fb):
+def bytes_per_cell(newton, gmres, backtracks, has_prev, fb, chords=0):
     """Algorithmic HBM bytes per cell of one column-step: each phase of the
     method reads its operands from HBM and writes its results to HBM once
     (fb = bytes per stored preconditioner value)."""
@@ -52,15 +52,17 @@ def bytes_per_cell(newton, gmres, backtracks, has_prev, fb):
         b += backtracks * (trial + app)
         if k > 1:
             b += newton * 16.0 * (k + 1)       # direction from k Krylov vectors
+    b += chords * (trial + app)                # simplified-Newton steps: trial + its correction
     b += 32.0                                  # result back to the caller
     return b
 
 
-def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None, stream=None):
+def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None, stream=None, chord=None):
     """Warm-up then timed episodes of the batched solver; per-step records."""
     import torch
+    kw = {} if chord is None else dict(chord_tol=chord)
     cfg = J.config_for_dims(len(ns), int(ns.sum()), int(ns.max()), prec_precision=prec, guess=guess,
-                            schedule=J.SCHED_BATCHED, threads_override=args.threads)
+                            schedule=J.SCHED_BATCHED, threads_override=args.threads, **kw)
     solver = J.Solver(cfg)
     if net is not None:
         solver.set_model(net)
@@ -85,7 +87,7 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
             record.append(dict(rc=rc, ms=ms, has_prev=has_prev, newton=st.newton_iters.copy(),
                                gmres=st.gmres_iters.copy(), bt=st.backtracks.copy(),
                                res=st.res_scaled.copy(), status=st.status.copy(),
-                               guess=st.guess_used.copy()))
+                               guess=st.guess_used.copy(), chords=st.chord_steps.copy()))
         return rc
 
     for _ in range(args.warmup):
@@ -103,7 +105,7 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
         r["conv"] = int(np.sum(r["status"] == 0))
         r["res"] = float(r["res"].max())
         r["bytes"] = float(np.sum(ns * np.array([
-            bytes_per_cell(r["newton"][i], r["gmres"][i], r["bt"][i], r["has_prev"], fb)
+            bytes_per_cell(r["newton"][i], r["gmres"][i], r["bt"][i], r["has_prev"], fb, r["chords"][i])
             for i in range(len(ns))])))
     converged = sum(r["conv"] for r in rec)
     kern_ms = sum(r["ms"] for r in rec)
@@ -111,6 +113,7 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
     newton = np.concatenate([r["newton"] for r in rec])
     gmres = np.concatenate([r["gmres"] for r in rec])
     used = np.concatenate([r["guess"] for r in rec])
+    chords = np.concatenate([r["chords"] for r in rec])
     return dict(
         value=converged / wall, wall=wall, ms_per_step=1e3 * wall / args.steps,
         converged=converged, total=len(ns) * args.steps, max_res=max(r["res"] for r in rec),
@@ -118,6 +121,7 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
         bytes_per_launch=kern_bytes / len(rec),
         newton_mean=float(newton.mean()), newton_max=int(newton.max()),
         gmres_per_newton=float(gmres.sum() / max(newton.sum(), 1)),
+        chord_mean=float(chords.mean()),
         guess_used={"prev": int(np.sum(used == 0)), "extrap": int(np.sum(used == 1)),
                     "learned": int(np.sum(used == 2))},
     )
@@ -177,13 +181,15 @@ def run_gpu(args):
     out["train"] = train_info
     if not args.skip_ablations:
         abl = {}
-        for name, pr, gs in (("batched_fp32_extrap", J.PREC_FP32, J.GUESS_EXTRAP),
-                             ("batched_fp64_extrap", J.PREC_FP64, J.GUESS_EXTRAP)):
-            if pr == prec and gs == guess:
+        for name, pr, gs, ch in (("batched_fp32_extrap", J.PREC_FP32, J.GUESS_EXTRAP, None),
+                                 ("batched_fp64_extrap", J.PREC_FP64, J.GUESS_EXTRAP, None),
+                                 ("batched_fp32_extrap_no_chord", J.PREC_FP32, J.GUESS_EXTRAP, 0.0)):
+            if pr == prec and gs == guess and ch is None:
                 continue
-            r = measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, pr, gs, None, stream)
+            r = measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, pr, gs, None, stream, ch)
             abl[name] = dict(value=r["value"], ms_per_step=r["ms_per_step"], converged=r["converged"],
-                             max_res=r["max_res"], kernel_ms_avg=r["kernel_ms_avg"])
+                             max_res=r["max_res"], kernel_ms_avg=r["kernel_ms_avg"],
+                             newton_mean=r["newton_mean"], chord_mean=r["chord_mean"])
         out["ablations"] = abl
     if net is not None:
         net.close()
@@ -344,6 +350,7 @@ def main():
             "converged": g["converged"], "column_steps": g["total"], "max_res": g["max_res"],
             "newton_mean": g["newton_mean"], "newton_max": g["newton_max"],
             "gmres_per_newton": g["gmres_per_newton"], "guess_used": g["guess_used"],
+            "chord_steps_mean": g["chord_mean"],
         },
     }
     print(json.dumps(line), flush=True)

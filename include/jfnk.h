@@ -94,6 +94,14 @@ typedef struct {
     double ls_theta;             /* backtracking accepts X + lam d when the
                                     simplified Newton correction there satisfies
                                     ||P^-1 S_F^-1 F||_inf <= (1 - ls_theta lam) ||d||_inf */
+    double chord_tol;            /* 0: off (every iteration is a GMRES Newton
+                                    iteration).  Else, while the error estimate
+                                    e = ||P^-1 S_F^-1 F||_inf of the iterate is in
+                                    (tol_x, chord_tol], the step X + S_X d with
+                                    d = -P^-1 S_F^-1 F (a Newton step with the
+                                    analytic Jacobian of the latest factorisation)
+                                    is tried first and kept if the estimate there
+                                    is <= (1 - ls_theta) e; at most 4 in a row */
     int32_t prec_precision;      /* JFNK_PREC_* */
     int32_t guess;               /* JFNK_GUESS_* */
     int32_t schedule;            /* JFNK_SCHED_* */
@@ -140,11 +148,12 @@ typedef struct {
     int32_t *backtracks;
     int32_t *guess_used;         /* JFNK_GUESS_* actually taken */
     double *res_scaled;          /* final ||S_F^-1 F||_inf */
+    int32_t *chord_steps;        /* simplified-Newton steps taken (see chord_tol) */
 } jfnk_stats;
 
 /* Fill cfg with the defaults: restart 30, 5 restarts, 50 Newton iterations,
-   10 backtracks, tol_f 1e-10, tol_x 1e-10, gamma 1e-4, ls_theta 0.25, FP32
-   preconditioner, extrapolated guess, batched schedule. */
+   10 backtracks, tol_f 1e-10, tol_x 1e-10, gamma 1e-4, ls_theta 0.25,
+   chord_tol 1e-3, FP32 preconditioner, extrapolated guess, batched schedule. */
 void jfnk_config_default(jfnk_config *cfg);
 
 /* Allocate a context and its workspace on the current HIP device for the

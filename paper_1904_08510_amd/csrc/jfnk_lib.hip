@@ -367,6 +367,7 @@ SolverParams make_params(const jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_
     s.tol_x = ctx->cfg.tol_x;
     s.gamma = ctx->cfg.gamma;
     s.theta = ctx->cfg.ls_theta;
+    s.chord_tol = ctx->cfg.chord_tol;
     return s;
 }
 
@@ -508,6 +509,13 @@ struct HostExecT {
     }
     Norms trial(int cur, int out, double lam) {
         a.cur = cur; a.out = out; a.lam = lam; a.v = dir_ref();
+        launch(PH_TRIAL);
+        const double* s = fetch(4);
+        return Norms{s[0], s[1], s[2], s[3]};
+    }
+    Norms chord_trial(int cur, int out) {
+        const int m = a.prm.m;
+        a.cur = cur; a.out = out; a.lam = 1.0; a.v = VecRef{Vb(m, 0), Vb(m, 1), 1.0, 1.0};
         launch(PH_TRIAL);
         const double* s = fetch(4);
         return Norms{s[0], s[1], s[2], s[3]};
@@ -660,6 +668,7 @@ int gather_stats(jfnk_ctx* ctx, int ncols, jfnk_stats* stt, hipStream_t st, int*
             if (stt->gmres_iters) stt->gmres_iters[c] = s.gmres;
             if (stt->backtracks) stt->backtracks[c] = s.backtracks;
             if (stt->guess_used) stt->guess_used[c] = s.guess;
+            if (stt->chord_steps) stt->chord_steps[c] = s.chords;
             if (stt->res_scaled) stt->res_scaled[c] = s.res_inf;
         }
     }
@@ -762,6 +771,7 @@ void jfnk_config_default(jfnk_config* cfg) {
     cfg->tol_x = 1e-10;
     cfg->gamma = 1e-4;
     cfg->ls_theta = 0.25;
+    cfg->chord_tol = 1e-3;
     cfg->prec_precision = JFNK_PREC_FP32;
     cfg->guess = JFNK_GUESS_EXTRAP;
     cfg->schedule = JFNK_SCHED_BATCHED;
@@ -776,6 +786,7 @@ int jfnk_create(const jfnk_config* cfg, jfnk_ctx** out) {
         cfg->gmres_restart < 1 || cfg->gmres_restart > kMaxRestart || cfg->max_restarts < 0 ||
         cfg->max_newton < 0 || cfg->max_backtracks < 0 || !(cfg->tol_f > 0.0) || !(cfg->tol_x >= 0.0) ||
         !(cfg->gamma > 0.0 && cfg->gamma < 1.0) || !(cfg->ls_theta >= 0.0 && cfg->ls_theta < 1.0) ||
+        !(cfg->chord_tol >= 0.0 && cfg->chord_tol < 1.0) ||
         (cfg->prec_precision != JFNK_PREC_FP64 && cfg->prec_precision != JFNK_PREC_FP32) ||
         cfg->guess < 0 || cfg->guess > 2 ||
         (cfg->schedule != JFNK_SCHED_PLAIN && cfg->schedule != JFNK_SCHED_BATCHED))

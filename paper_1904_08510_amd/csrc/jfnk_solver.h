@@ -14,7 +14,7 @@
 namespace jfnk {
 
 struct ColOutcome {
-    int status, newton, gmres, backtracks, guess, restarts;
+    int status, newton, gmres, backtracks, guess, restarts, chords;
     double rinf, r2;
     int cur;
 };
@@ -69,6 +69,8 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
     double y[kMaxRestart];
     int factored = -1;   // buffer whose state the current factorisation was built at
     double est = -1.0;   // ||S_X^-1 P^-1 S_F^-1 F(X)||_inf of the current iterate (-1: unknown)
+    int corr_at = -1;    // buffer whose correction -P^-1 S_F^-1 F sits in the last Krylov slot
+    int chords = 0, chord_run = 0;
     for (;;) {
         if (isnan(nr.r2)) { status = COL_NONFINITE; break; }
         if (nr.rinf <= p.tol_f) {
@@ -78,10 +80,33 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
             if (est < 0.0) {
                 if (factored < 0) { ex.factor(cur); factored = cur; }
                 est = ex.correction(cur).y;
+                corr_at = cur;
             }
             if (est <= p.tol_x) { status = COL_CONVERGED; break; }
         }
         if (it >= p.max_newton) break;
+        // Near the root the correction already at hand is a Newton step with
+        // the analytic Jacobian of the latest factorisation: take it as a
+        // simplified-Newton step (no Krylov solve) while it passes the same
+        // natural monotonicity test as the line search at lambda = 1.  The
+        // convergence test above is unchanged.
+        if (p.chord_tol > 0.0 && corr_at == cur && est > 0.0 && est <= p.chord_tol && chord_run < 4) {
+            const int out = (cur + 1) % 3;
+            const Norms tc = ex.chord_trial(cur, out);
+            double e2 = INFINITY;
+            if (!isnan(tc.r2)) e2 = ex.correction(out).y;
+            if (e2 <= (1.0 - p.theta) * est) {
+                cur = out;
+                nr = tc;
+                est = e2;
+                corr_at = out;
+                ++chords;
+                ++chord_run;
+                continue;
+            }
+            corr_at = -1;    // the slot now holds the rejected trial's correction
+        }
+        chord_run = 0;
         if (factored != cur) ex.factor(cur);
         factored = cur;
         // GMRES on S_F^-1 J S_X d = -S_F^-1 F, right preconditioned, d_0 = 0
@@ -169,6 +194,7 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
             else if (isnan(tn.r2)) { status = COL_NONFINITE; break; }
         }
         est = e_acc;
+        corr_at = accepted ? outb : -1;
         cur = outb;
         nr = tn;
         ++it;
@@ -179,6 +205,7 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
     out.backtracks = btot;
     out.guess = guess;
     out.restarts = rtot;
+    out.chords = chords;
     out.rinf = nr.rinf;
     out.r2 = nr.r2;
     out.cur = cur;
@@ -320,6 +347,10 @@ struct DevExec {
     __device__ Norms trial(int cur, int out, double lam) {
         return col.trial(cur, out, dir_ref(), lam);
     }
+    // X_out = X_cur + S_X d with d the correction in the last Krylov slot
+    __device__ Norms chord_trial(int cur, int out) {
+        return col.trial(cur, out, VecRef{col.Vb(col.prm.m, 0), col.Vb(col.prm.m, 1), 1.0, 1.0}, 1.0);
+    }
     __device__ void finalize(const ColOutcome& o) {
         col.write_back(col.xb(o.cur, 0), col.xb(o.cur, 1), U.ne, U.phi);
         if (threadIdx.x == 0) {
@@ -327,6 +358,7 @@ struct DevExec {
             cs->res_inf = o.rinf; cs->res2 = o.r2;
             cs->status = o.status; cs->newton = o.newton; cs->gmres = o.gmres;
             cs->backtracks = o.backtracks; cs->guess = o.guess; cs->restarts = o.restarts;
+            cs->chords = o.chords;
         }
     }
 };

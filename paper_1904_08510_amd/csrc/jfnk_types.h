@@ -45,7 +45,7 @@ struct ColState {
     double sfn, sfp, sxn, sxp;      // S_F and S_X block scalars
     double rR, gR, wR;              // right-wall face coefficients
     double res_inf, res2;
-    int32_t status, newton, gmres, backtracks, guess, restarts;
+    int32_t status, newton, gmres, backtracks, guess, restarts, chords, pad;
 };
 
 struct SolverParams {
@@ -58,6 +58,7 @@ struct SolverParams {
     int32_t has_learned;    // learned candidate supplied
     int32_t has_u;          // advective face velocities supplied
     double tol_f, tol_x, gamma, theta;
+    double chord_tol;       // simplified-Newton steps while the error estimate is below this (0: off)
 };
 
 // Caller arrays (natural layout, device pointers).

@@ -34,7 +34,7 @@ class jfnk_config(C.Structure):
                 ("max_cells_per_col", C.c_int32), ("gmres_restart", C.c_int32),
                 ("max_restarts", C.c_int32), ("max_newton", C.c_int32),
                 ("max_backtracks", C.c_int32), ("tol_f", C.c_double), ("tol_x", C.c_double),
-                ("gamma", C.c_double), ("ls_theta", C.c_double),
+                ("gamma", C.c_double), ("ls_theta", C.c_double), ("chord_tol", C.c_double),
                 ("prec_precision", C.c_int32), ("guess", C.c_int32), ("schedule", C.c_int32),
                 ("threads_override", C.c_int32)]
 
@@ -61,7 +61,7 @@ class jfnk_net_config(C.Structure):
 
 class jfnk_stats(C.Structure):
     _fields_ = [("status", _ip), ("newton_iters", _ip), ("gmres_iters", _ip),
-                ("backtracks", _ip), ("guess_used", _ip), ("res_scaled", _dp)]
+                ("backtracks", _ip), ("guess_used", _ip), ("res_scaled", _dp), ("chord_steps", _ip)]
 
 
 _LIB = None
@@ -222,10 +222,11 @@ class Stats:
         self.backtracks = np.zeros(n, np.int32)
         self.guess_used = np.zeros(n, np.int32)
         self.res_scaled = np.zeros(n, np.float64)
+        self.chord_steps = np.zeros(n, np.int32)
 
     def cstruct(self) -> jfnk_stats:
         s = jfnk_stats()
-        for name in ("status", "newton_iters", "gmres_iters", "backtracks", "guess_used"):
+        for name in ("status", "newton_iters", "gmres_iters", "backtracks", "guess_used", "chord_steps"):
             setattr(s, name, getattr(self, name).ctypes.data_as(_ip))
         s.res_scaled = self.res_scaled.ctypes.data_as(_dp)
         return s

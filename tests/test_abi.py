@@ -38,13 +38,17 @@ def test_config_defaults(libjfnk):
     cfg = libjfnk.default_config()
     assert cfg.gmres_restart == 30 and cfg.max_newton == 50 and cfg.tol_f == 1e-10
     assert cfg.gamma == 1e-4 and cfg.prec_precision == libjfnk.PREC_FP32
+    assert cfg.ls_theta == 0.25 and cfg.chord_tol == 1e-3 and cfg.tol_x == 1e-10
+    ncfg = libjfnk.net_default_config()
+    assert ncfg.max_cols == 0 and abs(ncfg.out_scale_ne - 0.1) < 1e-7 and abs(ncfg.beta2 - 0.999) < 1e-7
 
 
 def test_create_rejects_bad_config_without_touching_a_device(libjfnk):
     L = libjfnk.lib()
     h = ctypes.c_void_p()
     for kw in (dict(gmres_restart=31), dict(gmres_restart=0), dict(tol_f=0.0), dict(gamma=1.5),
-               dict(max_cols=0), dict(threads_override=100), dict(schedule=7)):
+               dict(max_cols=0), dict(threads_override=100), dict(schedule=7), dict(chord_tol=-1.0),
+               dict(chord_tol=1.0), dict(ls_theta=1.0)):
         cfg = libjfnk.default_config(**kw)
         assert L.jfnk_create(ctypes.byref(cfg), ctypes.byref(h)) == libjfnk.JFNK_EINVAL
         assert not h.value
@@ -56,3 +60,16 @@ def test_null_safety(libjfnk):
     L.jfnk_destroy(None)
     assert L.jfnk_last_error(None) == b"null context"
     assert L.jfnk_step(None, None, None, None, None) == libjfnk.JFNK_EINVAL
+
+
+def test_net_create_rejects_bad_config_without_touching_a_device(libjfnk):
+    L = libjfnk.lib()
+    h = ctypes.c_void_p()
+    for kw in (dict(max_cols=4), dict(max_total_cells=100), dict(out_scale_ne=0.0), dict(beta1=1.0),
+               dict(adam_eps=0.0), dict(max_cols=-1, max_total_cells=-1)):
+        cfg = libjfnk.net_default_config(**kw)
+        assert L.jfnk_net_create(ctypes.byref(cfg), ctypes.byref(h)) == libjfnk.JFNK_EINVAL
+        assert not h.value
+    assert L.jfnk_net_param_count() == 85442
+    L.jfnk_net_destroy(None)
+    assert L.jfnk_net_last_error(None) == b"null network"

@@ -235,3 +235,52 @@ def test_learned_errors(J, R):
     with pytest.raises(J.JfnkError) as e:
         net.predict(prob, ne, phi)
     assert e.value.code == J.JFNK_EINVAL
+
+
+def test_trained_network_gain(J):
+    """Trains the network on solver-generated episodes of training seeds and
+    measures, on a held-out batch of the same distribution, what the learned
+    guess changes against the extrapolated guess: how often its candidate is
+    taken, Newton and GMRES iterations, and device time.  The roots must not
+    change (the guess only moves Newton's starting point)."""
+    from paper_1904_08510_amd import train_guess as TG
+    data = TG.generate(list(W.training_seeds())[:12], ncols=16, steps=20, nmin=512, nmax=2048,
+                       log=lambda *a: None)
+    net = TG.make_net(data)
+    net.set_params(TG.init_params(0))
+    hist = TG.train(net, data, epochs=3, log=lambda *a: None)
+    assert np.all(np.isfinite(hist)) and hist[-1] < hist[0]
+    packed = W.pack(W.config2(seed=2026, ncols=64, nmin=512, nmax=2048))
+    res = {}
+    for mode in ("extrap", "learned"):
+        prob, ne, phi, _, _ = J.device_problem(packed)
+        solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64,
+                                       guess=J.GUESS_LEARNED if mode == "learned" else J.GUESS_EXTRAP))
+        if mode == "learned":
+            solver.set_model(net)
+        pne = pph = None
+        newton = gmres = taken = 0
+        ms = 0.0
+        for k in range(20):
+            cur = (ne.clone(), phi.clone())
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            rc, st = solver.step(prob, ne, phi, pne, pph)
+            t1.record()
+            torch.cuda.synchronize()
+            ms += t0.elapsed_time(t1)
+            assert rc == J.JFNK_OK
+            newton += int(st.newton_iters.sum())
+            gmres += int(st.gmres_iters.sum())
+            taken += int(np.sum(st.guess_used == J.GUESS_LEARNED))
+            pne, pph = cur
+        res[mode] = dict(newton=newton, gmres=gmres, taken=taken, ms=ms, ne=ne.cpu().numpy(),
+                         phi=phi.cpu().numpy())
+    a, b = res["extrap"], res["learned"]
+    print(f"learned guess over 64 held-out columns x 20 steps: candidate taken {b['taken']} times; "
+          f"Newton {a['newton']} -> {b['newton']}, GMRES {a['gmres']} -> {b['gmres']}, "
+          f"device time {a['ms']:.1f} -> {b['ms']:.1f} ms (training loss {hist[0]:.3g} -> {hist[-1]:.3g})")
+    assert a["taken"] == 0
+    for x, y in ((a["ne"], b["ne"]), (a["phi"], b["phi"])):
+        assert np.linalg.norm(x - y) <= 1e-9 * np.linalg.norm(x)
