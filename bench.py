@@ -66,6 +66,12 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
     solver = J.Solver(cfg)
     if net is not None:
         solver.set_model(net)
+    tuned = None
+    if args.threads == 0 and not args.no_autotune:
+        # workgroup size per column for this layout, timed on the episode's first steps
+        ne.copy_(ne0)
+        phi.copy_(phi0)
+        tuned = solver.autotune(prob, ne, phi, steps=3, stream=stream)
     fb = 4.0 if prec == J.PREC_FP32 else 8.0
     prev_n, prev_p = torch.empty_like(ne), torch.empty_like(phi)
     state = {"e": 0}
@@ -122,6 +128,7 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
         newton_mean=float(newton.mean()), newton_max=int(newton.max()),
         gmres_per_newton=float(gmres.sum() / max(newton.sum(), 1)),
         chord_mean=float(chords.mean()),
+        autotune=None if tuned is None else dict(chosen=tuned[0], ms_first_3_steps=tuned[1]),
         guess_used={"prev": int(np.sum(used == 0)), "extrap": int(np.sum(used == 1)),
                     "learned": int(np.sum(used == 2))},
     )
@@ -288,6 +295,7 @@ def main():
     ap.add_argument("--train-cols", type=int, default=50)
     ap.add_argument("--train-epochs", type=int, default=4)
     ap.add_argument("--skip-ablations", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--plain-cols", type=int, default=16)
@@ -350,7 +358,7 @@ def main():
             "converged": g["converged"], "column_steps": g["total"], "max_res": g["max_res"],
             "newton_mean": g["newton_mean"], "newton_max": g["newton_max"],
             "gmres_per_newton": g["gmres_per_newton"], "guess_used": g["guess_used"],
-            "chord_steps_mean": g["chord_mean"],
+            "chord_steps_mean": g["chord_mean"], "autotune": g["autotune"],
         },
     }
     print(json.dumps(line), flush=True)

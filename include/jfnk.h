@@ -174,6 +174,20 @@ void jfnk_destroy(jfnk_ctx *ctx);
 /* Message of the last error on this context (never NULL). */
 const char *jfnk_last_error(const jfnk_ctx *ctx);
 
+/* Schedule autotuner (batched schedule, threads_override = 0).  Runs `steps`
+   steps from the state x (x itself is not modified; the steps run on device
+   copies, X^{n-1} taken from x when given) once for every workgroup size
+   per column in {64, 128, 256, 512} that suits the longest column (at most
+   64 cells per thread, not more threads than half its cells), measures the
+   solve time of each with HIP events and keeps the fastest for this column
+   layout: later steps with the same col_offset use it.  A learned guess is
+   replaced by EXTRAP while tuning.  chosen (HOST, may be NULL) receives the
+   workgroup size; times_ms (HOST [4], may be NULL) the summed solve times
+   of the four candidates (-1: not tried).  Allocates and frees device
+   scratch of 6 x total cells doubles.  Synchronises the stream. */
+int jfnk_autotune(jfnk_ctx *ctx, const jfnk_problem *p, const jfnk_state *x, int32_t steps,
+                  int32_t *chosen, double *times_ms, void *stream);
+
 /* Device time of the last jfnk_step's solve (ms, HIP events recorded on the
    step's stream right before and after the solve launches; for the plain
    schedule the span of all its phase launches; the learned guess, evaluated

@@ -241,6 +241,10 @@ struct jfnk_ctx {
     bool learn_active = false;
     bool hist_valid = false;     // the per-column records below describe the current layout
     std::vector<int32_t> last_newton, last_status;
+    // schedule autotuner: workgroup size measured best for a column layout
+    int force_T = 0;                      // set while the tuner tries a candidate
+    int tuned_T = 0;
+    std::vector<int64_t> tuned_off;
     std::vector<uint8_t> evaluated;       // network evaluated for the column this step
     std::vector<int32_t> reject_streak;   // consecutive steps its candidate lost
     std::vector<int32_t> skip_left;       // steps to skip before evaluating it again
@@ -328,7 +332,14 @@ int validate(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x) {
     }
     if (p->col_offset[p->ncols] > ctx->cfg.max_total_cells)
         return fail(ctx, JFNK_ECAPACITY, "total cells exceed capacity");
-    const int T = choose_T(ctx->cfg, nmax);
+    int T = choose_T(ctx->cfg, nmax);
+    if (ctx->force_T > 0) {
+        T = ctx->force_T;
+    } else if (ctx->cfg.threads_override == 0 && ctx->tuned_T > 0 &&
+               (int)ctx->tuned_off.size() == p->ncols + 1 &&
+               memcmp(ctx->tuned_off.data(), p->col_offset, sizeof(int64_t) * (p->ncols + 1)) == 0) {
+        T = ctx->tuned_T;
+    }
     int64_t ws = 0, red = 0;
     for (int c = 0; c < p->ncols; ++c) {
         const int n = (int)(p->col_offset[c + 1] - p->col_offset[c]);
@@ -892,6 +903,74 @@ int jfnk_step(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, jfnk_stats* s
     }
     ctx->hist_valid = true;
     return nfail ? JFNK_NOT_CONVERGED : JFNK_OK;
+}
+
+int jfnk_autotune(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, int32_t steps,
+                  int32_t* chosen, double* times_ms, void* stream) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!p || !x || !x->ne || !x->phi || !p->col_offset || p->ncols < 1 || steps < 1)
+        return fail(ctx, JFNK_EINVAL, "autotune: bad arguments");
+    if (ctx->cfg.schedule != JFNK_SCHED_BATCHED || ctx->cfg.threads_override != 0)
+        return fail(ctx, JFNK_EINVAL, "autotune: needs the batched schedule and no threads_override");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t total = p->col_offset[p->ncols];
+    if (total < 1 || total > ctx->cfg.max_total_cells) return fail(ctx, JFNK_ECAPACITY, "autotune: capacity");
+    int nmax = 0;
+    for (int c = 0; c < p->ncols; ++c) nmax = std::max(nmax, (int)(p->col_offset[c + 1] - p->col_offset[c]));
+    // scratch state: current, previous and a save slot (ne, phi each)
+    double* buf = nullptr;
+    HIP_OK(hipMalloc((void**)&buf, sizeof(double) * 6 * total));
+    double *cn = buf, *cp = buf + total, *pn = buf + 2 * total, *pp = buf + 3 * total;
+    double *sn = buf + 4 * total, *sp = buf + 5 * total;
+    const int saved_guess = ctx->cfg.guess;
+    if (ctx->cfg.guess == JFNK_GUESS_LEARNED) ctx->cfg.guess = JFNK_GUESS_EXTRAP;
+    const int cand[4] = {64, 128, 256, 512};
+    double best_ms = INFINITY;
+    int best = 0;
+    for (int k = 0; k < 4 && rc == JFNK_OK; ++k) {
+        const int T = cand[k];
+        if (times_ms) times_ms[k] = -1.0;
+        if (T > kTmax || (nmax + T - 1) / T > 64 || (T > 64 && nmax <= T / 2)) continue;
+        ctx->force_T = T;
+        ctx->sched_valid = false;
+        const size_t nb = sizeof(double) * total;
+        if (hipMemcpyAsync(cn, x->ne, nb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(cp, x->phi, nb, hipMemcpyDeviceToDevice, st) != hipSuccess) { rc = JFNK_EHIP; break; }
+        bool have_prev = x->ne_prev && x->phi_prev;
+        if (have_prev && (hipMemcpyAsync(pn, x->ne_prev, nb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                          hipMemcpyAsync(pp, x->phi_prev, nb, hipMemcpyDeviceToDevice, st) != hipSuccess)) {
+            rc = JFNK_EHIP;
+            break;
+        }
+        double ms = 0.0;
+        for (int s = 0; s < steps && rc == JFNK_OK; ++s) {
+            if (hipMemcpyAsync(sn, cn, nb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                hipMemcpyAsync(sp, cp, nb, hipMemcpyDeviceToDevice, st) != hipSuccess) { rc = JFNK_EHIP; break; }
+            jfnk_state xs{cn, cp, have_prev ? pn : nullptr, have_prev ? pp : nullptr};
+            rc = jfnk_step(ctx, p, &xs, nullptr, stream);
+            if (rc == JFNK_NOT_CONVERGED) rc = JFNK_OK;
+            if (rc) break;
+            ms += ctx->last_ms;
+            std::swap(pn, sn);
+            std::swap(pp, sp);
+            have_prev = true;
+        }
+        if (rc) break;
+        if (times_ms) times_ms[k] = ms;
+        if (ms < best_ms) { best_ms = ms; best = T; }
+    }
+    ctx->force_T = 0;
+    ctx->cfg.guess = saved_guess;
+    ctx->sched_valid = false;
+    ctx->hist_valid = false;
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    if (rc) return rc == JFNK_EHIP ? fail(ctx, rc, "autotune: HIP copy failed") : rc;
+    ctx->tuned_T = best;
+    ctx->tuned_off.assign(p->col_offset, p->col_offset + p->ncols + 1);
+    if (chosen) *chosen = best;
+    return JFNK_OK;
 }
 
 int jfnk_set_model(jfnk_ctx* ctx, jfnk_net* net) {

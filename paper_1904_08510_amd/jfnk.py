@@ -121,6 +121,9 @@ def lib():
         L.jfnk_net_train_step.argtypes = [C.c_void_p, P, S, C.c_void_p, C.c_void_p, C.c_float, _dp,
                                           C.c_void_p]
         L.jfnk_net_train_step.restype = C.c_int
+        L.jfnk_autotune.argtypes = [C.c_void_p, C.POINTER(jfnk_problem), C.POINTER(jfnk_state), C.c_int32,
+                                    _ip, _dp, C.c_void_p]
+        L.jfnk_autotune.restype = C.c_int
         L.jfnk_set_model.argtypes = [C.c_void_p, C.c_void_p]
         L.jfnk_set_model.restype = C.c_int
         _LIB = L
@@ -132,7 +135,7 @@ EXPORTED_SYMBOLS = ("jfnk_config_default", "jfnk_create", "jfnk_step", "jfnk_des
                     "jfnk_block_solve", "jfnk_net_config_default", "jfnk_net_param_count",
                     "jfnk_net_create", "jfnk_net_destroy", "jfnk_net_last_error",
                     "jfnk_net_set_params", "jfnk_net_get_params", "jfnk_net_predict",
-                    "jfnk_net_grad", "jfnk_net_train_step", "jfnk_set_model")
+                    "jfnk_net_grad", "jfnk_net_train_step", "jfnk_set_model", "jfnk_autotune")
 
 
 class JfnkError(RuntimeError):
@@ -297,6 +300,18 @@ class Solver:
             return rc, st
         self._check(rc)
         return rc, st
+
+    def autotune(self, prob: DeviceProblem, ne, phi, ne_prev=None, phi_prev=None, steps: int = 3,
+                 stream=None):
+        """Pick the workgroup size per column for this layout by timing
+        `steps` steps per candidate; returns (chosen, {T: ms})."""
+        p = prob.cstruct()
+        s = self._state(ne, phi, ne_prev, phi_prev)
+        ch = C.c_int32()
+        t = np.zeros(4)
+        self._check(lib().jfnk_autotune(self.h, C.byref(p), C.byref(s), int(steps), C.byref(ch),
+                                        t.ctypes.data_as(_dp), _stream_ptr(stream)), (JFNK_OK,))
+        return ch.value, {T: float(v) for T, v in zip((64, 128, 256, 512), t) if v >= 0}
 
     def set_model(self, net: Optional["Net"]):
         """Attach a learned-guess network (None detaches)."""

@@ -304,3 +304,28 @@ def test_newton_cap_flags_columns(J):
     rc, st = solver.step(prob, ne, phi)
     assert rc == J.JFNK_NOT_CONVERGED
     assert st.status[0] == J.COL_MAX_NEWTON and st.newton_iters[0] == 1
+
+
+def test_autotune_keeps_state_and_roots(J):
+    """The tuner times workgroup sizes on copies (the caller's state is not
+    touched) and the tuned schedule reaches the same roots."""
+    cols = ragged_batch(seed=21)
+    packed = W.pack(cols)
+    res = {}
+    for tune in (False, True):
+        prob, ne, phi, _, _ = J.device_problem(packed)
+        solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64))
+        if tune:
+            before = (ne.clone(), phi.clone())
+            T, times = solver.autotune(prob, ne, phi, steps=2)
+            assert T in times and times[T] == min(times.values()) and T in (64, 128, 256, 512)
+            assert torch.equal(ne, before[0]) and torch.equal(phi, before[1])
+        pne = pph = None
+        for _ in range(3):
+            cur = (ne.clone(), phi.clone())
+            rc, _ = solver.step(prob, ne, phi, pne, pph)
+            assert rc == J.JFNK_OK
+            pne, pph = cur
+        res[tune] = (ne.cpu().numpy(), phi.cpu().numpy())
+    for a, b in zip(res[False], res[True]):
+        assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(a)
