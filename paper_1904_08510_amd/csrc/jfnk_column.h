@@ -173,6 +173,7 @@ struct Column {
     double ih, dth, epsh;            // 1/h, dt/h, (eps/e)/h
     double rR, gR, wR;               // right-wall face coefficients
     double sfn, sfp, sxn, sxp, isfn, isfp;
+    bool fac_reuse = false;          // setup found the previous step's factors usable
 
     __device__ void init(const ColDesc& d, const Work& w, const SolverParams& p, double* l) {
         cd = d; W = w; prm = p; lds = l;
@@ -349,6 +350,12 @@ struct Column {
         double* X20 = xb(2, 0); double* X21 = xb(2, 1);
         const bool extrap = prm.guess >= 1 && prm.has_prev;
         const bool learn = prm.guess == 2 && prm.has_learned && W.lmask[cd.index] != 0;
+        // the previous step's record of this column (read before it is rewritten)
+        const ColState* csp = W.cst + cd.index;
+        const bool may_reuse = prm.fac_reuse && csp->fac_valid;
+        const double o_rR = csp->rR, o_gR = csp->gR, o_wR = csp->wR;
+        const double o_sf[4] = {csp->fsfn, csp->fsfp, csp->fsxn, csp->fsxp};
+        bool changed = false;    // a Jacobian coefficient of this thread's cells differs
         // Natural-order pass: thread t takes cells c = k T + t, so the reads of
         // the caller's arrays are coalesced and independent; each cell is
         // written to its chunk-interleaved slot.  Loads of U cells go first.
@@ -398,6 +405,9 @@ struct Column {
                     g = Df / cd.h;
                     if (prm.has_u) w = uf[v] * cd.h / Df;
                 }
+                if (may_reuse)
+                    changed = changed || W.fa[s] != r || W.fg[s] != g || W.kd[s] != dt * kl[v] ||
+                              (prm.has_u && W.fw[s] != w);
                 W.fa[s] = r; W.fg[s] = g;
                 if (prm.has_u) W.fw[s] = w;
                 W.f[s] = ne[v] + dt * sr[v];
@@ -495,6 +505,17 @@ struct Column {
             if (!isnan(e.r2) && (isnan(best.r2) || e.rinf <= best.rinf)) {
                 best = e; *cur = 1; *guess_used = 1;
             }
+        }
+        // factors of the previous step stay usable (as a lagged preconditioner
+        // and for the error estimate) when the Jacobian coefficients are the
+        // same and the scalings moved by less than 1 %
+        {
+            double ch[1] = {changed ? 1.0 : 0.0};
+            wg_max<T, 1>(ch, scr);
+            const double nsf[4] = {sfn, sfp, sxn, sxp};
+            bool ok = may_reuse && ch[0] == 0.0 && rR == o_rR && gR == o_gR && wR == o_wR;
+            for (int k = 0; k < 4 && ok; ++k) ok = o_sf[k] > 0.0 && fabs(nsf[k] / o_sf[k] - 1.0) < 1e-2;
+            fac_reuse = ok;
         }
         if (learn) {
             Norms l = residual([&](int64_t s, double& a, double& b) { a = X20[s]; b = X21[s]; },
@@ -702,6 +723,11 @@ struct Column {
         }
         const Blk<double> Di = binv(Dr);
         red(k + 0)[0] = Di.a; red(k + 1)[0] = Di.b; red(k + 2)[0] = Di.c; red(k + 3)[0] = Di.d;
+        if (t == 0) {
+            ColState* cs = W.cst + cd.index;
+            cs->fac_valid = 1;
+            cs->fsfn = sfn; cs->fsfp = sfp; cs->fsxn = sxn; cs->fsxp = sxp;
+        }
         __syncthreads();
     }
 

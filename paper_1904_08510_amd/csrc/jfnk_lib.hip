@@ -89,6 +89,7 @@ __global__ __launch_bounds__(T) void k_phase(PhaseArgs a) {
         if (threadIdx.x == 0) {
             scal[0] = cur; scal[1] = g; scal[2] = n.rinf; scal[3] = n.r2; scal[4] = n.xn2;
             scal[5] = n.step; scal[6] = col.sfn; scal[7] = col.sfp; scal[8] = col.sxn; scal[9] = col.sxp;
+            scal[10] = col.fac_reuse ? 1.0 : 0.0;
         }
         break;
     }
@@ -167,7 +168,7 @@ __global__ __launch_bounds__(T) void k_phase(PhaseArgs a) {
             ColState* cs = a.W.cst + col.cd.index;
             cs->res_inf = a.o.rinf; cs->res2 = a.o.r2; cs->status = a.o.status;
             cs->newton = a.o.newton; cs->gmres = a.o.gmres; cs->backtracks = a.o.backtracks;
-            cs->guess = a.o.guess; cs->restarts = a.o.restarts;
+            cs->guess = a.o.guess; cs->restarts = a.o.restarts; cs->chords = a.o.chords;
         }
         break;
     }
@@ -239,6 +240,7 @@ struct jfnk_ctx {
     int32_t* d_lmask = nullptr;  // [max_cols]
     int32_t* h_lmask = nullptr;  // pinned
     bool learn_active = false;
+    bool fac_reuse_ok = false;   // the workspace holds factors of the current layout from the last step
     bool hist_valid = false;     // the per-column records below describe the current layout
     std::vector<int32_t> last_newton, last_status;
     // schedule autotuner: workgroup size measured best for a column layout
@@ -374,6 +376,7 @@ SolverParams make_params(const jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_
     s.has_prev = x->ne_prev != nullptr;
     s.has_learned = ctx->learn_active ? 1 : 0;
     s.has_u = p->u_face != nullptr;
+    s.fac_reuse = ctx->fac_reuse_ok ? 1 : 0;
     s.tol_f = ctx->cfg.tol_f;
     s.tol_x = ctx->cfg.tol_x;
     s.gamma = ctx->cfg.gamma;
@@ -435,11 +438,14 @@ struct HostExecT {
         return hs;
     }
 
+    bool lagged = false;
+    bool lagged_factors() const { return lagged; }
     Norms setup(int* cur, int* guess) {
         launch(PH_SETUP);
-        const double* s = fetch(10);
+        const double* s = fetch(11);
         *cur = (int)s[0]; *guess = (int)s[1];
         Norms n{s[2], s[3], s[4], s[5]};
+        lagged = s[10] == 1.0;
         sfn = s[6]; sfp = s[7];
         isfn = 1.0 / sfn; isfp = 1.0 / sfp;
         if (herr != hipSuccess) n.r2 = NAN;
@@ -646,6 +652,7 @@ int schedule_cached(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, h
     }
     ctx->sched_valid = false;
     ctx->hist_valid = false;
+    ctx->fac_reuse_ok = false;
     int rc = validate(ctx, p, x);
     if (rc) return rc;
     rc = upload_schedule(ctx, p->ncols, st);
@@ -699,6 +706,7 @@ int prepare_test(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, hipS
     ctx->sched_valid = false;
     ctx->hist_valid = false;
     ctx->learn_active = false;
+    ctx->fac_reuse_ok = false;
     int rc = validate(ctx, p, x);
     if (rc) return rc;
     rc = upload_schedule(ctx, p->ncols, st);
@@ -902,6 +910,7 @@ int jfnk_step(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, jfnk_stats* s
         }
     }
     ctx->hist_valid = true;
+    ctx->fac_reuse_ok = true;
     return nfail ? JFNK_NOT_CONVERGED : JFNK_OK;
 }
 
@@ -964,6 +973,7 @@ int jfnk_autotune(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, int
     ctx->cfg.guess = saved_guess;
     ctx->sched_valid = false;
     ctx->hist_valid = false;
+    ctx->fac_reuse_ok = false;
     (void)hipStreamSynchronize(st);
     (void)hipFree(buf);
     if (rc) return rc == JFNK_EHIP ? fail(ctx, rc, "autotune: HIP copy failed") : rc;

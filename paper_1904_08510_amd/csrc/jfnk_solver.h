@@ -67,7 +67,10 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
     int status = COL_MAX_NEWTON;
     double hcol[kMaxRestart + 2];
     double y[kMaxRestart];
-    int factored = -1;   // buffer whose state the current factorisation was built at
+    // buffer whose state the current factorisation was built at; 3: the
+    // previous step's factors (a lagged preconditioner: used for the error
+    // estimate and simplified-Newton steps, replaced before any GMRES solve)
+    int factored = ex.lagged_factors() ? 3 : -1;
     double est = -1.0;   // ||S_X^-1 P^-1 S_F^-1 F(X)||_inf of the current iterate (-1: unknown)
     int corr_at = -1;    // buffer whose correction -P^-1 S_F^-1 F sits in the last Krylov slot
     int chords = 0, chord_run = 0;
@@ -226,6 +229,7 @@ struct DevExec {
     __device__ double* Hl() { return col.lds + Lds<T>::kH; }
 
     __device__ Norms setup(int* cur, int* guess) { return col.setup(U, cur, guess); }
+    __device__ bool lagged_factors() const { return col.fac_reuse; }
     __device__ void factor(int cur) { col.factor(cur); }
 
     __device__ VecRef fref(int cur, double sc) {

@@ -45,7 +45,9 @@ struct ColState {
     double sfn, sfp, sxn, sxp;      // S_F and S_X block scalars
     double rR, gR, wR;              // right-wall face coefficients
     double res_inf, res2;
-    int32_t status, newton, gmres, backtracks, guess, restarts, chords, pad;
+    int32_t status, newton, gmres, backtracks, guess, restarts, chords;
+    int32_t fac_valid;              // the workspace holds factors of this column
+    double fsfn, fsfp, fsxn, fsxp;  // scalings those factors were built with
 };
 
 struct SolverParams {
@@ -57,6 +59,7 @@ struct SolverParams {
     int32_t has_prev;       // X^{n-1} supplied
     int32_t has_learned;    // learned candidate supplied
     int32_t has_u;          // advective face velocities supplied
+    int32_t fac_reuse;      // factors left by the previous step may serve this step
     double tol_f, tol_x, gamma, theta;
     double chord_tol;       // simplified-Newton steps while the error estimate is below this (0: off)
 };

@@ -329,3 +329,30 @@ def test_autotune_keeps_state_and_roots(J):
         res[tune] = (ne.cpu().numpy(), phi.cpu().numpy())
     for a, b in zip(res[False], res[True]):
         assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(a)
+
+
+def test_factor_reuse_follows_coefficient_changes(J):
+    """A context that keeps its factors between steps gives the roots a fresh
+    context gives, also when the mobility and diffusivity change between two
+    steps (the stale factors must then be replaced)."""
+    cols = ragged_batch(seed=23)
+    packed = W.pack(cols)
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    kept = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64))
+    pne = pph = None
+    for k in range(5):
+        if k == 3:
+            prob.mu.mul_(1.3)
+            prob.diff.mul_(1.3)
+        before = (ne.clone(), phi.clone())
+        fresh = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64))
+        fn, fp = ne.clone(), phi.clone()
+        rc, _ = fresh.step(prob, fn, fp, pne, pph)
+        assert rc == J.JFNK_OK
+        fresh.close()
+        rc, _ = kept.step(prob, ne, phi, pne, pph)
+        assert rc == J.JFNK_OK
+        for a, b in ((fn, ne), (fp, phi)):
+            a, b = a.cpu().numpy(), b.cpu().numpy()
+            assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(a), k
+        pne, pph = before
