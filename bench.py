@@ -30,31 +30,23 @@ EPISODE = 20
 HBM_PEAK_GBS = 8000.0
 
 
-def bytes_per_cell(newton, gmres, backtracks, has_prev, fb, chords=0):
-    """Algorithmic HBM bytes per cell of one column-step: each phase of the
-    method reads its operands from HBM and writes its results to HBM once
-    (fb = bytes per stored preconditioner value)."""
+def bytes_per_cell(has_prev, fb, counts):
+    """Algorithmic HBM bytes per cell of one column-step, from the phases the
+    step executed (jfnk_stats.phase_counts: factorisations, preconditioner
+    applies, residual evaluations, J.v products, CGS passes, direction
+    assemblies); each phase reads its operands from HBM and writes its
+    results once (fb = bytes per stored preconditioner value)."""
     R = 72.0                                   # residual: X + 5 coefficients -> F
-    fac = 40.0 + 20.0 * fb                     # X + 3 coefficients -> 20 factor values
-    app = 32.0 + 20.0 * fb                     # v + factors -> z
-    trial = 104.0                              # X + direction + 5 coefficients -> X_t, F_t
-    b = 112.0 + R                              # set-up: 7 inputs -> 5 coefficients + X; F(X^n)
+    setup = 112.0 + R                          # 7 inputs -> 5 coefficients + X; F(X^n)
     if has_prev:
-        b += 32.0 + R                          # extrapolated candidate and its residual
-    if newton == 0:
-        b += fac + app                         # stopping-test error estimate
-    else:
-        k = gmres / newton                     # GMRES iterations per Newton iteration
-        extra = max(gmres - newton, 0)         # iterations that needed the two CGS passes
-        # factor, k x (apply + J.v with fused dots), trial + its simplified correction
-        b += newton * (fac + k * (app + 104.0) + 16.0 * k * (k - 1) / 2.0 + trial + app)
-        b += extra * 2 * (32.0 + 16.0 * (k + 1) / 2.0)
-        b += backtracks * (trial + app)
-        if k > 1:
-            b += newton * 16.0 * (k + 1)       # direction from k Krylov vectors
-    b += chords * (trial + app)                # simplified-Newton steps: trial + its correction
-    b += 32.0                                  # result back to the caller
-    return b
+        setup += 32.0 + R                      # extrapolated candidate and its residual
+    per_phase = (40.0 + 20.0 * fb,             # factor: X + 3 coefficients -> 20 factor values
+                 32.0 + 20.0 * fb,             # apply: v + 20 factor values -> z
+                 104.0,                        # trial: X + direction + 5 coefficients -> X_t, F_t
+                 120.0,                        # J.v: X, z, F, 5 coefficients -> w, fused dots
+                 64.0,                         # CGS pass: w and the basis vectors it projects out
+                 64.0)                         # direction: sum of the Krylov vectors
+    return setup + sum(c * b for c, b in zip(counts, per_phase)) + 32.0   # + result to the caller
 
 
 def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None, stream=None, chord=None):
@@ -93,7 +85,8 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
             record.append(dict(rc=rc, ms=ms, has_prev=has_prev, newton=st.newton_iters.copy(),
                                gmres=st.gmres_iters.copy(), bt=st.backtracks.copy(),
                                res=st.res_scaled.copy(), status=st.status.copy(),
-                               guess=st.guess_used.copy(), chords=st.chord_steps.copy()))
+                               guess=st.guess_used.copy(), chords=st.chord_steps.copy(),
+                               counts=st.phase_counts.copy()))
         return rc
 
     for _ in range(args.warmup):
@@ -111,8 +104,7 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
         r["conv"] = int(np.sum(r["status"] == 0))
         r["res"] = float(r["res"].max())
         r["bytes"] = float(np.sum(ns * np.array([
-            bytes_per_cell(r["newton"][i], r["gmres"][i], r["bt"][i], r["has_prev"], fb, r["chords"][i])
-            for i in range(len(ns))])))
+            bytes_per_cell(r["has_prev"], fb, r["counts"][i][:6]) for i in range(len(ns))])))
     converged = sum(r["conv"] for r in rec)
     kern_ms = sum(r["ms"] for r in rec)
     kern_bytes = sum(r["bytes"] for r in rec)

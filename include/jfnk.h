@@ -149,6 +149,10 @@ typedef struct {
     int32_t *guess_used;         /* JFNK_GUESS_* actually taken */
     double *res_scaled;          /* final ||S_F^-1 F||_inf */
     int32_t *chord_steps;        /* simplified-Newton steps taken (see chord_tol) */
+    int32_t *phase_counts;       /* HOST [ncols][8]: factorisations, preconditioner
+                                    applies, residual evaluations after set-up
+                                    (trials), J.v products, CGS passes, direction
+                                    assemblies, 0, 0 (what the step executed) */
 } jfnk_stats;
 
 /* Fill cfg with the defaults: restart 30, 5 restarts, 50 Newton iterations,

@@ -169,6 +169,7 @@ __global__ __launch_bounds__(T) void k_phase(PhaseArgs a) {
             cs->res_inf = a.o.rinf; cs->res2 = a.o.r2; cs->status = a.o.status;
             cs->newton = a.o.newton; cs->gmres = a.o.gmres; cs->backtracks = a.o.backtracks;
             cs->guess = a.o.guess; cs->restarts = a.o.restarts; cs->chords = a.o.chords;
+            for (int i = 0; i < kWorkCounts; ++i) cs->work[i] = a.o.work[i];
         }
         break;
     }
@@ -687,6 +688,8 @@ int gather_stats(jfnk_ctx* ctx, int ncols, jfnk_stats* stt, hipStream_t st, int*
             if (stt->backtracks) stt->backtracks[c] = s.backtracks;
             if (stt->guess_used) stt->guess_used[c] = s.guess;
             if (stt->chord_steps) stt->chord_steps[c] = s.chords;
+            if (stt->phase_counts)
+                for (int i = 0; i < kWorkCounts; ++i) stt->phase_counts[(int64_t)c * kWorkCounts + i] = s.work[i];
             if (stt->res_scaled) stt->res_scaled[c] = s.res_inf;
         }
     }

@@ -15,6 +15,7 @@ namespace jfnk {
 
 struct ColOutcome {
     int status, newton, gmres, backtracks, guess, restarts, chords;
+    int work[kWorkCounts];
     double rinf, r2;
     int cur;
 };
@@ -74,6 +75,7 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
     double est = -1.0;   // ||S_X^-1 P^-1 S_F^-1 F(X)||_inf of the current iterate (-1: unknown)
     int corr_at = -1;    // buffer whose correction -P^-1 S_F^-1 F sits in the last Krylov slot
     int chords = 0, chord_run = 0;
+    int wk[kWorkCounts] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (;;) {
         if (isnan(nr.r2)) { status = COL_NONFINITE; break; }
         if (nr.rinf <= p.tol_f) {
@@ -81,8 +83,9 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
             // stopping test on the Newton correction: the error estimate
             // ||S_X^-1 (X - X*)||_inf ~ ||P^-1 S_F^-1 F(X)||_inf with the latest factorisation
             if (est < 0.0) {
-                if (factored < 0) { ex.factor(cur); factored = cur; }
+                if (factored < 0) { ex.factor(cur); factored = cur; ++wk[kWorkFactor]; }
                 est = ex.correction(cur).y;
+                ++wk[kWorkApply];
                 corr_at = cur;
             }
             if (est <= p.tol_x) { status = COL_CONVERGED; break; }
@@ -96,8 +99,9 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
         if (p.chord_tol > 0.0 && corr_at == cur && est > 0.0 && est <= p.chord_tol && chord_run < 4) {
             const int out = (cur + 1) % 3;
             const Norms tc = ex.chord_trial(cur, out);
+            ++wk[kWorkResidual];
             double e2 = INFINITY;
-            if (!isnan(tc.r2)) e2 = ex.correction(out).y;
+            if (!isnan(tc.r2)) { e2 = ex.correction(out).y; ++wk[kWorkApply]; }
             if (e2 <= (1.0 - p.theta) * est) {
                 cur = out;
                 nr = tc;
@@ -110,7 +114,7 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
             corr_at = -1;    // the slot now holds the rejected trial's correction
         }
         chord_run = 0;
-        if (factored != cur) ex.factor(cur);
+        if (factored != cur) { ex.factor(cur); ++wk[kWorkFactor]; }
         factored = cur;
         // GMRES on S_F^-1 J S_X d = -S_F^-1 F, right preconditioned, d_0 = 0
         const double beta0 = nr.r2;
@@ -124,6 +128,8 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
             } else {
                 // restart from the true linear residual -F~ - J dX
                 beta = ex.restart_residual(cur, xnorm);
+                ++wk[kWorkJv];
+                ++wk[kWorkLincomb];
                 if (!(beta > 0.0)) break;
                 ex.set_basis(0, ex.vslot(0, 1.0 / beta));
             }
@@ -132,11 +138,13 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
             bool conv = false;
             for (j = 0; j < p.m; ++j) {
                 const double zn2 = ex.apply(ex.basis(j), j).x;
+                ++wk[kWorkApply];
                 if (!(zn2 > 0.0)) { lucky = true; break; }
                 const double eps = lam_fd * (lam_fd + xnorm / sqrt(zn2));
                 // w = J Z_j into V slot j+1, with first-pass dots and ||w||^2
                 ex.jv(cur, j, eps, j + 1, hcol);
                 ++gtot;
+                ++wk[kWorkJv];
                 double hsq = 0.0;
                 for (int i = 0; i <= j; ++i) hsq += hcol[i] * hcol[i];
                 const double hn_est = sqrt(fmax(hcol[j + 1] - hsq, 0.0));
@@ -152,6 +160,7 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
                 ex.cgs(j + 1, j + 1, hcol, h2);        // w -= V h ; h2 = V^T w
                 double h3[kMaxRestart + 2];
                 ex.cgs(j + 1, j + 1, h2, h3);          // w -= V h2 ; ||w||^2
+                wk[kWorkCgs] += 2;
                 for (int i = 0; i <= j; ++i) hcol[i] += h2[i];
                 const double hn = sqrt(h3[j + 1]);
                 const double res = ex.gm_commit(j, hcol, hn);
@@ -163,6 +172,7 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
             if (k > 0) {
                 ex.gm_solve(k, y);
                 ex.direction(k, y, have_dx);
+                if (k > 1 || have_dx) ++wk[kWorkLincomb];
                 have_dx = true;
             }
             if (conv || lucky || cyc >= p.max_restarts) break;
@@ -181,9 +191,11 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
         for (;;) {
             outb = (bt == 0) ? ba : bb;
             tn = ex.trial(cur, outb, lam);
+            ++wk[kWorkResidual];
             if (bt == 0) { tfull = tn; dinf = tn.step; }
             if (!isnan(tn.r2)) {
                 const double e = ex.correction(outb).y;
+                ++wk[kWorkApply];
                 if (bt == 0) e_full = e;
                 if (e <= (1.0 - p.theta * lam) * dinf) { accepted = true; e_acc = e; break; }
             }
@@ -209,6 +221,7 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
     out.guess = guess;
     out.restarts = rtot;
     out.chords = chords;
+    for (int i = 0; i < kWorkCounts; ++i) out.work[i] = wk[i];
     out.rinf = nr.rinf;
     out.r2 = nr.r2;
     out.cur = cur;
@@ -363,6 +376,7 @@ struct DevExec {
             cs->status = o.status; cs->newton = o.newton; cs->gmres = o.gmres;
             cs->backtracks = o.backtracks; cs->guess = o.guess; cs->restarts = o.restarts;
             cs->chords = o.chords;
+            for (int i = 0; i < kWorkCounts; ++i) cs->work[i] = o.work[i];
         }
     }
 };

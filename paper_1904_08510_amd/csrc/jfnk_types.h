@@ -24,6 +24,9 @@ constexpr int kRedPerChunk = 96;     // doubles of reduced-system data per chunk
 constexpr int kFactorSlots = 20;     // FT values per cell stored by the factorisation
 constexpr int kTempSlots = 8;        // FP64 values per cell kept between factor sweeps
 
+// Per-column counts of the phases a step executed (order of jfnk_stats.phase_counts).
+enum { kWorkFactor = 0, kWorkApply, kWorkResidual, kWorkJv, kWorkCgs, kWorkLincomb, kWorkCounts = 8 };
+
 // Column status codes (also in include/jfnk.h).
 enum { COL_CONVERGED = 0, COL_MAX_NEWTON = 1, COL_NONFINITE = 2, COL_LINESEARCH = 3,
        COL_BAD_INPUT = 4 };
@@ -47,6 +50,7 @@ struct ColState {
     double res_inf, res2;
     int32_t status, newton, gmres, backtracks, guess, restarts, chords;
     int32_t fac_valid;              // the workspace holds factors of this column
+    int32_t work[kWorkCounts];      // phases executed this step (see kWork*)
     double fsfn, fsfp, fsxn, fsxp;  // scalings those factors were built with
 };
 

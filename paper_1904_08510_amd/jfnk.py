@@ -61,7 +61,8 @@ class jfnk_net_config(C.Structure):
 
 class jfnk_stats(C.Structure):
     _fields_ = [("status", _ip), ("newton_iters", _ip), ("gmres_iters", _ip),
-                ("backtracks", _ip), ("guess_used", _ip), ("res_scaled", _dp), ("chord_steps", _ip)]
+                ("backtracks", _ip), ("guess_used", _ip), ("res_scaled", _dp), ("chord_steps", _ip),
+                ("phase_counts", _ip)]
 
 
 _LIB = None
@@ -226,10 +227,12 @@ class Stats:
         self.guess_used = np.zeros(n, np.int32)
         self.res_scaled = np.zeros(n, np.float64)
         self.chord_steps = np.zeros(n, np.int32)
+        self.phase_counts = np.zeros((n, 8), np.int32)
 
     def cstruct(self) -> jfnk_stats:
         s = jfnk_stats()
-        for name in ("status", "newton_iters", "gmres_iters", "backtracks", "guess_used", "chord_steps"):
+        for name in ("status", "newton_iters", "gmres_iters", "backtracks", "guess_used", "chord_steps",
+                     "phase_counts"):
             setattr(s, name, getattr(self, name).ctypes.data_as(_ip))
         s.res_scaled = self.res_scaled.ctypes.data_as(_dp)
         return s
