@@ -266,6 +266,83 @@ struct Column {
         for (int j = jr; j < M; ++j) pad(sidx(t, j));
     }
 
+    // The same sweep over two states A and B at once (shared coefficient
+    // loads and one pass): faceA/faceB build the face records of each state,
+    // cell(s, c, nA, pA, nB, pB, LA, RA, LB, RB, own) sees both.
+    template <int U, class RecA, class RecB, class GetXA, class GetXB, class FaceA, class FaceB, class OwnFn,
+              class CellFn, class PadFn>
+    __device__ __forceinline__ void sweep2(GetXA gxa, GetXB gxb, FaceA fA, FaceB fB, OwnFn own, CellFn cell,
+                                           PadFn pad) {
+        using Own = decltype(own(int64_t(0)));
+        const int M = cd.M, n = cd.n;
+        const int c0 = t * M;
+        if (c0 >= n) {
+            for (int j = 0; j < M; ++j) pad(sidx(t, j));
+            return;
+        }
+        const int jr = (n - c0 < M) ? (n - c0) : M;
+        const int64_t s0 = sidx(t, 0);
+        double nA, pA, nB, pB, nAL, pAL, nBL, pBL, ihL;
+        gxa(s0, nA, pA);
+        gxb(s0, nB, pB);
+        if (c0 == 0) {
+            nAL = nBL = cd.nel; pAL = pBL = cd.phil; ihL = 2.0 * ih;
+        } else {
+            const int64_t sl = sidx(t - 1, M - 1);
+            gxa(sl, nAL, pAL);
+            gxb(sl, nBL, pBL);
+            ihL = ih;
+        }
+        const double fw0 = prm.has_u ? W.fw[s0] : 0.0;
+        RecA FLA = fA(W.fa[s0], W.fg[s0], fw0, ihL, nAL, pAL, nA, pA);
+        RecB FLB = fB(W.fa[s0], W.fg[s0], fw0, ihL, nBL, pBL, nB, pB);
+        for (int j0 = 0; j0 < jr; j0 += U) {
+            double an[U], ap[U], bn[U], bp[U], fa[U], fg[U], fw[U];
+            Own ow[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u;
+                an[u] = ap[u] = bn[u] = bp[u] = fa[u] = fg[u] = fw[u] = 0.0;
+                if (j < jr) {
+                    const int64_t s = sidx(t, j);
+                    ow[u] = own(s);
+                    if (c0 + j < n - 1) {
+                        const int64_t sn = (j + 1 < M) ? s + T : sidx(t + 1, 0);
+                        gxa(sn, an[u], ap[u]);
+                        gxb(sn, bn[u], bp[u]);
+                        fa[u] = W.fa[sn];
+                        fg[u] = W.fg[sn];
+                        if (prm.has_u) fw[u] = W.fw[sn];
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u;
+                if (j < jr) {
+                    const int c = c0 + j;
+                    const int64_t s = sidx(t, j);
+                    RecA FRA;
+                    RecB FRB;
+                    double nAR, pAR, nBR, pBR;
+                    if (c == n - 1) {
+                        nAR = nBR = cd.ner; pAR = pBR = cd.phir;
+                        FRA = fA(rR, gR, wR, 2.0 * ih, nA, pA, nAR, pAR);
+                        FRB = fB(rR, gR, wR, 2.0 * ih, nB, pB, nBR, pBR);
+                    } else {
+                        nAR = an[u]; pAR = ap[u]; nBR = bn[u]; pBR = bp[u];
+                        FRA = fA(fa[u], fg[u], fw[u], ih, nA, pA, nAR, pAR);
+                        FRB = fB(fa[u], fg[u], fw[u], ih, nB, pB, nBR, pBR);
+                    }
+                    cell(s, c, nA, pA, nB, pB, FLA, FRA, FLB, FRB, ow[u]);
+                    nA = nAR; pA = pAR; nB = nBR; pB = pBR;
+                    FLA = FRA; FLB = FRB;
+                }
+            }
+        }
+        for (int j = jr; j < M; ++j) pad(sidx(t, j));
+    }
+
     struct FluxRec { double gam, grd; };
 
     // electron flux and potential gradient of one face
@@ -432,51 +509,78 @@ struct Column {
         }
         __syncthreads();
 
-        // Sweep A: scalings from X^n (term magnitudes) + residual at X^n.
+        // Sweep A: scalings from X^n (term magnitudes) + residual at X^n, and
+        // in the same pass the residual of the extrapolated candidate.
         struct ScRec { double gam, grd, mag; };
-        double mx[5] = {0.0, 0.0, 0.0, 0.0, 0.0};     // te, tp, |n|, |q|, |phi|
-        double mr[2] = {0.0, 0.0};                    // max|Fe|, max|Fp|
-        double sm[4] = {0.0, 0.0, 0.0, 0.0};
+        // te, tp, |n|, |q|, |phi|, then max|Fe|, max|Fp| of X^n and of the extrapolation
+        double mx[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        // sums Fe^2, Fp^2, n^2, phi^2 of X^n, then of the extrapolation
+        double sm[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         {
             const double dt_h = dth, eps_h = epsh;
             double* F0 = Fb(0, 0); double* F1 = Fb(0, 1);
+            double* E0 = Fb(1, 0); double* E1 = Fb(1, 1);
             struct Own { double f, k, q; };
-            sweep<2, ScRec>(
-                [&](int64_t s, double& a, double& b) { a = X00[s]; b = X01[s]; },
-                [](double r, double g, double w, double ihf, double nA, double pA, double nB, double pB) {
-                    const double pe = w + r * (pB - pA);
-                    double bx, bmx;
-                    bernoulli_pair(pe, bx, bmx);
-                    ScRec o;
-                    o.gam = g * (bmx * nA - bx * nB);
-                    o.grd = (pB - pA) * ihf;
-                    o.mag = g * (bmx * fabs(nA) + bx * fabs(nB));
-                    return o;
-                },
-                [&](int64_t s) { return Own{W.f[s], W.kd[s], W.q[s]}; },
-                [&](int64_t s, int c, double nC, double pC, const ScRec& L, const ScRec& R, const Own& o) {
-                    const double fv = o.f, kv = o.k, qv = o.q;
-                    const double fe = -nC + fv - kv * nC - dt_h * (R.gam - L.gam);
-                    const double fp = -nC + qv + eps_h * (R.grd - L.grd);
-                    F0[s] = fe; F1[s] = fp;
-                    const double te = fabs(fv) + kv * fabs(nC) + dt_h * (L.mag + R.mag);
-                    const double tp = fabs(nC) + fabs(qv) + eps_h * (fabs(L.grd) + fabs(R.grd));
-                    mx[0] = fmax(mx[0], te);
-                    mx[1] = fmax(mx[1], tp);
-                    mx[2] = fmax(mx[2], fabs(nC));
-                    mx[3] = fmax(mx[3], fabs(qv));
-                    mx[4] = fmax(mx[4], fabs(pC));
-                    mr[0] = fmax(mr[0], fabs(fe));
-                    mr[1] = fmax(mr[1], fabs(fp));
-                    sm[0] += fe * fe; sm[1] += fp * fp;
-                    sm[2] += nC * nC; sm[3] += pC * pC;
-                },
-                [&](int64_t s) { F0[s] = 0.0; F1[s] = 0.0; });
+            const auto scface = [](double r, double g, double w, double ihf, double nA, double pA, double nB,
+                                   double pB) {
+                const double pe = w + r * (pB - pA);
+                double bx, bmx;
+                bernoulli_pair(pe, bx, bmx);
+                ScRec o;
+                o.gam = g * (bmx * nA - bx * nB);
+                o.grd = (pB - pA) * ihf;
+                o.mag = g * (bmx * fabs(nA) + bx * fabs(nB));
+                return o;
+            };
+            const auto own = [&](int64_t s) { return Own{W.f[s], W.kd[s], W.q[s]}; };
+            const auto cellA = [&](int64_t s, double nC, double pC, const ScRec& L, const ScRec& R, const Own& o) {
+                const double fv = o.f, kv = o.k, qv = o.q;
+                const double fe = -nC + fv - kv * nC - dt_h * (R.gam - L.gam);
+                const double fp = -nC + qv + eps_h * (R.grd - L.grd);
+                F0[s] = fe; F1[s] = fp;
+                const double te = fabs(fv) + kv * fabs(nC) + dt_h * (L.mag + R.mag);
+                const double tp = fabs(nC) + fabs(qv) + eps_h * (fabs(L.grd) + fabs(R.grd));
+                mx[0] = fmax(mx[0], te);
+                mx[1] = fmax(mx[1], tp);
+                mx[2] = fmax(mx[2], fabs(nC));
+                mx[3] = fmax(mx[3], fabs(qv));
+                mx[4] = fmax(mx[4], fabs(pC));
+                mx[5] = fmax(mx[5], fabs(fe));
+                mx[6] = fmax(mx[6], fabs(fp));
+                sm[0] += fe * fe; sm[1] += fp * fp;
+                sm[2] += nC * nC; sm[3] += pC * pC;
+            };
+            if (extrap) {
+                sweep2<2, ScRec, FluxRec>(
+                    [&](int64_t s, double& a, double& b) { a = X00[s]; b = X01[s]; },
+                    [&](int64_t s, double& a, double& b) { a = X10[s]; b = X11[s]; },
+                    scface, FluxFace{}, own,
+                    [&](int64_t s, int c, double nC, double pC, double nE, double pE, const ScRec& L,
+                        const ScRec& R, const FluxRec& LE, const FluxRec& RE, const Own& o) {
+                        cellA(s, nC, pC, L, R, o);
+                        const double fe = -nE + o.f - o.k * nE - dt_h * (RE.gam - LE.gam);
+                        const double fp = -nE + o.q + eps_h * (RE.grd - LE.grd);
+                        E0[s] = fe; E1[s] = fp;
+                        mx[7] = fmax(mx[7], fabs(fe));
+                        mx[8] = fmax(mx[8], fabs(fp));
+                        sm[4] += fe * fe; sm[5] += fp * fp;
+                        sm[6] += nE * nE; sm[7] += pE * pE;
+                    },
+                    [&](int64_t s) { F0[s] = 0.0; F1[s] = 0.0; E0[s] = 0.0; E1[s] = 0.0; });
+            } else {
+                sweep<2, ScRec>(
+                    [&](int64_t s, double& a, double& b) { a = X00[s]; b = X01[s]; },
+                    scface, own,
+                    [&](int64_t s, int c, double nC, double pC, const ScRec& L, const ScRec& R, const Own& o) {
+                        cellA(s, nC, pC, L, R, o);
+                    },
+                    [&](int64_t s) { F0[s] = 0.0; F1[s] = 0.0; });
+            }
         }
         double* scr = lds + Lds<T>::kScr;
-        wg_max<T, 5>(mx, scr);
-        wg_max<T, 2>(mr, scr);
-        wg_sum<T, 4>(sm, scr);
+        wg_max<T, 9>(mx, scr);
+        wg_sum<T, 8>(sm, scr);
+        const double mr[2] = {mx[5], mx[6]};
         sfn = mx[0];
         sfp = mx[1];
         sxn = fmax(1.0, fmax(mx[2], mx[3]));
@@ -496,8 +600,11 @@ struct Column {
         *guess_used = 0;
         const VecRef none{nullptr, nullptr, 0.0, 0.0};
         if (extrap) {
-            Norms e = residual([&](int64_t s, double& a, double& b) { a = X10[s]; b = X11[s]; },
-                               Fb(1, 0), Fb(1, 1), nullptr, nullptr, none, 0.0);
+            Norms e;
+            e.rinf = fmax(mx[7] * isfn, mx[8] * isfp);
+            e.r2 = sqrt(sm[4] * isfn * isfn + sm[5] * isfp * isfp);
+            e.xn2 = sm[6] / (sxn * sxn) + sm[7] / (sxp * sxp);
+            if (isnan(sm[4]) || isnan(sm[5])) e.r2 = NAN;
             e.step = INFINITY;
             // X^n or the extrapolation, whichever has the smaller scaled
             // residual (ties to the extrapolation): after a sharp transient the
