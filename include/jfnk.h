@@ -66,6 +66,13 @@ enum { JFNK_BC_DIRICHLET = 0, JFNK_BC_ZERO_FLUX = 1 };
 enum { JFNK_GUESS_PREV = 0, JFNK_GUESS_EXTRAP = 1, JFNK_GUESS_LEARNED = 2 };
 /* storage and arithmetic of the per-cell preconditioner factors */
 enum { JFNK_PREC_FP64 = 0, JFNK_PREC_FP32 = 1 };
+/* preconditioner.  BLOCK: the exact factorisation of the 2x2 block
+   tridiagonal Jacobian (P = J; eq:prec with the true Schur complement).
+   SCHUR: the paper's eq:prec_recast, the block factorisation with the Schur
+   complement replaced by S~ = L + I_e dt D_r (Section 3.2), each block solved
+   exactly (the tridiagonal solves the paper uses in 1D instead of multigrid):
+   three solves per apply. */
+enum { JFNK_PRECK_BLOCK = 0, JFNK_PRECK_SCHUR = 1 };
 /* PLAIN: one column at a time, every phase a launch, control on the host.
    BATCHED: one launch per step solves all columns, control on the GPU. */
 enum { JFNK_SCHED_PLAIN = 0, JFNK_SCHED_BATCHED = 1 };
@@ -106,6 +113,7 @@ typedef struct {
     int32_t guess;               /* JFNK_GUESS_* */
     int32_t schedule;            /* JFNK_SCHED_* */
     int32_t threads_override;    /* 0: autotuned; else workgroup size per column */
+    int32_t prec_kind;           /* JFNK_PRECK_* */
 } jfnk_config;
 
 /* One step's problem: ncols columns packed back to back. */

@@ -433,20 +433,38 @@ struct Column {
         const double o_rR = csp->rR, o_gR = csp->gR, o_wR = csp->wR;
         const double o_sf[4] = {csp->fsfn, csp->fsfp, csp->fsxn, csp->fsxp};
         bool changed = false;    // a Jacobian coefficient of this thread's cells differs
-        // Natural-order pass: thread t takes cells c = k T + t, so the reads of
-        // the caller's arrays are coalesced and independent; each cell is
-        // written to its chunk-interleaved slot.  Loads of U cells go first.
+        // Copy pass in tiles of 8 chunk owners x 8 rows per wave: lane l takes
+        // owner 8g + l/8 and row 8b + l%8 of tile (b, g), so 8 lanes read 8
+        // consecutive cells of the caller's arrays and 8 lanes write 8
+        // consecutive chunk-interleaved slots (64-byte pieces on both sides).
+        // Loads of UC tiles go first.
         constexpr int UC = 2;
         (void)c0;
-        for (int k0 = 0; k0 < M; k0 += UC) {
+        const int lane = t & 63, wv = t >> 6;
+        const int Mr = (M + 7) & ~7;             // rows rounded up to whole tiles
+        auto tile_cell = [&](int i, int& tt, int& j) {
+            const int k = i * (T / 64) + wv;     // tile index
+            tt = (k % (T / 8)) * 8 + (lane >> 3);
+            j = (k / (T / 8)) * 8 + (lane & 7);
+        };
+        for (int k0 = 0; k0 < Mr; k0 += UC) {
             double mu[UC], D[UC], mum[UC], Dm[UC], ne[UC], ph[UC], sr[UC], kl[UC], qq[UC];
             double pn[UC], pp[UC], ln[UC], lp[UC], uf[UC];
+            double ofa[UC], ofg[UC], ofw[UC], okd[UC];   // this column's coefficients of the last step
 #pragma unroll
             for (int v = 0; v < UC; ++v) {
-                const int c = (k0 + v) * T + t;
+                int tt, j;
+                tile_cell(k0 + v, tt, j);
+                const int c = tt * M + j;
                 mu[v] = D[v] = mum[v] = Dm[v] = ne[v] = ph[v] = sr[v] = kl[v] = qq[v] = 0.0;
                 pn[v] = pp[v] = ln[v] = lp[v] = uf[v] = 0.0;
-                if (k0 + v < M && c < n) {
+                ofa[v] = ofg[v] = ofw[v] = okd[v] = 0.0;
+                if (may_reuse && k0 + v < Mr && j < M && c < n) {
+                    const int64_t s = cd.ws + (int64_t)j * T + tt;
+                    ofa[v] = W.fa[s]; ofg[v] = W.fg[s]; okd[v] = W.kd[s];
+                    if (prm.has_u) ofw[v] = W.fw[s];
+                }
+                if (k0 + v < Mr && j < M && c < n) {
                     const int64_t u = cd.uoff + c;
                     mu[v] = U.mu[u]; D[v] = U.diff[u];
                     if (c > 0) { mum[v] = U.mu[u - 1]; Dm[v] = U.diff[u - 1]; }
@@ -460,9 +478,11 @@ struct Column {
             }
 #pragma unroll
             for (int v = 0; v < UC; ++v) {
-                const int c = (k0 + v) * T + t;
-                if (k0 + v >= M) continue;
-                const int64_t s = cd.ws + (int64_t)(c % M) * T + c / M;
+                int tt, j;
+                tile_cell(k0 + v, tt, j);
+                const int c = tt * M + j;
+                if (k0 + v >= Mr || j >= M) continue;
+                const int64_t s = cd.ws + (int64_t)j * T + tt;
                 if (c >= n) {
                     W.fa[s] = 0.0; W.fg[s] = 0.0;
                     if (prm.has_u) W.fw[s] = 0.0;
@@ -483,8 +503,8 @@ struct Column {
                     if (prm.has_u) w = uf[v] * cd.h / Df;
                 }
                 if (may_reuse)
-                    changed = changed || W.fa[s] != r || W.fg[s] != g || W.kd[s] != dt * kl[v] ||
-                              (prm.has_u && W.fw[s] != w);
+                    changed = changed || ofa[v] != r || ofg[v] != g || okd[v] != dt * kl[v] ||
+                              (prm.has_u && ofw[v] != w);
                 W.fa[s] = r; W.fg[s] = g;
                 if (prm.has_u) W.fw[s] = w;
                 W.f[s] = ne[v] + dt * sr[v];
@@ -742,10 +762,25 @@ struct Column {
                 } else {
                     C = bzero();
                 }
+                if (prm.prec_kind == 1) {
+                    // eq:prec_recast: keep the couplings dt D_r (row of F_e in phi)
+                    // and I_e (F_phi in n, diagonal) for the apply, and factor
+                    // diag(dt D_f - I, S~) with S~ = L + I_e dt D_r, the Schur
+                    // complement with (dt D_f - I)^-1 replaced by -I (scaled units:
+                    // -(s_Fn / s_Xn) I)
+                    fac(20)[s] = (FT)A.b; fac(21)[s] = (FT)B.b; fac(22)[s] = (FT)C.b; fac(23)[s] = (FT)B.c;
+                    const double kap = B.c / s_en;
+                    A = Blk<double>{A.a, 0.0, 0.0, A.d + kap * A.b};
+                    C = Blk<double>{C.a, 0.0, 0.0, C.d + kap * C.b};
+                    B = Blk<double>{B.a, 0.0, 0.0, B.d + kap * B.b};
+                }
                 rowproc(j, s, A, B, C);
             },
             [&](int64_t s) {
                 const int j = (int)((s - cd.ws) / T);
+                if (prm.prec_kind == 1) {
+                    fac(20)[s] = FT(0); fac(21)[s] = FT(0); fac(22)[s] = FT(0); fac(23)[s] = FT(0);
+                }
                 rowproc(j, s, bzero(), beye(), bzero());
             });
 
@@ -839,10 +874,62 @@ struct Column {
     }
 
     // ------------------------------------------------------------------
-    // Preconditioner apply z = P^-1 v (chunk sweeps in FT, reduced system
-    // in FP64).  Returns (||z||_2^2, ||z||_inf).  v and z must not alias.
+    // Preconditioner apply z = P^-1 v.  Returns (||z||_2^2, ||z||_inf).
+    // v and z must not alias.
     // ------------------------------------------------------------------
     __device__ Vec2<double> apply(const VecRef& v, double* z0, double* z1) {
+        return prm.prec_kind == 1 ? apply_schur(v, z0, z1) : block_apply(v, z0, z1);
+    }
+
+    // Approximate Schur preconditioner, eq:prec_recast applied right to left:
+    //   z_e' = (dt D_f - I)^-1 v_e,  z_phi = S~^-1 (v_phi - I_e z_e'),
+    //   z_e  = z_e' - (dt D_f - I)^-1 dt D_r z_phi,
+    // three solves with the factors of diag(dt D_f - I, S~) (each a pass of
+    // the block solver with one component of the right-hand side zero).
+    __device__ Vec2<double> apply_schur(const VecRef& v, double* z0, double* z1) {
+        const int M = cd.M, n = cd.n;
+        double* Y0 = W.sch;
+        double* Y1 = W.sch + W.P;
+        double* Y2 = W.sch + 2 * W.P;
+        double* Y3 = W.sch + 3 * W.P;
+        block_apply(VecRef{v.p0, v.p1, v.s0, 0.0}, Y0, Y1);            // Y0 = z_e'
+        for (int j = 0; j < M; ++j) {
+            const int64_t s = sidx(t, j);
+            Y2[s] = v.p1[s] * v.s1 - (double)fac(23)[s] * Y0[s];        // v_phi - I_e z_e'
+        }
+        block_apply(VecRef{Y2, Y2, 0.0, 1.0}, Y3, z1);                  // z1 = z_phi
+        // dt D_r z_phi (tridiagonal; neighbours across chunks are visible after
+        // the solve's closing barriers)
+        for (int j = 0; j < M; ++j) {
+            const int64_t s = sidx(t, j);
+            const int c = t * M + j;
+            double w = 0.0;
+            if (c < n) {
+                const double zl = c > 0 ? z1[sidx((c - 1) / M, (c - 1) % M)] : 0.0;
+                const double zr = c < n - 1 ? z1[sidx((c + 1) / M, (c + 1) % M)] : 0.0;
+                w = (double)fac(20)[s] * zl + (double)fac(21)[s] * z1[s] + (double)fac(22)[s] * zr;
+            }
+            Y2[s] = w;
+        }
+        block_apply(VecRef{Y2, Y2, 1.0, 0.0}, Y3, Y1);                  // Y3 = (dt D_f - I)^-1 dt D_r z_phi
+        double zz = 0.0, zm = 0.0;
+        for (int j = 0; j < M; ++j) {
+            const int64_t s = sidx(t, j);
+            const double ze = Y0[s] - Y3[s];
+            z0[s] = ze;
+            zz += ze * ze + z1[s] * z1[s];
+            zm = fmax(zm, fmax(fabs(ze), fabs(z1[s])));
+        }
+        double sm[1] = {zz};
+        double mm[1] = {zm};
+        wg_sum<T, 1>(sm, lds + Lds<T>::kScr);
+        wg_max<T, 1>(mm, lds + Lds<T>::kScr);
+        return Vec2<double>{sm[0], mm[0]};
+    }
+
+    // Block solve with the stored factors (chunk sweeps in FT, reduced
+    // system in FP64).  Returns (||z||_2^2, ||z||_inf).
+    __device__ Vec2<double> block_apply(const VecRef& v, double* z0, double* z1) {
         constexpr int U = 4;
         const int M = cd.M;
         FT* D0 = tmpv(0);

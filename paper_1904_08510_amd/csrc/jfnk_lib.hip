@@ -279,8 +279,8 @@ int choose_T(const jfnk_config& cfg, int nmax) {
 
 int64_t work_doubles_per_cell(int m) {
     // fa fg fw f kd q (6) x (6) F (6) V (2(m+1)) Z (2m) dX (2) ftmp (8)
-    // fac (20, sized for FP64) tmp (2, sized for FP64)
-    return 6 + 6 + 6 + 2 * (m + 1) + 2 * m + 2 + kTempSlots + kFactorSlots + 2;
+    // fac (24, sized for FP64) tmp (2, sized for FP64) approximate-Schur temporaries (4)
+    return 6 + 6 + 6 + 2 * (m + 1) + 2 * m + 2 + kTempSlots + kFactorSlots + 2 + 4;
 }
 
 void carve(jfnk_ctx* c) {
@@ -299,6 +299,7 @@ void carve(jfnk_ctx* c) {
     W.ftmp = take((int64_t)kTempSlots * P);
     W.fac = (void*)take((int64_t)kFactorSlots * P);
     W.tmp = (void*)take(2 * P);
+    W.sch = take(4 * P);
     W.red = take(c->capRed);
     W.cols = (ColDesc*)take((c->cfg.max_cols * (int64_t)sizeof(ColDesc) + 7) / 8);
     W.cst = (ColState*)take((c->cfg.max_cols * (int64_t)sizeof(ColState) + 7) / 8);
@@ -378,6 +379,7 @@ SolverParams make_params(const jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_
     s.has_learned = ctx->learn_active ? 1 : 0;
     s.has_u = p->u_face != nullptr;
     s.fac_reuse = ctx->fac_reuse_ok ? 1 : 0;
+    s.prec_kind = ctx->cfg.prec_kind;
     s.tol_f = ctx->cfg.tol_f;
     s.tol_x = ctx->cfg.tol_x;
     s.gamma = ctx->cfg.gamma;
@@ -798,6 +800,7 @@ void jfnk_config_default(jfnk_config* cfg) {
     cfg->guess = JFNK_GUESS_EXTRAP;
     cfg->schedule = JFNK_SCHED_BATCHED;
     cfg->threads_override = 0;
+    cfg->prec_kind = JFNK_PRECK_BLOCK;
 }
 
 int jfnk_create(const jfnk_config* cfg, jfnk_ctx** out) {
@@ -810,6 +813,7 @@ int jfnk_create(const jfnk_config* cfg, jfnk_ctx** out) {
         !(cfg->gamma > 0.0 && cfg->gamma < 1.0) || !(cfg->ls_theta >= 0.0 && cfg->ls_theta < 1.0) ||
         !(cfg->chord_tol >= 0.0 && cfg->chord_tol < 1.0) ||
         (cfg->prec_precision != JFNK_PREC_FP64 && cfg->prec_precision != JFNK_PREC_FP32) ||
+        (cfg->prec_kind != JFNK_PRECK_BLOCK && cfg->prec_kind != JFNK_PRECK_SCHUR) ||
         cfg->guess < 0 || cfg->guess > 2 ||
         (cfg->schedule != JFNK_SCHED_PLAIN && cfg->schedule != JFNK_SCHED_BATCHED))
         return JFNK_EINVAL;

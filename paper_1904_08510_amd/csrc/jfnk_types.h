@@ -21,7 +21,9 @@ namespace jfnk {
 
 constexpr int kMaxRestart = 30;      // largest GMRES restart length supported
 constexpr int kRedPerChunk = 96;     // doubles of reduced-system data per chunk (T <= 1024)
-constexpr int kFactorSlots = 20;     // FT values per cell stored by the factorisation
+constexpr int kFactorSlots = 24;     // FT values per cell stored by the factorisation
+                                     // (20 block factors + 4 coupling entries of the
+                                     // approximate-Schur preconditioner)
 constexpr int kTempSlots = 8;        // FP64 values per cell kept between factor sweeps
 
 // Per-column counts of the phases a step executed (order of jfnk_stats.phase_counts).
@@ -64,6 +66,7 @@ struct SolverParams {
     int32_t has_learned;    // learned candidate supplied
     int32_t has_u;          // advective face velocities supplied
     int32_t fac_reuse;      // factors left by the previous step may serve this step
+    int32_t prec_kind;      // 0 exact block factorisation, 1 approximate Schur (eq:prec_recast)
     double tol_f, tol_x, gamma, theta;
     double chord_tol;       // simplified-Newton steps while the error estimate is below this (0: off)
 };
@@ -90,6 +93,7 @@ struct Work {
     void *tmp;                       // 2 x P values of the factor type (apply)
     double *ftmp;                    // kTempSlots x P doubles (factorisation)
     double *red;                     // per-chunk reduced-system data
+    double *sch;                     // 4 x P doubles: approximate-Schur apply temporaries
     ColDesc *cols;
     ColState *cst;
     double *scal;                    // per-column scalar exchange (host-driven mode)

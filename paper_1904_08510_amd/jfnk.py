@@ -21,6 +21,7 @@ JFNK_EINVAL, JFNK_ENOMEM, JFNK_EHIP, JFNK_ECAPACITY, JFNK_EMODEL = -1, -2, -3, -
 BC_DIRICHLET, BC_ZERO_FLUX = 0, 1
 GUESS_PREV, GUESS_EXTRAP, GUESS_LEARNED = 0, 1, 2
 PREC_FP64, PREC_FP32 = 0, 1
+PRECK_BLOCK, PRECK_SCHUR = 0, 1
 SCHED_PLAIN, SCHED_BATCHED = 0, 1
 COL_CONVERGED, COL_MAX_NEWTON, COL_NONFINITE, COL_LINESEARCH, COL_BAD_INPUT = 0, 1, 2, 3, 4
 
@@ -36,7 +37,7 @@ class jfnk_config(C.Structure):
                 ("max_backtracks", C.c_int32), ("tol_f", C.c_double), ("tol_x", C.c_double),
                 ("gamma", C.c_double), ("ls_theta", C.c_double), ("chord_tol", C.c_double),
                 ("prec_precision", C.c_int32), ("guess", C.c_int32), ("schedule", C.c_int32),
-                ("threads_override", C.c_int32)]
+                ("threads_override", C.c_int32), ("prec_kind", C.c_int32)]
 
 
 class jfnk_problem(C.Structure):
