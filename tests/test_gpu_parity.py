@@ -417,3 +417,72 @@ def test_schur_preconditioner_reaches_the_same_roots(J, prec):
     assert np.linalg.norm(a0 - b0) <= tol * np.linalg.norm(a0)
     assert np.linalg.norm(a1 - b1) <= tol * np.linalg.norm(a1)
     print(f"GMRES iterations over 3 steps, {prec}: block {ga}, approximate Schur {gb}")
+
+
+def test_degenerate_columns(J):
+    """Degenerate inputs: a column with no charge, source or loss starts at
+    its exact root (n = 0, phi linear between the electrodes) and must stay
+    there without a Newton iteration; a 3-cell column and a column with both
+    electrodes at 0 V converge beside it."""
+    empty = W.flame_column(700, 250.0, a_ion=0.0, src_peak=0.0, krec=0.0)
+    tiny = W.flame_column(3, 10.0)
+    grounded = W.flame_column(900, 0.0, a_ion=5e15)
+    cols = [empty, tiny, grounded]
+    packed = W.pack(cols)
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64))
+    rc, st = solver.step(prob, ne, phi)
+    assert rc == J.JFNK_OK, st.status
+    assert st.newton_iters[0] == 0 and st.chord_steps[0] == 0
+    got_n = ne.cpu().numpy()[:700]
+    got_p = phi.cpu().numpy()[:700]
+    assert np.all(got_n == 0.0)
+    np.testing.assert_allclose(got_p, empty.phi, rtol=0, atol=1e-12 * 250.0)
+    assert np.all(st.res_scaled <= 1e-10)
+
+
+def test_mirror_symmetry_of_a_symmetric_column(J):
+    """A column whose coefficients are mirror symmetric (ion and source peaks
+    at the centre, uniform 1000 K gas) with both electrodes grounded has a
+    mirror-symmetric root; so has the GPU's (4096 cells, 3 steps)."""
+    col = W.flame_column(4096, 0.0, a_ion=3e16, x_f=0.01)
+    col.temp = np.full(col.n, 1000.0)
+    col.mu = 0.4 * col.temp / 300.0
+    col.diff = col.mu * W.K_BOLTZMANN * col.temp / W.E_CHARGE
+    packed = W.pack([col])
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64))
+    pne = pph = None
+    for _ in range(3):
+        cur = (ne.clone(), phi.clone())
+        rc, _ = solver.step(prob, ne, phi, pne, pph)
+        assert rc == J.JFNK_OK
+        pne, pph = cur
+    n = ne.cpu().numpy()
+    p = phi.cpu().numpy()
+    assert np.linalg.norm(n - n[::-1]) <= 1e-9 * np.linalg.norm(n)
+    assert np.linalg.norm(p - p[::-1]) <= 1e-9 * np.linalg.norm(p)
+
+
+def test_zero_flux_walls_conserve_electrons(J):
+    """With zero-flux walls, no source and no loss the electron count is
+    conserved by every step (flux telescoping), for uneven columns of up to
+    8192 cells."""
+    rng = np.random.default_rng(31)
+    cols = []
+    for n in (777, 2048, 8192):
+        c = W.flame_column(n, float(rng.uniform(-500, 500)), a_ion=float(10 ** rng.uniform(15, 16.5)),
+                           src_peak=0.0, krec=0.0)
+        c.bc_left = c.bc_right = W.BC_ZERO_FLUX
+        cols.append(c)
+    packed = W.pack(cols)
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64))
+    before = ne.cpu().numpy().copy()
+    for _ in range(3):
+        rc, _ = solver.step(prob, ne, phi)
+        assert rc == J.JFNK_OK
+    after = ne.cpu().numpy()
+    for i in range(len(cols)):
+        sl = slice(packed.col_offset[i], packed.col_offset[i + 1])
+        assert abs(after[sl].sum() - before[sl].sum()) <= 1e-9 * before[sl].sum(), i
