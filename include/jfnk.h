@@ -204,8 +204,17 @@ int jfnk_autotune(jfnk_ctx *ctx, const jfnk_problem *p, const jfnk_state *x, int
    step's stream right before and after the solve launches; for the plain
    schedule the span of all its phase launches; the learned guess, evaluated
    before, is not included) and the number of launches it spans (-1:
-   host-driven).  Returns JFNK_EINVAL on NULL arguments. */
+   host-driven; 3 for the batched schedule: gather, solve, write-back).
+   Returns JFNK_EINVAL on NULL arguments. */
 int jfnk_last_timing(const jfnk_ctx *ctx, double *solve_ms, int32_t *launches);
+
+/* Batched schedule: device times (ms, HIP events on the step's stream) of
+   the last jfnk_step's three launches: ms3[0] the gather (caller arrays ->
+   workspace coefficients and start states), ms3[1] the solve (Algorithm 2
+   per column), ms3[2] the write-back of X^{n+1}.  -1 each when the last step
+   ran the plain schedule or has not been timed.  ms3: HOST [3].  Returns
+   JFNK_EINVAL on NULL arguments. */
+int jfnk_last_kernel_times(const jfnk_ctx *ctx, double *ms3);
 
 /* ---- learned Newton initial guess --------------------------------------
  *

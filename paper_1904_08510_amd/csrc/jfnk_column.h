@@ -417,9 +417,27 @@ struct Column {
     // guess candidates and the choice between them.  Returns the norms of
     // the chosen guess; *cur receives its buffer.
     // ------------------------------------------------------------------
-    __device__ Norms setup(const UserArrays& U, int* cur, int* guess_used) {
+    // ------------------------------------------------------------------
+    // Gather pass: the caller's arrays (natural layout) -> the face and cell
+    // coefficients and the start states X^n, the extrapolation 2 X^n - X^{n-1}
+    // and the learned candidate (chunk-interleaved layout).  Tiles of 8 chunk
+    // owners x 8 rows, one per wave: lane l takes owner 8g + l/8 and row
+    // 8b + l%8 of tile (b, g), so 8 lanes read 8 consecutive cells of the
+    // caller's arrays and 8 lanes write 8 consecutive chunk-interleaved slots
+    // (64-byte pieces on both sides).  Wave w of nw takes tiles w, w + nw, ...
+    // (the loads of UC tiles go first).  Tiles run through the row groups of
+    // 8 owners first, so the UC * nw tiles a workgroup has in flight cover
+    // whole chunks of adjacent owners: one contiguous range of the caller's
+    // arrays, and whole (or half) cache lines of the interleaved rows.  Returns whether a face coefficient of
+    // the cells this thread wrote differs from the one the stored factors were
+    // built with; the thread of the last cell writes the right-wall face
+    // coefficients to wall[0..2].
+    // ------------------------------------------------------------------
+    // tiles of 8 x 8 cells of this column's layout
+    __device__ __forceinline__ int ntiles() const { return ((cd.M + 7) >> 3) * (T / 8); }
+
+    __device__ bool gather(const UserArrays& U, int kb, int ke, int w, int nw, double* wall) {
         const int M = cd.M, n = cd.n;
-        const int c0 = t * M;
         const double dt = cd.dt, hb = 0.5 * cd.h;
         const int64_t fo = cd.uoff + cd.index;   // faces of column: n + 1 per column
         double* X00 = xb(0, 0); double* X01 = xb(0, 1);
@@ -427,44 +445,34 @@ struct Column {
         double* X20 = xb(2, 0); double* X21 = xb(2, 1);
         const bool extrap = prm.guess >= 1 && prm.has_prev;
         const bool learn = prm.guess == 2 && prm.has_learned && W.lmask[cd.index] != 0;
-        // the previous step's record of this column (read before it is rewritten)
-        const ColState* csp = W.cst + cd.index;
-        const bool may_reuse = prm.fac_reuse && csp->fac_valid;
-        const double o_rR = csp->rR, o_gR = csp->gR, o_wR = csp->wR;
-        const double o_sf[4] = {csp->fsfn, csp->fsfp, csp->fsxn, csp->fsxp};
-        bool changed = false;    // a Jacobian coefficient of this thread's cells differs
-        // Copy pass in tiles of 8 chunk owners x 8 rows per wave: lane l takes
-        // owner 8g + l/8 and row 8b + l%8 of tile (b, g), so 8 lanes read 8
-        // consecutive cells of the caller's arrays and 8 lanes write 8
-        // consecutive chunk-interleaved slots (64-byte pieces on both sides).
-        // Loads of UC tiles go first.
+        const bool may_reuse = prm.fac_reuse && W.cst[cd.index].fac_valid;
+        bool changed = false;
         constexpr int UC = 2;
-        (void)c0;
-        const int lane = t & 63, wv = t >> 6;
-        const int Mr = (M + 7) & ~7;             // rows rounded up to whole tiles
-        auto tile_cell = [&](int i, int& tt, int& j) {
-            const int k = i * (T / 64) + wv;     // tile index
-            tt = (k % (T / 8)) * 8 + (lane >> 3);
-            j = (k / (T / 8)) * 8 + (lane & 7);
+        const int lane = threadIdx.x & 63;
+        const int nrg = (M + 7) >> 3;            // row groups of 8
+        auto tile_cell = [&](int k, int& tt, int& j) {
+            tt = (k / nrg) * 8 + (lane >> 3);
+            j = (k % nrg) * 8 + (lane & 7);
         };
-        for (int k0 = 0; k0 < Mr; k0 += UC) {
+        for (int k0 = kb + w; k0 < ke; k0 += UC * nw) {
             double mu[UC], D[UC], mum[UC], Dm[UC], ne[UC], ph[UC], sr[UC], kl[UC], qq[UC];
             double pn[UC], pp[UC], ln[UC], lp[UC], uf[UC];
             double ofa[UC], ofg[UC], ofw[UC], okd[UC];   // this column's coefficients of the last step
 #pragma unroll
             for (int v = 0; v < UC; ++v) {
+                const int k = k0 + v * nw;
                 int tt, j;
-                tile_cell(k0 + v, tt, j);
+                tile_cell(k, tt, j);
                 const int c = tt * M + j;
                 mu[v] = D[v] = mum[v] = Dm[v] = ne[v] = ph[v] = sr[v] = kl[v] = qq[v] = 0.0;
                 pn[v] = pp[v] = ln[v] = lp[v] = uf[v] = 0.0;
                 ofa[v] = ofg[v] = ofw[v] = okd[v] = 0.0;
-                if (may_reuse && k0 + v < Mr && j < M && c < n) {
+                if (may_reuse && k < ke && j < M && c < n) {
                     const int64_t s = cd.ws + (int64_t)j * T + tt;
                     ofa[v] = W.fa[s]; ofg[v] = W.fg[s]; okd[v] = W.kd[s];
                     if (prm.has_u) ofw[v] = W.fw[s];
                 }
-                if (k0 + v < Mr && j < M && c < n) {
+                if (k < ke && j < M && c < n) {
                     const int64_t u = cd.uoff + c;
                     mu[v] = U.mu[u]; D[v] = U.diff[u];
                     if (c > 0) { mum[v] = U.mu[u - 1]; Dm[v] = U.diff[u - 1]; }
@@ -478,10 +486,11 @@ struct Column {
             }
 #pragma unroll
             for (int v = 0; v < UC; ++v) {
+                const int k = k0 + v * nw;
                 int tt, j;
-                tile_cell(k0 + v, tt, j);
+                tile_cell(k, tt, j);
                 const int c = tt * M + j;
-                if (k0 + v >= Mr || j >= M) continue;
+                if (k >= ke || j >= M) continue;
                 const int64_t s = cd.ws + (int64_t)j * T + tt;
                 if (c >= n) {
                     W.fa[s] = 0.0; W.fg[s] = 0.0;
@@ -490,23 +499,23 @@ struct Column {
                     X00[s] = X01[s] = X10[s] = X11[s] = X20[s] = X21[s] = 0.0;
                     continue;
                 }
-                double r, g, w = 0.0;
+                double r, g, wf = 0.0;
                 if (c == 0) {
                     r = mu[v] / D[v];
                     g = (cd.bcl == 1) ? 0.0 : D[v] / hb;
-                    if (prm.has_u) w = uf[v] * hb / D[v];
+                    if (prm.has_u) wf = uf[v] * hb / D[v];
                 } else {
                     const double muf = 0.5 * (mum[v] + mu[v]);
                     const double Df = 0.5 * (Dm[v] + D[v]);
                     r = muf / Df;
                     g = Df / cd.h;
-                    if (prm.has_u) w = uf[v] * cd.h / Df;
+                    if (prm.has_u) wf = uf[v] * cd.h / Df;
                 }
                 if (may_reuse)
                     changed = changed || ofa[v] != r || ofg[v] != g || okd[v] != dt * kl[v] ||
-                              (prm.has_u && ofw[v] != w);
+                              (prm.has_u && ofw[v] != wf);
                 W.fa[s] = r; W.fg[s] = g;
-                if (prm.has_u) W.fw[s] = w;
+                if (prm.has_u) W.fw[s] = wf;
                 W.f[s] = ne[v] + dt * sr[v];
                 W.kd[s] = dt * kl[v];
                 W.q[s] = qq[v];
@@ -515,19 +524,77 @@ struct Column {
                 if (learn) { X20[s] = ln[v]; X21[s] = lp[v]; }
                 if (c == n - 1) {
                     // right wall face: the last cell's mu and D at distance h/2
-                    double* misc = lds + Lds<T>::kMisc;
-                    misc[0] = mu[v] / D[v];
-                    misc[1] = (cd.bcr == 1) ? 0.0 : D[v] / hb;
-                    misc[2] = prm.has_u ? U.uface[fo + n] * hb / D[v] : 0.0;
+                    wall[0] = mu[v] / D[v];
+                    wall[1] = (cd.bcr == 1) ? 0.0 : D[v] / hb;
+                    wall[2] = prm.has_u ? U.uface[fo + n] * hb / D[v] : 0.0;
                 }
             }
         }
-        __syncthreads();
-        {
+        return changed;
+    }
+
+    // Workspace buffer -> caller arrays (natural layout), tiles [kb, ke) of
+    // gather in the other direction.
+    __device__ void scatter(const double* s0p, const double* s1p, double* o0, double* o1, int kb, int ke,
+                            int w, int nw) {
+        const int M = cd.M, n = cd.n;
+        const int lane = threadIdx.x & 63;
+        const int nrg = (M + 7) >> 3;
+        constexpr int UC = 4;
+        for (int k0 = kb + w; k0 < ke; k0 += UC * nw) {
+            double a[UC], b[UC];
+#pragma unroll
+            for (int v = 0; v < UC; ++v) {
+                const int k = k0 + v * nw;
+                const int tt = (k / nrg) * 8 + (lane >> 3);
+                const int j = (k % nrg) * 8 + (lane & 7);
+                a[v] = b[v] = 0.0;
+                if (k < ke && j < M && tt * M + j < n) {
+                    const int64_t s = cd.ws + (int64_t)j * T + tt;
+                    a[v] = s0p[s]; b[v] = s1p[s];
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < UC; ++v) {
+                const int k = k0 + v * nw;
+                const int tt = (k / nrg) * 8 + (lane >> 3);
+                const int j = (k % nrg) * 8 + (lane & 7);
+                const int c = tt * M + j;
+                if (k < ke && j < M && c < n) {
+                    o0[cd.uoff + c] = a[v];
+                    o1[cd.uoff + c] = b[v];
+                }
+            }
+        }
+    }
+
+    // Start of a step: gather (unless separate launches already gathered
+    // this column: then its wall coefficients sit in the column's ColState
+    // and the change flags of its gather workgroups in W.gflag[g0, g0 + gn)),
+    // scalings, residuals of the start candidates.
+    __device__ Norms setup(const UserArrays& U, int* cur, int* guess_used, bool gathered = false) {
+        const double* X00 = xb(0, 0); const double* X01 = xb(0, 1);
+        const double* X10 = xb(1, 0); const double* X11 = xb(1, 1);
+        const double* X20 = xb(2, 0); const double* X21 = xb(2, 1);
+        const bool extrap = prm.guess >= 1 && prm.has_prev;
+        const bool learn = prm.guess == 2 && prm.has_learned && W.lmask[cd.index] != 0;
+        // the previous step's record of this column (read before it is rewritten)
+        const ColState* csp = W.cst + cd.index;
+        const bool may_reuse = prm.fac_reuse && csp->fac_valid;
+        const double o_rR = csp->rR, o_gR = csp->gR, o_wR = csp->wR;
+        const double o_sf[4] = {csp->fsfn, csp->fsfp, csp->fsxn, csp->fsxp};
+        bool changed;    // a Jacobian coefficient of this thread's cells differs
+        if (gathered) {
+            rR = csp->nrR; gR = csp->ngR; wR = csp->nwR;
+            changed = false;
+            for (int i = cd.g0; i < cd.g0 + cd.gn; ++i) changed = changed || W.gflag[i] != 0;
+        } else {
+            changed = gather(U, 0, ntiles(), t >> 6, T / 64, lds + Lds<T>::kMisc);
+            __syncthreads();
             const double* misc = lds + Lds<T>::kMisc;
             rR = misc[0]; gR = misc[1]; wR = misc[2];
+            __syncthreads();
         }
-        __syncthreads();
 
         // Sweep A: scalings from X^n (term magnitudes) + residual at X^n, and
         // in the same pass the residual of the extrapolated candidate.

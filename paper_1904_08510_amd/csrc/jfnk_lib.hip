@@ -20,6 +20,7 @@ namespace {
 constexpr int kTmax = 512;          // largest workgroup that owns a column
 constexpr int kScalSlots = 64;      // doubles of scalar exchange per column
 constexpr int kMaxBackoff = 5;      // a losing learned guess is skipped up to 2^5 - 1 steps
+constexpr int kMoveTiles = 32;      // 8 x 8-cell tiles per gather / write-back workgroup
 
 // ---------------------------------------------------------------------------
 // Batched schedule: one workgroup per column, whole step in one launch.
@@ -29,6 +30,7 @@ struct SolveArgs {
     SolverParams prm;
     UserArrays U;
     const int* order;   // blockIdx -> column
+    const int* mcol;    // gather / write-back workgroup -> column
 };
 
 template <int T, class FT>
@@ -40,6 +42,37 @@ __global__ __launch_bounds__(T) void k_solve(SolveArgs a) {
     ex.U = a.U;
     ColOutcome o;
     jfnk_solve(ex, a.prm, o);
+}
+
+// The data-movement ends of a batched step as launches of their own: they
+// need few registers, so many waves per SIMD hide the memory latency that
+// the solve's single wave per SIMD cannot, and they split every column into
+// workgroups of at most kMoveTiles tiles so that long columns do not leave a
+// tail.  Workgroup g serves column mcol[g], tiles [(g - g0) kMoveTiles, ...).
+constexpr int kMoveThreads = 256;
+
+template <int T>
+__global__ __launch_bounds__(kMoveThreads) void k_gather(SolveArgs a) {
+    const int ci = a.mcol[blockIdx.x];
+    Column<T, float> col;
+    col.init(a.W.cols[ci], a.W, a.prm, nullptr);
+    ColState* cs = a.W.cst + col.cd.index;
+    const int kb = ((int)blockIdx.x - col.cd.g0) * kMoveTiles;
+    const int ke = min(kb + kMoveTiles, col.ntiles());
+    const bool ch = col.gather(a.U, kb, ke, threadIdx.x >> 6, kMoveThreads / 64, &cs->nrR);
+    const int any = __syncthreads_or(ch ? 1 : 0);
+    if (threadIdx.x == 0) a.W.gflag[blockIdx.x] = any != 0 ? 1 : 0;
+}
+
+template <int T>
+__global__ __launch_bounds__(kMoveThreads) void k_scatter(SolveArgs a) {
+    const int ci = a.mcol[blockIdx.x];
+    Column<T, float> col;
+    col.init(a.W.cols[ci], a.W, a.prm, nullptr);
+    const int b = a.W.cst[col.cd.index].cur;
+    const int kb = ((int)blockIdx.x - col.cd.g0) * kMoveTiles;
+    const int ke = min(kb + kMoveTiles, col.ntiles());
+    col.scatter(col.xb(b, 0), col.xb(b, 1), a.U.ne, a.U.phi, kb, ke, threadIdx.x >> 6, kMoveThreads / 64);
 }
 
 // ---------------------------------------------------------------------------
@@ -227,6 +260,14 @@ struct jfnk_ctx {
     bool poisoned = false;
     int Tsel = 0;                // workgroup size of the last schedule
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // around the solve launches
+    hipEvent_t evg = nullptr, evs = nullptr;   // batched: after the gather and after the solve launch
+    int64_t capMove = 0;                       // gather / write-back workgroups the tables hold
+    int32_t* d_mcol = nullptr;                 // [capMove] workgroup -> column
+    int32_t* h_mcol = nullptr;                 // pinned
+    int32_t* d_gflag = nullptr;                // [capMove] coefficient-change flag per gather workgroup
+    int nmove = 0;                             // gather / write-back workgroups of the current schedule
+    bool timed3 = false;                       // the last step recorded evg and evs
+    double last_kms[3] = {0.0, 0.0, 0.0};      // gather, solve, write-back (ms)
     // schedule cache: the per-column inputs the last uploaded schedule was built from
     std::vector<int64_t> last_off;
     std::vector<double> last_scal;
@@ -364,6 +405,18 @@ int validate(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x) {
     for (int c = 0; c < p->ncols; ++c) ord[c] = c;
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return ctx->h_cols[a].n > ctx->h_cols[b].n; });
     for (int c = 0; c < p->ncols; ++c) ctx->h_order[c] = ord[c];
+    // gather / write-back workgroups: up to kMoveTiles tiles of one column each
+    int64_t g = 0;
+    for (int i = 0; i < p->ncols; ++i) {
+        ColDesc& d = ctx->h_cols[ord[i]];
+        const int64_t tiles = (int64_t)((d.M + 7) / 8) * (T / 8);
+        const int64_t gn = (tiles + kMoveTiles - 1) / kMoveTiles;
+        if (g + gn > ctx->capMove) return fail(ctx, JFNK_ECAPACITY, "gather workgroups exceed capacity");
+        d.g0 = (int32_t)g; d.gn = (int32_t)gn;
+        for (int64_t k = 0; k < gn; ++k) ctx->h_mcol[g + k] = ord[i];
+        g += gn;
+    }
+    ctx->nmove = (int)g;
     ctx->Tsel = T;
     return JFNK_OK;
 }
@@ -580,12 +633,20 @@ int run_batched(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t
     a.prm = make_params(ctx, p, x);
     a.U = make_user(ctx, p, x);
     a.order = ctx->d_order;
+    a.mcol = ctx->d_mcol;
     HIP_OK(hipEventRecord(ctx->ev0, st));
+    hipLaunchKernelGGL((k_gather<T>), dim3(ctx->nmove), dim3(kMoveThreads), 0, st, a);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipEventRecord(ctx->evg, st));
     hipLaunchKernelGGL((k_solve<T, FT>), dim3(p->ncols), dim3(T), Lds<T>::bytes(), st, a);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipEventRecord(ctx->evs, st));
+    hipLaunchKernelGGL((k_scatter<T>), dim3(ctx->nmove), dim3(kMoveThreads), 0, st, a);
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(ctx->ev1, st));
     ctx->timed = true;
-    ctx->last_launches = 1;
+    ctx->timed3 = true;
+    ctx->last_launches = 3;
     return JFNK_OK;
 }
 
@@ -627,6 +688,7 @@ int dispatch_phases(jfnk_ctx* ctx, hipStream_t st, PhaseArgs& a, const std::vect
 int upload_schedule(jfnk_ctx* ctx, int ncols, hipStream_t st) {
     HIP_OK(hipMemcpyAsync(ctx->W.cols, ctx->h_cols, sizeof(ColDesc) * ncols, hipMemcpyHostToDevice, st));
     HIP_OK(hipMemcpyAsync(ctx->d_order, ctx->h_order, sizeof(int) * ncols, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(ctx->d_mcol, ctx->h_mcol, sizeof(int32_t) * ctx->nmove, hipMemcpyHostToDevice, st));
     return JFNK_OK;
 }
 
@@ -678,6 +740,16 @@ int gather_stats(jfnk_ctx* ctx, int ncols, jfnk_stats* stt, hipStream_t st, int*
         HIP_OK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
         ctx->last_ms = ms;
         ctx->timed = false;
+        if (ctx->timed3) {
+            float k0 = 0.0f, k1 = 0.0f, k2 = 0.0f;
+            HIP_OK(hipEventElapsedTime(&k0, ctx->ev0, ctx->evg));
+            HIP_OK(hipEventElapsedTime(&k1, ctx->evg, ctx->evs));
+            HIP_OK(hipEventElapsedTime(&k2, ctx->evs, ctx->ev1));
+            ctx->last_kms[0] = k0; ctx->last_kms[1] = k1; ctx->last_kms[2] = k2;
+        } else {
+            ctx->last_kms[0] = ctx->last_kms[1] = ctx->last_kms[2] = -1.0;
+        }
+        ctx->timed3 = false;
     }
     int bad = 0;
     for (int c = 0; c < ncols; ++c) {
@@ -840,8 +912,16 @@ int jfnk_create(const jfnk_config* cfg, jfnk_ctx** out) {
     if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_cst, sizeof(ColState) * cfg->max_cols, 0);
     if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_scal, sizeof(double) * kScalSlots * 2, 0);
     if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_order, sizeof(int) * cfg->max_cols, 0);
+    // gather / write-back tables: a column of M rows and T owners has ceil(M/8) T/8 tiles
+    ctx->capMove = (ctx->capP + 8 * (int64_t)Tcap * cfg->max_cols) / (64 * kMoveTiles) + cfg->max_cols + 1;
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_mcol, sizeof(int32_t) * ctx->capMove);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_gflag, sizeof(int32_t) * ctx->capMove);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_mcol, sizeof(int32_t) * ctx->capMove, 0);
+    if (e == hipSuccess) ctx->W.gflag = ctx->d_gflag;
     if (e == hipSuccess) e = hipEventCreate(&ctx->ev0);
     if (e == hipSuccess) e = hipEventCreate(&ctx->ev1);
+    if (e == hipSuccess) e = hipEventCreate(&ctx->evg);
+    if (e == hipSuccess) e = hipEventCreate(&ctx->evs);
     if (e != hipSuccess) { (void)hipGetLastError(); jfnk_destroy(ctx); return JFNK_ENOMEM; }
     // zero the whole workspace once: padding cells must read as zero
     e = hipMemset(ctx->base, 0, sizeof(double) * words);
@@ -855,12 +935,17 @@ void jfnk_destroy(jfnk_ctx* ctx) {
     if (!ctx) return;
     if (ctx->base) (void)hipFree(ctx->base);
     if (ctx->d_order) (void)hipFree(ctx->d_order);
+    if (ctx->d_mcol) (void)hipFree(ctx->d_mcol);
+    if (ctx->d_gflag) (void)hipFree(ctx->d_gflag);
+    if (ctx->h_mcol) (void)hipHostFree(ctx->h_mcol);
     if (ctx->h_cols) (void)hipHostFree(ctx->h_cols);
     if (ctx->h_cst) (void)hipHostFree(ctx->h_cst);
     if (ctx->h_scal) (void)hipHostFree(ctx->h_scal);
     if (ctx->h_order) (void)hipHostFree(ctx->h_order);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->evg) (void)hipEventDestroy(ctx->evg);
+    if (ctx->evs) (void)hipEventDestroy(ctx->evs);
     if (ctx->d_learn) (void)hipFree(ctx->d_learn);
     if (ctx->d_lmask) (void)hipFree(ctx->d_lmask);
     if (ctx->h_lmask) (void)hipHostFree(ctx->h_lmask);
@@ -871,6 +956,12 @@ int jfnk_last_timing(const jfnk_ctx* ctx, double* solve_ms, int32_t* launches) {
     if (!ctx || !solve_ms) return JFNK_EINVAL;
     *solve_ms = ctx->last_ms;
     if (launches) *launches = ctx->last_launches;
+    return JFNK_OK;
+}
+
+int jfnk_last_kernel_times(const jfnk_ctx* ctx, double* ms3) {
+    if (!ctx || !ms3) return JFNK_EINVAL;
+    for (int k = 0; k < 3; ++k) ms3[k] = ctx->last_kms[k];
     return JFNK_OK;
 }
 

@@ -59,6 +59,12 @@ __host__ __device__ inline void givens_solve(const double* H, int ld, const doub
     }
 }
 
+// Contraction ratio e_{k+1} / e_k of a simplified-Newton step above which
+// the factors are rebuilt at the new iterate (the choice of stiff-integrator
+// practice for modified Newton iterations, which re-evaluate the Jacobian once
+// the observed rate exceeds a few tenths).
+constexpr double kChordRefactorRate = 0.2;
+
 template <class Ex>
 __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& out) {
     const double lam_fd = 6.0554544523933395e-06;   // cbrt(2^-52)
@@ -103,12 +109,27 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
             double e2 = INFINITY;
             if (!isnan(tc.r2)) { e2 = ex.correction(out).y; ++wk[kWorkApply]; }
             if (e2 <= (1.0 - p.theta) * est) {
+                const double rate = e2 / est;
                 cur = out;
                 nr = tc;
                 est = e2;
                 corr_at = out;
                 ++chords;
                 ++chord_run;
+                // A slow contraction means the factors (built at an earlier
+                // iterate, or in the previous time step) no longer describe the
+                // Jacobian: refactor at the new iterate, so that the next
+                // simplified-Newton step is a Newton step again.  Also when one
+                // more step at the observed rate would not reach tol_x: the
+                // refactorisation and one step cost about as much as two steps,
+                // and a step after it converges quadratically.
+                if (est > p.tol_x && (rate > kChordRefactorRate || est * rate > p.tol_x)) {
+                    ex.factor(cur);
+                    factored = cur;
+                    ++wk[kWorkFactor];
+                    est = ex.correction(cur).y;
+                    ++wk[kWorkApply];
+                }
                 continue;
             }
             corr_at = -1;    // the slot now holds the rejected trial's correction
@@ -241,7 +262,10 @@ struct DevExec {
     __device__ VecRef* basis_lds() { return (VecRef*)(col.lds + Lds<T>::kBasis); }
     __device__ double* Hl() { return col.lds + Lds<T>::kH; }
 
-    __device__ Norms setup(int* cur, int* guess) { return col.setup(U, cur, guess); }
+    // the batched schedule runs the gather and the write-back as launches of their own
+    static constexpr bool split = true;
+
+    __device__ Norms setup(int* cur, int* guess) { return col.setup(U, cur, guess, split); }
     __device__ bool lagged_factors() const { return col.fac_reuse; }
     __device__ void factor(int cur) { col.factor(cur); }
 
@@ -369,9 +393,10 @@ struct DevExec {
         return col.trial(cur, out, VecRef{col.Vb(col.prm.m, 0), col.Vb(col.prm.m, 1), 1.0, 1.0}, 1.0);
     }
     __device__ void finalize(const ColOutcome& o) {
-        col.write_back(col.xb(o.cur, 0), col.xb(o.cur, 1), U.ne, U.phi);
+        if (!split) col.write_back(col.xb(o.cur, 0), col.xb(o.cur, 1), U.ne, U.phi);
         if (threadIdx.x == 0) {
             ColState* cs = col.W.cst + col.cd.index;
+            cs->cur = o.cur;
             cs->res_inf = o.rinf; cs->res2 = o.r2;
             cs->status = o.status; cs->newton = o.newton; cs->gmres = o.gmres;
             cs->backtracks = o.backtracks; cs->guess = o.guess; cs->restarts = o.restarts;

@@ -39,6 +39,7 @@ struct ColDesc {
     int32_t bcl, bcr;   // 0 Dirichlet, 1 zero flux
     int32_t index;      // caller's column index
     int32_t T;          // workgroup size that owns this column
+    int32_t g0, gn;     // batched schedule: first gather/write-back workgroup, their count
     int64_t uoff;       // first cell in the caller's packed arrays
     int64_t ws;         // first padded cell in the workspace
     int64_t red;        // first double of the per-chunk data
@@ -54,6 +55,9 @@ struct ColState {
     int32_t fac_valid;              // the workspace holds factors of this column
     int32_t work[kWorkCounts];      // phases executed this step (see kWork*)
     double fsfn, fsfp, fsxn, fsxp;  // scalings those factors were built with
+    double nrR, ngR, nwR;           // right-wall face coefficients of the coming step (gather launch)
+    int32_t nchanged;               // gather launch: a face coefficient differs from the stored factors'
+    int32_t cur;                    // workspace buffer holding the column's X^{n+1} after the step
 };
 
 struct SolverParams {
@@ -98,6 +102,7 @@ struct Work {
     ColState *cst;
     double *scal;                    // per-column scalar exchange (host-driven mode)
     const int32_t *lmask;            // per column: learned candidate present (guess 2)
+    int32_t *gflag;                  // per gather workgroup: a face coefficient changed
 };
 
 }  // namespace jfnk

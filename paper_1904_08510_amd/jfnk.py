@@ -89,6 +89,8 @@ def lib():
         L.jfnk_last_error.restype = C.c_char_p
         L.jfnk_last_timing.argtypes = [C.c_void_p, _dp, _ip]
         L.jfnk_last_timing.restype = C.c_int
+        L.jfnk_last_kernel_times.argtypes = [C.c_void_p, _dp]
+        L.jfnk_last_kernel_times.restype = C.c_int
         L.jfnk_eval_residual.argtypes = [C.c_void_p, C.POINTER(jfnk_problem), C.POINTER(jfnk_state),
                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, _dp, C.c_void_p]
         L.jfnk_eval_residual.restype = C.c_int
@@ -133,7 +135,7 @@ def lib():
 
 
 EXPORTED_SYMBOLS = ("jfnk_config_default", "jfnk_create", "jfnk_step", "jfnk_destroy",
-                    "jfnk_last_error", "jfnk_last_timing", "jfnk_eval_residual", "jfnk_eval_jv",
+                    "jfnk_last_error", "jfnk_last_timing", "jfnk_last_kernel_times", "jfnk_eval_residual", "jfnk_eval_jv",
                     "jfnk_block_solve", "jfnk_net_config_default", "jfnk_net_param_count",
                     "jfnk_net_create", "jfnk_net_destroy", "jfnk_net_last_error",
                     "jfnk_net_set_params", "jfnk_net_get_params", "jfnk_net_predict",
@@ -280,6 +282,12 @@ class Solver:
         n = C.c_int32()
         self._check(lib().jfnk_last_timing(self.h, C.byref(ms), C.byref(n)), (JFNK_OK,))
         return ms.value, n.value
+
+    def last_kernel_times(self):
+        """(gather, solve, write-back) ms of the last batched step (-1 each otherwise)."""
+        out = (C.c_double * 3)()
+        self._check(lib().jfnk_last_kernel_times(self.h, out), (JFNK_OK,))
+        return tuple(out)
 
     def _check(self, rc, allow=(JFNK_OK, JFNK_NOT_CONVERGED)):
         if rc not in allow:
