@@ -30,23 +30,34 @@ EPISODE = 20
 HBM_PEAK_GBS = 8000.0
 
 
-def bytes_per_cell(has_prev, fb, counts):
-    """Algorithmic HBM bytes per cell of one column-step, from the phases the
-    step executed (jfnk_stats.phase_counts: factorisations, preconditioner
-    applies, residual evaluations, J.v products, CGS passes, direction
-    assemblies); each phase reads its operands from HBM and writes its
-    results once (fb = bytes per stored preconditioner value)."""
-    R = 72.0                                   # residual: X + 5 coefficients -> F
-    setup = 112.0 + R                          # 7 inputs -> 5 coefficients + X; F(X^n)
+def gather_bytes_per_cell(has_prev):
+    """Algorithmic HBM bytes per cell of the gather launch: 7 caller arrays
+    (mu, D, n_e, phi, source, loss, q) in, 5 coefficients + X^n out, plus
+    X^{n-1} in and the extrapolation out when it is supplied, plus the 3
+    stored coefficients the factor-reuse test compares against."""
+    return 112.0 + (32.0 if has_prev else 0.0) + 24.0
+
+
+WRITEBACK_BYTES_PER_CELL = 32.0               # X^{n+1} from the workspace to the caller's arrays
+
+
+def solve_bytes_per_cell(has_prev, fb, counts):
+    """Algorithmic HBM bytes per cell of one column-step inside the solve
+    launch, from the phases the step executed (jfnk_stats.phase_counts:
+    factorisations, preconditioner applies, residual evaluations, J.v
+    products, CGS passes, direction assemblies); each phase reads its
+    operands from HBM and writes its results once (fb = bytes per stored
+    preconditioner value)."""
+    setup = 72.0                               # F(X^n): X + 5 coefficients -> F
     if has_prev:
-        setup += 32.0 + R                      # extrapolated candidate and its residual
+        setup += 32.0                          # same sweep: the extrapolation in, its residual out
     per_phase = (40.0 + 20.0 * fb,             # factor: X + 3 coefficients -> 20 factor values
                  32.0 + 20.0 * fb,             # apply: v + 20 factor values -> z
                  104.0,                        # trial: X + direction + 5 coefficients -> X_t, F_t
                  120.0,                        # J.v: X, z, F, 5 coefficients -> w, fused dots
                  64.0,                         # CGS pass: w and the basis vectors it projects out
                  64.0)                         # direction: sum of the Krylov vectors
-    return setup + sum(c * b for c, b in zip(counts, per_phase)) + 32.0   # + result to the caller
+    return setup + sum(c * b for c, b in zip(counts, per_phase))
 
 
 def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None, stream=None, chord=None):
@@ -82,7 +93,8 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
         state["e"] = (e + 1) % EPISODE
         if record is not None:
             ms, _ = solver.last_timing()
-            record.append(dict(rc=rc, ms=ms, has_prev=has_prev, newton=st.newton_iters.copy(),
+            kms = solver.last_kernel_times()
+            record.append(dict(rc=rc, ms=ms, kms=kms, has_prev=has_prev, newton=st.newton_iters.copy(),
                                gmres=st.gmres_iters.copy(), bt=st.backtracks.copy(),
                                res=st.res_scaled.copy(), status=st.status.copy(),
                                guess=st.guess_used.copy(), chords=st.chord_steps.copy(),
@@ -104,10 +116,15 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
         r["conv"] = int(np.sum(r["status"] == 0))
         r["res"] = float(r["res"].max())
         r["bytes"] = float(np.sum(ns * np.array([
-            bytes_per_cell(r["has_prev"], fb, r["counts"][i][:6]) for i in range(len(ns))])))
+            solve_bytes_per_cell(r["has_prev"], fb, r["counts"][i][:6]) for i in range(len(ns))])))
+        r["gbytes"] = float(np.sum(ns)) * gather_bytes_per_cell(r["has_prev"])
+        r["wbytes"] = float(np.sum(ns)) * WRITEBACK_BYTES_PER_CELL
     converged = sum(r["conv"] for r in rec)
-    kern_ms = sum(r["ms"] for r in rec)
+    kern_ms = sum(r["kms"][1] for r in rec)
     kern_bytes = sum(r["bytes"] for r in rec)
+    g_ms = sum(r["kms"][0] for r in rec)
+    w_ms = sum(r["kms"][2] for r in rec)
+    step_ms = sum(r["ms"] for r in rec)
     newton = np.concatenate([r["newton"] for r in rec])
     gmres = np.concatenate([r["gmres"] for r in rec])
     used = np.concatenate([r["guess"] for r in rec])
@@ -117,6 +134,15 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
         converged=converged, total=len(ns) * args.steps, max_res=max(r["res"] for r in rec),
         kernel_ms_avg=kern_ms / len(rec), achieved_gbs=kern_bytes / (kern_ms * 1e-3) / 1e9,
         bytes_per_launch=kern_bytes / len(rec),
+        launches={
+            "k_gather": dict(ms_avg=g_ms / len(rec), bytes_per_launch=sum(r["gbytes"] for r in rec) / len(rec),
+                             achieved_gbs=sum(r["gbytes"] for r in rec) / (g_ms * 1e-3) / 1e9),
+            "k_solve": dict(ms_avg=kern_ms / len(rec), bytes_per_launch=kern_bytes / len(rec),
+                            achieved_gbs=kern_bytes / (kern_ms * 1e-3) / 1e9),
+            "k_scatter": dict(ms_avg=w_ms / len(rec), bytes_per_launch=sum(r["wbytes"] for r in rec) / len(rec),
+                              achieved_gbs=sum(r["wbytes"] for r in rec) / (w_ms * 1e-3) / 1e9),
+            "step_ms_avg": step_ms / len(rec),
+        },
         newton_mean=float(newton.mean()), newton_max=int(newton.max()),
         gmres_per_newton=float(gmres.sum() / max(newton.sum(), 1)),
         chord_mean=float(chords.mean()),
@@ -341,6 +367,7 @@ def main():
             "kernel_ms_avg": g["kernel_ms_avg"],
             "bytes_per_launch": g["bytes_per_launch"],
         },
+        "launches": g["launches"],
         "cpu_baseline": cpu,
         "plain": g.get("plain"),
         "ablations": g.get("ablations"),

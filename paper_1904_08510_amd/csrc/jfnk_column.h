@@ -22,6 +22,8 @@ namespace jfnk {
 // ---------------------------------------------------------------------------
 // 2x2 blocks
 // ---------------------------------------------------------------------------
+__host__ __device__ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
+
 template <class R>
 struct Blk { R a, b, c, d; };   // [[a b] [c d]]
 template <class R>
@@ -229,19 +231,18 @@ struct Column {
             Own ow[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int j = j0 + u;
-                xn[u] = xp[u] = fa[u] = fg[u] = fw[u] = 0.0;
-                if (j < jr) {
-                    const int64_t s = sidx(t, j);
-                    ow[u] = own(s);
-                    if (c0 + j < n - 1) {
-                        const int64_t sn = (j + 1 < M) ? s + T : sidx(t + 1, 0);
-                        getx(sn, xn[u], xp[u]);
-                        fa[u] = W.fa[sn];
-                        fg[u] = W.fg[sn];
-                        if (prm.has_u) fw[u] = W.fw[sn];
-                    }
-                }
+                // Loads without conditions, so that the U rows' loads issue back
+                // to back: rows past the chunk's end reload its last real row, and
+                // the last cell of the column reloads itself in place of its
+                // (absent) right neighbour.  Neither value is used.
+                const int j = min(j0 + u, jr - 1);
+                const int64_t s = sidx(t, j);
+                ow[u] = own(s);
+                const int64_t sn = (c0 + j >= n - 1) ? s : ((j + 1 < M) ? s + T : sidx(t + 1, 0));
+                getx(sn, xn[u], xp[u]);
+                fa[u] = W.fa[sn];
+                fg[u] = W.fg[sn];
+                fw[u] = W.fw[sn];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -256,7 +257,7 @@ struct Column {
                         FR = face(rR, gR, wR, 2.0 * ih, nC, pC, nR, pR);
                     } else {
                         nR = xn[u]; pR = xp[u];
-                        FR = face(fa[u], fg[u], fw[u], ih, nC, pC, nR, pR);
+                        FR = face(fa[u], fg[u], prm.has_u ? fw[u] : 0.0, ih, nC, pC, nR, pR);
                     }
                     cell(s, c, nC, pC, FL, FR, ow[u]);
                     nC = nR; pC = pR; FL = FR;
@@ -301,20 +302,16 @@ struct Column {
             Own ow[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int j = j0 + u;
-                an[u] = ap[u] = bn[u] = bp[u] = fa[u] = fg[u] = fw[u] = 0.0;
-                if (j < jr) {
-                    const int64_t s = sidx(t, j);
-                    ow[u] = own(s);
-                    if (c0 + j < n - 1) {
-                        const int64_t sn = (j + 1 < M) ? s + T : sidx(t + 1, 0);
-                        gxa(sn, an[u], ap[u]);
-                        gxb(sn, bn[u], bp[u]);
-                        fa[u] = W.fa[sn];
-                        fg[u] = W.fg[sn];
-                        if (prm.has_u) fw[u] = W.fw[sn];
-                    }
-                }
+                // unconditional loads, as in sweep
+                const int j = min(j0 + u, jr - 1);
+                const int64_t s = sidx(t, j);
+                ow[u] = own(s);
+                const int64_t sn = (c0 + j >= n - 1) ? s : ((j + 1 < M) ? s + T : sidx(t + 1, 0));
+                gxa(sn, an[u], ap[u]);
+                gxb(sn, bn[u], bp[u]);
+                fa[u] = W.fa[sn];
+                fg[u] = W.fg[sn];
+                fw[u] = W.fw[sn];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -331,8 +328,9 @@ struct Column {
                         FRB = fB(rR, gR, wR, 2.0 * ih, nB, pB, nBR, pBR);
                     } else {
                         nAR = an[u]; pAR = ap[u]; nBR = bn[u]; pBR = bp[u];
-                        FRA = fA(fa[u], fg[u], fw[u], ih, nA, pA, nAR, pAR);
-                        FRB = fB(fa[u], fg[u], fw[u], ih, nB, pB, nBR, pBR);
+                        const double wu = prm.has_u ? fw[u] : 0.0;
+                        FRA = fA(fa[u], fg[u], wu, ih, nA, pA, nAR, pAR);
+                        FRB = fB(fa[u], fg[u], wu, ih, nB, pB, nBR, pBR);
                     }
                     cell(s, c, nA, pA, nB, pB, FLA, FRA, FLB, FRB, ow[u]);
                     nA = nAR; pA = pAR; nB = nBR; pB = pBR;
@@ -370,13 +368,17 @@ struct Column {
         const double* kv = W.kd;
         const double* qv = W.q;
         const bool wantstep = stepdir.p0 != nullptr;
+        // without a step direction the step loads read a valid array instead
+        // (unconditional loads issue back to back) and are not used
+        const double* dp0 = wantstep ? stepdir.p0 : fv;
+        const double* dp1 = wantstep ? stepdir.p1 : fv;
         struct Own { double f, k, q, d0, d1; };
         sweep<2, FluxRec>(getx, FluxFace{},
             [&](int64_t s) {
                 Own o;
                 o.f = fv[s]; o.k = kv[s]; o.q = qv[s];
-                o.d0 = wantstep ? stepdir.p0[s] : 0.0;
-                o.d1 = wantstep ? stepdir.p1[s] : 0.0;
+                o.d0 = dp0[s];
+                o.d1 = dp1[s];
                 return o;
             },
             [&](int64_t s, int c, double nC, double pC, const FluxRec& L, const FluxRec& R, const Own& o) {
@@ -863,12 +865,9 @@ struct Column {
                 Blk<double> aa[U], gg[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int j = j0 - u;
-                    if (j >= 1) {
-                        const int64_t s = sidx(t, j);
-                        aa[u] = Blk<double>{T0[s], T1[s], T2[s], T3[s]};
-                        gg[u] = Blk<double>{T4[s], T5[s], T6[s], T7[s]};
-                    }
+                    const int64_t s = sidx(t, max(j0 - u, 1));   // unconditional loads
+                    aa[u] = Blk<double>{T0[s], T1[s], T2[s], T3[s]};
+                    gg[u] = Blk<double>{T4[s], T5[s], T6[s], T7[s]};
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -998,9 +997,16 @@ struct Column {
     // system in FP64).  Returns (||z||_2^2, ||z||_inf).
     __device__ Vec2<double> block_apply(const VecRef& v, double* z0, double* z1) {
         constexpr int U = 4;
+        constexpr int LG = ilog2(T);             // PCR stages of the interface system
         const int M = cd.M;
         FT* D0 = tmpv(0);
         FT* D1 = tmpv(1);
+        // The interface system's coefficients do not depend on v: their loads
+        // are issued first, so that their latency overlaps the chunk sweeps
+        // instead of adding one memory round trip per PCR stage.
+        double pc[8 * LG + 12];
+#pragma unroll
+        for (int i = 0; i < 8 * LG + 12; ++i) pc[i] = red(i)[0];
         Vec2<double> d0{v.p0[sidx(t, 0)] * v.s0, v.p1[sidx(t, 0)] * v.s1};
         // down sweep: d_j = m_j v_j - At_j d_{j-1}, loads of U rows issued first
         Vec2<FT> dprev{FT(0), FT(0)};
@@ -1009,13 +1015,10 @@ struct Column {
             Vec2<FT> vv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int j = j0 + u;
-                if (j < M) {
-                    const int64_t s = sidx(t, j);
-                    mm[u] = load_blk(0, s);
-                    aa[u] = load_blk(4, s);
-                    vv[u] = Vec2<FT>{(FT)(v.p0[s] * v.s0), (FT)(v.p1[s] * v.s1)};
-                }
+                const int64_t s = sidx(t, min(j0 + u, M - 1));   // unconditional loads
+                mm[u] = load_blk(0, s);
+                aa[u] = load_blk(4, s);
+                vv[u] = Vec2<FT>{(FT)(v.p0[s] * v.s0), (FT)(v.p1[s] * v.s1)};
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -1042,12 +1045,9 @@ struct Column {
                 Vec2<FT> dd[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int j = j0 - u;
-                    if (j >= 1) {
-                        const int64_t s = sidx(t, j);
-                        gg[u] = load_blk(8, s);
-                        dd[u] = Vec2<FT>{D0[s], D1[s]};
-                    }
+                    const int64_t s = sidx(t, max(j0 - u, 1));   // unconditional loads
+                    gg[u] = load_blk(8, s);
+                    dd[u] = Vec2<FT>{D0[s], D1[s]};
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -1068,27 +1068,29 @@ struct Column {
         __syncthreads();
         Vec2<double> dLp{0.0, 0.0};
         if (t > 0) dLp = {P[2 * (t - 1)], P[2 * (t - 1) + 1]};
-        const Blk<double> A0{red(0)[0], red(1)[0], red(2)[0], red(3)[0]};
-        const Blk<double> C0{red(4)[0], red(5)[0], red(6)[0], red(7)[0]};
+        const Blk<double> A0{pc[0], pc[1], pc[2], pc[3]};
+        const Blk<double> C0{pc[4], pc[5], pc[6], pc[7]};
         const Vec2<double> qa = bmv(A0, dLp), qc = bmv(C0, dFirst);
         Vec2<double> r{d0.x - qa.x - qc.x, d0.y - qa.y - qc.y};
-        int k = 8;
-        for (int st = 1; st < T; st <<= 1, k += 8) {
+#pragma unroll
+        for (int lv = 0; lv < LG; ++lv) {
+            const int st = 1 << lv, k = 8 + 8 * lv;
             __syncthreads();
             P[2 * t] = r.x; P[2 * t + 1] = r.y;
             __syncthreads();
             if (t >= st) {
-                const Blk<double> k1{red(k)[0], red(k + 1)[0], red(k + 2)[0], red(k + 3)[0]};
+                const Blk<double> k1{pc[k], pc[k + 1], pc[k + 2], pc[k + 3]};
                 const Vec2<double> q = bmv(k1, Vec2<double>{P[2 * (t - st)], P[2 * (t - st) + 1]});
                 r.x -= q.x; r.y -= q.y;
             }
             if (t + st < T) {
-                const Blk<double> k2{red(k + 4)[0], red(k + 5)[0], red(k + 6)[0], red(k + 7)[0]};
+                const Blk<double> k2{pc[k + 4], pc[k + 5], pc[k + 6], pc[k + 7]};
                 const Vec2<double> q = bmv(k2, Vec2<double>{P[2 * (t + st)], P[2 * (t + st) + 1]});
                 r.x -= q.x; r.y -= q.y;
             }
         }
-        const Blk<double> Di{red(k)[0], red(k + 1)[0], red(k + 2)[0], red(k + 3)[0]};
+        constexpr int k = 8 + 8 * LG;
+        const Blk<double> Di{pc[k], pc[k + 1], pc[k + 2], pc[k + 3]};
         const Vec2<double> x0 = bmv(Di, r);
         __syncthreads();
         P[2 * t] = x0.x; P[2 * t + 1] = x0.y;
@@ -1107,13 +1109,10 @@ struct Column {
             Vec2<FT> dd[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int j = j0 + u;
-                if (j < M) {
-                    const int64_t s = sidx(t, j);
-                    aa[u] = load_blk(12, s);
-                    gg[u] = load_blk(16, s);
-                    dd[u] = Vec2<FT>{D0[s], D1[s]};
-                }
+                const int64_t s = sidx(t, min(j0 + u, M - 1));   // unconditional loads
+                aa[u] = load_blk(12, s);
+                gg[u] = load_blk(16, s);
+                dd[u] = Vec2<FT>{D0[s], D1[s]};
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -1164,8 +1163,8 @@ struct Column {
                 Own o;
                 o.f = W.f[s]; o.k = W.kd[s]; o.q = W.q[s]; o.F0 = F0[s]; o.F1 = F1[s];
                 o.v00 = b0.p0[s]; o.v01 = b0.p1[s];
-                o.v10 = nbf > 1 ? b1.p0[s] : 0.0;
-                o.v11 = nbf > 1 ? b1.p1[s] : 0.0;
+                o.v10 = b1.p0[s];            // b1 is a valid array for any nb; its dot
+                o.v11 = b1.p1[s];            // is used only when nb > 1
                 return o;
             },
             [&](int64_t s, int c, double nC, double pC, const FluxRec& L, const FluxRec& R, const Own& o) {
@@ -1188,17 +1187,41 @@ struct Column {
     // dots[i] = basis[i] . w for i in [i0, nb)
     __device__ void dots_more(const double* w0, const double* w1, const VecRef* basis, int i0, int nb,
                               double* dots) {
+        constexpr int U = 2;
         const int M = cd.M;
         for (int g = i0; g < nb; g += 8) {
             double acc[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) acc[i] = 0.0;
-            for (int j = 0; j < M; ++j) {
-                const int64_t s = sidx(t, j);
-                const double a = w0[s], b = w1[s];
+            VecRef bv[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) bv[i] = basis[min(g + i, nb - 1)];
+            for (int j0 = 0; j0 < M; j0 += U) {
+                // every load of U rows x 8 vectors issues before any use: rows
+                // past the chunk's end and vectors past nb reload valid ones,
+                // and their terms are dropped by selects
+                int64_t sl[U];
+                double a[U], b[U], p[8][U], q[8][U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    sl[u] = sidx(t, min(j0 + u, M - 1));
+                    a[u] = w0[sl[u]];
+                    b[u] = w1[sl[u]];
+                }
 #pragma unroll
                 for (int i = 0; i < 8; ++i)
-                    if (g + i < nb) acc[i] += basis[g + i].p0[s] * basis[g + i].s0 * a + basis[g + i].p1[s] * basis[g + i].s1 * b;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        p[i][u] = bv[i].p0[sl[u]];
+                        q[i][u] = bv[i].p1[sl[u]];
+                    }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const double term = p[i][u] * bv[i].s0 * a[u] + q[i][u] * bv[i].s1 * b[u];
+                        acc[i] += (g + i < nb && j0 + u < M) ? term : 0.0;
+                    }
             }
             wg_sum<T, 8>(acc, lds + Lds<T>::kScr);
             for (int i = 0; i < 8 && g + i < nb; ++i) dots[g + i] = acc[i];
@@ -1216,38 +1239,47 @@ struct Column {
         for (int i = 0; i < 9; ++i) acc[i] = 0.0;
         const int nbf = nb < 8 ? nb : 8;
         for (int j0 = 0; j0 < M; j0 += U) {
+            // unconditional loads (rows past the chunk's end reload its last
+            // row; their results are neither stored nor summed)
             double a[U], b[U];
+            int64_t sl[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                a[u] = b[u] = 0.0;
-                if (j0 + u < M) { const int64_t s = sidx(t, j0 + u); a[u] = w0[s]; b[u] = w1[s]; }
+                sl[u] = sidx(t, min(j0 + u, M - 1));
+                a[u] = w0[sl[u]];
+                b[u] = w1[sl[u]];
             }
+#pragma unroll 4
             for (int i = 0; i < nb; ++i) {
                 const VecRef bi = basis[i];
+                const double hi = h[i];
+                double p[U], q[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (j0 + u < M) {
-                        const int64_t s = sidx(t, j0 + u);
-                        a[u] -= h[i] * bi.p0[s] * bi.s0;
-                        b[u] -= h[i] * bi.p1[s] * bi.s1;
-                    }
+                for (int u = 0; u < U; ++u) { p[u] = bi.p0[sl[u]]; q[u] = bi.p1[sl[u]]; }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    a[u] -= hi * p[u] * bi.s0;
+                    b[u] -= hi * q[u] * bi.s1;
+                }
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (j0 + u < M) {
-                    const int64_t s = sidx(t, j0 + u);
-                    w0[s] = a[u]; w1[s] = b[u];
-                    acc[8] += a[u] * a[u] + b[u] * b[u];
-                }
+            for (int u = 0; u < U; ++u) {
+                const bool ok = j0 + u < M;
+                if (ok) { w0[sl[u]] = a[u]; w1[sl[u]] = b[u]; }
+                acc[8] += ok ? a[u] * a[u] + b[u] * b[u] : 0.0;
+            }
+#pragma unroll 4
             for (int i = 0; i < nbf; ++i) {
                 const VecRef bi = basis[i];
+                double p[U], q[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) { p[u] = bi.p0[sl[u]]; q[u] = bi.p1[sl[u]]; }
                 double sacc = 0.0;
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (j0 + u < M) {
-                        const int64_t s = sidx(t, j0 + u);
-                        sacc += bi.p0[s] * bi.s0 * a[u] + bi.p1[s] * bi.s1 * b[u];
-                    }
+                for (int u = 0; u < U; ++u) {
+                    const double term = p[u] * bi.s0 * a[u] + q[u] * bi.s1 * b[u];
+                    sacc += (j0 + u < M) ? term : 0.0;
+                }
                 acc[i] += sacc;
             }
         }
@@ -1263,25 +1295,32 @@ struct Column {
         constexpr int U = 4;
         const int M = cd.M;
         for (int j0 = 0; j0 < M; j0 += U) {
+            // unconditional loads, as in cgs_pass
             double a[U], b[U];
+            int64_t sl[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                a[u] = b[u] = 0.0;
-                if (accumulate && j0 + u < M) { const int64_t s = sidx(t, j0 + u); a[u] = o0[s]; b[u] = o1[s]; }
+                sl[u] = sidx(t, min(j0 + u, M - 1));
+                const double x = o0[sl[u]], y = o1[sl[u]];
+                a[u] = accumulate ? x : 0.0;
+                b[u] = accumulate ? y : 0.0;
             }
+#pragma unroll 4
             for (int i = 0; i < nv; ++i) {
                 const VecRef vi = vecs[i];
+                const double ci = c[i];
+                double p[U], q[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (j0 + u < M) {
-                        const int64_t s = sidx(t, j0 + u);
-                        a[u] += c[i] * vi.p0[s] * vi.s0;
-                        b[u] += c[i] * vi.p1[s] * vi.s1;
-                    }
+                for (int u = 0; u < U; ++u) { p[u] = vi.p0[sl[u]]; q[u] = vi.p1[sl[u]]; }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    a[u] += ci * p[u] * vi.s0;
+                    b[u] += ci * q[u] * vi.s1;
+                }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (j0 + u < M) { const int64_t s = sidx(t, j0 + u); o0[s] = a[u]; o1[s] = b[u]; }
+                if (j0 + u < M) { o0[sl[u]] = a[u]; o1[sl[u]] = b[u]; }
         }
         __syncthreads();
     }

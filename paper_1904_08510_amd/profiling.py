@@ -5,10 +5,11 @@
 
 `stats` prints the per-kernel time table of a kernel-trace run.  `pmc`
 combines a FETCH_SIZE run and a WRITE_SIZE run (counters in KiB per
-dispatch) into HBM bytes per launch of the solve kernel, each counter scaled
-by what it reads for the calibration copy (a device-to-device copy of known
-size that bench.py --calib-copy performs), and records the hash of the
-kernel sources the counters were taken with.
+dispatch) into HBM bytes per launch of each launch of a batched step (the
+gather, the solve, the write-back), each counter scaled by what it reads for
+the calibration copy (a device-to-device copy of known size that bench.py
+--calib-copy performs), and records the hash of the kernel sources the
+counters were taken with.
 """
 from __future__ import annotations
 
@@ -22,6 +23,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOLVE_KERNEL = "k_solve"
+STEP_KERNELS = ("k_gather", "k_solve", "k_scatter")
 COPY_KERNEL = "copyBuffer"
 CALIB_BYTES = 256 * 1024 * 1024   # bench.py --calib-copy: one copy of this many bytes
 
@@ -57,34 +59,43 @@ def stats(d: str) -> str:
 
 def _counter_per_dispatch(d: str, counter: str):
     rows = list(csv.DictReader(open(_find(d, "counter_collection.csv"))))
-    solve, copy = [], []
+    per = {k: [] for k in STEP_KERNELS}
+    copy = []
     for r in rows:
         if r.get("Counter_Name") != counter:
             continue
         name = r.get("Kernel_Name", "")
         v = float(r["Counter_Value"])
-        if SOLVE_KERNEL in name:
-            solve.append(v)
-        elif COPY_KERNEL in name:
-            copy.append(v)
-    return solve, copy
+        for k in STEP_KERNELS:
+            if k in name:
+                per[k].append(v)
+                break
+        else:
+            if COPY_KERNEL in name:
+                copy.append(v)
+    return per, copy
 
 
 def pmc(fetch_dir: str, write_dir: str, out_path: str) -> dict:
     fs, fc = _counter_per_dispatch(fetch_dir, "FETCH_SIZE")
     ws, wc = _counter_per_dispatch(write_dir, "WRITE_SIZE")
-    if not fs or not ws or not fc or not wc:
+    if not fs[SOLVE_KERNEL] or not ws[SOLVE_KERNEL] or not fc or not wc:
         raise RuntimeError("missing solve or calibration-copy dispatches in the counter runs")
     # the calibration copy is the largest copy dispatch (it reads and writes CALIB_BYTES)
     f_scale = CALIB_BYTES / (max(fc) * 1024.0)
     w_scale = CALIB_BYTES / (max(wc) * 1024.0)
-    fetch = sum(fs) / len(fs) * 1024.0 * f_scale
-    write = sum(ws) / len(ws) * 1024.0 * w_scale
-    res = dict(source_hash=source_hash(), kernel=SOLVE_KERNEL, dispatches=len(fs),
-               fetch_kib_per_dispatch=sum(fs) / len(fs), write_kib_per_dispatch=sum(ws) / len(ws),
-               copy_fetch_kib=max(fc), copy_write_kib=max(wc), fetch_scale=f_scale,
-               write_scale=w_scale, fetch_bytes=fetch, write_bytes=write,
-               traffic_bytes_per_launch=fetch + write)
+    kernels = {}
+    for k in STEP_KERNELS:
+        if not fs[k] or not ws[k]:
+            continue
+        fetch = sum(fs[k]) / len(fs[k]) * 1024.0 * f_scale
+        write = sum(ws[k]) / len(ws[k]) * 1024.0 * w_scale
+        kernels[k] = dict(dispatches=len(fs[k]), fetch_kib_per_dispatch=sum(fs[k]) / len(fs[k]),
+                          write_kib_per_dispatch=sum(ws[k]) / len(ws[k]), fetch_bytes=fetch,
+                          write_bytes=write, traffic_bytes_per_launch=fetch + write)
+    res = dict(source_hash=source_hash(), kernel=SOLVE_KERNEL, copy_fetch_kib=max(fc), copy_write_kib=max(wc),
+               fetch_scale=f_scale, write_scale=w_scale, kernels=kernels,
+               traffic_bytes_per_launch=kernels[SOLVE_KERNEL]["traffic_bytes_per_launch"])
     with open(out_path, "w") as fh:
         json.dump(res, fh, indent=1)
     return res
