@@ -373,7 +373,7 @@ struct Column {
         const double* dp0 = wantstep ? stepdir.p0 : fv;
         const double* dp1 = wantstep ? stepdir.p1 : fv;
         struct Own { double f, k, q, d0, d1; };
-        sweep<2, FluxRec>(getx, FluxFace{},
+        sweep<4, FluxRec>(getx, FluxFace{},
             [&](int64_t s) {
                 Own o;
                 o.f = fv[s]; o.k = kv[s]; o.q = qv[s];
@@ -513,13 +513,17 @@ struct Column {
                     g = Df / cd.h;
                     if (prm.has_u) wf = uf[v] * cd.h / Df;
                 }
-                if (may_reuse)
-                    changed = changed || ofa[v] != r || ofg[v] != g || okd[v] != dt * kl[v] ||
-                              (prm.has_u && ofw[v] != wf);
-                W.fa[s] = r; W.fg[s] = g;
-                if (prm.has_u) W.fw[s] = wf;
+                // coefficients equal to the stored ones (bit for bit) are not
+                // written again
+                const bool same = may_reuse && ofa[v] == r && ofg[v] == g && okd[v] == dt * kl[v] &&
+                                  (!prm.has_u || ofw[v] == wf);
+                changed = changed || (may_reuse && !same);
+                if (!same) {
+                    W.fa[s] = r; W.fg[s] = g;
+                    if (prm.has_u) W.fw[s] = wf;
+                    W.kd[s] = dt * kl[v];
+                }
                 W.f[s] = ne[v] + dt * sr[v];
-                W.kd[s] = dt * kl[v];
                 W.q[s] = qq[v];
                 X00[s] = ne[v]; X01[s] = ph[v];
                 if (extrap) { X10[s] = 2.0 * ne[v] - pn[v]; X11[s] = 2.0 * ph[v] - pp[v]; }
@@ -640,7 +644,7 @@ struct Column {
                 sm[2] += nC * nC; sm[3] += pC * pC;
             };
             if (extrap) {
-                sweep2<2, ScRec, FluxRec>(
+                sweep2<4, ScRec, FluxRec>(
                     [&](int64_t s, double& a, double& b) { a = X00[s]; b = X01[s]; },
                     [&](int64_t s, double& a, double& b) { a = X10[s]; b = X11[s]; },
                     scface, FluxFace{}, own,
@@ -804,7 +808,7 @@ struct Column {
             gprev = ga; aprev = al;
         };
 
-        sweep<2, JacRec>(
+        sweep<4, JacRec>(
             [&](int64_t s, double& a, double& b) { a = X0[s]; b = X1[s]; },
             JacFace{},
             [&](int64_t s) { return W.kd[s]; },
@@ -1156,7 +1160,7 @@ struct Column {
         const VecRef b0 = nbf > 0 ? basis[0] : VecRef{F0, F1, 0.0, 0.0};
         const VecRef b1 = nbf > 1 ? basis[1] : VecRef{F0, F1, 0.0, 0.0};
         struct Own { double f, k, q, F0, F1, v00, v01, v10, v11; };
-        sweep<2, FluxRec>(
+        sweep<4, FluxRec>(
             [&](int64_t s, double& a, double& b) { a = X0[s] + e0 * z.p0[s]; b = X1[s] + e1 * z.p1[s]; },
             FluxFace{},
             [&](int64_t s) {
