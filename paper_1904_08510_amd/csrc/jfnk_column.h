@@ -28,6 +28,11 @@ template <class R>
 struct Blk { R a, b, c, d; };   // [[a b] [c d]]
 template <class R>
 struct Vec2 { R x, y; };
+// aligned records for vector loads and stores (one instruction per record)
+template <class R>
+struct alignas(4 * sizeof(R)) V4 { R a, b, c, d; };
+template <class R>
+struct alignas(2 * sizeof(R)) V2 { R x, y; };
 
 template <class R> __device__ __forceinline__ Blk<R> bmul(const Blk<R>& p, const Blk<R>& q) {
     return {p.a * q.a + p.b * q.c, p.a * q.b + p.b * q.d, p.c * q.a + p.d * q.c, p.c * q.b + p.d * q.d};
@@ -44,6 +49,12 @@ template <class R> __device__ __forceinline__ Blk<R> binv(const Blk<R>& p) {
     return {p.d * id, -p.b * id, -p.c * id, p.a * id};
 }
 __device__ __forceinline__ Blk<double> bzero() { return {0.0, 0.0, 0.0, 0.0}; }
+
+// Store through the global address space.  A store through a generic (flat)
+// pointer also counts against the LDS wait counter, so the next barrier or
+// LDS reduction would wait for it to reach memory; a global store does not.
+template <class R>
+__device__ __forceinline__ void gst(R* p, R v) { *(__attribute__((address_space(1))) R*)p = v; }
 __device__ __forceinline__ Blk<double> beye() { return {1.0, 0.0, 0.0, 1.0}; }
 
 // ---------------------------------------------------------------------------
@@ -81,8 +92,14 @@ __device__ __forceinline__ void bernoulli_dpair(double x, double bx, double bmx,
 // Workgroup reductions (wave64 butterflies + LDS across waves).  Fixed order:
 // bitwise reproducible from run to run.
 // ---------------------------------------------------------------------------
-template <int T, int K>
-__device__ __forceinline__ void wg_sum(double (&v)[K], double* scr) {
+// LDS-typed double: the solver keeps its workgroup scratch behind a pointer
+// of this type, so accesses compile to LDS instructions even in phase
+// functions the compiler keeps out of line (a generic pointer would compile
+// to flat accesses, which also wait on the vector-memory counter).
+typedef __attribute__((address_space(3))) double ldbl;
+
+template <int T, int K, class SP>
+__device__ __forceinline__ void wg_sum(double (&v)[K], SP scr) {
     constexpr int NW = T / 64;
 #pragma unroll
     for (int k = 0; k < K; ++k)
@@ -104,8 +121,8 @@ __device__ __forceinline__ void wg_sum(double (&v)[K], double* scr) {
     __syncthreads();
 }
 
-template <int T, int K>
-__device__ __forceinline__ void wg_max(double (&v)[K], double* scr) {
+template <int T, int K, class SP>
+__device__ __forceinline__ void wg_max(double (&v)[K], SP scr) {
     constexpr int NW = T / 64;
 #pragma unroll
     for (int k = 0; k < K; ++k)
@@ -170,14 +187,14 @@ struct Column {
     ColDesc cd;
     Work W;
     SolverParams prm;
-    double* lds;
+    ldbl* lds;
     int t;
     double ih, dth, epsh;            // 1/h, dt/h, (eps/e)/h
     double rR, gR, wR;               // right-wall face coefficients
     double sfn, sfp, sxn, sxp, isfn, isfp;
     bool fac_reuse = false;          // setup found the previous step's factors usable
 
-    __device__ void init(const ColDesc& d, const Work& w, const SolverParams& p, double* l) {
+    __device__ void init(const ColDesc& d, const Work& w, const SolverParams& p, ldbl* l) {
         cd = d; W = w; prm = p; lds = l;
         t = threadIdx.x;
         ih = 1.0 / cd.h;
@@ -193,9 +210,23 @@ struct Column {
     __device__ __forceinline__ double* Vb(int k, int comp) const { return W.V + (2 * (int64_t)k + comp) * W.P; }
     __device__ __forceinline__ double* Zb(int k, int comp) const { return W.Z + (2 * (int64_t)k + comp) * W.P; }
     __device__ __forceinline__ double* dXb(int comp) const { return W.dX + comp * W.P; }
-    __device__ __forceinline__ FT* fac(int slot) const { return (FT*)W.fac + slot * W.P; }
-    __device__ __forceinline__ FT* tmpv(int comp) const { return (FT*)W.tmp + comp * W.P; }
-    __device__ __forceinline__ double* ftmp(int slot) const { return W.ftmp + slot * W.P; }
+    // Per-cell factor values (FT), one record per cell for each sweep that
+    // reads them, so a sweep loads whole records with vector instructions:
+    //   [P][8]  slots 0..7:   m and m A      (apply down sweep)
+    //   [P][4]  slots 8..11:  g = m C        (apply up sweep)
+    //   [P][8]  slots 12..19: a'' and g''    (apply final sweep)
+    //   [P][4]  slots 20..23: approximate-Schur couplings
+    __device__ __forceinline__ FT* facp(int slot, int64_t s) const {
+        FT* base = (FT*)W.fac;
+        if (slot < 8) return base + s * 8 + slot;
+        if (slot < 12) return base + 8 * W.P + s * 4 + (slot - 8);
+        if (slot < 20) return base + 12 * W.P + s * 8 + (slot - 12);
+        return base + 20 * W.P + s * 4 + (slot - 20);
+    }
+    // the apply's intermediate d (2 FT per cell) and the factorisation's FP64
+    // temporaries (8 per cell), one record per cell
+    __device__ __forceinline__ V2<FT>* tmpp(int64_t s) const { return (V2<FT>*)W.tmp + s; }
+    __device__ __forceinline__ double* ftmpp(int64_t s) const { return W.ftmp + 8 * s; }
     // this thread's chunk entry of per-chunk slot k (SoA over the chunks)
     __device__ __forceinline__ double* red(int k) const { return W.red + cd.red + (int64_t)k * T + t; }
 
@@ -402,7 +433,7 @@ struct Column {
                 oF0[s] = 0.0; oF1[s] = 0.0;
                 if (oX0) { oX0[s] = 0.0; oX1[s] = 0.0; }
             });
-        double* scr = lds + Lds<T>::kScr;
+        ldbl* scr = lds + Lds<T>::kScr;
         wg_max<T, 3>(mx, scr);
         wg_sum<T, 4>(sm, scr);
         Norms r;
@@ -595,9 +626,9 @@ struct Column {
             changed = false;
             for (int i = cd.g0; i < cd.g0 + cd.gn; ++i) changed = changed || W.gflag[i] != 0;
         } else {
-            changed = gather(U, 0, ntiles(), t >> 6, T / 64, lds + Lds<T>::kMisc);
+            changed = gather(U, 0, ntiles(), t >> 6, T / 64, (double*)(lds + Lds<T>::kMisc));
             __syncthreads();
-            const double* misc = lds + Lds<T>::kMisc;
+            const ldbl* misc = lds + Lds<T>::kMisc;
             rR = misc[0]; gR = misc[1]; wR = misc[2];
             __syncthreads();
         }
@@ -670,7 +701,7 @@ struct Column {
                     [&](int64_t s) { F0[s] = 0.0; F1[s] = 0.0; });
             }
         }
-        double* scr = lds + Lds<T>::kScr;
+        ldbl* scr = lds + Lds<T>::kScr;
         wg_max<T, 9>(mx, scr);
         wg_sum<T, 8>(sm, scr);
         const double mr[2] = {mx[5], mx[6]};
@@ -767,12 +798,12 @@ struct Column {
         }
     };
 
-    __device__ void store_blk(int slot, int64_t s, const Blk<double>& m) {
-        fac(slot + 0)[s] = (FT)m.a; fac(slot + 1)[s] = (FT)m.b;
-        fac(slot + 2)[s] = (FT)m.c; fac(slot + 3)[s] = (FT)m.d;
+    __device__ __forceinline__ void store_blk(int slot, int64_t s, const Blk<double>& m) {
+        *(V4<FT>*)facp(slot, s) = V4<FT>{(FT)m.a, (FT)m.b, (FT)m.c, (FT)m.d};
     }
-    __device__ Blk<FT> load_blk(int slot, int64_t s) const {
-        return {fac(slot + 0)[s], fac(slot + 1)[s], fac(slot + 2)[s], fac(slot + 3)[s]};
+    __device__ __forceinline__ Blk<FT> load_blk(int slot, int64_t s) const {
+        const V4<FT> r = *(const V4<FT>*)facp(slot, s);
+        return {r.a, r.b, r.c, r.d};
     }
 
     __device__ void factor(int cur) {
@@ -785,8 +816,6 @@ struct Column {
         const double s_en = isfn * sxn, s_ep = isfn * sxp, s_pn = isfp * sxn, s_pp = isfp * sxp;
         Blk<double> A0 = bzero(), B0 = beye(), C0 = bzero();
         Blk<double> gprev = bzero(), aprev = bzero();
-        double* T0 = ftmp(0); double* T1 = ftmp(1); double* T2 = ftmp(2); double* T3 = ftmp(3);
-        double* T4 = ftmp(4); double* T5 = ftmp(5); double* T6 = ftmp(6); double* T7 = ftmp(7);
 
         auto rowproc = [&](int j, int64_t s, const Blk<double>& A, const Blk<double>& B,
                            const Blk<double>& C) {
@@ -803,8 +832,9 @@ struct Column {
             store_blk(0, s, m);
             store_blk(4, s, bmul(m, A));
             store_blk(8, s, ga);
-            T0[s] = al.a; T1[s] = al.b; T2[s] = al.c; T3[s] = al.d;
-            T4[s] = ga.a; T5[s] = ga.b; T6[s] = ga.c; T7[s] = ga.d;
+            V4<double>* tr = (V4<double>*)ftmpp(s);
+            tr[0] = V4<double>{al.a, al.b, al.c, al.d};
+            tr[1] = V4<double>{ga.a, ga.b, ga.c, ga.d};
             gprev = ga; aprev = al;
         };
 
@@ -841,7 +871,7 @@ struct Column {
                     // diag(dt D_f - I, S~) with S~ = L + I_e dt D_r, the Schur
                     // complement with (dt D_f - I)^-1 replaced by -I (scaled units:
                     // -(s_Fn / s_Xn) I)
-                    fac(20)[s] = (FT)A.b; fac(21)[s] = (FT)B.b; fac(22)[s] = (FT)C.b; fac(23)[s] = (FT)B.c;
+                    *(V4<FT>*)facp(20, s) = V4<FT>{(FT)A.b, (FT)B.b, (FT)C.b, (FT)B.c};
                     const double kap = B.c / s_en;
                     A = Blk<double>{A.a, 0.0, 0.0, A.d + kap * A.b};
                     C = Blk<double>{C.a, 0.0, 0.0, C.d + kap * C.b};
@@ -852,7 +882,7 @@ struct Column {
             [&](int64_t s) {
                 const int j = (int)((s - cd.ws) / T);
                 if (prm.prec_kind == 1) {
-                    fac(20)[s] = FT(0); fac(21)[s] = FT(0); fac(22)[s] = FT(0); fac(23)[s] = FT(0);
+                    *(V4<FT>*)facp(20, s) = V4<FT>{FT(0), FT(0), FT(0), FT(0)};
                 }
                 rowproc(j, s, bzero(), beye(), bzero());
             });
@@ -870,8 +900,10 @@ struct Column {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int64_t s = sidx(t, max(j0 - u, 1));   // unconditional loads
-                    aa[u] = Blk<double>{T0[s], T1[s], T2[s], T3[s]};
-                    gg[u] = Blk<double>{T4[s], T5[s], T6[s], T7[s]};
+                    const V4<double>* tr = (const V4<double>*)ftmpp(s);
+                    const V4<double> ra = tr[0], rg = tr[1];
+                    aa[u] = Blk<double>{ra.a, ra.b, ra.c, ra.d};
+                    gg[u] = Blk<double>{rg.a, rg.b, rg.c, rg.d};
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -888,7 +920,7 @@ struct Column {
             a1 = an; g1 = gn;
         }
         // reduced system row of chunk t
-        double* P = lds + Lds<T>::kPcr;
+        ldbl* P = lds + Lds<T>::kPcr;
         __syncthreads();
         P[8 * t + 0] = aL.a; P[8 * t + 1] = aL.b; P[8 * t + 2] = aL.c; P[8 * t + 3] = aL.d;
         P[8 * t + 4] = gL.a; P[8 * t + 5] = gL.b; P[8 * t + 6] = gL.c; P[8 * t + 7] = gL.d;
@@ -901,27 +933,31 @@ struct Column {
         Blk<double> Lr = bneg(bmul(A0, aLp));
         Blk<double> Dr = bsub(bsub(B0, bmul(A0, gLp)), bmul(C0, a1));
         Blk<double> Ur = bneg(bmul(C0, g1));
-        red(0)[0] = A0.a; red(1)[0] = A0.b; red(2)[0] = A0.c; red(3)[0] = A0.d;
-        red(4)[0] = C0.a; red(5)[0] = C0.b; red(6)[0] = C0.c; red(7)[0] = C0.d;
+        // locals: the barriers below make the compiler reload members of an
+        // out-of-line phase function's object from memory after each of them
+        const int tl = t;
+        double* const rb = W.red + cd.red + tl;      // red(k) = rb + k T
+        gst(rb + 0 * T, A0.a); gst(rb + 1 * T, A0.b); gst(rb + 2 * T, A0.c); gst(rb + 3 * T, A0.d);
+        gst(rb + 4 * T, C0.a); gst(rb + 5 * T, C0.b); gst(rb + 6 * T, C0.c); gst(rb + 7 * T, C0.d);
         // parallel cyclic reduction (FP64)
         int k = 8;
         for (int st = 1; st < T; st <<= 1, k += 8) {
             __syncthreads();
-            double* row = P + 12 * t;
+            ldbl* row = P + 12 * tl;
             row[0] = Lr.a; row[1] = Lr.b; row[2] = Lr.c; row[3] = Lr.d;
             row[4] = Dr.a; row[5] = Dr.b; row[6] = Dr.c; row[7] = Dr.d;
             row[8] = Ur.a; row[9] = Ur.b; row[10] = Ur.c; row[11] = Ur.d;
             __syncthreads();
             Blk<double> k1 = bzero(), k2 = bzero(), Lm = bzero(), Um = bzero(), Lp = bzero(), Up = bzero();
-            if (t >= st) {
-                const double* o = P + 12 * (t - st);
+            if (tl >= st) {
+                const ldbl* o = P + 12 * (tl - st);
                 Lm = {o[0], o[1], o[2], o[3]};
                 const Blk<double> Dm{o[4], o[5], o[6], o[7]};
                 Um = {o[8], o[9], o[10], o[11]};
                 k1 = bmul(Lr, binv(Dm));
             }
-            if (t + st < T) {
-                const double* o = P + 12 * (t + st);
+            if (tl + st < T) {
+                const ldbl* o = P + 12 * (tl + st);
                 Lp = {o[0], o[1], o[2], o[3]};
                 const Blk<double> Dp{o[4], o[5], o[6], o[7]};
                 Up = {o[8], o[9], o[10], o[11]};
@@ -930,11 +966,13 @@ struct Column {
             Dr = bsub(bsub(Dr, bmul(k1, Um)), bmul(k2, Lp));
             Lr = bneg(bmul(k1, Lm));
             Ur = bneg(bmul(k2, Up));
-            red(k + 0)[0] = k1.a; red(k + 1)[0] = k1.b; red(k + 2)[0] = k1.c; red(k + 3)[0] = k1.d;
-            red(k + 4)[0] = k2.a; red(k + 5)[0] = k2.b; red(k + 6)[0] = k2.c; red(k + 7)[0] = k2.d;
+            double* const rk = rb + (int64_t)k * T;
+            gst(rk + 0 * T, k1.a); gst(rk + 1 * T, k1.b); gst(rk + 2 * T, k1.c); gst(rk + 3 * T, k1.d);
+            gst(rk + 4 * T, k2.a); gst(rk + 5 * T, k2.b); gst(rk + 6 * T, k2.c); gst(rk + 7 * T, k2.d);
         }
         const Blk<double> Di = binv(Dr);
-        red(k + 0)[0] = Di.a; red(k + 1)[0] = Di.b; red(k + 2)[0] = Di.c; red(k + 3)[0] = Di.d;
+        double* const rk = rb + (int64_t)k * T;
+        gst(rk + 0 * T, Di.a); gst(rk + 1 * T, Di.b); gst(rk + 2 * T, Di.c); gst(rk + 3 * T, Di.d);
         if (t == 0) {
             ColState* cs = W.cst + cd.index;
             cs->fac_valid = 1;
@@ -965,7 +1003,7 @@ struct Column {
         block_apply(VecRef{v.p0, v.p1, v.s0, 0.0}, Y0, Y1);            // Y0 = z_e'
         for (int j = 0; j < M; ++j) {
             const int64_t s = sidx(t, j);
-            Y2[s] = v.p1[s] * v.s1 - (double)fac(23)[s] * Y0[s];        // v_phi - I_e z_e'
+            Y2[s] = v.p1[s] * v.s1 - (double)*facp(23, s) * Y0[s];        // v_phi - I_e z_e'
         }
         block_apply(VecRef{Y2, Y2, 0.0, 1.0}, Y3, z1);                  // z1 = z_phi
         // dt D_r z_phi (tridiagonal; neighbours across chunks are visible after
@@ -977,7 +1015,7 @@ struct Column {
             if (c < n) {
                 const double zl = c > 0 ? z1[sidx((c - 1) / M, (c - 1) % M)] : 0.0;
                 const double zr = c < n - 1 ? z1[sidx((c + 1) / M, (c + 1) % M)] : 0.0;
-                w = (double)fac(20)[s] * zl + (double)fac(21)[s] * z1[s] + (double)fac(22)[s] * zr;
+                w = (double)*facp(20, s) * zl + (double)*facp(21, s) * z1[s] + (double)*facp(22, s) * zr;
             }
             Y2[s] = w;
         }
@@ -1000,18 +1038,17 @@ struct Column {
     // Block solve with the stored factors (chunk sweeps in FT, reduced
     // system in FP64).  Returns (||z||_2^2, ||z||_inf).
     __device__ Vec2<double> block_apply(const VecRef& v, double* z0, double* z1) {
+        const int tl = t;   // a local: members are reloaded after every barrier
         constexpr int U = 4;
         constexpr int LG = ilog2(T);             // PCR stages of the interface system
         const int M = cd.M;
-        FT* D0 = tmpv(0);
-        FT* D1 = tmpv(1);
         // The interface system's coefficients do not depend on v: their loads
         // are issued first, so that their latency overlaps the chunk sweeps
         // instead of adding one memory round trip per PCR stage.
         double pc[8 * LG + 12];
 #pragma unroll
         for (int i = 0; i < 8 * LG + 12; ++i) pc[i] = red(i)[0];
-        Vec2<double> d0{v.p0[sidx(t, 0)] * v.s0, v.p1[sidx(t, 0)] * v.s1};
+        Vec2<double> d0{v.p0[sidx(tl, 0)] * v.s0, v.p1[sidx(tl, 0)] * v.s1};
         // down sweep: d_j = m_j v_j - At_j d_{j-1}, loads of U rows issued first
         Vec2<FT> dprev{FT(0), FT(0)};
         for (int j0 = 1; j0 < M; j0 += U) {
@@ -1019,7 +1056,7 @@ struct Column {
             Vec2<FT> vv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int64_t s = sidx(t, min(j0 + u, M - 1));   // unconditional loads
+                const int64_t s = sidx(tl, min(j0 + u, M - 1));   // unconditional loads
                 mm[u] = load_blk(0, s);
                 aa[u] = load_blk(4, s);
                 vv[u] = Vec2<FT>{(FT)(v.p0[s] * v.s0), (FT)(v.p1[s] * v.s1)};
@@ -1028,13 +1065,13 @@ struct Column {
             for (int u = 0; u < U; ++u) {
                 const int j = j0 + u;
                 if (j < M) {
-                    const int64_t s = sidx(t, j);
+                    const int64_t s = sidx(tl, j);
                     Vec2<FT> de = bmv(mm[u], vv[u]);
                     if (j >= 2) {
                         const Vec2<FT> q = bmv(aa[u], dprev);
                         de.x -= q.x; de.y -= q.y;
                     }
-                    D0[s] = de.x; D1[s] = de.y;
+                    *tmpp(s) = V2<FT>{de.x, de.y};
                     dprev = de;
                 }
             }
@@ -1049,29 +1086,29 @@ struct Column {
                 Vec2<FT> dd[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int64_t s = sidx(t, max(j0 - u, 1));   // unconditional loads
+                    const int64_t s = sidx(tl, max(j0 - u, 1));   // unconditional loads
                     gg[u] = load_blk(8, s);
-                    dd[u] = Vec2<FT>{D0[s], D1[s]};
+                    { const V2<FT> r = *tmpp(s); dd[u] = Vec2<FT>{r.x, r.y}; }
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int j = j0 - u;
                     if (j >= 1) {
-                        const int64_t s = sidx(t, j);
+                        const int64_t s = sidx(tl, j);
                         const Vec2<FT> q = bmv(gg[u], dn);
                         dn = {dd[u].x - q.x, dd[u].y - q.y};
-                        D0[s] = dn.x; D1[s] = dn.y;
+                        *tmpp(s) = V2<FT>{dn.x, dn.y};
                     }
                 }
             }
             dFirst = {(double)dn.x, (double)dn.y};
         }
-        double* P = lds + Lds<T>::kPcr;
+        ldbl* P = lds + Lds<T>::kPcr;
         __syncthreads();
-        P[2 * t] = dLast.x; P[2 * t + 1] = dLast.y;
+        P[2 * tl] = dLast.x; P[2 * tl + 1] = dLast.y;
         __syncthreads();
         Vec2<double> dLp{0.0, 0.0};
-        if (t > 0) dLp = {P[2 * (t - 1)], P[2 * (t - 1) + 1]};
+        if (tl > 0) dLp = {P[2 * (tl - 1)], P[2 * (tl - 1) + 1]};
         const Blk<double> A0{pc[0], pc[1], pc[2], pc[3]};
         const Blk<double> C0{pc[4], pc[5], pc[6], pc[7]};
         const Vec2<double> qa = bmv(A0, dLp), qc = bmv(C0, dFirst);
@@ -1080,16 +1117,16 @@ struct Column {
         for (int lv = 0; lv < LG; ++lv) {
             const int st = 1 << lv, k = 8 + 8 * lv;
             __syncthreads();
-            P[2 * t] = r.x; P[2 * t + 1] = r.y;
+            P[2 * tl] = r.x; P[2 * tl + 1] = r.y;
             __syncthreads();
-            if (t >= st) {
+            if (tl >= st) {
                 const Blk<double> k1{pc[k], pc[k + 1], pc[k + 2], pc[k + 3]};
-                const Vec2<double> q = bmv(k1, Vec2<double>{P[2 * (t - st)], P[2 * (t - st) + 1]});
+                const Vec2<double> q = bmv(k1, Vec2<double>{P[2 * (tl - st)], P[2 * (tl - st) + 1]});
                 r.x -= q.x; r.y -= q.y;
             }
-            if (t + st < T) {
+            if (tl + st < T) {
                 const Blk<double> k2{pc[k + 4], pc[k + 5], pc[k + 6], pc[k + 7]};
-                const Vec2<double> q = bmv(k2, Vec2<double>{P[2 * (t + st)], P[2 * (t + st) + 1]});
+                const Vec2<double> q = bmv(k2, Vec2<double>{P[2 * (tl + st)], P[2 * (tl + st) + 1]});
                 r.x -= q.x; r.y -= q.y;
             }
         }
@@ -1097,13 +1134,13 @@ struct Column {
         const Blk<double> Di{pc[k], pc[k + 1], pc[k + 2], pc[k + 3]};
         const Vec2<double> x0 = bmv(Di, r);
         __syncthreads();
-        P[2 * t] = x0.x; P[2 * t + 1] = x0.y;
+        P[2 * tl] = x0.x; P[2 * tl + 1] = x0.y;
         __syncthreads();
         Vec2<double> xn{0.0, 0.0};
-        if (t + 1 < T) xn = {P[2 * (t + 1)], P[2 * (t + 1) + 1]};
+        if (tl + 1 < T) xn = {P[2 * (tl + 1)], P[2 * (tl + 1) + 1]};
         double zz = 0.0, zm = 0.0;
         {
-            const int64_t s = sidx(t, 0);
+            const int64_t s = sidx(tl, 0);
             z0[s] = x0.x; z1[s] = x0.y;
             zz += x0.x * x0.x + x0.y * x0.y;
             zm = fmax(fabs(x0.x), fabs(x0.y));
@@ -1113,16 +1150,16 @@ struct Column {
             Vec2<FT> dd[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int64_t s = sidx(t, min(j0 + u, M - 1));   // unconditional loads
+                const int64_t s = sidx(tl, min(j0 + u, M - 1));   // unconditional loads
                 aa[u] = load_blk(12, s);
                 gg[u] = load_blk(16, s);
-                dd[u] = Vec2<FT>{D0[s], D1[s]};
+                { const V2<FT> r = *tmpp(s); dd[u] = Vec2<FT>{r.x, r.y}; }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = j0 + u;
                 if (j < M) {
-                    const int64_t s = sidx(t, j);
+                    const int64_t s = sidx(tl, j);
                     const Blk<FT> a = aa[u], g = gg[u];
                     const double zx = (double)dd[u].x - ((double)a.a * x0.x + (double)a.b * x0.y) -
                                       ((double)g.a * xn.x + (double)g.b * xn.y);
@@ -1146,8 +1183,9 @@ struct Column {
     // written to (w0, w1), fused with up to 8 dot products against basis
     // vectors and ||w||^2 (dots[nb] on return).
     // ------------------------------------------------------------------
+    template <class BP>
     __device__ void jv(int cur, const VecRef& z, double eps, double* w0, double* w1,
-                       const VecRef* basis, int nb, double* dots) {
+                       BP basis, int nb, double* dots) {
         const double* X0 = xb(cur, 0);
         const double* X1 = xb(cur, 1);
         const double* F0 = Fb(cur, 0);
@@ -1189,7 +1227,8 @@ struct Column {
     }
 
     // dots[i] = basis[i] . w for i in [i0, nb)
-    __device__ void dots_more(const double* w0, const double* w1, const VecRef* basis, int i0, int nb,
+    template <class BP>
+    __device__ void dots_more(const double* w0, const double* w1, BP basis, int i0, int nb,
                               double* dots) {
         constexpr int U = 2;
         const int M = cd.M;
@@ -1234,7 +1273,8 @@ struct Column {
 
     // One classical Gram-Schmidt pass: w -= sum_i h[i] basis[i]; then
     // dots[i] = basis[i] . w (i < nb) and dots[nb] = ||w||^2.
-    __device__ void cgs_pass(double* w0, double* w1, const VecRef* basis, int nb, const double* h,
+    template <class BP>
+    __device__ void cgs_pass(double* w0, double* w1, BP basis, int nb, const double* h,
                              double* dots) {
         constexpr int U = 4;
         const int M = cd.M;

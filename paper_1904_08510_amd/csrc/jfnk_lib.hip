@@ -38,7 +38,7 @@ __global__ __launch_bounds__(T) void k_solve(SolveArgs a) {
     extern __shared__ double lds[];
     const int ci = a.order[blockIdx.x];
     DevExec<T, FT> ex;
-    ex.col.init(a.W.cols[ci], a.W, a.prm, lds);
+    ex.col.init(a.W.cols[ci], a.W, a.prm, (ldbl*)lds);
     ex.U = a.U;
     ColOutcome o;
     jfnk_solve(ex, a.prm, o);
@@ -106,7 +106,7 @@ template <int T, class FT>
 __global__ __launch_bounds__(T) void k_phase(PhaseArgs a) {
     extern __shared__ double lds[];
     Column<T, FT> col;
-    col.init(a.W.cols[a.ci], a.W, a.prm, lds);
+    col.init(a.W.cols[a.ci], a.W, a.prm, (ldbl*)lds);
     double* scal = a.W.scal + (int64_t)a.ci * kScalSlots;
     VecRef* bl = (VecRef*)(lds + Lds<T>::kBasis);
     if (a.phase != PH_SETUP) col.load_state();
@@ -898,7 +898,8 @@ int jfnk_create(const jfnk_config* cfg, jfnk_ctx** out) {
     ctx->cfg = *cfg;
     if (hipGetDevice(&ctx->device) != hipSuccess) { delete ctx; return JFNK_EHIP; }
     const int Tcap = cfg->threads_override > 0 ? cfg->threads_override : kTmax;
-    ctx->capP = cfg->max_total_cells + (int64_t)cfg->max_cols * Tcap;
+    // a multiple of 64 cells: every workspace array then starts 512-byte aligned
+    ctx->capP = (cfg->max_total_cells + (int64_t)cfg->max_cols * Tcap + 63) / 64 * 64;
     ctx->capRed = (int64_t)cfg->max_cols * Tcap * kRedPerChunk;
     const int64_t per = work_doubles_per_cell(cfg->gmres_restart);
     const int64_t words = per * ctx->capP + ctx->capRed +

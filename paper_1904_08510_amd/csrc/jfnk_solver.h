@@ -259,8 +259,10 @@ struct DevExec {
     Column<T, FT> col;
     UserArrays U;
 
-    __device__ VecRef* basis_lds() { return (VecRef*)(col.lds + Lds<T>::kBasis); }
-    __device__ double* Hl() { return col.lds + Lds<T>::kH; }
+    __device__ VecRef* basis_lds() { return (VecRef*)(double*)(col.lds + Lds<T>::kBasis); }
+    // the small dense GMRES state (shared host/device routines take generic pointers)
+    __device__ double* Hl() { return (double*)(col.lds + Lds<T>::kH); }
+    __device__ double* lg(int off) { return (double*)(col.lds + off); }
 
     // the batched schedule runs the gather and the write-back as launches of their own
     static constexpr bool split = true;
@@ -298,34 +300,34 @@ struct DevExec {
     __device__ void gm_begin(double beta) {
         __syncthreads();
         if (threadIdx.x == 0) {
-            double* g = col.lds + Lds<T>::kG;
+            ldbl* g = col.lds + Lds<T>::kG;
             g[0] = beta;
             for (int i = 1; i <= kMaxRestart; ++i) g[i] = 0.0;
         }
         __syncthreads();
     }
     __device__ double gm_probe(int j, const double* h, double hn) {
-        return givens_column(Hl(), kMaxRestart + 1, col.lds + Lds<T>::kCs, col.lds + Lds<T>::kSn,
-                             col.lds + Lds<T>::kG, j, h, hn, false);
+        return givens_column(Hl(), kMaxRestart + 1, lg(Lds<T>::kCs), lg(Lds<T>::kSn),
+                             lg(Lds<T>::kG), j, h, hn, false);
     }
     __device__ double gm_commit(int j, const double* h, double hn) {
-        double r = givens_column(Hl(), kMaxRestart + 1, col.lds + Lds<T>::kCs, col.lds + Lds<T>::kSn,
-                                 col.lds + Lds<T>::kG, j, h, hn, false);
+        double r = givens_column(Hl(), kMaxRestart + 1, lg(Lds<T>::kCs), lg(Lds<T>::kSn),
+                                 lg(Lds<T>::kG), j, h, hn, false);
         __syncthreads();
         if (threadIdx.x == 0)
-            givens_column(Hl(), kMaxRestart + 1, col.lds + Lds<T>::kCs, col.lds + Lds<T>::kSn,
-                          col.lds + Lds<T>::kG, j, h, hn, true);
+            givens_column(Hl(), kMaxRestart + 1, lg(Lds<T>::kCs), lg(Lds<T>::kSn),
+                          lg(Lds<T>::kG), j, h, hn, true);
         __syncthreads();
         return r;
     }
     __device__ void gm_solve(int k, double* y) {
-        givens_solve(Hl(), kMaxRestart + 1, col.lds + Lds<T>::kG, k, y);
+        givens_solve(Hl(), kMaxRestart + 1, lg(Lds<T>::kG), k, y);
     }
     // Newton direction d = (dX if have_dx) + sum_i y_i Z_i.  A first-cycle
     // direction made of a single Krylov vector stays implicit (y_0 Z_0, no
     // sweep); restart_residual materialises it before Z_0 is reused.
     __device__ int direction(int k, const double* y, bool have_dx) {
-        double* misc = col.lds + Lds<T>::kMisc;
+        ldbl* misc = col.lds + Lds<T>::kMisc;
         if (k == 1 && !have_dx) {
             __syncthreads();
             if (threadIdx.x == 0) { misc[8] = 1.0; misc[9] = y[0]; }
@@ -340,14 +342,14 @@ struct DevExec {
         return k;
     }
     __device__ VecRef dir_ref() {
-        const double* misc = col.lds + Lds<T>::kMisc;
+        const ldbl* misc = col.lds + Lds<T>::kMisc;
         if (misc[8] == 1.0) return VecRef{col.Zb(0, 0), col.Zb(0, 1), misc[9], misc[9]};
         return VecRef{col.dXb(0), col.dXb(1), 1.0, 1.0};
     }
     // r = -F~ - J dX into V slot 0; returns ||r||.  Materialises an implicit
     // single-vector direction into dX first.
     __device__ double restart_residual(int cur, double xnorm) {
-        double* misc = col.lds + Lds<T>::kMisc;
+        ldbl* misc = col.lds + Lds<T>::kMisc;
         if (misc[8] == 1.0) {
             const VecRef z0{col.Zb(0, 0), col.Zb(0, 1), 1.0, 1.0};
             const double c = misc[9];
