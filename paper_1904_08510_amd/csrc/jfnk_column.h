@@ -146,9 +146,18 @@ __device__ __forceinline__ void wg_max(double (&v)[K], SP scr) {
 
 // A two-component vector of one column with a scale per component:
 // value(s) = (p0[s] * s0, p1[s] * s1).
+// One component of a two-component per-cell field (n_e, phi) stored as
+// interleaved pairs: element s of component c sits at base[2 s + c].  The
+// two components of a cell then sit in one 16-byte record, and a sweep that
+// reads both issues one vector load for them.
+struct CP {
+    double* p;
+    __host__ __device__ __forceinline__ double& operator[](int64_t s) const { return p[2 * s]; }
+};
+
 struct VecRef {
-    const double* p0;
-    const double* p1;
+    CP p0;
+    CP p1;
     double s0, s1;
 };
 
@@ -205,11 +214,13 @@ struct Column {
     __device__ __forceinline__ int64_t sidx(int tt, int j) const {
         return cd.ws + (int64_t)j * T + tt;
     }
-    __device__ __forceinline__ double* xb(int b, int comp) const { return W.x + (2 * b + comp) * W.P; }
-    __device__ __forceinline__ double* Fb(int b, int comp) const { return W.F + (2 * b + comp) * W.P; }
-    __device__ __forceinline__ double* Vb(int k, int comp) const { return W.V + (2 * (int64_t)k + comp) * W.P; }
-    __device__ __forceinline__ double* Zb(int k, int comp) const { return W.Z + (2 * (int64_t)k + comp) * W.P; }
-    __device__ __forceinline__ double* dXb(int comp) const { return W.dX + comp * W.P; }
+    // two-component fields: buffer b is an array of P (n_e, phi) pairs
+    __device__ __forceinline__ CP xb(int b, int comp) const { return CP{W.x + 2 * b * W.P + comp}; }
+    __device__ __forceinline__ CP Fb(int b, int comp) const { return CP{W.F + 2 * b * W.P + comp}; }
+    __device__ __forceinline__ CP Vb(int k, int comp) const { return CP{W.V + 2 * (int64_t)k * W.P + comp}; }
+    __device__ __forceinline__ CP Zb(int k, int comp) const { return CP{W.Z + 2 * (int64_t)k * W.P + comp}; }
+    __device__ __forceinline__ CP dXb(int comp) const { return CP{W.dX + comp}; }
+    __device__ __forceinline__ CP schb(int k) const { return CP{W.sch + 2 * (k >> 1) * W.P + (k & 1)}; }
     // Per-cell factor values (FT), one record per cell for each sweep that
     // reads them, so a sweep loads whole records with vector instructions:
     //   [P][8]  slots 0..7:   m and m A      (apply down sweep)
@@ -390,7 +401,7 @@ struct Column {
     // optionally, the state itself; returns the scaled norms.
     // ------------------------------------------------------------------
     template <class GetX>
-    __device__ Norms residual(GetX getx, double* oF0, double* oF1, double* oX0, double* oX1,
+    __device__ Norms residual(GetX getx, CP oF0, CP oF1, CP oX0, CP oX1,
                               VecRef stepdir, double steplam) {
         double mx[3] = {0.0, 0.0, 0.0};       // max|Fe|, max|Fp|, max|step|
         double sm[4] = {0.0, 0.0, 0.0, 0.0};  // sum Fe^2, sum Fp^2, sum n^2, sum phi^2
@@ -398,11 +409,11 @@ struct Column {
         const double* fv = W.f;
         const double* kv = W.kd;
         const double* qv = W.q;
-        const bool wantstep = stepdir.p0 != nullptr;
+        const bool wantstep = stepdir.p0.p != nullptr;
         // without a step direction the step loads read a valid array instead
         // (unconditional loads issue back to back) and are not used
-        const double* dp0 = wantstep ? stepdir.p0 : fv;
-        const double* dp1 = wantstep ? stepdir.p1 : fv;
+        const CP dp0 = wantstep ? stepdir.p0 : xb(0, 0);
+        const CP dp1 = wantstep ? stepdir.p1 : xb(0, 1);
         struct Own { double f, k, q, d0, d1; };
         sweep<4, FluxRec>(getx, FluxFace{},
             [&](int64_t s) {
@@ -417,7 +428,7 @@ struct Column {
                 const double fp = -nC + o.q + eps_h * (R.grd - L.grd);
                 oF0[s] = fe;
                 oF1[s] = fp;
-                if (oX0) { oX0[s] = nC; oX1[s] = pC; }
+                if (oX0.p) { oX0[s] = nC; oX1[s] = pC; }
                 mx[0] = fmax(mx[0], fabs(fe));
                 mx[1] = fmax(mx[1], fabs(fp));
                 sm[0] += fe * fe;
@@ -431,7 +442,7 @@ struct Column {
             },
             [&](int64_t s) {
                 oF0[s] = 0.0; oF1[s] = 0.0;
-                if (oX0) { oX0[s] = 0.0; oX1[s] = 0.0; }
+                if (oX0.p) { oX0[s] = 0.0; oX1[s] = 0.0; }
             });
         ldbl* scr = lds + Lds<T>::kScr;
         wg_max<T, 3>(mx, scr);
@@ -473,9 +484,9 @@ struct Column {
         const int M = cd.M, n = cd.n;
         const double dt = cd.dt, hb = 0.5 * cd.h;
         const int64_t fo = cd.uoff + cd.index;   // faces of column: n + 1 per column
-        double* X00 = xb(0, 0); double* X01 = xb(0, 1);
-        double* X10 = xb(1, 0); double* X11 = xb(1, 1);
-        double* X20 = xb(2, 0); double* X21 = xb(2, 1);
+        const CP X00 = xb(0, 0); const CP X01 = xb(0, 1);
+        const CP X10 = xb(1, 0); const CP X11 = xb(1, 1);
+        const CP X20 = xb(2, 0); const CP X21 = xb(2, 1);
         const bool extrap = prm.guess >= 1 && prm.has_prev;
         const bool learn = prm.guess == 2 && prm.has_learned && W.lmask[cd.index] != 0;
         const bool may_reuse = prm.fac_reuse && W.cst[cd.index].fac_valid;
@@ -572,7 +583,7 @@ struct Column {
 
     // Workspace buffer -> caller arrays (natural layout), tiles [kb, ke) of
     // gather in the other direction.
-    __device__ void scatter(const double* s0p, const double* s1p, double* o0, double* o1, int kb, int ke,
+    __device__ void scatter(CP s0p, CP s1p, double* o0, double* o1, int kb, int ke,
                             int w, int nw) {
         const int M = cd.M, n = cd.n;
         const int lane = threadIdx.x & 63;
@@ -610,9 +621,9 @@ struct Column {
     // and the change flags of its gather workgroups in W.gflag[g0, g0 + gn)),
     // scalings, residuals of the start candidates.
     __device__ Norms setup(const UserArrays& U, int* cur, int* guess_used, bool gathered = false) {
-        const double* X00 = xb(0, 0); const double* X01 = xb(0, 1);
-        const double* X10 = xb(1, 0); const double* X11 = xb(1, 1);
-        const double* X20 = xb(2, 0); const double* X21 = xb(2, 1);
+        const CP X00 = xb(0, 0); const CP X01 = xb(0, 1);
+        const CP X10 = xb(1, 0); const CP X11 = xb(1, 1);
+        const CP X20 = xb(2, 0); const CP X21 = xb(2, 1);
         const bool extrap = prm.guess >= 1 && prm.has_prev;
         const bool learn = prm.guess == 2 && prm.has_learned && W.lmask[cd.index] != 0;
         // the previous step's record of this column (read before it is rewritten)
@@ -642,8 +653,8 @@ struct Column {
         double sm[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         {
             const double dt_h = dth, eps_h = epsh;
-            double* F0 = Fb(0, 0); double* F1 = Fb(0, 1);
-            double* E0 = Fb(1, 0); double* E1 = Fb(1, 1);
+            const CP F0 = Fb(0, 0); const CP F1 = Fb(0, 1);
+            const CP E0 = Fb(1, 0); const CP E1 = Fb(1, 1);
             struct Own { double f, k, q; };
             const auto scface = [](double r, double g, double w, double ihf, double nA, double pA, double nB,
                                    double pB) {
@@ -722,7 +733,7 @@ struct Column {
         if (isnan(sm[0]) || isnan(sm[1])) best.r2 = NAN;
         *cur = 0;
         *guess_used = 0;
-        const VecRef none{nullptr, nullptr, 0.0, 0.0};
+        const VecRef none{CP{nullptr}, CP{nullptr}, 0.0, 0.0};
         if (extrap) {
             Norms e;
             e.rinf = fmax(mx[7] * isfn, mx[8] * isfp);
@@ -750,7 +761,7 @@ struct Column {
         }
         if (learn) {
             Norms l = residual([&](int64_t s, double& a, double& b) { a = X20[s]; b = X21[s]; },
-                               Fb(2, 0), Fb(2, 1), nullptr, nullptr, none, 0.0);
+                               Fb(2, 0), Fb(2, 1), CP{nullptr}, CP{nullptr}, none, 0.0);
             l.step = INFINITY;
             // fallback rule: the learned guess must beat the plain one strictly
             if (!isnan(l.r2) && (isnan(best.r2) || l.rinf < best.rinf)) {
@@ -809,8 +820,8 @@ struct Column {
     __device__ void factor(int cur) {
         const int M = cd.M, n = cd.n;
         const int c0 = t * M;
-        const double* X0 = xb(cur, 0);
-        const double* X1 = xb(cur, 1);
+        const CP X0 = xb(cur, 0);
+        const CP X1 = xb(cur, 1);
         const double dt_h = dth, eps_h = epsh;
         // scale factors of the four block entries
         const double s_en = isfn * sxn, s_ep = isfn * sxp, s_pn = isfp * sxn, s_pp = isfp * sxp;
@@ -985,7 +996,7 @@ struct Column {
     // Preconditioner apply z = P^-1 v.  Returns (||z||_2^2, ||z||_inf).
     // v and z must not alias.
     // ------------------------------------------------------------------
-    __device__ Vec2<double> apply(const VecRef& v, double* z0, double* z1) {
+    __device__ Vec2<double> apply(const VecRef& v, CP z0, CP z1) {
         return prm.prec_kind == 1 ? apply_schur(v, z0, z1) : block_apply(v, z0, z1);
     }
 
@@ -994,12 +1005,9 @@ struct Column {
     //   z_e  = z_e' - (dt D_f - I)^-1 dt D_r z_phi,
     // three solves with the factors of diag(dt D_f - I, S~) (each a pass of
     // the block solver with one component of the right-hand side zero).
-    __device__ Vec2<double> apply_schur(const VecRef& v, double* z0, double* z1) {
+    __device__ Vec2<double> apply_schur(const VecRef& v, CP z0, CP z1) {
         const int M = cd.M, n = cd.n;
-        double* Y0 = W.sch;
-        double* Y1 = W.sch + W.P;
-        double* Y2 = W.sch + 2 * W.P;
-        double* Y3 = W.sch + 3 * W.P;
+        const CP Y0 = schb(0), Y1 = schb(1), Y2 = schb(2), Y3 = schb(3);
         block_apply(VecRef{v.p0, v.p1, v.s0, 0.0}, Y0, Y1);            // Y0 = z_e'
         for (int j = 0; j < M; ++j) {
             const int64_t s = sidx(t, j);
@@ -1037,7 +1045,7 @@ struct Column {
 
     // Block solve with the stored factors (chunk sweeps in FT, reduced
     // system in FP64).  Returns (||z||_2^2, ||z||_inf).
-    __device__ Vec2<double> block_apply(const VecRef& v, double* z0, double* z1) {
+    __device__ Vec2<double> block_apply(const VecRef& v, CP z0, CP z1) {
         const int tl = t;   // a local: members are reloaded after every barrier
         constexpr int U = 4;
         constexpr int LG = ilog2(T);             // PCR stages of the interface system
@@ -1184,12 +1192,12 @@ struct Column {
     // vectors and ||w||^2 (dots[nb] on return).
     // ------------------------------------------------------------------
     template <class BP>
-    __device__ void jv(int cur, const VecRef& z, double eps, double* w0, double* w1,
+    __device__ void jv(int cur, const VecRef& z, double eps, CP w0, CP w1,
                        BP basis, int nb, double* dots) {
-        const double* X0 = xb(cur, 0);
-        const double* X1 = xb(cur, 1);
-        const double* F0 = Fb(cur, 0);
-        const double* F1 = Fb(cur, 1);
+        const CP X0 = xb(cur, 0);
+        const CP X1 = xb(cur, 1);
+        const CP F0 = Fb(cur, 0);
+        const CP F1 = Fb(cur, 1);
         const double e0 = eps * sxn * z.s0, e1 = eps * sxp * z.s1;
         const double c0 = isfn / eps, c1 = isfp / eps;
         const double dt_h = dth, eps_h = epsh;
@@ -1228,7 +1236,7 @@ struct Column {
 
     // dots[i] = basis[i] . w for i in [i0, nb)
     template <class BP>
-    __device__ void dots_more(const double* w0, const double* w1, BP basis, int i0, int nb,
+    __device__ void dots_more(CP w0, CP w1, BP basis, int i0, int nb,
                               double* dots) {
         constexpr int U = 2;
         const int M = cd.M;
@@ -1274,7 +1282,7 @@ struct Column {
     // One classical Gram-Schmidt pass: w -= sum_i h[i] basis[i]; then
     // dots[i] = basis[i] . w (i < nb) and dots[nb] = ||w||^2.
     template <class BP>
-    __device__ void cgs_pass(double* w0, double* w1, BP basis, int nb, const double* h,
+    __device__ void cgs_pass(CP w0, CP w1, BP basis, int nb, const double* h,
                              double* dots) {
         constexpr int U = 4;
         const int M = cd.M;
@@ -1334,7 +1342,7 @@ struct Column {
     }
 
     // out = (accumulate ? out : 0) + sum_i c[i] vecs[i]
-    __device__ void lincomb(double* o0, double* o1, const VecRef* vecs, const double* c, int nv,
+    __device__ void lincomb(CP o0, CP o1, const VecRef* vecs, const double* c, int nv,
                             bool accumulate) {
         constexpr int U = 4;
         const int M = cd.M;
@@ -1371,8 +1379,8 @@ struct Column {
 
     // Line-search trial X_t = X + lam S_X d, its residual and norms.
     __device__ Norms trial(int cur, int out, const VecRef& d, double lam) {
-        const double* X0 = xb(cur, 0);
-        const double* X1 = xb(cur, 1);
+        const CP X0 = xb(cur, 0);
+        const CP X1 = xb(cur, 1);
         const double a0 = lam * sxn * d.s0, a1 = lam * sxp * d.s1;
         return residual(
             [&](int64_t s, double& a, double& b) { a = X0[s] + a0 * d.p0[s]; b = X1[s] + a1 * d.p1[s]; },
@@ -1381,15 +1389,15 @@ struct Column {
 
     // Residual of buffer b (test export / re-evaluation)
     __device__ Norms eval(int b) {
-        const double* X0 = xb(b, 0);
-        const double* X1 = xb(b, 1);
-        const VecRef none{nullptr, nullptr, 0.0, 0.0};
+        const CP X0 = xb(b, 0);
+        const CP X1 = xb(b, 1);
+        const VecRef none{CP{nullptr}, CP{nullptr}, 0.0, 0.0};
         return residual([&](int64_t s, double& a, double& c) { a = X0[s]; c = X1[s]; },
-                        Fb(b, 0), Fb(b, 1), nullptr, nullptr, none, 0.0);
+                        Fb(b, 0), Fb(b, 1), CP{nullptr}, CP{nullptr}, none, 0.0);
     }
 
     // Workspace buffer -> caller arrays (natural layout)
-    __device__ void write_back(const double* s0p, const double* s1p, double* o0, double* o1) {
+    __device__ void write_back(CP s0p, CP s1p, double* o0, double* o1) {
         const int M = cd.M, n = cd.n;
         for (int j = 0; j < M; ++j) {
             const int c = t * M + j;

@@ -163,8 +163,8 @@ __global__ __launch_bounds__(T) void k_phase(PhaseArgs a) {
     }
     case PH_NORM_DX: {
         double dd[1] = {0.0};
-        const double* d0 = col.dXb(0);
-        const double* d1 = col.dXb(1);
+        const CP d0 = col.dXb(0);
+        const CP d1 = col.dXb(1);
         for (int j = 0; j < col.cd.M; ++j) {
             const int64_t s = col.sidx(col.t, j);
             dd[0] += d0[s] * d0[s] + d1[s] * d1[s];
@@ -174,10 +174,10 @@ __global__ __launch_bounds__(T) void k_phase(PhaseArgs a) {
         break;
     }
     case PH_RES0: {
-        double* v0 = col.Vb(0, 0);
-        double* v1 = col.Vb(0, 1);
-        const double* F0 = col.Fb(a.cur, 0);
-        const double* F1 = col.Fb(a.cur, 1);
+        const CP v0 = col.Vb(0, 0);
+        const CP v1 = col.Vb(0, 1);
+        const CP F0 = col.Fb(a.cur, 0);
+        const CP F1 = col.Fb(a.cur, 1);
         double acc[1] = {0.0};
         for (int j = 0; j < col.cd.M; ++j) {
             const int64_t s = col.sidx(col.t, j);
@@ -214,8 +214,8 @@ __global__ __launch_bounds__(T) void k_phase(PhaseArgs a) {
     case PH_LOAD_X:
     case PH_LOAD_V: {
         // natural-layout caller arrays -> buffer (x[cur] or Z[zslot])
-        double* o0 = (a.phase == PH_LOAD_X) ? col.xb(a.cur, 0) : col.Zb(a.zslot, 0);
-        double* o1 = (a.phase == PH_LOAD_X) ? col.xb(a.cur, 1) : col.Zb(a.zslot, 1);
+        const CP o0 = (a.phase == PH_LOAD_X) ? col.xb(a.cur, 0) : col.Zb(a.zslot, 0);
+        const CP o1 = (a.phase == PH_LOAD_X) ? col.xb(a.cur, 1) : col.Zb(a.zslot, 1);
         for (int j = 0; j < col.cd.M; ++j) {
             const int c = col.t * col.cd.M + j;
             const int64_t s = col.sidx(col.t, j);
@@ -472,11 +472,12 @@ struct HostExecT {
     double implicit_y = 0.0;
 
     const ColDesc& cd() const { return ctx->h_cols[a.ci]; }
-    double* xb(int b, int comp) const { return ctx->W.x + (2 * b + comp) * ctx->W.P; }
-    double* Fb(int b, int comp) const { return ctx->W.F + (2 * b + comp) * ctx->W.P; }
-    double* Vb(int k, int comp) const { return ctx->W.V + (2 * (int64_t)k + comp) * ctx->W.P; }
-    double* Zb(int k, int comp) const { return ctx->W.Z + (2 * (int64_t)k + comp) * ctx->W.P; }
-    double* dXb(int comp) const { return ctx->W.dX + comp * ctx->W.P; }
+    // device addresses of the two-component fields (interleaved pairs, as Column)
+    CP xb(int b, int comp) const { return CP{ctx->W.x + 2 * b * ctx->W.P + comp}; }
+    CP Fb(int b, int comp) const { return CP{ctx->W.F + 2 * b * ctx->W.P + comp}; }
+    CP Vb(int k, int comp) const { return CP{ctx->W.V + 2 * (int64_t)k * ctx->W.P + comp}; }
+    CP Zb(int k, int comp) const { return CP{ctx->W.Z + 2 * (int64_t)k * ctx->W.P + comp}; }
+    CP dXb(int comp) const { return CP{ctx->W.dX + comp}; }
 
     void launch(int phase) {
         a.phase = phase;
@@ -1201,7 +1202,7 @@ int jfnk_block_solve(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, 
         a.zslot = 0; a.in0 = r_ne; a.in1 = r_phi;
         rc = run({PH_LOAD_V});
         if (rc) return rc;
-        a.v = VecRef{ctx->W.Z, ctx->W.Z + ctx->W.P, 1.0, 1.0};
+        a.v = VecRef{CP{ctx->W.Z}, CP{ctx->W.Z + 1}, 1.0, 1.0};
         a.zslot = 1;
         rc = run({PH_APPLY});
         if (rc) return rc;

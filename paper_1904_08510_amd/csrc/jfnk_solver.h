@@ -272,7 +272,7 @@ struct DevExec {
     __device__ void factor(int cur) { col.factor(cur); }
 
     __device__ VecRef fref(int cur, double sc) {
-        return VecRef{col.Fb(cur, 0) + 0, col.Fb(cur, 1) + 0, sc * col.isfn, sc * col.isfp};
+        return VecRef{col.Fb(cur, 0), col.Fb(cur, 1), sc * col.isfn, sc * col.isfp};
     }
     __device__ VecRef vslot(int k, double sc) { return VecRef{col.Vb(k, 0), col.Vb(k, 1), sc, sc}; }
     __device__ void set_basis(int i, VecRef r) {
@@ -372,10 +372,10 @@ struct DevExec {
         double dots[2];
         col.jv(cur, d, eps, col.Vb(0, 0), col.Vb(0, 1), basis_lds(), 0, dots);
         // r = -F~ - w
-        double* v0 = col.Vb(0, 0);
-        double* v1 = col.Vb(0, 1);
-        const double* F0 = col.Fb(cur, 0);
-        const double* F1 = col.Fb(cur, 1);
+        const CP v0 = col.Vb(0, 0);
+        const CP v1 = col.Vb(0, 1);
+        const CP F0 = col.Fb(cur, 0);
+        const CP F1 = col.Fb(cur, 1);
         double acc[1] = {0.0};
         for (int j = 0; j < col.cd.M; ++j) {
             const int64_t s = col.sidx(col.t, j);
