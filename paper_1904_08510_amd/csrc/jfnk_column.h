@@ -161,6 +161,14 @@ struct VecRef {
     double s0, s1;
 };
 
+// Both components of cell s of a vector whose components are the two halves
+// of one pair array (p1 = p0 + 1: every Krylov vector, preconditioned
+// vector, residual and direction), with one 16-byte load.
+__device__ __forceinline__ Vec2<double> ld_pair(const VecRef& v, int64_t s) {
+    const V2<double> r = *(const V2<double>*)(v.p0.p + 2 * s);
+    return {r.x, r.y};
+}
+
 struct Norms {
     double rinf;    // ||S_F^-1 F||_inf
     double r2;      // ||S_F^-1 F||_2
@@ -1212,9 +1220,10 @@ struct Column {
             [&](int64_t s) {
                 Own o;
                 o.f = W.f[s]; o.k = W.kd[s]; o.q = W.q[s]; o.F0 = F0[s]; o.F1 = F1[s];
-                o.v00 = b0.p0[s]; o.v01 = b0.p1[s];
-                o.v10 = b1.p0[s];            // b1 is a valid array for any nb; its dot
-                o.v11 = b1.p1[s];            // is used only when nb > 1
+                const Vec2<double> e0 = ld_pair(b0, s), e1 = ld_pair(b1, s);
+                o.v00 = e0.x; o.v01 = e0.y;
+                o.v10 = e1.x;                // b1 is a valid array for any nb; its dot
+                o.v11 = e1.y;                // is used only when nb > 1
                 return o;
             },
             [&](int64_t s, int c, double nC, double pC, const FluxRec& L, const FluxRec& R, const Own& o) {
@@ -1263,8 +1272,9 @@ struct Column {
                 for (int i = 0; i < 8; ++i)
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        p[i][u] = bv[i].p0[sl[u]];
-                        q[i][u] = bv[i].p1[sl[u]];
+                        const Vec2<double> e = ld_pair(bv[i], sl[u]);
+                        p[i][u] = e.x;
+                        q[i][u] = e.y;
                     }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
@@ -1307,7 +1317,7 @@ struct Column {
                 const double hi = h[i];
                 double p[U], q[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) { p[u] = bi.p0[sl[u]]; q[u] = bi.p1[sl[u]]; }
+                for (int u = 0; u < U; ++u) { const Vec2<double> e = ld_pair(bi, sl[u]); p[u] = e.x; q[u] = e.y; }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     a[u] -= hi * p[u] * bi.s0;
@@ -1325,7 +1335,7 @@ struct Column {
                 const VecRef bi = basis[i];
                 double p[U], q[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) { p[u] = bi.p0[sl[u]]; q[u] = bi.p1[sl[u]]; }
+                for (int u = 0; u < U; ++u) { const Vec2<double> e = ld_pair(bi, sl[u]); p[u] = e.x; q[u] = e.y; }
                 double sacc = 0.0;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -1363,7 +1373,7 @@ struct Column {
                 const double ci = c[i];
                 double p[U], q[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) { p[u] = vi.p0[sl[u]]; q[u] = vi.p1[sl[u]]; }
+                for (int u = 0; u < U; ++u) { const Vec2<double> e = ld_pair(vi, sl[u]); p[u] = e.x; q[u] = e.y; }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     a[u] += ci * p[u] * vi.s0;
