@@ -276,24 +276,35 @@ struct Column {
         if (c0 == 0) { nL = cd.nel; pL = cd.phil; ihL = 2.0 * ih; }
         else { getx(sidx(t - 1, M - 1), nL, pL); ihL = ih; }
         FaceRec FL = face(W.fa[s0], W.fg[s0], prm.has_u ? W.fw[s0] : 0.0, ihL, nL, pL, nC, pC);
-        for (int j0 = 0; j0 < jr; j0 += U) {
+        // Group of U rows' operands.  Loads carry no conditions, so a group's
+        // loads issue back to back: rows past the chunk's end reload its last
+        // real row, and the last cell of the column reloads itself in place of
+        // its (absent) right neighbour; neither value is used.
+        struct Grp {
             double xn[U], xp[U], fa[U], fg[U], fw[U];
             Own ow[U];
+        };
+        auto load_grp = [&](int j0, Grp& g) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                // Loads without conditions, so that the U rows' loads issue back
-                // to back: rows past the chunk's end reload its last real row, and
-                // the last cell of the column reloads itself in place of its
-                // (absent) right neighbour.  Neither value is used.
                 const int j = min(j0 + u, jr - 1);
                 const int64_t s = sidx(t, j);
-                ow[u] = own(s);
+                g.ow[u] = own(s);
                 const int64_t sn = (c0 + j >= n - 1) ? s : ((j + 1 < M) ? s + T : sidx(t + 1, 0));
-                getx(sn, xn[u], xp[u]);
-                fa[u] = W.fa[sn];
-                fg[u] = W.fg[sn];
-                fw[u] = W.fw[sn];
+                getx(sn, g.xn[u], g.xp[u]);
+                g.fa[u] = W.fa[sn];
+                g.fg[u] = W.fg[sn];
+                g.fw[u] = W.fw[sn];
             }
+        };
+        // Double buffer: the next group's loads issue before this group's
+        // results are stored.  Loads and stores share one in-order counter, so
+        // loads issued after the stores would also wait for the stores to
+        // reach memory.
+        Grp gc, gn;
+        load_grp(0, gc);
+        for (int j0 = 0; j0 < jr; j0 += U) {
+            load_grp(j0 + U, gn);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = j0 + u;
@@ -306,13 +317,14 @@ struct Column {
                         nR = cd.ner; pR = cd.phir;
                         FR = face(rR, gR, wR, 2.0 * ih, nC, pC, nR, pR);
                     } else {
-                        nR = xn[u]; pR = xp[u];
-                        FR = face(fa[u], fg[u], prm.has_u ? fw[u] : 0.0, ih, nC, pC, nR, pR);
+                        nR = gc.xn[u]; pR = gc.xp[u];
+                        FR = face(gc.fa[u], gc.fg[u], prm.has_u ? gc.fw[u] : 0.0, ih, nC, pC, nR, pR);
                     }
-                    cell(s, c, nC, pC, FL, FR, ow[u]);
+                    cell(s, c, nC, pC, FL, FR, gc.ow[u]);
                     nC = nR; pC = pR; FL = FR;
                 }
             }
+            gc = gn;
         }
         for (int j = jr; j < M; ++j) pad(sidx(t, j));
     }
@@ -423,7 +435,7 @@ struct Column {
         const CP dp0 = wantstep ? stepdir.p0 : xb(0, 0);
         const CP dp1 = wantstep ? stepdir.p1 : xb(0, 1);
         struct Own { double f, k, q, d0, d1; };
-        sweep<4, FluxRec>(getx, FluxFace{},
+        sweep<2, FluxRec>(getx, FluxFace{},
             [&](int64_t s) {
                 Own o;
                 o.f = fv[s]; o.k = kv[s]; o.q = qv[s];
@@ -857,7 +869,7 @@ struct Column {
             gprev = ga; aprev = al;
         };
 
-        sweep<4, JacRec>(
+        sweep<2, JacRec>(
             [&](int64_t s, double& a, double& b) { a = X0[s]; b = X1[s]; },
             JacFace{},
             [&](int64_t s) { return W.kd[s]; },
@@ -1214,7 +1226,7 @@ struct Column {
         const VecRef b0 = nbf > 0 ? basis[0] : VecRef{F0, F1, 0.0, 0.0};
         const VecRef b1 = nbf > 1 ? basis[1] : VecRef{F0, F1, 0.0, 0.0};
         struct Own { double f, k, q, F0, F1, v00, v01, v10, v11; };
-        sweep<4, FluxRec>(
+        sweep<2, FluxRec>(
             [&](int64_t s, double& a, double& b) { a = X0[s] + e0 * z.p0[s]; b = X1[s] + e1 * z.p1[s]; },
             FluxFace{},
             [&](int64_t s) {
