@@ -1078,30 +1078,40 @@ struct Column {
         for (int i = 0; i < 8 * LG + 12; ++i) pc[i] = red(i)[0];
         Vec2<double> d0{v.p0[sidx(tl, 0)] * v.s0, v.p1[sidx(tl, 0)] * v.s1};
         // down sweep: d_j = m_j v_j - At_j d_{j-1}, loads of U rows issued first
+        // Each of the three sweeps double-buffers its U-row groups: the next
+        // group's (unconditional) loads issue before this group's stores, which
+        // would otherwise hold them up in the shared in-order memory counter.
         Vec2<FT> dprev{FT(0), FT(0)};
-        for (int j0 = 1; j0 < M; j0 += U) {
-            Blk<FT> mm[U], aa[U];
-            Vec2<FT> vv[U];
+        if (M >= 2) {
+            struct GD { Blk<FT> mm[U], aa[U]; Vec2<FT> vv[U]; };
+            auto load_d = [&](int j0, GD& g) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t s = sidx(tl, min(j0 + u, M - 1));   // unconditional loads
-                mm[u] = load_blk(0, s);
-                aa[u] = load_blk(4, s);
-                vv[u] = Vec2<FT>{(FT)(v.p0[s] * v.s0), (FT)(v.p1[s] * v.s1)};
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int j = j0 + u;
-                if (j < M) {
-                    const int64_t s = sidx(tl, j);
-                    Vec2<FT> de = bmv(mm[u], vv[u]);
-                    if (j >= 2) {
-                        const Vec2<FT> q = bmv(aa[u], dprev);
-                        de.x -= q.x; de.y -= q.y;
-                    }
-                    *tmpp(s) = V2<FT>{de.x, de.y};
-                    dprev = de;
+                for (int u = 0; u < U; ++u) {
+                    const int64_t s = sidx(tl, min(j0 + u, M - 1));
+                    g.mm[u] = load_blk(0, s);
+                    g.aa[u] = load_blk(4, s);
+                    g.vv[u] = Vec2<FT>{(FT)(v.p0[s] * v.s0), (FT)(v.p1[s] * v.s1)};
                 }
+            };
+            GD gc, gn;
+            load_d(1, gc);
+            for (int j0 = 1; j0 < M; j0 += U) {
+                load_d(j0 + U, gn);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = j0 + u;
+                    if (j < M) {
+                        const int64_t s = sidx(tl, j);
+                        Vec2<FT> de = bmv(gc.mm[u], gc.vv[u]);
+                        if (j >= 2) {
+                            const Vec2<FT> q = bmv(gc.aa[u], dprev);
+                            de.x -= q.x; de.y -= q.y;
+                        }
+                        *tmpp(s) = V2<FT>{de.x, de.y};
+                        dprev = de;
+                    }
+                }
+                gc = gn;
             }
         }
         // up sweep: d''_j = d_j - g_j d''_{j+1}
@@ -1109,25 +1119,33 @@ struct Column {
         Vec2<double> dLast{0.0, 0.0}, dFirst{0.0, 0.0};
         if (M >= 2) {
             dLast = {(double)dn.x, (double)dn.y};
-            for (int j0 = M - 2; j0 >= 1; j0 -= U) {
-                Blk<FT> gg[U];
-                Vec2<FT> dd[U];
+            // the next group holds rows below the current one, which this sweep
+            // has not rewritten yet (the clamped rows of a last prefetch go unused)
+            struct GU { Blk<FT> gg[U]; Vec2<FT> dd[U]; };
+            auto load_u = [&](int j0, GU& g) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int64_t s = sidx(tl, max(j0 - u, 1));   // unconditional loads
-                    gg[u] = load_blk(8, s);
-                    { const V2<FT> r = *tmpp(s); dd[u] = Vec2<FT>{r.x, r.y}; }
+                    const int64_t s = sidx(tl, max(j0 - u, 1));
+                    g.gg[u] = load_blk(8, s);
+                    const V2<FT> r = *tmpp(s);
+                    g.dd[u] = Vec2<FT>{r.x, r.y};
                 }
+            };
+            GU gc, gn;
+            if (M >= 3) load_u(M - 2, gc);
+            for (int j0 = M - 2; j0 >= 1; j0 -= U) {
+                load_u(j0 - U, gn);
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int j = j0 - u;
                     if (j >= 1) {
                         const int64_t s = sidx(tl, j);
-                        const Vec2<FT> q = bmv(gg[u], dn);
-                        dn = {dd[u].x - q.x, dd[u].y - q.y};
+                        const Vec2<FT> q = bmv(gc.gg[u], dn);
+                        dn = {gc.dd[u].x - q.x, gc.dd[u].y - q.y};
                         *tmpp(s) = V2<FT>{dn.x, dn.y};
                     }
                 }
+                gc = gn;
             }
             dFirst = {(double)dn.x, (double)dn.y};
         }
@@ -1173,30 +1191,38 @@ struct Column {
             zz += x0.x * x0.x + x0.y * x0.y;
             zm = fmax(fabs(x0.x), fabs(x0.y));
         }
-        for (int j0 = 1; j0 < M; j0 += U) {
-            Blk<FT> aa[U], gg[U];
-            Vec2<FT> dd[U];
+        if (M >= 2) {
+            struct GF { Blk<FT> aa[U], gg[U]; Vec2<FT> dd[U]; };
+            auto load_f = [&](int j0, GF& g) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t s = sidx(tl, min(j0 + u, M - 1));   // unconditional loads
-                aa[u] = load_blk(12, s);
-                gg[u] = load_blk(16, s);
-                { const V2<FT> r = *tmpp(s); dd[u] = Vec2<FT>{r.x, r.y}; }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int j = j0 + u;
-                if (j < M) {
-                    const int64_t s = sidx(tl, j);
-                    const Blk<FT> a = aa[u], g = gg[u];
-                    const double zx = (double)dd[u].x - ((double)a.a * x0.x + (double)a.b * x0.y) -
-                                      ((double)g.a * xn.x + (double)g.b * xn.y);
-                    const double zy = (double)dd[u].y - ((double)a.c * x0.x + (double)a.d * x0.y) -
-                                      ((double)g.c * xn.x + (double)g.d * xn.y);
-                    z0[s] = zx; z1[s] = zy;
-                    zz += zx * zx + zy * zy;
-                    zm = fmax(zm, fmax(fabs(zx), fabs(zy)));
+                for (int u = 0; u < U; ++u) {
+                    const int64_t s = sidx(tl, min(j0 + u, M - 1));
+                    g.aa[u] = load_blk(12, s);
+                    g.gg[u] = load_blk(16, s);
+                    const V2<FT> r = *tmpp(s);
+                    g.dd[u] = Vec2<FT>{r.x, r.y};
                 }
+            };
+            GF gc, gn;
+            load_f(1, gc);
+            for (int j0 = 1; j0 < M; j0 += U) {
+                load_f(j0 + U, gn);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = j0 + u;
+                    if (j < M) {
+                        const int64_t s = sidx(tl, j);
+                        const Blk<FT> a = gc.aa[u], g = gc.gg[u];
+                        const double zx = (double)gc.dd[u].x - ((double)a.a * x0.x + (double)a.b * x0.y) -
+                                          ((double)g.a * xn.x + (double)g.b * xn.y);
+                        const double zy = (double)gc.dd[u].y - ((double)a.c * x0.x + (double)a.d * x0.y) -
+                                          ((double)g.c * xn.x + (double)g.d * xn.y);
+                        z0[s] = zx; z1[s] = zy;
+                        zz += zx * zx + zy * zy;
+                        zm = fmax(zm, fmax(fabs(zx), fabs(zy)));
+                    }
+                }
+                gc = gn;
             }
         }
         double sm[1] = {zz};
