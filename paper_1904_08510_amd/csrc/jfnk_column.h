@@ -359,22 +359,29 @@ struct Column {
         const double fw0 = prm.has_u ? W.fw[s0] : 0.0;
         RecA FLA = fA(W.fa[s0], W.fg[s0], fw0, ihL, nAL, pAL, nA, pA);
         RecB FLB = fB(W.fa[s0], W.fg[s0], fw0, ihL, nBL, pBL, nB, pB);
-        for (int j0 = 0; j0 < jr; j0 += U) {
+        // double-buffered groups with unconditional loads, as in sweep
+        struct Grp {
             double an[U], ap[U], bn[U], bp[U], fa[U], fg[U], fw[U];
             Own ow[U];
+        };
+        auto load_grp = [&](int j0, Grp& g) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                // unconditional loads, as in sweep
                 const int j = min(j0 + u, jr - 1);
                 const int64_t s = sidx(t, j);
-                ow[u] = own(s);
+                g.ow[u] = own(s);
                 const int64_t sn = (c0 + j >= n - 1) ? s : ((j + 1 < M) ? s + T : sidx(t + 1, 0));
-                gxa(sn, an[u], ap[u]);
-                gxb(sn, bn[u], bp[u]);
-                fa[u] = W.fa[sn];
-                fg[u] = W.fg[sn];
-                fw[u] = W.fw[sn];
+                gxa(sn, g.an[u], g.ap[u]);
+                gxb(sn, g.bn[u], g.bp[u]);
+                g.fa[u] = W.fa[sn];
+                g.fg[u] = W.fg[sn];
+                g.fw[u] = W.fw[sn];
             }
+        };
+        Grp gc, gn;
+        load_grp(0, gc);
+        for (int j0 = 0; j0 < jr; j0 += U) {
+            load_grp(j0 + U, gn);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = j0 + u;
@@ -389,16 +396,17 @@ struct Column {
                         FRA = fA(rR, gR, wR, 2.0 * ih, nA, pA, nAR, pAR);
                         FRB = fB(rR, gR, wR, 2.0 * ih, nB, pB, nBR, pBR);
                     } else {
-                        nAR = an[u]; pAR = ap[u]; nBR = bn[u]; pBR = bp[u];
-                        const double wu = prm.has_u ? fw[u] : 0.0;
-                        FRA = fA(fa[u], fg[u], wu, ih, nA, pA, nAR, pAR);
-                        FRB = fB(fa[u], fg[u], wu, ih, nB, pB, nBR, pBR);
+                        nAR = gc.an[u]; pAR = gc.ap[u]; nBR = gc.bn[u]; pBR = gc.bp[u];
+                        const double wu = prm.has_u ? gc.fw[u] : 0.0;
+                        FRA = fA(gc.fa[u], gc.fg[u], wu, ih, nA, pA, nAR, pAR);
+                        FRB = fB(gc.fa[u], gc.fg[u], wu, ih, nB, pB, nBR, pBR);
                     }
-                    cell(s, c, nA, pA, nB, pB, FLA, FRA, FLB, FRB, ow[u]);
+                    cell(s, c, nA, pA, nB, pB, FLA, FRA, FLB, FRB, gc.ow[u]);
                     nA = nAR; pA = pAR; nB = nBR; pB = pBR;
                     FLA = FRA; FLB = FRB;
                 }
             }
+            gc = gn;
         }
         for (int j = jr; j < M; ++j) pad(sidx(t, j));
     }
@@ -926,27 +934,34 @@ struct Column {
             store_blk(12, sidx(t, M - 1), an);
             store_blk(16, sidx(t, M - 1), gn);
             constexpr int U = 2;
-            for (int j0 = M - 2; j0 >= 1; j0 -= U) {
-                Blk<double> aa[U], gg[U];
+            // double-buffered groups (unconditional loads, as in the apply)
+            struct GT { Blk<double> aa[U], gg[U]; };
+            auto load_t = [&](int j0, GT& g) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int64_t s = sidx(t, max(j0 - u, 1));   // unconditional loads
+                    const int64_t s = sidx(t, max(j0 - u, 1));
                     const V4<double>* tr = (const V4<double>*)ftmpp(s);
                     const V4<double> ra = tr[0], rg = tr[1];
-                    aa[u] = Blk<double>{ra.a, ra.b, ra.c, ra.d};
-                    gg[u] = Blk<double>{rg.a, rg.b, rg.c, rg.d};
+                    g.aa[u] = Blk<double>{ra.a, ra.b, ra.c, ra.d};
+                    g.gg[u] = Blk<double>{rg.a, rg.b, rg.c, rg.d};
                 }
+            };
+            GT gc, gq;
+            if (M >= 3) load_t(M - 2, gc);
+            for (int j0 = M - 2; j0 >= 1; j0 -= U) {
+                load_t(j0 - U, gq);
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int j = j0 - u;
                     if (j >= 1) {
                         const int64_t s = sidx(t, j);
-                        an = bsub(aa[u], bmul(gg[u], an));
-                        gn = bneg(bmul(gg[u], gn));
+                        an = bsub(gc.aa[u], bmul(gc.gg[u], an));
+                        gn = bneg(bmul(gc.gg[u], gn));
                         store_blk(12, s, an);
                         store_blk(16, s, gn);
                     }
                 }
+                gc = gq;
             }
             a1 = an; g1 = gn;
         }
