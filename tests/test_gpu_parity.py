@@ -177,6 +177,29 @@ def test_plain_and_batched_agree(J):
     assert np.array_equal(a[2], b[2])
 
 
+def test_batched_step_launch_times(J):
+    """A batched step is three launches (gather, solve, write-back), each
+    timed on the step's stream; the plain schedule reports none of them."""
+    cols = ragged_batch(seed=13)
+    packed = W.pack(cols)
+    for sched in (J.SCHED_BATCHED, J.SCHED_PLAIN):
+        prob, ne, phi, _, _ = J.device_problem(packed)
+        solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64, schedule=sched))
+        rc, st = solver.step(prob, ne, phi)
+        assert rc == J.JFNK_OK
+        ms, launches = solver.last_timing()
+        kt = solver.last_kernel_times()
+        if sched == J.SCHED_BATCHED:
+            assert launches == 3
+            assert all(x > 0.0 for x in kt), kt
+            # the three launches lie inside the span the step timing covers
+            assert sum(kt) <= ms * 1.001 + 1e-3, (kt, ms)
+        else:
+            assert launches == -1
+            assert kt == (-1.0, -1.0, -1.0)
+        solver.close()
+
+
 def test_config0_single_column(J, orc):
     cols = W.config0()
     packed = W.pack(cols)
