@@ -299,7 +299,8 @@ int jfnk_net_train_step(jfnk_net *net, const jfnk_problem *p, const jfnk_state *
    previous step on this context needed at least one Newton iteration (all
    columns on the first step and whenever the column layout changes); after
    r consecutive evaluations whose candidate lost to the fallback, a column
-   skips the network for the next 2^min(r,5) - 1 steps. */
+   skips the network at its next 2^min(r,5) - 1 chances (steps at which it
+   would otherwise be evaluated). */
 int jfnk_set_model(jfnk_ctx *ctx, jfnk_net *net);
 
 /* ---- test exports: single phases of the step, same kernels ----------- */

@@ -19,7 +19,7 @@ namespace {
 
 constexpr int kTmax = 512;          // largest workgroup that owns a column
 constexpr int kScalSlots = 64;      // doubles of scalar exchange per column
-constexpr int kMaxBackoff = 5;      // a losing learned guess is skipped up to 2^5 - 1 steps
+constexpr int kMaxBackoff = 5;      // a losing learned guess is skipped at up to 2^5 - 1 chances
 constexpr int kMoveTiles = 32;      // 8 x 8-cell tiles per gather / write-back workgroup
 
 // ---------------------------------------------------------------------------
@@ -291,7 +291,7 @@ struct jfnk_ctx {
     std::vector<int64_t> tuned_off;
     std::vector<uint8_t> evaluated;       // network evaluated for the column this step
     std::vector<int32_t> reject_streak;   // consecutive steps its candidate lost
-    std::vector<int32_t> skip_left;       // steps to skip before evaluating it again
+    std::vector<int32_t> skip_left;       // chances to skip before evaluating it again
 };
 
 namespace {
@@ -821,15 +821,19 @@ int learned_guess(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream
     int nuse = nc;
     if (ctx->hist_valid && (int)ctx->last_newton.size() == nc) {
         // skip columns that converged at their initial guess last step, and
-        // back off exponentially from columns whose learned candidate keeps losing
+        // back off exponentially from columns whose learned candidate keeps
+        // losing: after r losses in a row, the next 2^r - 1 chances (steps at
+        // which the column would be evaluated) are skipped
         nuse = 0;
         for (int c = 0; c < nc; ++c) {
             const bool settled = ctx->last_status[c] == COL_CONVERGED && ctx->last_newton[c] == 0;
-            if (ctx->skip_left[c] > 0) {
+            if (settled) {
+                use[c] = 0;
+            } else if (ctx->skip_left[c] > 0) {
                 --ctx->skip_left[c];
                 use[c] = 0;
             } else {
-                use[c] = !settled;
+                use[c] = 1;
             }
             nuse += use[c];
         }
