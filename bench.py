@@ -47,18 +47,24 @@ def solve_bytes_per_cell(has_prev, fb, counts):
     """Algorithmic HBM bytes per cell of one column-step inside the solve
     launch, from the phases the step executed (jfnk_stats.phase_counts:
     factorisations, preconditioner applies, residual evaluations, J.v
-    products, CGS passes, direction assemblies); each phase reads its
-    operands from HBM and writes its results once (fb = bytes per stored
-    preconditioner value)."""
+    products, CGS passes, direction assemblies, extra vector reads, learned
+    candidates evaluated); each
+    phase reads its operands from HBM and writes its results once (fb = bytes
+    per stored preconditioner value).  The Arnoldi dot sweeps, Gram-Schmidt
+    passes and direction assemblies also read a number of basis vectors that
+    grows with the Krylov index: those are the extra vector reads, 16 bytes
+    per cell each."""
     setup = 72.0                               # F(X^n): X + 5 coefficients -> F
     if has_prev:
         setup += 32.0                          # same sweep: the extrapolation in, its residual out
     per_phase = (40.0 + 20.0 * fb,             # factor: X + 3 coefficients -> 20 factor values
                  32.0 + 20.0 * fb,             # apply: v + 20 factor values -> z
                  104.0,                        # trial: X + direction + 5 coefficients -> X_t, F_t
-                 120.0,                        # J.v: X, z, F, 5 coefficients -> w, fused dots
-                 64.0,                         # CGS pass: w and the basis vectors it projects out
-                 64.0)                         # direction: sum of the Krylov vectors
+                 120.0,                        # J.v: X, z, F, 5 coefficients, 2 basis vectors -> w
+                 32.0,                         # CGS pass: w in and out (basis vectors: extra reads)
+                 16.0,                         # direction: dX out (summed vectors: extra reads)
+                 16.0,                         # one extra FP64 vector pair read
+                 72.0)                         # learned candidate: X_l + 5 coefficients -> F_l
     return setup + sum(c * b for c, b in zip(counts, per_phase))
 
 
@@ -118,7 +124,7 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
         r["conv"] = int(np.sum(r["status"] == 0))
         r["res"] = float(r["res"].max())
         r["bytes"] = float(np.sum(ns * np.array([
-            solve_bytes_per_cell(r["has_prev"], fb, r["counts"][i][:6]) for i in range(len(ns))])))
+            solve_bytes_per_cell(r["has_prev"], fb, r["counts"][i]) for i in range(len(ns))])))
         r["gbytes"] = float(np.sum(ns)) * gather_bytes_per_cell(r["has_prev"])
         r["wbytes"] = float(np.sum(ns)) * WRITEBACK_BYTES_PER_CELL
     converged = sum(r["conv"] for r in rec)

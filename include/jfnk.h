@@ -160,7 +160,16 @@ typedef struct {
     int32_t *phase_counts;       /* HOST [ncols][8]: factorisations, preconditioner
                                     applies, residual evaluations after set-up
                                     (trials), J.v products, CGS passes, direction
-                                    assemblies, 0, 0 (what the step executed) */
+                                    assemblies, extra vector reads, learned
+                                    candidates evaluated (0 or 1) (what the
+                                    step executed).  Extra vector reads count the
+                                    FP64 vector pairs read by the Arnoldi dot
+                                    sweeps, Gram-Schmidt passes and direction
+                                    assemblies beyond their fixed operands: J.v's
+                                    dots past the first two basis vectors (plus a
+                                    re-read of w), every basis vector a CGS pass
+                                    projects out (plus a re-read of w past the
+                                    eighth), every vector summed into a direction. */
 } jfnk_stats;
 
 /* Fill cfg with the defaults: restart 30, 5 restarts, 50 Newton iterations,
@@ -299,8 +308,9 @@ int jfnk_net_train_step(jfnk_net *net, const jfnk_problem *p, const jfnk_state *
    previous step on this context needed at least one Newton iteration (all
    columns on the first step and whenever the column layout changes); after
    r consecutive evaluations whose candidate lost to the fallback, a column
-   skips the network at its next 2^min(r,5) - 1 chances (steps at which it
-   would otherwise be evaluated). */
+   skips the network at its next 4^min(r,5) - 1 chances (steps at which it
+   would otherwise be evaluated); any change of the network's weights
+   (jfnk_net_set_params, jfnk_net_train_step) clears that record. */
 int jfnk_set_model(jfnk_ctx *ctx, jfnk_net *net);
 
 /* ---- test exports: single phases of the step, same kernels ----------- */

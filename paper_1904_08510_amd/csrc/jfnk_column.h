@@ -1407,6 +1407,14 @@ struct Column {
     // out = (accumulate ? out : 0) + sum_i c[i] vecs[i]
     __device__ void lincomb(CP o0, CP o1, const VecRef* vecs, const double* c, int nv,
                             bool accumulate) {
+        if (accumulate)
+            lincomb_t<true>(o0, o1, vecs, c, nv);
+        else
+            lincomb_t<false>(o0, o1, vecs, c, nv);
+        __syncthreads();
+    }
+    template <bool ACC>
+    __device__ void lincomb_t(CP o0, CP o1, const VecRef* vecs, const double* c, int nv) {
         constexpr int U = 4;
         const int M = cd.M;
         for (int j0 = 0; j0 < M; j0 += U) {
@@ -1416,9 +1424,8 @@ struct Column {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 sl[u] = sidx(t, min(j0 + u, M - 1));
-                const double x = o0[sl[u]], y = o1[sl[u]];
-                a[u] = accumulate ? x : 0.0;
-                b[u] = accumulate ? y : 0.0;
+                a[u] = ACC ? o0[sl[u]] : 0.0;
+                b[u] = ACC ? o1[sl[u]] : 0.0;
             }
 #pragma unroll 4
             for (int i = 0; i < nv; ++i) {
@@ -1437,7 +1444,6 @@ struct Column {
             for (int u = 0; u < U; ++u)
                 if (j0 + u < M) { o0[sl[u]] = a[u]; o1[sl[u]] = b[u]; }
         }
-        __syncthreads();
     }
 
     // Line-search trial X_t = X + lam S_X d, its residual and norms.

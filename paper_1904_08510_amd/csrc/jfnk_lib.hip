@@ -19,7 +19,7 @@ namespace {
 
 constexpr int kTmax = 512;          // largest workgroup that owns a column
 constexpr int kScalSlots = 64;      // doubles of scalar exchange per column
-constexpr int kMaxBackoff = 5;      // a losing learned guess is skipped at up to 2^5 - 1 chances
+constexpr int kMaxBackoff = 5;      // a losing learned guess is skipped at up to 4^5 - 1 chances
 constexpr int kMoveTiles = 32;      // 8 x 8-cell tiles per gather / write-back workgroup
 
 // ---------------------------------------------------------------------------
@@ -278,6 +278,7 @@ struct jfnk_ctx {
     int last_launches = 0;
     // learned guess
     jfnk_net* model = nullptr;
+    uint64_t model_version = 0;  // weight version the back-off records below were judged with
     double* d_learn = nullptr;   // [2][max_total_cells]: guess n, phi
     int32_t* d_lmask = nullptr;  // [max_cols]
     int32_t* h_lmask = nullptr;  // pinned
@@ -290,7 +291,7 @@ struct jfnk_ctx {
     int tuned_T = 0;
     std::vector<int64_t> tuned_off;
     std::vector<uint8_t> evaluated;       // network evaluated for the column this step
-    std::vector<int32_t> reject_streak;   // consecutive steps its candidate lost
+    std::vector<int32_t> reject_streak;   // consecutive evaluations its candidate lost
     std::vector<int32_t> skip_left;       // chances to skip before evaluating it again
 };
 
@@ -819,11 +820,18 @@ int learned_guess(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream
     std::vector<uint8_t>& use = ctx->evaluated;
     use.assign(nc, 1);
     int nuse = nc;
+    const uint64_t ver = net_version(ctx->model);
+    if (ctx->hist_valid && (int)ctx->last_newton.size() == nc && ctx->model_version != ver) {
+        ctx->reject_streak.assign(nc, 0);
+        ctx->skip_left.assign(nc, 0);
+    }
+    ctx->model_version = ver;
     if (ctx->hist_valid && (int)ctx->last_newton.size() == nc) {
         // skip columns that converged at their initial guess last step, and
         // back off exponentially from columns whose learned candidate keeps
-        // losing: after r losses in a row, the next 2^r - 1 chances (steps at
-        // which the column would be evaluated) are skipped
+        // losing: after r losses in a row, the next 4^r - 1 chances (steps at
+        // which the column would be evaluated) are skipped.  New weights
+        // restart the judgement.
         nuse = 0;
         for (int c = 0; c < nc; ++c) {
             const bool settled = ctx->last_status[c] == COL_CONVERGED && ctx->last_newton[c] == 0;
@@ -991,11 +999,15 @@ int jfnk_step(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, jfnk_stats* s
     }
     rc = ctx->cfg.prec_precision == JFNK_PREC_FP32 ? dispatch_run<float>(ctx, p, x, st)
                                                    : dispatch_run<double>(ctx, p, x, st);
+    const bool learned_ran = ctx->learn_active && (int)ctx->evaluated.size() == p->ncols;
     ctx->learn_active = false;
     if (rc) return rc;
     int nfail = 0;
     rc = gather_stats(ctx, p->ncols, stt, st, &nfail);
     if (rc) return rc;
+    if (stt && stt->phase_counts)
+        for (int c = 0; c < p->ncols; ++c)
+            stt->phase_counts[(int64_t)c * kWorkCounts + kWorkLearned] = learned_ran && ctx->evaluated[c] ? 1 : 0;
     // which columns needed Newton iterations (the learned guess is evaluated for those)
     ctx->last_newton.resize(p->ncols);
     ctx->last_status.resize(p->ncols);
@@ -1009,7 +1021,7 @@ int jfnk_step(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, jfnk_stats* s
                 ctx->reject_streak[c] = 0;
             } else {
                 ctx->reject_streak[c] = std::min(ctx->reject_streak[c] + 1, kMaxBackoff);
-                ctx->skip_left[c] = (1 << ctx->reject_streak[c]) - 1;
+                ctx->skip_left[c] = (1 << (2 * ctx->reject_streak[c])) - 1;
             }
         }
     }

@@ -36,5 +36,8 @@ constexpr int64_t kParams = poffset(kLayers);
 int net_predict_masked(jfnk_net* net, const jfnk_problem* p, const jfnk_state* x,
                        const uint8_t* use_col, double* ne_out, double* phi_out, void* stream);
 int net_ensure_predict_capacity(jfnk_net* net, int32_t max_cols, int64_t max_total_cells);
+// Counter of weight changes (set_params, train_step): a context that judged
+// the network's candidates re-judges them after the weights change.
+uint64_t net_version(const jfnk_net* net);
 
 }  // namespace jfnk

@@ -584,6 +584,7 @@ struct jfnk_net {
     void* base = nullptr;            // parameters, packed weights, training workspace
     float *params = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
     int64_t step = 0;
+    uint64_t version = 0;            // weight changes so far
     uint16_t* wf[kLayers] = {};
     uint16_t* wt[kLayers] = {};
     float* bias[kLayers] = {};
@@ -884,6 +885,8 @@ int net_ensure_predict_capacity(jfnk_net* net, int32_t max_cols, int64_t max_tot
     return stage_reserve(net, tiles, max_cols);
 }
 
+uint64_t net_version(const jfnk_net* net) { return net->version; }
+
 int net_predict_masked(jfnk_net* net, const jfnk_problem* p, const jfnk_state* x, const uint8_t* use_col,
                        double* ne_out, double* phi_out, void* stream) {
     if (!net) return JFNK_EINVAL;
@@ -1041,6 +1044,7 @@ int jfnk_net_set_params(jfnk_net* net, const float* params, int64_t n) {
     NET_HIP(hipMemset(net->m, 0, 4 * kParams));
     NET_HIP(hipMemset(net->v, 0, 4 * kParams));
     net->step = 0;
+    ++net->version;
     if (int rc = launch_pack(net, nullptr)) return rc;
     NET_HIP(hipDeviceSynchronize());
     return JFNK_OK;
@@ -1095,6 +1099,7 @@ int jfnk_net_train_step(jfnk_net* net, const jfnk_problem* p, const jfnk_state* 
     a.c2 = (float)(1.0 / (1.0 - std::pow((double)net->cfg.beta2, (double)net->step)));
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((kParams + 255) / 256)), dim3(256), 0, st, a);
     NET_HIP(hipGetLastError());
+    ++net->version;
     if (int rc = launch_pack(net, st)) return rc;
     if (loss) {
         NET_HIP(hipMemcpyAsync(loss, net->loss_dev, 8, hipMemcpyDeviceToHost, st));

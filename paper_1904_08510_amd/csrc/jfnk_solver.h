@@ -151,6 +151,7 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
                 beta = ex.restart_residual(cur, xnorm);
                 ++wk[kWorkJv];
                 ++wk[kWorkLincomb];
+                ++wk[kWorkVecReads];
                 if (!(beta > 0.0)) break;
                 ex.set_basis(0, ex.vslot(0, 1.0 / beta));
             }
@@ -166,6 +167,7 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
                 ex.jv(cur, j, eps, j + 1, hcol);
                 ++gtot;
                 ++wk[kWorkJv];
+                if (j + 1 > 2) wk[kWorkVecReads] += j;      // w and basis vectors 2..j
                 double hsq = 0.0;
                 for (int i = 0; i <= j; ++i) hsq += hcol[i] * hcol[i];
                 const double hn_est = sqrt(fmax(hcol[j + 1] - hsq, 0.0));
@@ -182,6 +184,7 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
                 double h3[kMaxRestart + 2];
                 ex.cgs(j + 1, j + 1, h2, h3);          // w -= V h2 ; ||w||^2
                 wk[kWorkCgs] += 2;
+                wk[kWorkVecReads] += 2 * (j + 1 + (j + 1 > 8 ? j - 6 : 0));
                 for (int i = 0; i <= j; ++i) hcol[i] += h2[i];
                 const double hn = sqrt(h3[j + 1]);
                 const double res = ex.gm_commit(j, hcol, hn);
@@ -193,7 +196,10 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
             if (k > 0) {
                 ex.gm_solve(k, y);
                 ex.direction(k, y, have_dx);
-                if (k > 1 || have_dx) ++wk[kWorkLincomb];
+                if (k > 1 || have_dx) {
+                    ++wk[kWorkLincomb];
+                    wk[kWorkVecReads] += k + (have_dx ? 1 : 0);
+                }
                 have_dx = true;
             }
             if (conv || lucky || cyc >= p.max_restarts) break;

@@ -27,7 +27,15 @@ constexpr int kFactorSlots = 24;     // FT values per cell stored by the factori
 constexpr int kTempSlots = 8;        // FP64 values per cell kept between factor sweeps
 
 // Per-column counts of the phases a step executed (order of jfnk_stats.phase_counts).
-enum { kWorkFactor = 0, kWorkApply, kWorkResidual, kWorkJv, kWorkCgs, kWorkLincomb, kWorkCounts = 8 };
+// kWorkVecReads counts the FP64 vector pairs (16 bytes per cell each) that the
+// dot-product sweeps, Gram-Schmidt passes and direction assemblies read beyond
+// the fixed operands of those phases: basis vectors past the first two in a
+// J.v product's dots (plus one re-read of w), every basis vector of a
+// Gram-Schmidt pass (plus w again past the eighth), and every vector summed
+// into a direction.  kWorkLearned (1 when the learned candidate's residual was
+// evaluated in the set-up) is filled in by the host, which chose the columns.
+enum { kWorkFactor = 0, kWorkApply, kWorkResidual, kWorkJv, kWorkCgs, kWorkLincomb, kWorkVecReads,
+       kWorkLearned, kWorkCounts = 8 };
 
 // Column status codes (also in include/jfnk.h).
 enum { COL_CONVERGED = 0, COL_MAX_NEWTON = 1, COL_NONFINITE = 2, COL_LINESEARCH = 3,

@@ -219,6 +219,63 @@ def test_learned_guess_keeps_the_root(J, R):
     assert all(set(u.tolist()) <= {0, 1, 2} for u in b[2])
 
 
+def test_learned_backoff_schedule(J, R):
+    """Which columns evaluate the learned candidate (phase_counts[:, 7])
+    follows the back-off rule: every column on the first step of a layout;
+    afterwards only columns whose last step needed Newton iterations, less
+    4^r - 1 skipped chances after r consecutive losses (r <= 5); new weights
+    clear the record."""
+    cols = W.config2(seed=2101, ncols=8, nmin=300, nmax=900)
+    packed = W.pack(cols)
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    ne0, phi0 = ne.clone(), phi.clone()
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64, guess=J.GUESS_LEARNED))
+    net = J.Net(J.net_default_config(out_scale_ne=S0, out_scale_phi=S1))
+    net.set_params(params32(R, 9))
+    solver.set_model(net)
+    nc = packed.ncols
+    streak = np.zeros(nc, int)
+    skip = np.zeros(nc, int)
+    last = None          # (status, Newton iterations) of the previous step
+    evaluations = []
+    for ep in range(3):
+        ne.copy_(ne0)
+        phi.copy_(phi0)
+        pne = pph = None
+        if ep == 2:
+            net.set_params(params32(R, 10))
+            streak[:] = 0
+            skip[:] = 0
+        for k in range(8):
+            if last is None:
+                use = np.ones(nc, bool)
+            else:
+                use = np.zeros(nc, bool)
+                for c in range(nc):
+                    if last[0][c] == 0 and last[1][c] == 0:
+                        continue
+                    if skip[c] > 0:
+                        skip[c] -= 1
+                        continue
+                    use[c] = True
+            cur = (ne.clone(), phi.clone())
+            rc, st = solver.step(prob, ne, phi, pne, pph)
+            assert rc == J.JFNK_OK, st.status
+            got = st.phase_counts[:, 7] != 0
+            np.testing.assert_array_equal(got, use, err_msg=f"episode {ep} step {k}")
+            for c in np.nonzero(use)[0]:
+                if st.guess_used[c] == J.GUESS_LEARNED:
+                    streak[c] = 0
+                else:
+                    streak[c] = min(streak[c] + 1, 5)
+                    skip[c] = 4 ** streak[c] - 1
+            last = (st.status.copy(), st.newton_iters.copy())
+            evaluations.append(int(use.sum()))
+            pne, pph = cur
+    print("columns evaluated per step:", evaluations)
+    assert evaluations[0] == nc and sum(evaluations[16:]) > 0
+
+
 def test_learned_errors(J, R):
     cols, prev, nxt = batch(seed=15)
     packed, prob, ne, phi, pne, pph, nne, nph = to_dev(J, cols, prev, nxt)
