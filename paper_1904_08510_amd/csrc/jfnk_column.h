@@ -982,12 +982,15 @@ struct Column {
         // locals: the barriers below make the compiler reload members of an
         // out-of-line phase function's object from memory after each of them
         const int tl = t;
-        double* const rb = W.red + cd.red + tl;      // red(k) = rb + k T
-        gst(rb + 0 * T, A0.a); gst(rb + 1 * T, A0.b); gst(rb + 2 * T, A0.c); gst(rb + 3 * T, A0.d);
-        gst(rb + 4 * T, C0.a); gst(rb + 5 * T, C0.b); gst(rb + 6 * T, C0.c); gst(rb + 7 * T, C0.d);
-        // parallel cyclic reduction (FP64)
-        int k = 8;
-        for (int st = 1; st < T; st <<= 1, k += 8) {
+        // parallel cyclic reduction (FP64).  The elimination factors of every
+        // stage stay in registers and are stored after the last stage: a
+        // barrier waits for the workgroup's outstanding global stores, so
+        // stores inside the loop would add one memory round trip per stage.
+        constexpr int LG = ilog2(T);
+        Blk<double> K1[LG], K2[LG];
+#pragma unroll
+        for (int lv = 0; lv < LG; ++lv) {
+            const int st = 1 << lv;
             __syncthreads();
             ldbl* row = P + 12 * tl;
             row[0] = Lr.a; row[1] = Lr.b; row[2] = Lr.c; row[3] = Lr.d;
@@ -1012,12 +1015,21 @@ struct Column {
             Dr = bsub(bsub(Dr, bmul(k1, Um)), bmul(k2, Lp));
             Lr = bneg(bmul(k1, Lm));
             Ur = bneg(bmul(k2, Up));
-            double* const rk = rb + (int64_t)k * T;
-            gst(rk + 0 * T, k1.a); gst(rk + 1 * T, k1.b); gst(rk + 2 * T, k1.c); gst(rk + 3 * T, k1.d);
-            gst(rk + 4 * T, k2.a); gst(rk + 5 * T, k2.b); gst(rk + 6 * T, k2.c); gst(rk + 7 * T, k2.d);
+            K1[lv] = k1;
+            K2[lv] = k2;
         }
         const Blk<double> Di = binv(Dr);
-        double* const rk = rb + (int64_t)k * T;
+        // red(k) = rb + k T: A0, C0, then (k1, k2) of each stage, then D^-1
+        double* const rb = W.red + cd.red + tl;
+        gst(rb + 0 * T, A0.a); gst(rb + 1 * T, A0.b); gst(rb + 2 * T, A0.c); gst(rb + 3 * T, A0.d);
+        gst(rb + 4 * T, C0.a); gst(rb + 5 * T, C0.b); gst(rb + 6 * T, C0.c); gst(rb + 7 * T, C0.d);
+#pragma unroll
+        for (int lv = 0; lv < LG; ++lv) {
+            double* const rk = rb + (int64_t)(8 + 8 * lv) * T;
+            gst(rk + 0 * T, K1[lv].a); gst(rk + 1 * T, K1[lv].b); gst(rk + 2 * T, K1[lv].c); gst(rk + 3 * T, K1[lv].d);
+            gst(rk + 4 * T, K2[lv].a); gst(rk + 5 * T, K2[lv].b); gst(rk + 6 * T, K2[lv].c); gst(rk + 7 * T, K2[lv].d);
+        }
+        double* const rk = rb + (int64_t)(8 + 8 * LG) * T;
         gst(rk + 0 * T, Di.a); gst(rk + 1 * T, Di.b); gst(rk + 2 * T, Di.c); gst(rk + 3 * T, Di.d);
         if (t == 0) {
             ColState* cs = W.cst + cd.index;
