@@ -1359,6 +1359,88 @@ struct Column {
     template <class BP>
     __device__ void cgs_pass(CP w0, CP w1, BP basis, int nb, const double* h,
                              double* dots) {
+        if (nb <= 0) cgs_pass_any(w0, w1, basis, nb, h, dots);
+        else if (nb == 1) cgs_pass_n<1>(w0, w1, basis, nb, h, dots);
+        else if (nb == 2) cgs_pass_n<2>(w0, w1, basis, nb, h, dots);
+        else if (nb == 3) cgs_pass_n<3>(w0, w1, basis, nb, h, dots);
+        else if (nb == 4) cgs_pass_n<4>(w0, w1, basis, nb, h, dots);
+        else if (nb <= 8) cgs_pass_n<8>(w0, w1, basis, nb, h, dots);
+        else cgs_pass_any(w0, w1, basis, nb, h, dots);
+    }
+
+    // The pass for nb <= NB basis vectors.  Their references and coefficients
+    // are read once, ahead of the row loop: read inside it, each would wait
+    // behind the rows' loads in the in-order memory counter, one round trip
+    // per vector.  Slots past nb repeat the last vector with weight 0.
+    template <int NB, class BP>
+    __device__ void cgs_pass_n(CP w0, CP w1, BP basis, int nb, const double* h,
+                               double* dots) {
+        constexpr int U = NB <= 4 ? 4 : 2;
+        const int M = cd.M;
+        VecRef bv[NB];
+        double hs0[NB], hs1[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            bv[i] = basis[min(i, nb - 1)];
+            const double hi = i < nb ? h[min(i, nb - 1)] : 0.0;
+            hs0[i] = hi * bv[i].s0;
+            hs1[i] = hi * bv[i].s1;
+        }
+        double acc[NB + 1];
+#pragma unroll
+        for (int i = 0; i <= NB; ++i) acc[i] = 0.0;
+        for (int j0 = 0; j0 < M; j0 += U) {
+            // unconditional loads (rows past the chunk's end reload its last
+            // row; their results are neither stored nor summed)
+            double a[U], b[U], p[NB][U], q[NB][U];
+            int64_t sl[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                sl[u] = sidx(t, min(j0 + u, M - 1));
+                a[u] = w0[sl[u]];
+                b[u] = w1[sl[u]];
+            }
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const Vec2<double> e = ld_pair(bv[i], sl[u]);
+                    p[i][u] = e.x;
+                    q[i][u] = e.y;
+                }
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    a[u] -= hs0[i] * p[i][u];
+                    b[u] -= hs1[i] * q[i][u];
+                }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = j0 + u < M;
+                if (ok) { w0[sl[u]] = a[u]; w1[sl[u]] = b[u]; }
+                acc[NB] += ok ? a[u] * a[u] + b[u] * b[u] : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                double sacc = 0.0;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const double term = p[i][u] * bv[i].s0 * a[u] + q[i][u] * bv[i].s1 * b[u];
+                    sacc += (j0 + u < M) ? term : 0.0;
+                }
+                acc[i] += sacc;
+            }
+        }
+        wg_sum<T, NB + 1>(acc, lds + Lds<T>::kScr);
+        for (int i = 0; i < nb; ++i) dots[i] = acc[i];
+        dots[nb] = acc[NB];
+    }
+
+    // The pass for any nb (references read per vector inside the row loop).
+    template <class BP>
+    __device__ void cgs_pass_any(CP w0, CP w1, BP basis, int nb, const double* h,
+                                 double* dots) {
         constexpr int U = 4;
         const int M = cd.M;
         double acc[9];
@@ -1419,11 +1501,65 @@ struct Column {
     // out = (accumulate ? out : 0) + sum_i c[i] vecs[i]
     __device__ void lincomb(CP o0, CP o1, const VecRef* vecs, const double* c, int nv,
                             bool accumulate) {
-        if (accumulate)
-            lincomb_t<true>(o0, o1, vecs, c, nv);
-        else
-            lincomb_t<false>(o0, o1, vecs, c, nv);
+        if (nv <= 0) {
+            if (accumulate) lincomb_t<true>(o0, o1, vecs, c, nv);
+            else lincomb_t<false>(o0, o1, vecs, c, nv);
+        } else if (accumulate) {
+            if (nv <= 4) lincomb_n<4, true>(o0, o1, vecs, c, nv);
+            else if (nv <= 8) lincomb_n<8, true>(o0, o1, vecs, c, nv);
+            else lincomb_t<true>(o0, o1, vecs, c, nv);
+        } else {
+            if (nv == 1) lincomb_n<1, false>(o0, o1, vecs, c, nv);
+            else if (nv == 2) lincomb_n<2, false>(o0, o1, vecs, c, nv);
+            else if (nv <= 4) lincomb_n<4, false>(o0, o1, vecs, c, nv);
+            else if (nv <= 8) lincomb_n<8, false>(o0, o1, vecs, c, nv);
+            else lincomb_t<false>(o0, o1, vecs, c, nv);
+        }
         __syncthreads();
+    }
+    // nv <= NV vectors, references and weights read ahead of the row loop
+    // (as in cgs_pass_n); slots past nv repeat the last vector with weight 0
+    template <int NV, bool ACC>
+    __device__ void lincomb_n(CP o0, CP o1, const VecRef* vecs, const double* c, int nv) {
+        constexpr int U = NV <= 4 ? 4 : 2;
+        const int M = cd.M;
+        VecRef vv[NV];
+        double cs0[NV], cs1[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            vv[i] = vecs[min(i, nv - 1)];
+            const double ci = i < nv ? c[min(i, nv - 1)] : 0.0;
+            cs0[i] = ci * vv[i].s0;
+            cs1[i] = ci * vv[i].s1;
+        }
+        for (int j0 = 0; j0 < M; j0 += U) {
+            double a[U], b[U], p[NV][U], q[NV][U];
+            int64_t sl[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                sl[u] = sidx(t, min(j0 + u, M - 1));
+                a[u] = ACC ? o0[sl[u]] : 0.0;
+                b[u] = ACC ? o1[sl[u]] : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const Vec2<double> e = ld_pair(vv[i], sl[u]);
+                    p[i][u] = e.x;
+                    q[i][u] = e.y;
+                }
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    a[u] += cs0[i] * p[i][u];
+                    b[u] += cs1[i] * q[i][u];
+                }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (j0 + u < M) { o0[sl[u]] = a[u]; o1[sl[u]] = b[u]; }
+        }
     }
     template <bool ACC>
     __device__ void lincomb_t(CP o0, CP o1, const VecRef* vecs, const double* c, int nv) {
