@@ -177,6 +177,30 @@ def test_plain_and_batched_agree(J):
     assert np.array_equal(a[2], b[2])
 
 
+@pytest.mark.parametrize("threads", [64, 256])
+def test_batched_steps_are_reproducible(J, threads):
+    """The solve launch has no data race between the threads of a column:
+    the same steps from the same state give bit-identical states and
+    iteration counts (every reduction runs in a fixed order)."""
+    packed = W.pack(W.config2(seed=2300, ncols=24, nmin=400, nmax=3000))
+    runs = []
+    for rep in range(2):
+        prob, ne, phi, _, _ = J.device_problem(packed)
+        solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP32, threads_override=threads))
+        pne = pph = None
+        counts = []
+        for k in range(6):
+            cur = (ne.clone(), phi.clone())
+            rc, st = solver.step(prob, ne, phi, pne, pph)
+            assert rc == J.JFNK_OK, st.status
+            counts.append(np.stack([st.newton_iters, st.gmres_iters, st.chord_steps, st.phase_counts[:, 0]]))
+            pne, pph = cur
+        solver.close()
+        runs.append((ne.cpu().numpy(), phi.cpu().numpy(), np.array(counts)))
+    for x, y in zip(runs[0], runs[1]):
+        assert np.array_equal(x, y)
+
+
 def test_batched_step_launch_times(J):
     """A batched step is three launches (gather, solve, write-back), each
     timed on the step's stream; the plain schedule reports none of them."""
