@@ -102,7 +102,9 @@ def pmc(fetch_dir: str, write_dir: str, out_path: str) -> dict:
 
 
 if __name__ == "__main__":
-    if sys.argv[1] == "stats":
+    if len(sys.argv) == 1:
+        print(source_hash())
+    elif sys.argv[1] == "stats":
         print(stats(sys.argv[2]))
     elif sys.argv[1] == "pmc":
         print(json.dumps(pmc(sys.argv[2], sys.argv[3], sys.argv[4]), indent=1))
