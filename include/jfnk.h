@@ -71,8 +71,12 @@ enum { JFNK_PREC_FP64 = 0, JFNK_PREC_FP32 = 1 };
    SCHUR: the paper's eq:prec_recast, the block factorisation with the Schur
    complement replaced by S~ = L + I_e dt D_r (Section 3.2), each block solved
    exactly (the tridiagonal solves the paper uses in 1D instead of multigrid):
-   three solves per apply. */
-enum { JFNK_PRECK_BLOCK = 0, JFNK_PRECK_SCHUR = 1 };
+   three solves per apply.  NONE: no preconditioner (P = I in the scaled
+   variables, GMRES on S_F^-1 J S_X itself), the baseline of the paper's
+   comparison of preconditioned and unpreconditioned iteration counts
+   (Section 3.2); the error estimate then equals the scaled residual, and
+   simplified-Newton steps are not taken (chord_tol is ignored). */
+enum { JFNK_PRECK_BLOCK = 0, JFNK_PRECK_SCHUR = 1, JFNK_PRECK_NONE = 2 };
 /* PLAIN: one column at a time, every phase a launch, control on the host.
    BATCHED: one launch per step solves all columns, control on the GPU. */
 enum { JFNK_SCHED_PLAIN = 0, JFNK_SCHED_BATCHED = 1 };

@@ -846,6 +846,16 @@ struct Column {
     }
 
     __device__ void factor(int cur) {
+        if (prm.prec_kind == 2) {
+            // no preconditioner: nothing to factor
+            if (t == 0) {
+                ColState* cs = W.cst + cd.index;
+                cs->fac_valid = 1;
+                cs->fsfn = sfn; cs->fsfp = sfp; cs->fsxn = sxn; cs->fsxp = sxp;
+            }
+            __syncthreads();
+            return;
+        }
         const int M = cd.M, n = cd.n;
         const int c0 = t * M;
         const CP X0 = xb(cur, 0);
@@ -1044,7 +1054,28 @@ struct Column {
     // v and z must not alias.
     // ------------------------------------------------------------------
     __device__ Vec2<double> apply(const VecRef& v, CP z0, CP z1) {
+        if (prm.prec_kind == 2) return apply_identity(v, z0, z1);
         return prm.prec_kind == 1 ? apply_schur(v, z0, z1) : block_apply(v, z0, z1);
+    }
+
+    // No preconditioner: z = v (with v's component scales), every row of the
+    // chunk (padding rows of v hold zeros).
+    __device__ Vec2<double> apply_identity(const VecRef& v, CP z0, CP z1) {
+        const int M = cd.M;
+        double zz = 0.0, zm = 0.0;
+        for (int j = 0; j < M; ++j) {
+            const int64_t s = sidx(t, j);
+            const double a = v.p0[s] * v.s0, b = v.p1[s] * v.s1;
+            z0[s] = a;
+            z1[s] = b;
+            zz += a * a + b * b;
+            zm = fmax(zm, fmax(fabs(a), fabs(b)));
+        }
+        double sm[1] = {zz};
+        double mm[1] = {zm};
+        wg_sum<T, 1>(sm, lds + Lds<T>::kScr);
+        wg_max<T, 1>(mm, lds + Lds<T>::kScr);
+        return Vec2<double>{sm[0], mm[0]};
     }
 
     // Approximate Schur preconditioner, eq:prec_recast applied right to left:

@@ -438,7 +438,9 @@ SolverParams make_params(const jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_
     s.tol_x = ctx->cfg.tol_x;
     s.gamma = ctx->cfg.gamma;
     s.theta = ctx->cfg.ls_theta;
-    s.chord_tol = ctx->cfg.chord_tol;
+    // without a preconditioner a simplified-Newton step would be a unit
+    // Richardson step on the scaled system: none is taken
+    s.chord_tol = ctx->cfg.prec_kind == JFNK_PRECK_NONE ? 0.0 : ctx->cfg.chord_tol;
     return s;
 }
 
@@ -898,7 +900,8 @@ int jfnk_create(const jfnk_config* cfg, jfnk_ctx** out) {
         !(cfg->gamma > 0.0 && cfg->gamma < 1.0) || !(cfg->ls_theta >= 0.0 && cfg->ls_theta < 1.0) ||
         !(cfg->chord_tol >= 0.0 && cfg->chord_tol < 1.0) ||
         (cfg->prec_precision != JFNK_PREC_FP64 && cfg->prec_precision != JFNK_PREC_FP32) ||
-        (cfg->prec_kind != JFNK_PRECK_BLOCK && cfg->prec_kind != JFNK_PRECK_SCHUR) ||
+        (cfg->prec_kind != JFNK_PRECK_BLOCK && cfg->prec_kind != JFNK_PRECK_SCHUR &&
+         cfg->prec_kind != JFNK_PRECK_NONE) ||
         cfg->guess < 0 || cfg->guess > 2 ||
         (cfg->schedule != JFNK_SCHED_PLAIN && cfg->schedule != JFNK_SCHED_BATCHED))
         return JFNK_EINVAL;

@@ -78,7 +78,7 @@ struct SolverParams {
     int32_t has_learned;    // learned candidate supplied
     int32_t has_u;          // advective face velocities supplied
     int32_t fac_reuse;      // factors left by the previous step may serve this step
-    int32_t prec_kind;      // 0 exact block factorisation, 1 approximate Schur (eq:prec_recast)
+    int32_t prec_kind;      // 0 exact block factorisation, 1 approximate Schur (eq:prec_recast), 2 none
     double tol_f, tol_x, gamma, theta;
     double chord_tol;       // simplified-Newton steps while the error estimate is below this (0: off)
 };

@@ -21,7 +21,7 @@ JFNK_EINVAL, JFNK_ENOMEM, JFNK_EHIP, JFNK_ECAPACITY, JFNK_EMODEL = -1, -2, -3, -
 BC_DIRICHLET, BC_ZERO_FLUX = 0, 1
 GUESS_PREV, GUESS_EXTRAP, GUESS_LEARNED = 0, 1, 2
 PREC_FP64, PREC_FP32 = 0, 1
-PRECK_BLOCK, PRECK_SCHUR = 0, 1
+PRECK_BLOCK, PRECK_SCHUR, PRECK_NONE = 0, 1, 2
 SCHED_PLAIN, SCHED_BATCHED = 0, 1
 COL_CONVERGED, COL_MAX_NEWTON, COL_NONFINITE, COL_LINESEARCH, COL_BAD_INPUT = 0, 1, 2, 3, 4
 

@@ -466,6 +466,49 @@ def test_schur_preconditioner_reaches_the_same_roots(J, prec):
     print(f"GMRES iterations over 3 steps, {prec}: block {ga}, approximate Schur {gb}")
 
 
+def test_unpreconditioned_gmres(J):
+    """Without a preconditioner (P = I, the baseline of the paper's comparison
+    of iteration counts in Section 3.2) the apply is the identity, and JFNK
+    reaches the roots of the preconditioned runs with many more GMRES
+    iterations.  Short columns and dt = 1e-8 s keep the scaled Jacobian's
+    condition number within reach of restarted GMRES(30)."""
+    cols = W.config2(seed=2400, ncols=6, nmin=40, nmax=96, dt=1e-8)
+    packed = W.pack(cols)
+    rng = np.random.default_rng(31)
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64, prec_kind=J.PRECK_NONE))
+    xn = torch.from_numpy(packed.ne * rng.uniform(0.8, 1.2, packed.total)).cuda()
+    xp = torch.from_numpy(packed.phi + rng.uniform(-1, 1, packed.total)).cuda()
+    r = rng.standard_normal((2, packed.total))
+    zn, zp = solver.block_solve(prob, ne, phi, xn, xp, torch.from_numpy(r[0].copy()).cuda(),
+                                torch.from_numpy(r[1].copy()).cuda())
+    assert np.array_equal(zn.cpu().numpy(), r[0]) and np.array_equal(zp.cpu().numpy(), r[1])
+    solver.close()
+    out = {}
+    for kind in (J.PRECK_BLOCK, J.PRECK_SCHUR, J.PRECK_NONE):
+        prob, ne, phi, _, _ = J.device_problem(packed)
+        solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64, prec_kind=kind, max_restarts=60))
+        pne = pph = None
+        gm = nw = 0
+        for _ in range(3):
+            cur = (ne.clone(), phi.clone())
+            rc, st = solver.step(prob, ne, phi, pne, pph)
+            assert rc == J.JFNK_OK, (kind, np.bincount(st.status))
+            gm += int(st.gmres_iters.sum())
+            nw += int(st.newton_iters.sum())
+            pne, pph = cur
+        solver.close()
+        out[kind] = (ne.cpu().numpy(), phi.cpu().numpy(), gm, nw)
+    a = out[J.PRECK_BLOCK]
+    for kind in (J.PRECK_SCHUR, J.PRECK_NONE):
+        b = out[kind]
+        assert np.linalg.norm(a[0] - b[0]) <= 1e-8 * np.linalg.norm(a[0]), kind
+        assert np.linalg.norm(a[1] - b[1]) <= 1e-8 * np.linalg.norm(a[1]), kind
+    print("GMRES iterations / Newton iterations over 3 steps: block %d/%d, approximate Schur %d/%d, none %d/%d"
+          % (out[0][2], out[0][3], out[1][2], out[1][3], out[2][2], out[2][3]))
+    assert out[J.PRECK_NONE][2] > out[J.PRECK_SCHUR][2] >= out[J.PRECK_BLOCK][2]
+
+
 def test_degenerate_columns(J):
     """Degenerate inputs: a column with no charge, source or loss starts at
     its exact root (n = 0, phi linear between the electrodes) and must stay
