@@ -286,6 +286,7 @@ struct jfnk_ctx {
     bool fac_reuse_ok = false;   // the workspace holds factors of the current layout from the last step
     bool hist_valid = false;     // the per-column records below describe the current layout
     std::vector<int32_t> last_newton, last_status;
+    std::vector<double> last_cost;   // bytes per cell the column's last step moved (estimate)
     // schedule autotuner: workgroup size measured best for a column layout
     int force_T = 0;                      // set while the tuner tries a candidate
     int tuned_T = 0;
@@ -632,6 +633,25 @@ int run_plain(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t s
 
 template <int T, class FT>
 int run_batched(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t st) {
+    // Workgroup order of the solve launch: by expected work, largest first
+    // (longest-processing-time), the work of a column taken as its cells
+    // times the bytes per cell its previous step moved; by cells alone
+    // without that record.  The dispatcher hands workgroups to CUs in this
+    // order, so a column that is still iterating starts early instead of
+    // extending the tail of the launch.
+    if (ctx->hist_valid && (int)ctx->last_cost.size() == p->ncols) {
+        std::vector<int> ord(p->ncols);
+        for (int c = 0; c < p->ncols; ++c) ord[c] = c;
+        std::vector<double> key(p->ncols);
+        for (int c = 0; c < p->ncols; ++c) key[c] = (double)ctx->h_cols[c].n * ctx->last_cost[c];
+        std::stable_sort(ord.begin(), ord.end(), [&](int i, int j) { return key[i] > key[j]; });
+        bool same = true;
+        for (int c = 0; c < p->ncols && same; ++c) same = ctx->h_order[c] == ord[c];
+        if (!same) {
+            for (int c = 0; c < p->ncols; ++c) ctx->h_order[c] = ord[c];
+            HIP_OK(hipMemcpyAsync(ctx->d_order, ctx->h_order, sizeof(int) * p->ncols, hipMemcpyHostToDevice, st));
+        }
+    }
     SolveArgs a;
     a.W = ctx->W;
     a.prm = make_params(ctx, p, x);
@@ -1016,9 +1036,15 @@ int jfnk_step(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, jfnk_stats* s
     ctx->last_status.resize(p->ncols);
     const bool learned = ctx->cfg.guess == JFNK_GUESS_LEARNED && (int)ctx->evaluated.size() == p->ncols &&
                          (int)ctx->reject_streak.size() == p->ncols;
+    ctx->last_cost.resize(p->ncols);
     for (int c = 0; c < p->ncols; ++c) {
         ctx->last_newton[c] = ctx->h_cst[c].newton;
         ctx->last_status[c] = ctx->h_cst[c].status;
+        // set-up, factorisations, applies, trials, J.v, CGS passes, directions, extra vectors
+        const int32_t* w = ctx->h_cst[c].work;
+        ctx->last_cost[c] = 104.0 + 120.0 * w[kWorkFactor] + 112.0 * w[kWorkApply] + 104.0 * w[kWorkResidual] +
+                            120.0 * w[kWorkJv] + 32.0 * w[kWorkCgs] + 16.0 * w[kWorkLincomb] +
+                            16.0 * w[kWorkVecReads];
         if (learned && ctx->evaluated[c]) {
             if (ctx->h_cst[c].guess == JFNK_GUESS_LEARNED) {
                 ctx->reject_streak[c] = 0;
