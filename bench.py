@@ -157,6 +157,9 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
         autotune=None if tuned is None else dict(chosen=tuned[0], ms_first_3_steps=tuned[1]),
         guess_used={"prev": int(np.sum(used == 0)), "extrap": int(np.sum(used == 1)),
                     "learned": int(np.sum(used == 2))},
+        # column-steps whose learned candidate was evaluated (network inference
+        # and one residual), from jfnk_stats.phase_counts[:, 7]
+        learned_evaluated=int(sum(int(np.sum(r["counts"][:, 7])) for r in rec)),
     )
 
 
@@ -379,7 +382,8 @@ def main():
         "cpu_baseline": cpu,
         "plain": g.get("plain"),
         "ablations": g.get("ablations"),
-        "learned": None if g.get("train") is None else dict(g["train"], guess_used=g["guess_used"]),
+        "learned": None if g.get("train") is None else dict(g["train"], guess_used=g["guess_used"],
+                                                               evaluated=g["learned_evaluated"]),
         "speedup_vs_plain": (g["value"] / g["plain"]["value"]) if g.get("plain") else None,
         "solver": {
             "converged": g["converged"], "column_steps": g["total"], "max_res": g["max_res"],
