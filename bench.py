@@ -84,8 +84,10 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
         phi.copy_(phi0)
         tuned = solver.autotune(prob, ne, phi, steps=3, stream=stream)
     fb = 4.0 if prec == J.PREC_FP32 else 8.0
-    prev_n, prev_p = torch.empty_like(ne), torch.empty_like(phi)
-    state = {"e": 0}
+    # the caller's time loop: X^n is saved before the in-place step and becomes
+    # X^{n-1} of the next step by swapping buffers (one copy per step)
+    state = {"e": 0, "prev": (torch.empty_like(ne), torch.empty_like(phi)),
+             "save": (torch.empty_like(ne), torch.empty_like(phi))}
 
     def one_step(record):
         e = state["e"]
@@ -93,11 +95,13 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
             ne.copy_(ne0)
             phi.copy_(phi0)
         has_prev = e > 0
-        cur_n, cur_p = ne.clone(), phi.clone()
+        prev_n, prev_p = state["prev"]
+        save_n, save_p = state["save"]
+        save_n.copy_(ne)
+        save_p.copy_(phi)
         rc, st = solver.step(prob, ne, phi, prev_n if has_prev else None,
                              prev_p if has_prev else None, stream=stream)
-        prev_n.copy_(cur_n)
-        prev_p.copy_(cur_p)
+        state["prev"], state["save"] = state["save"], state["prev"]
         state["e"] = (e + 1) % EPISODE
         if record is not None:
             ms, _ = solver.last_timing()
