@@ -229,7 +229,8 @@ def run_gpu(args):
             r = measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, pr, gs, None, stream, ch)
             abl[name] = dict(value=r["value"], ms_per_step=r["ms_per_step"], converged=r["converged"],
                              max_res=r["max_res"], kernel_ms_avg=r["kernel_ms_avg"],
-                             newton_mean=r["newton_mean"], chord_mean=r["chord_mean"])
+                             newton_mean=r["newton_mean"], chord_mean=r["chord_mean"],
+                             threads=None if r["autotune"] is None else r["autotune"]["chosen"])
         out["ablations"] = abl
     if net is not None:
         net.close()
