@@ -79,10 +79,13 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
         solver.set_model(net)
     tuned = None
     if args.threads == 0 and not args.no_autotune:
-        # workgroup size per column for this layout, timed on the episode's first steps
+        # workgroup size per column for this layout, timed over one whole
+        # episode from the start state (its first steps alone favour small
+        # workgroups: many columns at once, while the later steps are bound
+        # by the columns that still iterate)
         ne.copy_(ne0)
         phi.copy_(phi0)
-        tuned = solver.autotune(prob, ne, phi, steps=3, stream=stream)
+        tuned = solver.autotune(prob, ne, phi, steps=EPISODE, stream=stream)
     fb = 4.0 if prec == J.PREC_FP32 else 8.0
     # the caller's time loop: X^n is saved before the in-place step and becomes
     # X^{n-1} of the next step by swapping buffers (one copy per step)
@@ -158,7 +161,7 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
         newton_mean=float(newton.mean()), newton_max=int(newton.max()),
         gmres_per_newton=float(gmres.sum() / max(newton.sum(), 1)),
         chord_mean=float(chords.mean()),
-        autotune=None if tuned is None else dict(chosen=tuned[0], ms_first_3_steps=tuned[1]),
+        autotune=None if tuned is None else dict(chosen=tuned[0], ms_per_episode=tuned[1]),
         guess_used={"prev": int(np.sum(used == 0)), "extrap": int(np.sum(used == 1)),
                     "learned": int(np.sum(used == 2))},
         # column-steps whose learned candidate was evaluated (network inference
