@@ -91,6 +91,7 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
     # X^{n-1} of the next step by swapping buffers (one copy per step)
     state = {"e": 0, "prev": (torch.empty_like(ne), torch.empty_like(phi)),
              "save": (torch.empty_like(ne), torch.empty_like(phi))}
+    stats = J.Stats(len(ns))   # filled by every step; records copy what they keep
 
     def one_step(record):
         e = state["e"]
@@ -103,7 +104,7 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
         save_n.copy_(ne)
         save_p.copy_(phi)
         rc, st = solver.step(prob, ne, phi, prev_n if has_prev else None,
-                             prev_p if has_prev else None, stream=stream)
+                             prev_p if has_prev else None, stream=stream, stats=stats)
         state["prev"], state["save"] = state["save"], state["prev"]
         state["e"] = (e + 1) % EPISODE
         if record is not None:

@@ -640,11 +640,23 @@ int run_batched(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t
     // order, so a column that is still iterating starts early instead of
     // extending the tail of the launch.
     if (ctx->hist_valid && (int)ctx->last_cost.size() == p->ncols) {
-        std::vector<int> ord(p->ncols);
-        for (int c = 0; c < p->ncols; ++c) ord[c] = c;
-        std::vector<double> key(p->ncols);
-        for (int c = 0; c < p->ncols; ++c) key[c] = (double)ctx->h_cols[c].n * ctx->last_cost[c];
-        std::stable_sort(ord.begin(), ord.end(), [&](int i, int j) { return key[i] > key[j]; });
+        // LPT needs no exact sort: a counting sort on the key's binary
+        // exponent and top three mantissa bits (eighths of an octave; keys
+        // from 1 to 2^64), largest first, column order within a bucket
+        constexpr int kBuckets = 8 * 64;
+        const int nc = p->ncols;
+        std::vector<int> bucket(nc), ord(nc);
+        int cnt[kBuckets + 1] = {0};
+        for (int c = 0; c < nc; ++c) {
+            const double key = std::max(1.0, (double)ctx->h_cols[c].n * ctx->last_cost[c]);
+            uint64_t u;
+            std::memcpy(&u, &key, sizeof(u));
+            const int b = std::min(kBuckets - 1, (int)((u >> 49) - (uint64_t)1023 * 8));
+            bucket[c] = kBuckets - 1 - b;
+            ++cnt[bucket[c] + 1];
+        }
+        for (int b = 0; b < kBuckets; ++b) cnt[b + 1] += cnt[b];
+        for (int c = 0; c < nc; ++c) ord[cnt[bucket[c]]++] = c;
         bool same = true;
         for (int c = 0; c < p->ncols && same; ++c) same = ctx->h_order[c] == ord[c];
         if (!same) {

@@ -188,22 +188,39 @@ class DeviceProblem:
     temp: object
     uface: object = None
 
+    def __setattr__(self, name, value):
+        # any reassigned field invalidates the cached argument struct
+        object.__setattr__(self, "_cached", None)
+        object.__setattr__(self, name, value)
+
     def cstruct(self) -> jfnk_problem:
+        """The C argument struct.  It is cached while no field is reassigned
+        and every host array is already contiguous in the C type (it then
+        points at the arrays themselves, so in-place updates reach the
+        library); otherwise it is rebuilt from converted copies each call."""
+        cached = self.__dict__.get("_cached")
+        if cached is not None:
+            return cached
         p = jfnk_problem()
         p.ncols = self.ncols
-        self._keep = [np.ascontiguousarray(self.col_offset, dtype=np.int64)]
-        p.col_offset = self._keep[0].ctypes.data_as(_lp)
+        keep = [np.ascontiguousarray(self.col_offset, dtype=np.int64)]
+        direct = keep[0] is self.col_offset
+        p.col_offset = keep[0].ctypes.data_as(_lp)
         for name in ("length", "dt", "phi_left", "phi_right", "eps_over_e", "ne_left", "ne_right"):
             a = np.ascontiguousarray(getattr(self, name), dtype=np.float64)
-            self._keep.append(a)
+            direct = direct and a is getattr(self, name)
+            keep.append(a)
             setattr(p, name, a.ctypes.data_as(_dp))
         for name in ("bc_left", "bc_right"):
             a = np.ascontiguousarray(getattr(self, name), dtype=np.int32)
-            self._keep.append(a)
+            direct = direct and a is getattr(self, name)
+            keep.append(a)
             setattr(p, name, a.ctypes.data_as(_ip))
         p.mu, p.diff, p.src = _ptr(self.mu), _ptr(self.diff), _ptr(self.src)
         p.k_loss, p.q_ion = _ptr(self.kloss), _ptr(self.q)
         p.u_face, p.temp = _ptr(self.uface), _ptr(self.temp)
+        object.__setattr__(self, "_keep", keep)
+        object.__setattr__(self, "_cached", p if direct else None)
         return p
 
 
@@ -232,12 +249,24 @@ class Stats:
         self.chord_steps = np.zeros(n, np.int32)
         self.phase_counts = np.zeros((n, 8), np.int32)
 
+    def __setattr__(self, name, value):
+        # a reassigned array invalidates the cached argument struct
+        object.__setattr__(self, "_cached", None)
+        object.__setattr__(self, name, value)
+
     def cstruct(self) -> jfnk_stats:
+        cached = self.__dict__.get("_cached")
+        if cached is not None:
+            return cached
         s = jfnk_stats()
         for name in ("status", "newton_iters", "gmres_iters", "backtracks", "guess_used", "chord_steps",
                      "phase_counts"):
-            setattr(s, name, getattr(self, name).ctypes.data_as(_ip))
+            a = getattr(self, name)
+            assert a.dtype == np.int32 and a.flags.c_contiguous
+            setattr(s, name, a.ctypes.data_as(_ip))
+        assert self.res_scaled.dtype == np.float64 and self.res_scaled.flags.c_contiguous
         s.res_scaled = self.res_scaled.ctypes.data_as(_dp)
+        object.__setattr__(self, "_cached", s)
         return s
 
 
