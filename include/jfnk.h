@@ -78,7 +78,8 @@ enum { JFNK_PREC_FP64 = 0, JFNK_PREC_FP32 = 1 };
    simplified-Newton steps are not taken (chord_tol is ignored). */
 enum { JFNK_PRECK_BLOCK = 0, JFNK_PRECK_SCHUR = 1, JFNK_PRECK_NONE = 2 };
 /* PLAIN: one column at a time, every phase a launch, control on the host.
-   BATCHED: one launch per step solves all columns, control on the GPU. */
+   BATCHED: three launches per step (gather, solve, write-back); the solve
+   launch runs the whole step of every column, control on the GPU. */
 enum { JFNK_SCHED_PLAIN = 0, JFNK_SCHED_BATCHED = 1 };
 /* per-column status */
 enum {
