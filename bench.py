@@ -9,7 +9,8 @@ step = one jfnk_step over the whole batch (1024 column-steps).
 Prints one JSON line: whole-job column-steps/s of the batched solver at
 ||S_F^-1 F||_inf < 1e-10, with the plain (host-driven, one column at a time)
 solver and the CPU oracle measured beside it, and the roofline of the solve
-kernel from HIP events and the algorithmic byte model of the design doc.
+kernel from HIP events and the algorithmic byte model (solve_bytes_per_cell,
+gather_bytes_per_cell).
 """
 from __future__ import annotations
 

@@ -11,8 +11,8 @@
  * with partial pivoting).  The paper reaches the same root with JFNK
  * (Algorithm 2); a direct Newton is the plain definition of that root.
  *
- * Discrete residual (readings of the paper where it is silent or garbled are
- * listed in the design doc):
+ * Discrete residual (where the paper is silent or garbled, the reading taken
+ * is stated at the point it applies):
  *   cells i = 0..N-1 of width h = L/N; faces j = 0..N, face j left of cell j.
  *   interior face j (cells a=j-1, b=j): mu_f, D_f arithmetic means,
  *     Pe = (u_f h + mu_f (phi_b - phi_a)) / D_f,

@@ -97,7 +97,8 @@ def flame_column(n: int, volts: float, *, a_ion: float = 1e16, x_f: float = 0.01
 
 
 # ---------------------------------------------------------------------------
-# The five workloads.  Index 0..4 in the order they are listed in the design doc.
+# The five workloads, index 0..4: a single column, a single-column march, the
+# 1024-column batch, the learned guess's training batches and the stiff batch.
 # ---------------------------------------------------------------------------
 
 def config0() -> List[Column]:
