@@ -194,6 +194,27 @@ int jfnk_create(const jfnk_config *cfg, jfnk_ctx **out);
 int jfnk_step(jfnk_ctx *ctx, const jfnk_problem *p, jfnk_state *x, jfnk_stats *st,
               void *stream);
 
+/* The same step, returned as soon as it is queued (batched schedule only), so
+   that the host prepares the next step while this one runs (Section 3.2's
+   iteration per column is unchanged; only the host's waiting moves).  At most
+   one step is in flight: a call that queues step k+1 then waits for step k
+   and reports it through prev_stats (may be NULL) and *prev_rc (JFNK_OK or
+   JFNK_NOT_CONVERGED; -1 when no step was in flight).  The host's per-step
+   choices for step k+1 (workgroup order, which columns evaluate the learned
+   guess) then come from step k-1 instead of step k.  Inputs of a queued step
+   (the arrays behind p and x) must stay valid and unchanged until it is
+   reported; x->ne/phi are written in stream order.  jfnk_step_finish waits for
+   the step in flight and reports it.  Any other call on the context (a
+   synchronous step, autotuning, a new model, the test exports) first finishes
+   the step in flight and drops its statistics.  Allocates nothing.
+   Errors: JFNK_EINVAL (plain schedule), and those of jfnk_step. */
+int jfnk_step_async(jfnk_ctx *ctx, const jfnk_problem *p, jfnk_state *x, jfnk_stats *prev_stats,
+                    int32_t *prev_rc, void *stream);
+
+/* Wait for the step in flight and report it.  Returns JFNK_OK or
+   JFNK_NOT_CONVERGED for it; JFNK_EINVAL when no step is in flight. */
+int jfnk_step_finish(jfnk_ctx *ctx, jfnk_stats *st);
+
 /* Release the context and its workspace.  NULL-safe. */
 void jfnk_destroy(jfnk_ctx *ctx);
 

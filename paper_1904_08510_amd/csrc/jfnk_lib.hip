@@ -294,9 +294,29 @@ struct jfnk_ctx {
     std::vector<uint8_t> evaluated;       // network evaluated for the column this step
     std::vector<int32_t> reject_streak;   // consecutive evaluations its candidate lost
     std::vector<int32_t> skip_left;       // chances to skip before evaluating it again
+    // Steps in flight (jfnk_step_async).  The per-step host resources above
+    // (statistics buffer, events, staging of the work order and of the learned
+    // mask, the evaluated set) are swapped with this slot after every
+    // asynchronous enqueue, so the step in flight keeps its own while the next
+    // one is prepared.
+    struct Slot {
+        ColState* h_cst = nullptr;
+        int* h_order = nullptr;
+        int32_t* h_lmask = nullptr;
+        hipEvent_t ev0 = nullptr, evg = nullptr, evs = nullptr, ev1 = nullptr, done = nullptr;
+        std::vector<uint8_t> evaluated;
+        bool timed = false, timed3 = false, learned_ran = false;
+        int launches = 0;
+    } alt;
+    hipEvent_t evdone = nullptr;   // recorded after the statistics copy of the step
+    bool learned_ran = false;      // the step's set-up evaluated learned candidates
+    bool pending = false;          // an asynchronous step is in flight (its resources in alt)
+    int pending_ncols = 0;
 };
 
 namespace {
+
+int drain(jfnk_ctx* ctx);
 
 int fail(jfnk_ctx* c, int code, const std::string& msg) {
     if (c) c->err = msg;
@@ -730,20 +750,26 @@ int upload_schedule(jfnk_ctx* ctx, int ncols, hipStream_t st) {
 
 // Validate and upload the schedule, unless the per-column inputs are the
 // ones the resident schedule was built from (then only the pointers are checked).
+// The per-column inputs are the ones the resident schedule was built from.
+bool schedule_matches(const jfnk_ctx* ctx, const jfnk_problem* p) {
+    if (!(p && ctx->sched_valid && p->ncols >= 1 && p->col_offset && p->length && p->dt && p->phi_left &&
+          p->phi_right && p->eps_over_e && p->ne_left && p->ne_right && p->bc_left && p->bc_right &&
+          (int)ctx->last_off.size() == p->ncols + 1 &&
+          memcmp(ctx->last_off.data(), p->col_offset, sizeof(int64_t) * (p->ncols + 1)) == 0))
+        return false;
+    const double* srcs[7] = {p->length, p->dt, p->phi_left, p->phi_right, p->eps_over_e, p->ne_left,
+                             p->ne_right};
+    for (int k = 0; k < 7; ++k)
+        if (memcmp(ctx->last_scal.data() + (size_t)k * p->ncols, srcs[k], sizeof(double) * p->ncols) != 0)
+            return false;
+    return memcmp(ctx->last_bc.data(), p->bc_left, sizeof(int32_t) * p->ncols) == 0 &&
+           memcmp(ctx->last_bc.data() + p->ncols, p->bc_right, sizeof(int32_t) * p->ncols) == 0;
+}
+
 int schedule_cached(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, hipStream_t st) {
     if (!p || !x) return fail(ctx, JFNK_EINVAL, "null problem or state");
-    if (ctx->sched_valid && p->ncols >= 1 && p->col_offset && p->length && p->dt && p->phi_left &&
-        p->phi_right && p->eps_over_e && p->ne_left && p->ne_right && p->bc_left && p->bc_right &&
-        (int)ctx->last_off.size() == p->ncols + 1 &&
-        memcmp(ctx->last_off.data(), p->col_offset, sizeof(int64_t) * (p->ncols + 1)) == 0) {
-        const double* srcs[7] = {p->length, p->dt, p->phi_left, p->phi_right, p->eps_over_e, p->ne_left,
-                                 p->ne_right};
-        bool same = true;
-        for (int k = 0; k < 7 && same; ++k)
-            same = memcmp(ctx->last_scal.data() + (size_t)k * p->ncols, srcs[k], sizeof(double) * p->ncols) == 0;
-        same = same && memcmp(ctx->last_bc.data(), p->bc_left, sizeof(int32_t) * p->ncols) == 0 &&
-               memcmp(ctx->last_bc.data() + p->ncols, p->bc_right, sizeof(int32_t) * p->ncols) == 0;
-        if (same) {
+    {
+        if (schedule_matches(ctx, p)) {
             if (!p->mu || !p->diff || !p->src || !p->q_ion || !x->ne || !x->phi)
                 return fail(ctx, JFNK_EINVAL, "null per-cell array");
             if ((x->ne_prev == nullptr) != (x->phi_prev == nullptr))
@@ -768,9 +794,9 @@ int schedule_cached(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, h
     return JFNK_OK;
 }
 
-int gather_stats(jfnk_ctx* ctx, int ncols, jfnk_stats* stt, hipStream_t st, int* nfail) {
-    HIP_OK(hipMemcpyAsync(ctx->h_cst, ctx->W.cst, sizeof(ColState) * ncols, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
+// Statistics of the step whose copy to h_cst was enqueued before evdone.
+int gather_stats(jfnk_ctx* ctx, int ncols, jfnk_stats* stt, int* nfail) {
+    HIP_OK(hipEventSynchronize(ctx->evdone));
     if (ctx->timed) {
         float ms = 0.0f;
         HIP_OK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
@@ -816,6 +842,7 @@ int check_ctx(jfnk_ctx* ctx) {
 // common set-up of the single-phase test exports
 int prepare_test(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, hipStream_t st,
                  PhaseArgs& a) {
+    if (int rc = drain(ctx)) return rc;
     ctx->sched_valid = false;
     ctx->hist_valid = false;
     ctx->learn_active = false;
@@ -893,6 +920,89 @@ int learned_guess(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream
     return JFNK_OK;
 }
 
+void swap_slot(jfnk_ctx* ctx) {
+    jfnk_ctx::Slot& a = ctx->alt;
+    std::swap(ctx->h_cst, a.h_cst);
+    std::swap(ctx->h_order, a.h_order);
+    std::swap(ctx->h_lmask, a.h_lmask);
+    std::swap(ctx->ev0, a.ev0);
+    std::swap(ctx->evg, a.evg);
+    std::swap(ctx->evs, a.evs);
+    std::swap(ctx->ev1, a.ev1);
+    std::swap(ctx->evdone, a.done);
+    std::swap(ctx->evaluated, a.evaluated);
+    std::swap(ctx->timed, a.timed);
+    std::swap(ctx->timed3, a.timed3);
+    std::swap(ctx->learned_ran, a.learned_ran);
+    std::swap(ctx->last_launches, a.launches);
+}
+
+// Enqueue one step and the copy of its column statistics (evdone after it).
+int step_enqueue(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t st) {
+    int rc = schedule_cached(ctx, p, x, st);
+    if (rc) return rc;
+    ctx->learn_active = false;
+    if (ctx->cfg.guess == JFNK_GUESS_LEARNED) {
+        rc = learned_guess(ctx, p, x, st);
+        if (rc) return rc;
+    }
+    rc = ctx->cfg.prec_precision == JFNK_PREC_FP32 ? dispatch_run<float>(ctx, p, x, st)
+                                                   : dispatch_run<double>(ctx, p, x, st);
+    ctx->learned_ran = ctx->learn_active && (int)ctx->evaluated.size() == p->ncols;
+    ctx->learn_active = false;
+    if (rc) return rc;
+    HIP_OK(hipMemcpyAsync(ctx->h_cst, ctx->W.cst, sizeof(ColState) * p->ncols, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipEventRecord(ctx->evdone, st));
+    return JFNK_OK;
+}
+
+// Wait for the step whose resources are current, report its statistics and
+// update the per-column history the next steps' decisions use.
+int step_process(jfnk_ctx* ctx, int ncols, jfnk_stats* stt) {
+    int nfail = 0;
+    int rc = gather_stats(ctx, ncols, stt, &nfail);
+    if (rc) return rc;
+    const bool learned_ran = ctx->learned_ran && (int)ctx->evaluated.size() == ncols;
+    if (stt && stt->phase_counts)
+        for (int c = 0; c < ncols; ++c)
+            stt->phase_counts[(int64_t)c * kWorkCounts + kWorkLearned] = learned_ran && ctx->evaluated[c] ? 1 : 0;
+    // which columns needed Newton iterations (the learned guess is evaluated for those)
+    ctx->last_newton.resize(ncols);
+    ctx->last_status.resize(ncols);
+    const bool learned = ctx->cfg.guess == JFNK_GUESS_LEARNED && (int)ctx->evaluated.size() == ncols &&
+                         (int)ctx->reject_streak.size() == ncols;
+    ctx->last_cost.resize(ncols);
+    for (int c = 0; c < ncols; ++c) {
+        ctx->last_newton[c] = ctx->h_cst[c].newton;
+        ctx->last_status[c] = ctx->h_cst[c].status;
+        // set-up, factorisations, applies, trials, J.v, CGS passes, directions, extra vectors
+        const int32_t* w = ctx->h_cst[c].work;
+        ctx->last_cost[c] = 104.0 + 120.0 * w[kWorkFactor] + 112.0 * w[kWorkApply] + 104.0 * w[kWorkResidual] +
+                            120.0 * w[kWorkJv] + 32.0 * w[kWorkCgs] + 16.0 * w[kWorkLincomb] +
+                            16.0 * w[kWorkVecReads];
+        if (learned && ctx->evaluated[c]) {
+            if (ctx->h_cst[c].guess == JFNK_GUESS_LEARNED) {
+                ctx->reject_streak[c] = 0;
+            } else {
+                ctx->reject_streak[c] = std::min(ctx->reject_streak[c] + 1, kMaxBackoff);
+                ctx->skip_left[c] = (1 << (2 * ctx->reject_streak[c])) - 1;
+            }
+        }
+    }
+    ctx->hist_valid = true;
+    ctx->fac_reuse_ok = true;
+    return nfail ? JFNK_NOT_CONVERGED : JFNK_OK;
+}
+
+// Finish an asynchronous step still in flight (its statistics are dropped).
+int drain(jfnk_ctx* ctx) {
+    if (!ctx->pending) return JFNK_OK;
+    swap_slot(ctx);
+    ctx->pending = false;
+    const int rc = step_process(ctx, ctx->pending_ncols, nullptr);
+    return rc == JFNK_NOT_CONVERGED ? JFNK_OK : rc;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -961,6 +1071,8 @@ int jfnk_create(const jfnk_config* cfg, jfnk_ctx** out) {
     if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_cst, sizeof(ColState) * cfg->max_cols, 0);
     if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_scal, sizeof(double) * kScalSlots * 2, 0);
     if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_order, sizeof(int) * cfg->max_cols, 0);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->alt.h_cst, sizeof(ColState) * cfg->max_cols, 0);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->alt.h_order, sizeof(int) * cfg->max_cols, 0);
     // gather / write-back tables: a column of M rows and T owners has ceil(M/8) T/8 tiles
     ctx->capMove = (ctx->capP + 8 * (int64_t)Tcap * cfg->max_cols) / (64 * kMoveTiles) + cfg->max_cols + 1;
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_mcol, sizeof(int32_t) * ctx->capMove);
@@ -971,6 +1083,12 @@ int jfnk_create(const jfnk_config* cfg, jfnk_ctx** out) {
     if (e == hipSuccess) e = hipEventCreate(&ctx->ev1);
     if (e == hipSuccess) e = hipEventCreate(&ctx->evg);
     if (e == hipSuccess) e = hipEventCreate(&ctx->evs);
+    if (e == hipSuccess) e = hipEventCreate(&ctx->evdone);
+    if (e == hipSuccess) e = hipEventCreate(&ctx->alt.ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ctx->alt.ev1);
+    if (e == hipSuccess) e = hipEventCreate(&ctx->alt.evg);
+    if (e == hipSuccess) e = hipEventCreate(&ctx->alt.evs);
+    if (e == hipSuccess) e = hipEventCreate(&ctx->alt.done);
     if (e != hipSuccess) { (void)hipGetLastError(); jfnk_destroy(ctx); return JFNK_ENOMEM; }
     // zero the whole workspace once: padding cells must read as zero
     e = hipMemset(ctx->base, 0, sizeof(double) * words);
@@ -982,6 +1100,7 @@ int jfnk_create(const jfnk_config* cfg, jfnk_ctx** out) {
 
 void jfnk_destroy(jfnk_ctx* ctx) {
     if (!ctx) return;
+    if (ctx->pending && ctx->alt.done) (void)hipEventSynchronize(ctx->alt.done);   // step in flight
     if (ctx->base) (void)hipFree(ctx->base);
     if (ctx->d_order) (void)hipFree(ctx->d_order);
     if (ctx->d_mcol) (void)hipFree(ctx->d_mcol);
@@ -998,6 +1117,13 @@ void jfnk_destroy(jfnk_ctx* ctx) {
     if (ctx->d_learn) (void)hipFree(ctx->d_learn);
     if (ctx->d_lmask) (void)hipFree(ctx->d_lmask);
     if (ctx->h_lmask) (void)hipHostFree(ctx->h_lmask);
+    if (ctx->evdone) (void)hipEventDestroy(ctx->evdone);
+    jfnk_ctx::Slot& a = ctx->alt;
+    if (a.h_cst) (void)hipHostFree(a.h_cst);
+    if (a.h_order) (void)hipHostFree(a.h_order);
+    if (a.h_lmask) (void)hipHostFree(a.h_lmask);
+    for (hipEvent_t ev : {a.ev0, a.ev1, a.evg, a.evs, a.done})
+        if (ev) (void)hipEventDestroy(ev);
     delete ctx;
 }
 
@@ -1024,51 +1150,54 @@ int jfnk_step(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, jfnk_stats* s
     if (rc) return rc;
     if (ctx->cfg.guess == JFNK_GUESS_LEARNED && !ctx->model)
         return fail(ctx, JFNK_EMODEL, "learned guess requested but no model is loaded");
-    hipStream_t st = (hipStream_t)stream;
-    rc = schedule_cached(ctx, p, x, st);
+    rc = drain(ctx);
     if (rc) return rc;
-    ctx->learn_active = false;
-    if (ctx->cfg.guess == JFNK_GUESS_LEARNED) {
-        rc = learned_guess(ctx, p, x, st);
+    rc = step_enqueue(ctx, p, x, (hipStream_t)stream);
+    if (rc) return rc;
+    return step_process(ctx, p->ncols, stt);
+}
+
+int jfnk_step_async(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, jfnk_stats* prev_stats,
+                    int32_t* prev_rc, void* stream) {
+    if (prev_rc) *prev_rc = -1;
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (ctx->cfg.guess == JFNK_GUESS_LEARNED && !ctx->model)
+        return fail(ctx, JFNK_EMODEL, "learned guess requested but no model is loaded");
+    if (ctx->cfg.schedule != JFNK_SCHED_BATCHED)
+        return fail(ctx, JFNK_EINVAL, "asynchronous steps need the batched schedule");
+    // a new layout rewrites the staged schedule: finish the step in flight first
+    if (ctx->pending && !schedule_matches(ctx, p)) {
+        rc = drain(ctx);
         if (rc) return rc;
     }
-    rc = ctx->cfg.prec_precision == JFNK_PREC_FP32 ? dispatch_run<float>(ctx, p, x, st)
-                                                   : dispatch_run<double>(ctx, p, x, st);
-    const bool learned_ran = ctx->learn_active && (int)ctx->evaluated.size() == p->ncols;
-    ctx->learn_active = false;
+    rc = step_enqueue(ctx, p, x, (hipStream_t)stream);
     if (rc) return rc;
-    int nfail = 0;
-    rc = gather_stats(ctx, p->ncols, stt, st, &nfail);
-    if (rc) return rc;
-    if (stt && stt->phase_counts)
-        for (int c = 0; c < p->ncols; ++c)
-            stt->phase_counts[(int64_t)c * kWorkCounts + kWorkLearned] = learned_ran && ctx->evaluated[c] ? 1 : 0;
-    // which columns needed Newton iterations (the learned guess is evaluated for those)
-    ctx->last_newton.resize(p->ncols);
-    ctx->last_status.resize(p->ncols);
-    const bool learned = ctx->cfg.guess == JFNK_GUESS_LEARNED && (int)ctx->evaluated.size() == p->ncols &&
-                         (int)ctx->reject_streak.size() == p->ncols;
-    ctx->last_cost.resize(p->ncols);
-    for (int c = 0; c < p->ncols; ++c) {
-        ctx->last_newton[c] = ctx->h_cst[c].newton;
-        ctx->last_status[c] = ctx->h_cst[c].status;
-        // set-up, factorisations, applies, trials, J.v, CGS passes, directions, extra vectors
-        const int32_t* w = ctx->h_cst[c].work;
-        ctx->last_cost[c] = 104.0 + 120.0 * w[kWorkFactor] + 112.0 * w[kWorkApply] + 104.0 * w[kWorkResidual] +
-                            120.0 * w[kWorkJv] + 32.0 * w[kWorkCgs] + 16.0 * w[kWorkLincomb] +
-                            16.0 * w[kWorkVecReads];
-        if (learned && ctx->evaluated[c]) {
-            if (ctx->h_cst[c].guess == JFNK_GUESS_LEARNED) {
-                ctx->reject_streak[c] = 0;
-            } else {
-                ctx->reject_streak[c] = std::min(ctx->reject_streak[c] + 1, kMaxBackoff);
-                ctx->skip_left[c] = (1 << (2 * ctx->reject_streak[c])) - 1;
-            }
-        }
+    ctx->fac_reuse_ok = true;      // the next step runs after this one on the stream
+    // this step's resources move to the in-flight slot; those of the previous
+    // step in flight (if any) come back to the current one
+    swap_slot(ctx);
+    if (ctx->pending) {
+        // finish the previous step while this one runs
+        const int n = ctx->pending_ncols;
+        ctx->pending_ncols = p->ncols;
+        const int prc = step_process(ctx, n, prev_stats);
+        if (prc != JFNK_OK && prc != JFNK_NOT_CONVERGED) return prc;
+        if (prev_rc) *prev_rc = prc;
+    } else {
+        ctx->pending = true;
+        ctx->pending_ncols = p->ncols;
     }
-    ctx->hist_valid = true;
-    ctx->fac_reuse_ok = true;
-    return nfail ? JFNK_NOT_CONVERGED : JFNK_OK;
+    return JFNK_OK;
+}
+
+int jfnk_step_finish(jfnk_ctx* ctx, jfnk_stats* stt) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!ctx->pending) return fail(ctx, JFNK_EINVAL, "no asynchronous step in flight");
+    swap_slot(ctx);
+    ctx->pending = false;
+    return step_process(ctx, ctx->pending_ncols, stt);
 }
 
 int jfnk_autotune(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, int32_t steps,
@@ -1079,6 +1208,8 @@ int jfnk_autotune(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, int
         return fail(ctx, JFNK_EINVAL, "autotune: bad arguments");
     if (ctx->cfg.schedule != JFNK_SCHED_BATCHED || ctx->cfg.threads_override != 0)
         return fail(ctx, JFNK_EINVAL, "autotune: needs the batched schedule and no threads_override");
+    rc = drain(ctx);
+    if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     const int64_t total = p->col_offset[p->ncols];
     if (total < 1 || total > ctx->cfg.max_total_cells) return fail(ctx, JFNK_ECAPACITY, "autotune: capacity");
@@ -1143,6 +1274,8 @@ int jfnk_autotune(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, int
 int jfnk_set_model(jfnk_ctx* ctx, jfnk_net* net) {
     int rc = check_ctx(ctx);
     if (rc) return rc;
+    rc = drain(ctx);
+    if (rc) return rc;
     if (!net) {
         ctx->model = nullptr;
         return JFNK_OK;
@@ -1154,6 +1287,7 @@ int jfnk_set_model(jfnk_ctx* ctx, jfnk_net* net) {
         HIP_OK(hipMalloc((void**)&ctx->d_learn, sizeof(double) * 2 * ctx->cfg.max_total_cells));
         HIP_OK(hipMalloc((void**)&ctx->d_lmask, sizeof(int32_t) * ctx->cfg.max_cols));
         HIP_OK(hipHostMalloc((void**)&ctx->h_lmask, sizeof(int32_t) * ctx->cfg.max_cols, 0));
+        HIP_OK(hipHostMalloc((void**)&ctx->alt.h_lmask, sizeof(int32_t) * ctx->cfg.max_cols, 0));
         HIP_OK(hipMemset(ctx->d_lmask, 0, sizeof(int32_t) * ctx->cfg.max_cols));
         HIP_OK(hipDeviceSynchronize());
         ctx->W.lmask = ctx->d_lmask;

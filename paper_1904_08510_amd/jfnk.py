@@ -83,6 +83,11 @@ def lib():
         L.jfnk_step.argtypes = [C.c_void_p, C.POINTER(jfnk_problem), C.POINTER(jfnk_state),
                                 C.POINTER(jfnk_stats), C.c_void_p]
         L.jfnk_step.restype = C.c_int
+        L.jfnk_step_async.argtypes = [C.c_void_p, C.POINTER(jfnk_problem), C.POINTER(jfnk_state),
+                                      C.POINTER(jfnk_stats), C.POINTER(C.c_int32), C.c_void_p]
+        L.jfnk_step_async.restype = C.c_int
+        L.jfnk_step_finish.argtypes = [C.c_void_p, C.POINTER(jfnk_stats)]
+        L.jfnk_step_finish.restype = C.c_int
         L.jfnk_destroy.argtypes = [C.c_void_p]
         L.jfnk_destroy.restype = None
         L.jfnk_last_error.argtypes = [C.c_void_p]
@@ -134,7 +139,8 @@ def lib():
     return _LIB
 
 
-EXPORTED_SYMBOLS = ("jfnk_config_default", "jfnk_create", "jfnk_step", "jfnk_destroy",
+EXPORTED_SYMBOLS = ("jfnk_config_default", "jfnk_create", "jfnk_step", "jfnk_step_async", "jfnk_step_finish",
+                    "jfnk_destroy",
                     "jfnk_last_error", "jfnk_last_timing", "jfnk_last_kernel_times", "jfnk_eval_residual", "jfnk_eval_jv",
                     "jfnk_block_solve", "jfnk_net_config_default", "jfnk_net_param_count",
                     "jfnk_net_create", "jfnk_net_destroy", "jfnk_net_last_error",
@@ -340,6 +346,32 @@ class Solver:
         if raw:
             return rc, st
         self._check(rc)
+        return rc, st
+
+    def step_async(self, prob: DeviceProblem, ne, phi, ne_prev=None, phi_prev=None, stream=None,
+                   prev_stats: Optional[Stats] = None):
+        """Queue one step and return; if a step was in flight, wait for it and
+        return (its return code, its stats), else (None, None).  The tensors of
+        the queued step must stay alive until it is reported."""
+        p = prob.cstruct()
+        s = self._state(ne, phi, ne_prev, phi_prev)
+        st = prev_stats if prev_stats is not None else Stats(prob.ncols)
+        prc = C.c_int32(-1)
+        # the argument structs must outlive the queued step: keep them
+        self._inflight = (p, s, ne, phi, ne_prev, phi_prev)
+        rc = lib().jfnk_step_async(self.h, C.byref(p), C.byref(s), C.byref(st.cstruct()), C.byref(prc),
+                                   _stream_ptr(stream))
+        self._check(rc)
+        if prc.value < 0:
+            return None, None
+        return prc.value, st
+
+    def step_finish(self, stats: Optional[Stats] = None, ncols: Optional[int] = None):
+        """Wait for the step in flight; (its return code, its stats)."""
+        st = stats if stats is not None else Stats(ncols)
+        rc = lib().jfnk_step_finish(self.h, C.byref(st.cstruct()))
+        self._check(rc)
+        self._inflight = None
         return rc, st
 
     def autotune(self, prob: DeviceProblem, ne, phi, ne_prev=None, phi_prev=None, steps: int = 3,

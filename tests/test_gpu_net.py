@@ -276,6 +276,77 @@ def test_learned_backoff_schedule(J, R):
     assert evaluations[0] == nc and sum(evaluations[16:]) > 0
 
 
+@pytest.mark.parametrize("guess", ["extrap", "learned"])
+def test_async_steps_match_synchronous_steps(J, R, guess):
+    """jfnk_step_async queues a step and reports the previous one.  Over 8
+    steps it gives the states, iteration counts and statuses of synchronous
+    steps: bit for bit with the extrapolated guess (the host's per-step choices,
+    taken one step later, change only the workgroup order); with the learned
+    guess the set of evaluated columns may differ, the roots may not."""
+    packed = W.pack(W.config2(seed=2500, ncols=24, nmin=400, nmax=3000))
+    n = packed.ncols
+    runs = {}
+    for mode in ("sync", "async"):
+        prob, ne, phi, _, _ = J.device_problem(packed)
+        g = J.GUESS_LEARNED if guess == "learned" else J.GUESS_EXTRAP
+        solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP32, guess=g))
+        if guess == "learned":
+            net = J.Net(J.net_default_config(out_scale_ne=S0, out_scale_phi=S1))
+            net.set_params(params32(R, 9))
+            solver.set_model(net)
+        prev = (torch.empty_like(ne), torch.empty_like(phi))
+        save = (torch.empty_like(ne), torch.empty_like(phi))
+        rec = []
+        for k in range(8):
+            save[0].copy_(ne)
+            save[1].copy_(phi)
+            pa = (prev[0], prev[1]) if k else (None, None)
+            if mode == "sync":
+                rc, st = solver.step(prob, ne, phi, *pa)
+                rec.append((rc, st.status.copy(), st.newton_iters.copy(), st.gmres_iters.copy()))
+            else:
+                prc, st = solver.step_async(prob, ne, phi, *pa, prev_stats=J.Stats(n))
+                if k == 0:
+                    assert prc is None and st is None
+                else:
+                    rec.append((prc, st.status.copy(), st.newton_iters.copy(), st.gmres_iters.copy()))
+            prev, save = save, prev
+        if mode == "async":
+            rc, st = solver.step_finish(stats=J.Stats(n))
+            rec.append((rc, st.status.copy(), st.newton_iters.copy(), st.gmres_iters.copy()))
+            with pytest.raises(J.JfnkError) as e:
+                solver.step_finish(stats=J.Stats(n))
+            assert e.value.code == J.JFNK_EINVAL
+            # a synchronous step after asynchronous ones is an ordinary step
+            cur = (ne.clone(), phi.clone())
+            rc2, _ = solver.step(prob, cur[0], cur[1], prev[0], prev[1])
+            assert rc2 == J.JFNK_OK
+        torch.cuda.synchronize()
+        runs[mode] = (ne.cpu().numpy(), phi.cpu().numpy(), rec)
+        solver.close()
+    a, b = runs["sync"], runs["async"]
+    assert len(a[2]) == len(b[2]) == 8
+    for ra, rb in zip(a[2], b[2]):
+        assert ra[0] == rb[0] == J.JFNK_OK
+        for x, y in zip(ra[1:], rb[1:]):
+            assert np.array_equal(x, y)
+    if guess == "extrap":
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    else:
+        for x, y in ((a[0], b[0]), (a[1], b[1])):
+            assert np.linalg.norm(x - y) <= 1e-9 * np.linalg.norm(x)
+
+
+def test_async_step_needs_the_batched_schedule(J):
+    packed = W.pack(W.config2(seed=2501, ncols=2, nmin=100, nmax=200))
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    solver = J.Solver(J.config_for(packed, schedule=J.SCHED_PLAIN))
+    with pytest.raises(J.JfnkError) as e:
+        solver.step_async(prob, ne, phi)
+    assert e.value.code == J.JFNK_EINVAL
+    solver.close()
+
+
 def test_learned_errors(J, R):
     cols, prev, nxt = batch(seed=15)
     packed, prob, ne, phi, pne, pph, nne, nph = to_dev(J, cols, prev, nxt)
