@@ -94,6 +94,21 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
              "save": (torch.empty_like(ne), torch.empty_like(phi))}
     stats = J.Stats(len(ns))   # filled by every step; records copy what they keep
 
+    def report(rc, st, record):
+        has_prev = state["queued"].pop(0)
+        if record is not None:
+            ms, _ = solver.last_timing()
+            kms = solver.last_kernel_times()
+            record.append(dict(rc=rc, ms=ms, kms=kms, has_prev=has_prev, newton=st.newton_iters.copy(),
+                               gmres=st.gmres_iters.copy(), bt=st.backtracks.copy(),
+                               res=st.res_scaled.copy(), status=st.status.copy(),
+                               guess=st.guess_used.copy(), chords=st.chord_steps.copy(),
+                               counts=st.phase_counts.copy()))
+
+    # Steps are queued with jfnk_step_async: the host prepares step k+1 while
+    # step k runs, and each call reports the step before it.
+    state["queued"] = []
+
     def one_step(record):
         e = state["e"]
         if e == 0:
@@ -104,28 +119,29 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
         save_n, save_p = state["save"]
         save_n.copy_(ne)
         save_p.copy_(phi)
-        rc, st = solver.step(prob, ne, phi, prev_n if has_prev else None,
-                             prev_p if has_prev else None, stream=stream, stats=stats)
+        state["queued"].append(has_prev)
+        rc, st = solver.step_async(prob, ne, phi, prev_n if has_prev else None,
+                                   prev_p if has_prev else None, stream=stream, prev_stats=stats)
         state["prev"], state["save"] = state["save"], state["prev"]
         state["e"] = (e + 1) % EPISODE
-        if record is not None:
-            ms, _ = solver.last_timing()
-            kms = solver.last_kernel_times()
-            record.append(dict(rc=rc, ms=ms, kms=kms, has_prev=has_prev, newton=st.newton_iters.copy(),
-                               gmres=st.gmres_iters.copy(), bt=st.backtracks.copy(),
-                               res=st.res_scaled.copy(), status=st.status.copy(),
-                               guess=st.guess_used.copy(), chords=st.chord_steps.copy(),
-                               counts=st.phase_counts.copy()))
-        return rc
+        if rc is not None:
+            report(rc, st, record)
+
+    def finish(record):
+        rc, st = solver.step_finish(stats=stats)
+        report(rc, st, record)
 
     for _ in range(args.warmup):
         one_step(None)
+    if args.warmup > 0:
+        finish(None)
     state["e"] = 0
     torch.cuda.synchronize()
     rec = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         one_step(rec)
+    finish(rec)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     solver.close()
