@@ -195,8 +195,10 @@ class DeviceProblem:
     uface: object = None
 
     def __setattr__(self, name, value):
-        # any reassigned field invalidates the cached argument struct
-        object.__setattr__(self, "_cached", None)
+        # a field bound to another object invalidates the cached argument
+        # struct (an in-place update, x *= 2, rebinds the same object)
+        if self.__dict__.get(name, self) is not value:
+            object.__setattr__(self, "_cached", None)
         object.__setattr__(self, name, value)
 
     def cstruct(self) -> jfnk_problem:
@@ -256,8 +258,9 @@ class Stats:
         self.phase_counts = np.zeros((n, 8), np.int32)
 
     def __setattr__(self, name, value):
-        # a reassigned array invalidates the cached argument struct
-        object.__setattr__(self, "_cached", None)
+        # an array bound to another object invalidates the cached argument struct
+        if self.__dict__.get(name, self) is not value:
+            object.__setattr__(self, "_cached", None)
         object.__setattr__(self, name, value)
 
     def cstruct(self) -> jfnk_stats:

@@ -538,6 +538,27 @@ def test_plain_schedule_other_preconditioners(J, kind):
         assert np.linalg.norm(x - y) <= tol * np.linalg.norm(x), (kind, np.linalg.norm(x - y) / np.linalg.norm(x))
 
 
+def test_problem_struct_follows_reassigned_fields(J):
+    """The binding caches the C argument struct of a problem: in-place updates
+    of its arrays reach the library through the cached pointers, and a
+    reassigned field rebuilds it."""
+    packed = W.pack(W.config2(seed=2600, ncols=3, nmin=100, nmax=200))
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    p1 = prob.cstruct()
+    assert prob.cstruct() is p1
+    assert p1.mu == prob.mu.data_ptr()
+    dt_ptr = prob.dt.ctypes.data
+    prob.dt *= 0.5                       # in place: same array, same struct
+    assert prob.cstruct() is p1 and prob.dt.ctypes.data == dt_ptr
+    prob.mu = prob.mu * 1.3              # a new tensor
+    p2 = prob.cstruct()
+    assert p2 is not p1 and p2.mu == prob.mu.data_ptr()
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64))
+    rc, _ = solver.step(prob, ne, phi)
+    assert rc == J.JFNK_OK
+    solver.close()
+
+
 def test_degenerate_columns(J):
     """Degenerate inputs: a column with no charge, source or loss starts at
     its exact root (n = 0, phi linear between the electrodes) and must stay
