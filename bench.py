@@ -15,6 +15,7 @@ gather_bytes_per_cell).
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -138,12 +139,17 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
     state["e"] = 0
     torch.cuda.synchronize()
     rec = []
+    # Python's cyclic collector stays out of the timed loop (a pass over the
+    # heap left by the network's training can take milliseconds)
+    gc.collect()
+    gc.disable()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         one_step(rec)
     finish(rec)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    gc.enable()
     solver.close()
     for r in rec:   # outside the timed region
         r["conv"] = int(np.sum(r["status"] == 0))
