@@ -147,10 +147,15 @@ typedef struct {
 } jfnk_problem;
 
 typedef struct {
-    double *ne;                  /* [total] in: n^k, out: n^{k+1} */
-    double *phi;                 /* [total] in: phi^k, out: phi^{k+1} */
+    double *ne;                  /* [total] in: n^k, out: n^{k+1} (unless ne_out) */
+    double *phi;                 /* [total] in: phi^k, out: phi^{k+1} (unless phi_out) */
     const double *ne_prev;       /* [total] n^{k-1} for the guesses (NULL: none) */
     const double *phi_prev;      /* [total] */
+    double *ne_out;              /* [total] NULL: the step is in place; else n^{k+1} is
+                                    written here and ne, phi keep n^k, phi^k.  May be the
+                                    ne_prev array (read before it is written), so that a
+                                    caller alternates two states without a copy. */
+    double *phi_out;             /* [total] with ne_out (both or neither) */
 } jfnk_state;
 
 /* HOST arrays [ncols]; any pointer may be NULL */

@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kMoveThreads) void k_scatter(SolveArgs a) {
     const int b = a.W.cst[col.cd.index].cur;
     const int kb = ((int)blockIdx.x - col.cd.g0) * kMoveTiles;
     const int ke = min(kb + kMoveTiles, col.ntiles());
-    col.scatter(col.xb(b, 0), col.xb(b, 1), a.U.ne, a.U.phi, kb, ke, threadIdx.x >> 6, kMoveThreads / 64);
+    col.scatter(col.xb(b, 0), col.xb(b, 1), a.U.ne_out, a.U.phi_out, kb, ke, threadIdx.x >> 6, kMoveThreads / 64);
 }
 
 // ---------------------------------------------------------------------------
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(T) void k_phase(PhaseArgs a) {
         break;
     }
     case PH_FINAL: {
-        col.write_back(col.xb(a.o.cur, 0), col.xb(a.o.cur, 1), a.U.ne, a.U.phi);
+        col.write_back(col.xb(a.o.cur, 0), col.xb(a.o.cur, 1), a.U.ne_out, a.U.phi_out);
         if (threadIdx.x == 0) {
             ColState* cs = a.W.cst + col.cd.index;
             cs->res_inf = a.o.rinf; cs->res2 = a.o.r2; cs->status = a.o.status;
@@ -381,6 +381,8 @@ int validate(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x) {
         return fail(ctx, JFNK_EINVAL, "null per-cell array");
     if ((x->ne_prev == nullptr) != (x->phi_prev == nullptr))
         return fail(ctx, JFNK_EINVAL, "ne_prev and phi_prev must both be given or both NULL");
+    if ((x->ne_out == nullptr) != (x->phi_out == nullptr))
+        return fail(ctx, JFNK_EINVAL, "ne_out and phi_out must both be given or both NULL");
     if (p->col_offset[0] != 0) return fail(ctx, JFNK_EINVAL, "col_offset[0] != 0");
     int nmax = 0;
     for (int c = 0; c < p->ncols; ++c) {
@@ -470,6 +472,8 @@ UserArrays make_user(const jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x) 
     U.mu = p->mu; U.diff = p->diff; U.src = p->src; U.kloss = p->k_loss; U.q = p->q_ion;
     U.uface = p->u_face;
     U.ne = x->ne; U.phi = x->phi;
+    U.ne_out = x->ne_out ? x->ne_out : x->ne;
+    U.phi_out = x->phi_out ? x->phi_out : x->phi;
     U.ne_prev = x->ne_prev; U.phi_prev = x->phi_prev;
     U.ne_learn = nullptr; U.phi_learn = nullptr;
     if (ctx->learn_active) {
@@ -774,6 +778,8 @@ int schedule_cached(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, h
                 return fail(ctx, JFNK_EINVAL, "null per-cell array");
             if ((x->ne_prev == nullptr) != (x->phi_prev == nullptr))
                 return fail(ctx, JFNK_EINVAL, "ne_prev and phi_prev must both be given or both NULL");
+            if ((x->ne_out == nullptr) != (x->phi_out == nullptr))
+                return fail(ctx, JFNK_EINVAL, "ne_out and phi_out must both be given or both NULL");
             return JFNK_OK;
         }
     }

@@ -401,7 +401,7 @@ struct DevExec {
         return col.trial(cur, out, VecRef{col.Vb(col.prm.m, 0), col.Vb(col.prm.m, 1), 1.0, 1.0}, 1.0);
     }
     __device__ void finalize(const ColOutcome& o) {
-        if (!split) col.write_back(col.xb(o.cur, 0), col.xb(o.cur, 1), U.ne, U.phi);
+        if (!split) col.write_back(col.xb(o.cur, 0), col.xb(o.cur, 1), U.ne_out, U.phi_out);
         if (threadIdx.x == 0) {
             ColState* cs = col.W.cst + col.cd.index;
             cs->cur = o.cur;

@@ -86,8 +86,9 @@ struct SolverParams {
 // Caller arrays (natural layout, device pointers).
 struct UserArrays {
     const double *mu, *diff, *src, *kloss, *q, *uface;
-    double *ne, *phi;
+    double *ne, *phi;             // X^n
     const double *ne_prev, *phi_prev;
+    double *ne_out, *phi_out;     // where X^{n+1} goes (ne, phi for an in-place step)
     const double *ne_learn, *phi_learn;
 };
 

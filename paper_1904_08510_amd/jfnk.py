@@ -51,7 +51,7 @@ class jfnk_problem(C.Structure):
 
 class jfnk_state(C.Structure):
     _fields_ = [("ne", C.c_void_p), ("phi", C.c_void_p), ("ne_prev", C.c_void_p),
-                ("phi_prev", C.c_void_p)]
+                ("phi_prev", C.c_void_p), ("ne_out", C.c_void_p), ("phi_out", C.c_void_p)]
 
 
 class jfnk_net_config(C.Structure):
@@ -333,17 +333,19 @@ class Solver:
         return rc
 
     @staticmethod
-    def _state(ne, phi, ne_prev=None, phi_prev=None) -> jfnk_state:
+    def _state(ne, phi, ne_prev=None, phi_prev=None, ne_out=None, phi_out=None) -> jfnk_state:
         s = jfnk_state()
         s.ne, s.phi = _ptr(ne), _ptr(phi)
         s.ne_prev, s.phi_prev = _ptr(ne_prev), _ptr(phi_prev)
+        s.ne_out, s.phi_out = _ptr(ne_out), _ptr(phi_out)
         return s
 
     def step(self, prob: DeviceProblem, ne, phi, ne_prev=None, phi_prev=None, stream=None,
-             stats: Optional[Stats] = None, raw: bool = False):
-        """One backward-Euler step of all columns, in place on ne/phi."""
+             stats: Optional[Stats] = None, raw: bool = False, ne_out=None, phi_out=None):
+        """One backward-Euler step of all columns: in place on ne/phi, or into
+        ne_out/phi_out (which may be ne_prev/phi_prev) when given."""
         p = prob.cstruct()
-        s = self._state(ne, phi, ne_prev, phi_prev)
+        s = self._state(ne, phi, ne_prev, phi_prev, ne_out, phi_out)
         st = stats if stats is not None else Stats(prob.ncols)
         rc = lib().jfnk_step(self.h, C.byref(p), C.byref(s), C.byref(st.cstruct()), _stream_ptr(stream))
         if raw:
@@ -352,16 +354,16 @@ class Solver:
         return rc, st
 
     def step_async(self, prob: DeviceProblem, ne, phi, ne_prev=None, phi_prev=None, stream=None,
-                   prev_stats: Optional[Stats] = None):
+                   prev_stats: Optional[Stats] = None, ne_out=None, phi_out=None):
         """Queue one step and return; if a step was in flight, wait for it and
         return (its return code, its stats), else (None, None).  The tensors of
         the queued step must stay alive until it is reported."""
         p = prob.cstruct()
-        s = self._state(ne, phi, ne_prev, phi_prev)
+        s = self._state(ne, phi, ne_prev, phi_prev, ne_out, phi_out)
         st = prev_stats if prev_stats is not None else Stats(prob.ncols)
         prc = C.c_int32(-1)
-        # the argument structs must outlive the queued step: keep them
-        self._inflight = (p, s, ne, phi, ne_prev, phi_prev)
+        # the tensors of the queued step stay referenced until it is reported
+        self._inflight = (p, s, ne, phi, ne_prev, phi_prev, ne_out, phi_out)
         rc = lib().jfnk_step_async(self.h, C.byref(p), C.byref(s), C.byref(st.cstruct()), C.byref(prc),
                                    _stream_ptr(stream))
         self._check(rc)

@@ -559,6 +559,53 @@ def test_problem_struct_follows_reassigned_fields(J):
     solver.close()
 
 
+@pytest.mark.parametrize("asynchronous", [False, True])
+def test_out_of_place_steps_alternate_two_states(J, asynchronous):
+    """With ne_out/phi_out a step leaves X^n in place and writes X^{n+1}
+    elsewhere; written over X^{n-1}, it lets a caller alternate two states
+    without copies.  The states equal those of in-place steps bit for bit."""
+    packed = W.pack(W.config2(seed=2700, ncols=16, nmin=300, nmax=2000))
+    n = packed.ncols
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    ne0, phi0 = ne.clone(), phi.clone()
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP32))
+    pn = pp = None
+    ref = []
+    for k in range(6):
+        cur = (ne.clone(), phi.clone())
+        rc, _ = solver.step(prob, ne, phi, pn, pp)
+        assert rc == J.JFNK_OK
+        ref.append((ne.cpu().numpy(), phi.cpu().numpy()))
+        pn, pp = cur
+    solver.close()
+    a = (ne0.clone(), phi0.clone())
+    b = (torch.empty_like(ne0), torch.empty_like(phi0))
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP32))
+    got = []
+    for k in range(6):
+        prev = b if k else (None, None)
+        if asynchronous:
+            solver.step_async(prob, a[0], a[1], prev[0], prev[1], ne_out=b[0], phi_out=b[1],
+                              prev_stats=J.Stats(n))
+        else:
+            rc, _ = solver.step(prob, a[0], a[1], prev[0], prev[1], ne_out=b[0], phi_out=b[1])
+            assert rc == J.JFNK_OK
+        got.append((b[0].clone(), b[1].clone()))      # in stream order after the step
+        a, b = b, a
+    if asynchronous:
+        rc, _ = solver.step_finish(stats=J.Stats(n))
+        assert rc == J.JFNK_OK
+    torch.cuda.synchronize()
+    solver.close()
+    for (rn, rp), (gn, gp) in zip(ref, got):
+        assert np.array_equal(rn, gn.cpu().numpy()) and np.array_equal(rp, gp.cpu().numpy())
+    # both outputs or neither
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP32))
+    rc, _ = solver.step(prob, a[0], a[1], ne_out=b[0], raw=True)
+    assert rc == J.JFNK_EINVAL
+    solver.close()
+
+
 def test_degenerate_columns(J):
     """Degenerate inputs: a column with no charge, source or loss starts at
     its exact root (n = 0, phi linear between the electrodes) and must stay
