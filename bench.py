@@ -89,10 +89,9 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
         phi.copy_(phi0)
         tuned = solver.autotune(prob, ne, phi, steps=EPISODE, stream=stream)
     fb = 4.0 if prec == J.PREC_FP32 else 8.0
-    # the caller's time loop: X^n is saved before the in-place step and becomes
-    # X^{n-1} of the next step by swapping buffers (one copy per step)
-    state = {"e": 0, "prev": (torch.empty_like(ne), torch.empty_like(phi)),
-             "save": (torch.empty_like(ne), torch.empty_like(phi))}
+    # the caller's time loop alternates two states: a step reads X^n from one
+    # and X^{n-1} from the other, and writes X^{n+1} over X^{n-1} (no copies)
+    state = {"e": 0, "cur": (ne, phi), "other": (torch.empty_like(ne), torch.empty_like(phi))}
     stats = J.Stats(len(ns))   # filled by every step; records copy what they keep
 
     def report(rc, st, record):
@@ -112,18 +111,17 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
 
     def one_step(record):
         e = state["e"]
+        cur_n, cur_p = state["cur"]
+        oth_n, oth_p = state["other"]
         if e == 0:
-            ne.copy_(ne0)
-            phi.copy_(phi0)
+            cur_n.copy_(ne0)
+            cur_p.copy_(phi0)
         has_prev = e > 0
-        prev_n, prev_p = state["prev"]
-        save_n, save_p = state["save"]
-        save_n.copy_(ne)
-        save_p.copy_(phi)
         state["queued"].append(has_prev)
-        rc, st = solver.step_async(prob, ne, phi, prev_n if has_prev else None,
-                                   prev_p if has_prev else None, stream=stream, prev_stats=stats)
-        state["prev"], state["save"] = state["save"], state["prev"]
+        rc, st = solver.step_async(prob, cur_n, cur_p, oth_n if has_prev else None,
+                                   oth_p if has_prev else None, stream=stream, prev_stats=stats,
+                                   ne_out=oth_n, phi_out=oth_p)
+        state["cur"], state["other"] = state["other"], state["cur"]
         state["e"] = (e + 1) % EPISODE
         if rc is not None:
             report(rc, st, record)
