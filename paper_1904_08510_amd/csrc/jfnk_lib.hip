@@ -31,17 +31,60 @@ struct SolveArgs {
     UserArrays U;
     const int* order;   // blockIdx -> column
     const int* mcol;    // gather / write-back workgroup -> column
+    int ncols;
 };
 
 template <int T, class FT>
 __global__ __launch_bounds__(T) void k_solve(SolveArgs a) {
     extern __shared__ double lds[];
     const int ci = a.order[blockIdx.x];
+    if (ci < 0 || ci >= a.ncols) return;   // the order is a permutation; never taken
     DevExec<T, FT> ex;
     ex.col.init(a.W.cols[ci], a.W, a.prm, (ldbl*)lds);
     ex.U = a.U;
     ColOutcome o;
     jfnk_solve(ex, a.prm, o);
+}
+
+// Workgroup order of the next solve launch, by expected work, largest first
+// (longest-processing-time): a column's work is taken as its cells times the
+// bytes per cell its step just moved (from the phase counts).  A counting sort
+// on the key's binary exponent and top three mantissa bits (eighths of an
+// octave, keys 1..2^64); the order within a bucket is free.  One workgroup.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBuckets = 8 * 64;
+
+__device__ __forceinline__ int order_bucket(const ColState& s, int n) {
+    const int32_t* w = s.work;
+    const double cost = 104.0 + 120.0 * w[kWorkFactor] + 112.0 * w[kWorkApply] + 104.0 * w[kWorkResidual] +
+                        120.0 * w[kWorkJv] + 32.0 * w[kWorkCgs] + 16.0 * w[kWorkLincomb] + 16.0 * w[kWorkVecReads];
+    const double key = fmax(1.0, (double)n * cost);
+    const uint64_t u = (uint64_t)__double_as_longlong(key);
+    const int b = min(kOrderBuckets - 1, (int)((u >> 49) - (uint64_t)1023 * 8));
+    return kOrderBuckets - 1 - b;
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_order(const ColState* cst, const ColDesc* cols, int ncols,
+                                                         int* order) {
+    __shared__ int start[kOrderBuckets];
+    const int t = threadIdx.x;
+    for (int b = t; b < kOrderBuckets; b += kOrderThreads) start[b] = 0;
+    __syncthreads();
+    for (int c = t; c < ncols; c += kOrderThreads) atomicAdd(&start[order_bucket(cst[c], cols[c].n)], 1);
+    __syncthreads();
+    if (t == 0) {
+        int acc = 0;
+        for (int b = 0; b < kOrderBuckets; ++b) {
+            const int n = start[b];
+            start[b] = acc;
+            acc += n;
+        }
+    }
+    __syncthreads();
+    for (int c = t; c < ncols; c += kOrderThreads) {
+        const int pos = atomicAdd(&start[order_bucket(cst[c], cols[c].n)], 1);
+        if (pos < ncols) order[pos] = c;
+    }
 }
 
 // The data-movement ends of a batched step as launches of their own: they
@@ -286,7 +329,6 @@ struct jfnk_ctx {
     bool fac_reuse_ok = false;   // the workspace holds factors of the current layout from the last step
     bool hist_valid = false;     // the per-column records below describe the current layout
     std::vector<int32_t> last_newton, last_status;
-    std::vector<double> last_cost;   // bytes per cell the column's last step moved (estimate)
     // schedule autotuner: workgroup size measured best for a column layout
     int force_T = 0;                      // set while the tuner tries a candidate
     int tuned_T = 0;
@@ -657,43 +699,13 @@ int run_plain(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t s
 
 template <int T, class FT>
 int run_batched(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t st) {
-    // Workgroup order of the solve launch: by expected work, largest first
-    // (longest-processing-time), the work of a column taken as its cells
-    // times the bytes per cell its previous step moved; by cells alone
-    // without that record.  The dispatcher hands workgroups to CUs in this
-    // order, so a column that is still iterating starts early instead of
-    // extending the tail of the launch.
-    if (ctx->hist_valid && (int)ctx->last_cost.size() == p->ncols) {
-        // LPT needs no exact sort: a counting sort on the key's binary
-        // exponent and top three mantissa bits (eighths of an octave; keys
-        // from 1 to 2^64), largest first, column order within a bucket
-        constexpr int kBuckets = 8 * 64;
-        const int nc = p->ncols;
-        std::vector<int> bucket(nc), ord(nc);
-        int cnt[kBuckets + 1] = {0};
-        for (int c = 0; c < nc; ++c) {
-            const double key = std::max(1.0, (double)ctx->h_cols[c].n * ctx->last_cost[c]);
-            uint64_t u;
-            std::memcpy(&u, &key, sizeof(u));
-            const int b = std::min(kBuckets - 1, (int)((u >> 49) - (uint64_t)1023 * 8));
-            bucket[c] = kBuckets - 1 - b;
-            ++cnt[bucket[c] + 1];
-        }
-        for (int b = 0; b < kBuckets; ++b) cnt[b + 1] += cnt[b];
-        for (int c = 0; c < nc; ++c) ord[cnt[bucket[c]]++] = c;
-        bool same = true;
-        for (int c = 0; c < p->ncols && same; ++c) same = ctx->h_order[c] == ord[c];
-        if (!same) {
-            for (int c = 0; c < p->ncols; ++c) ctx->h_order[c] = ord[c];
-            HIP_OK(hipMemcpyAsync(ctx->d_order, ctx->h_order, sizeof(int) * p->ncols, hipMemcpyHostToDevice, st));
-        }
-    }
     SolveArgs a;
     a.W = ctx->W;
     a.prm = make_params(ctx, p, x);
     a.U = make_user(ctx, p, x);
     a.order = ctx->d_order;
     a.mcol = ctx->d_mcol;
+    a.ncols = p->ncols;
     HIP_OK(hipEventRecord(ctx->ev0, st));
     hipLaunchKernelGGL((k_gather<T>), dim3(ctx->nmove), dim3(kMoveThreads), 0, st, a);
     HIP_OK(hipGetLastError());
@@ -704,6 +716,10 @@ int run_batched(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t
     hipLaunchKernelGGL((k_scatter<T>), dim3(ctx->nmove), dim3(kMoveThreads), 0, st, a);
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(ctx->ev1, st));
+    // the next step's workgroup order from this step's work
+    hipLaunchKernelGGL(k_order, dim3(1), dim3(kOrderThreads), 0, st, (const ColState*)ctx->W.cst,
+                       (const ColDesc*)ctx->W.cols, p->ncols, ctx->d_order);
+    HIP_OK(hipGetLastError());
     ctx->timed = true;
     ctx->timed3 = true;
     ctx->last_launches = 3;
@@ -977,15 +993,9 @@ int step_process(jfnk_ctx* ctx, int ncols, jfnk_stats* stt) {
     ctx->last_status.resize(ncols);
     const bool learned = ctx->cfg.guess == JFNK_GUESS_LEARNED && (int)ctx->evaluated.size() == ncols &&
                          (int)ctx->reject_streak.size() == ncols;
-    ctx->last_cost.resize(ncols);
     for (int c = 0; c < ncols; ++c) {
         ctx->last_newton[c] = ctx->h_cst[c].newton;
         ctx->last_status[c] = ctx->h_cst[c].status;
-        // set-up, factorisations, applies, trials, J.v, CGS passes, directions, extra vectors
-        const int32_t* w = ctx->h_cst[c].work;
-        ctx->last_cost[c] = 104.0 + 120.0 * w[kWorkFactor] + 112.0 * w[kWorkApply] + 104.0 * w[kWorkResidual] +
-                            120.0 * w[kWorkJv] + 32.0 * w[kWorkCgs] + 16.0 * w[kWorkLincomb] +
-                            16.0 * w[kWorkVecReads];
         if (learned && ctx->evaluated[c]) {
             if (ctx->h_cst[c].guess == JFNK_GUESS_LEARNED) {
                 ctx->reject_streak[c] = 0;
