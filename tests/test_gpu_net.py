@@ -337,6 +337,46 @@ def test_async_steps_match_synchronous_steps(J, R, guess):
             assert np.linalg.norm(x - y) <= 1e-9 * np.linalg.norm(x)
 
 
+def test_calls_during_an_async_step_finish_it_first(J, R):
+    """A new model, autotuning or a synchronous step while an asynchronous
+    step is in flight finish that step first; stepping continues normally and
+    reaches the states of synchronous steps."""
+    packed = W.pack(W.config2(seed=2502, ncols=8, nmin=300, nmax=900))
+    n = packed.ncols
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    ne0, phi0 = ne.clone(), phi.clone()
+    ref = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64))
+    rn, rp = ne0.clone(), phi0.clone()
+    for _ in range(3):
+        rc, _ = ref.step(prob, rn, rp)
+        assert rc == J.JFNK_OK
+    ref.close()
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64, guess=J.GUESS_LEARNED))
+    net = J.Net(J.net_default_config(out_scale_ne=S0, out_scale_phi=S1))
+    net.set_params(params32(R, 9))
+    solver.set_model(net)
+    a = (ne0.clone(), phi0.clone())
+    b = (torch.empty_like(ne0), torch.empty_like(phi0))
+    solver.step_async(prob, a[0], a[1], ne_out=b[0], phi_out=b[1], prev_stats=J.Stats(n))
+    solver.set_model(net)                     # finishes the step in flight
+    with pytest.raises(J.JfnkError):
+        solver.step_finish(stats=J.Stats(n))  # nothing left in flight
+    a, b = b, a
+    rc, _ = solver.step(prob, a[0], a[1], ne_out=b[0], phi_out=b[1])
+    assert rc == J.JFNK_OK
+    a, b = b, a
+    solver.step_async(prob, a[0], a[1], ne_out=b[0], phi_out=b[1], prev_stats=J.Stats(n))
+    rc, _ = solver.step_finish(stats=J.Stats(n))
+    assert rc == J.JFNK_OK
+    torch.cuda.synchronize()
+    # three steps from the start state without X^{n-1}: the roots of the reference
+    for x, y in ((rn, b[0]), (rp, b[1])):
+        x, y = x.cpu().numpy(), y.cpu().numpy()
+        assert np.linalg.norm(x - y) <= 1e-9 * np.linalg.norm(x)
+    solver.close()
+    net.close()
+
+
 def test_async_step_needs_the_batched_schedule(J):
     packed = W.pack(W.config2(seed=2501, ncols=2, nmin=100, nmax=200))
     prob, ne, phi, _, _ = J.device_problem(packed)
