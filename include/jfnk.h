@@ -208,7 +208,8 @@ int jfnk_step(jfnk_ctx *ctx, const jfnk_problem *p, jfnk_state *x, jfnk_stats *s
    choices for step k+1 (workgroup order, which columns evaluate the learned
    guess) then come from step k-1 instead of step k.  Inputs of a queued step
    (the arrays behind p and x) must stay valid and unchanged until it is
-   reported; x->ne/phi are written in stream order.  jfnk_step_finish waits for
+   reported; x->ne/phi are written in stream order.  A step queued on another
+   stream than the one in flight first waits for it.  jfnk_step_finish waits for
    the step in flight and reports it.  Any other call on the context (a
    synchronous step, autotuning, a new model, the test exports) first finishes
    the step in flight and drops its statistics.  Allocates nothing.

@@ -354,6 +354,7 @@ struct jfnk_ctx {
     bool learned_ran = false;      // the step's set-up evaluated learned candidates
     bool pending = false;          // an asynchronous step is in flight (its resources in alt)
     int pending_ncols = 0;
+    hipStream_t pending_stream = nullptr;
 };
 
 namespace {
@@ -1182,8 +1183,9 @@ int jfnk_step_async(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, jfnk_st
         return fail(ctx, JFNK_EMODEL, "learned guess requested but no model is loaded");
     if (ctx->cfg.schedule != JFNK_SCHED_BATCHED)
         return fail(ctx, JFNK_EINVAL, "asynchronous steps need the batched schedule");
-    // a new layout rewrites the staged schedule: finish the step in flight first
-    if (ctx->pending && !schedule_matches(ctx, p)) {
+    // a new layout rewrites the staged schedule, and a step on another stream
+    // would not be ordered after it: finish the step in flight first
+    if (ctx->pending && (!schedule_matches(ctx, p) || ctx->pending_stream != (hipStream_t)stream)) {
         rc = drain(ctx);
         if (rc) return rc;
     }
@@ -1197,12 +1199,14 @@ int jfnk_step_async(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, jfnk_st
         // finish the previous step while this one runs
         const int n = ctx->pending_ncols;
         ctx->pending_ncols = p->ncols;
+        ctx->pending_stream = (hipStream_t)stream;
         const int prc = step_process(ctx, n, prev_stats);
         if (prc != JFNK_OK && prc != JFNK_NOT_CONVERGED) return prc;
         if (prev_rc) *prev_rc = prc;
     } else {
         ctx->pending = true;
         ctx->pending_ncols = p->ncols;
+        ctx->pending_stream = (hipStream_t)stream;
     }
     return JFNK_OK;
 }

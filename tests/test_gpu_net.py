@@ -377,6 +377,37 @@ def test_calls_during_an_async_step_finish_it_first(J, R):
     net.close()
 
 
+def test_async_steps_on_two_streams(J):
+    """Consecutive asynchronous steps queued on different streams: the second
+    waits for the first, and the states equal those of synchronous steps."""
+    packed = W.pack(W.config2(seed=2503, ncols=8, nmin=300, nmax=900))
+    n = packed.ncols
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    ne0, phi0 = ne.clone(), phi.clone()
+    ref = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64))
+    rn, rp = ne0.clone(), phi0.clone()
+    for _ in range(4):
+        rc, _ = ref.step(prob, rn, rp)
+        assert rc == J.JFNK_OK
+    ref.close()
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64))
+    a = (ne0.clone(), phi0.clone())
+    b = (torch.empty_like(ne0), torch.empty_like(phi0))
+    torch.cuda.synchronize()
+    for k in range(4):
+        solver.step_async(prob, a[0], a[1], ne_out=b[0], phi_out=b[1], stream=s1 if k % 2 == 0 else s2,
+                          prev_stats=J.Stats(n))
+        a, b = b, a
+    rc, _ = solver.step_finish(stats=J.Stats(n))
+    assert rc == J.JFNK_OK
+    torch.cuda.synchronize()
+    assert np.array_equal(rn.cpu().numpy(), a[0].cpu().numpy())
+    assert np.array_equal(rp.cpu().numpy(), a[1].cpu().numpy())
+    solver.close()
+
+
 def test_async_step_needs_the_batched_schedule(J):
     packed = W.pack(W.config2(seed=2501, ncols=2, nmin=100, nmax=200))
     prob, ne, phi, _, _ = J.device_problem(packed)
