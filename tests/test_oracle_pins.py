@@ -109,6 +109,34 @@ def test_residual_discrete_boltzmann(orc):
     assert np.max(np.abs(fe - expected)) <= 4e-15 * term
 
 
+def test_residual_boltzmann_dirichlet_walls(orc):
+    """The Boltzmann state also carries no flux through Dirichlet walls whose
+    densities continue it to the electrode potentials, n_w = C exp(phi_w / V_T)
+    (the wall faces use the half-cell distance): a nonzero wall density enters
+    the wall flux with the weight that balances drift against diffusion."""
+    rng = np.random.default_rng(5)
+    n = 36
+    phi = np.cumsum(rng.uniform(-0.05, 0.05, n))
+    c0 = 2e14
+    ne = c0 * np.exp(phi / V_T300)
+    phi_l, phi_r = phi[0] - 0.03, phi[-1] + 0.045
+    col = uniform_column(n, phi_l=phi_l, phi_r=phi_r, ne=ne, phi=phi)
+    col.ne_left = c0 * np.exp(phi_l / V_T300)
+    col.ne_right = c0 * np.exp(phi_r / V_T300)
+    gam = orc.face_fluxes(orc.OracleColumn(col), ne, phi)
+    scale = (col.diff[0] / (col.length / n)) * max(ne.max(), col.ne_left, col.ne_right)
+    assert np.max(np.abs(gam)) <= 1e-14 * scale
+    # a wall density off the Boltzmann value drives the wall flux it implies:
+    # (D / (h/2)) B(Pe_w) (n_eq - n_w) with n_eq the balancing density
+    col.ne_left *= 1.5
+    gam2 = orc.face_fluxes(orc.OracleColumn(col), ne, phi)
+    h = col.length / n
+    pe_w = (phi[0] - phi_l) / V_T300
+    expect = (col.diff[0] / (0.5 * h)) * _bern_dec(-pe_w) * (0.5 * c0 * np.exp(phi_l / V_T300))
+    assert gam2[0] == pytest.approx(expect, rel=1e-12)
+    assert np.max(np.abs(gam2[1:])) <= 1e-14 * scale
+
+
 def test_residual_boltzmann_nonuniform_mobility(orc):
     """With uniform T but mobility varying from cell to cell, D/mu = V_T still
     holds on every face only if mu and D are averaged the same way; the
@@ -207,6 +235,102 @@ def test_scalings_closed_form(orc):
         # linear phi: uniform gradient dV/L on every face
         assert s[1] == pytest.approx(5e13 + col.eps_over_e * 2 * 40.0 / length / h, rel=1e-13)
         assert s[2] == 5e13 and s[3] == 40.0
+
+
+def _exp_dec(x):
+    with decimal.localcontext() as ctx:
+        ctx.prec = 60
+        return decimal.Decimal(x).exp()
+
+
+def _sg_rates(v, pe):
+    """Forward and backward rates of a Scharfetter-Gummel face in a uniform
+    field, in 60-digit arithmetic: with drift velocity v = mu E and cell Peclet
+    number Pe = v h_f / D, the exact steady flux between two cells is
+    alpha n_upstream-side - beta n_other-side with alpha = v / (1 - e^-Pe) and
+    beta = v / (e^Pe - 1) (alpha - beta = v: pure drift far from equilibrium;
+    alpha = beta = D/h_f as Pe -> 0: pure diffusion)."""
+    with decimal.localcontext() as ctx:
+        ctx.prec = 60
+        V, P = decimal.Decimal(v), decimal.Decimal(pe)
+        return float(V / (1 - (-P).exp())), float(V / (P.exp() - 1))
+
+
+@pytest.mark.parametrize("volts", [-600.0, -40.0, -3.0, 3.0, 40.0, 600.0])
+def test_scalings_wall_inflow_drift(orc, volts):
+    """Electron-free column with a nonzero Dirichlet density n_w at one wall
+    in a uniform field: the only nonzero term of any electron row is the wall
+    face's inflow term of the first (or last) cell.  Electrons drift up the
+    potential gradient, so with the field pulling them into the column the
+    inflow rate is the drift speed over (1 - e^-Pe) (-> mu E for Pe >> 1), and
+    with the field pushing them out it is mu |E| / (e^|Pe| - 1) (-> 0).  The
+    scaling s_Fn = (dt/h) * (inflow rate) * n_w pins the orientation of the
+    drift part of the term magnitudes (Section 3.2, eq:newton_sc); exchanging
+    B(Pe) and B(-Pe) there reverses the two cases."""
+    n, length, dt, mu, temp, n_w = 48, 0.01, 2e-7, 0.4, 300.0, 7e13
+    h = length / n
+    vt = W.K_BOLTZMANN * temp / W.E_CHARGE
+    e_field = volts / length
+    pe_w = mu * e_field * (0.5 * h) / (mu * vt)        # wall face: distance h/2
+    for side in ("left", "right"):
+        col = uniform_column(n, length=length, dt=dt, mu=mu, temp=temp, ne=np.zeros(n),
+                             phi_l=0.0, phi_r=volts)
+        # wall face flux (+x) = alpha n_left - beta n_right: the left wall's
+        # density enters with alpha (large when the field pulls electrons to
+        # +x, volts > 0), the right wall's with beta (large when volts < 0)
+        fwd, bwd = _sg_rates(mu * e_field, pe_w)
+        if side == "left":
+            col.ne_left = n_w
+            rate = fwd
+        else:
+            col.ne_right = n_w
+            rate = bwd
+        expected = (dt / h) * abs(rate) * n_w
+        s = orc.scalings(orc.OracleColumn(col))
+        assert s[0] == pytest.approx(expected, rel=1e-13), (side, s[0], expected)
+    # the physical limits: drift-dominated inflow is mu E n_w, outflow vanishes
+    if abs(pe_w) > 20:
+        col = uniform_column(n, length=length, dt=dt, mu=mu, temp=temp, ne=np.zeros(n),
+                             phi_l=0.0, phi_r=volts)
+        col.ne_left = n_w
+        s = orc.scalings(orc.OracleColumn(col))
+        if volts > 0:
+            assert s[0] == pytest.approx((dt / h) * mu * e_field * n_w, rel=1e-12)
+        else:
+            assert s[0] < 1e-10 * (dt / h) * mu * abs(e_field) * n_w
+
+
+@pytest.mark.parametrize("volts", [-250.0, -5.0, 5.0, 250.0])
+def test_scalings_interior_pair_drift(orc, volts):
+    """Two adjacent charged cells (densities 2 n0 and n0) in a uniform field,
+    every other cell empty, no sources: the term magnitudes of the four rows
+    around the pair follow from the face rates alpha, beta of the uniform
+    field (60-digit arithmetic), and s_Fn is the largest row sum.  With unequal
+    densities the largest row sum changes when the upwind and downwind
+    weights of the drift part are exchanged."""
+    n, length, dt, mu, temp, n0, i0 = 40, 0.01, 3e-8, 0.4, 300.0, 4e13, 17
+    h = length / n
+    vt = W.K_BOLTZMANN * temp / W.E_CHARGE
+    v = mu * volts / length
+    pe = v * h / (mu * vt)
+    a, b = _sg_rates(v, pe)          # face flux = a n_left - b n_right
+    ne = np.zeros(n)
+    ne[i0], ne[i0 + 1] = 2 * n0, n0
+    col = uniform_column(n, length=length, dt=dt, mu=mu, temp=temp, ne=ne, phi_l=0.0, phi_r=volts)
+    # |terms| of the faces around the pair: (i0-1|i0), (i0|i0+1), (i0+1|i0+2)
+    f_left = abs(b) * 2 * n0
+    f_mid = abs(a) * 2 * n0 + abs(b) * n0
+    f_right = abs(a) * n0
+    rows = [(dt / h) * f_left,                          # row i0-1
+            2 * n0 + (dt / h) * (f_left + f_mid),        # row i0
+            n0 + (dt / h) * (f_mid + f_right),           # row i0+1
+            (dt / h) * f_right]                         # row i0+2
+    s = orc.scalings(orc.OracleColumn(col))
+    assert s[0] == pytest.approx(max(rows), rel=1e-13)
+    # the exchanged weights give a different largest row sum (the pin has teeth)
+    g_mid = abs(b) * 2 * n0 + abs(a) * n0
+    swapped = max(2 * n0 + (dt / h) * (abs(a) * 2 * n0 + g_mid), n0 + (dt / h) * (g_mid + abs(b) * n0))
+    assert abs(swapped - max(rows)) > 1e-6 * max(rows)
 
 
 def test_jacobian_against_central_differences(orc):
