@@ -70,8 +70,24 @@ def solve_bytes_per_cell(has_prev, fb, counts):
     return setup + sum(c * b for c, b in zip(counts, per_phase))
 
 
-def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None, stream=None, chord=None):
-    """Warm-up then timed episodes of the batched solver; per-step records."""
+def pick_parity_sample(rec, ns, episode=EPISODE, nextra=2, seed=99):
+    """Columns whose every step the oracle re-checks: the shortest, the
+    longest, the two that iterated latest in the timed episodes, and nextra
+    more drawn at random."""
+    last = np.zeros(len(ns), int)
+    for k, r in enumerate(rec[:episode]):
+        last[(r["newton"] + r["chords"]) > 0] = k
+    late = [int(c) for c in np.argsort(-last * 100000 - ns)[:2]]
+    rng = np.random.default_rng(seed)
+    extra = [int(c) for c in rng.choice(len(ns), nextra, replace=False)]
+    return sorted(set([int(np.argmin(ns)), int(np.argmax(ns))] + late + extra)), last
+
+
+def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None, stream=None, chord=None,
+                    parity=False, episode=EPISODE):
+    """Warm-up then timed episodes of the batched solver; per-step records.
+    With parity, one more (untimed) episode is run exactly like the timed
+    ones and the states of sampled columns are kept after every step."""
     import torch
     kw = {} if chord is None else dict(chord_tol=chord)
     cfg = J.config_for_dims(len(ns), int(ns.sum()), int(ns.max()), prec_precision=prec, guess=guess,
@@ -87,7 +103,7 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
         # by the columns that still iterate)
         ne.copy_(ne0)
         phi.copy_(phi0)
-        tuned = solver.autotune(prob, ne, phi, steps=EPISODE, stream=stream)
+        tuned = solver.autotune(prob, ne, phi, steps=episode, stream=stream)
     fb = 4.0 if prec == J.PREC_FP32 else 8.0
     # the caller's time loop alternates two states: a step reads X^n from one
     # and X^{n-1} from the other, and writes X^{n+1} over X^{n-1} (no copies)
@@ -122,7 +138,13 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
                                    oth_p if has_prev else None, stream=stream, prev_stats=stats,
                                    ne_out=oth_n, phi_out=oth_p)
         state["cur"], state["other"] = state["other"], state["cur"]
-        state["e"] = (e + 1) % EPISODE
+        state["e"] = (e + 1) % episode
+        if state.get("snap") is not None:
+            # X^{k+1} of the sampled columns, queued on the stream before the
+            # next step can overwrite the buffer it was written to
+            sl = state["snap_slices"]
+            state["snap"].append((torch.cat([oth_n[x] for x in sl]).clone(),
+                                  torch.cat([oth_p[x] for x in sl]).clone()))
         if rc is not None:
             report(rc, st, record)
 
@@ -148,6 +170,24 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gc.enable()
+    par = None
+    if parity:
+        sample, last = pick_parity_sample(rec, ns, episode, nextra=2 if len(ns) > 256 else 0)
+        off = np.concatenate([[0], np.cumsum(ns)])
+        state["snap_slices"] = [slice(int(off[c]), int(off[c + 1])) for c in sample]
+        state["e"] = 0
+        n0 = torch.cat([ne0[x] for x in state["snap_slices"]]).clone()
+        p0 = torch.cat([phi0[x] for x in state["snap_slices"]]).clone()
+        state["snap"] = [(n0, p0)]
+        prec_rec = []
+        for _ in range(episode):
+            one_step(prec_rec)
+        finish(prec_rec)
+        torch.cuda.synchronize()
+        par = dict(columns=sample, cells=[int(ns[c]) for c in sample], last_newton_step=[int(last[c]) for c in sample],
+                   states=[(a.cpu().numpy(), b.cpu().numpy()) for a, b in state["snap"]],
+                   converged=all(int(np.sum(r["status"] != 0)) == 0 for r in prec_rec))
+        state["snap"] = None
     solver.close()
     for r in rec:   # outside the timed region
         r["conv"] = int(np.sum(r["status"] == 0))
@@ -189,6 +229,11 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
         # column-steps whose learned candidate was evaluated (network inference
         # and one residual), from jfnk_stats.phase_counts[:, 7]
         learned_evaluated=int(sum(int(np.sum(r["counts"][:, 7])) for r in rec)),
+        per_step=[dict(newton_mean=float(r["newton"].mean()), newton_max=int(r["newton"].max()),
+                       gmres_mean=float(r["gmres"].mean()), gmres_max=int(r["gmres"].max()),
+                       chords_mean=float(r["chords"].mean()), solve_ms=float(r["kms"][1]))
+                  for r in rec[:episode]],
+        parity=par,
     )
 
 
@@ -241,9 +286,13 @@ def run_gpu(args):
     stream = torch.cuda.current_stream()
     prec = J.PREC_FP32 if args.prec == "fp32" else J.PREC_FP64
     guess = J.GUESS_LEARNED if args.guess == "learned" else J.GUESS_EXTRAP
-    out = measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net, stream)
+    out = measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net, stream,
+                          parity=not args.skip_parity)
     out["cells"] = int(packed.col_offset[-1])
     out["train"] = train_info
+    parities = {}
+    if out["parity"] is not None:
+        parities[f"headline_{args.prec}"] = (cols, out.pop("parity"), EPISODE)
     if not args.skip_ablations:
         abl = {}
         for name, pr, gs, ch in (("batched_fp32_extrap", J.PREC_FP32, J.GUESS_EXTRAP, None),
@@ -251,12 +300,19 @@ def run_gpu(args):
                                  ("batched_fp32_extrap_no_chord", J.PREC_FP32, J.GUESS_EXTRAP, 0.0)):
             if pr == prec and gs == guess and ch is None:
                 continue
-            r = measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, pr, gs, None, stream, ch)
+            want = pr == J.PREC_FP64 and not args.skip_parity and args.prec == "fp32"
+            r = measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, pr, gs, None, stream, ch, parity=want)
             abl[name] = dict(value=r["value"], ms_per_step=r["ms_per_step"], converged=r["converged"],
                              max_res=r["max_res"], kernel_ms_avg=r["kernel_ms_avg"],
                              newton_mean=r["newton_mean"], chord_mean=r["chord_mean"],
                              threads=None if r["autotune"] is None else r["autotune"]["chosen"])
+            if r["parity"] is not None:
+                parities[name] = (cols, r["parity"], EPISODE)
         out["ablations"] = abl
+    del prob, ne, phi, ne0, phi0
+    if not args.skip_stiff:
+        out["stiff"] = run_stiff(J, args, net, stream, parities)
+    out["parities"] = parities
     if net is not None:
         net.close()
 
@@ -286,6 +342,77 @@ def run_gpu(args):
     return out
 
 
+STIFF_EPISODE = 5
+
+
+def run_stiff(J, args, net, stream, parities):
+    """The stiff batch (256 columns x 65536 cells, 5-10 kV, dt = 1e-4 s):
+    batched with FP32 factors and the learned guess (extrapolated fallback)
+    against the plain schedule with FP64 factors on a sample of its columns.
+    Newton and GMRES counts per step; the oracle re-checks sampled columns."""
+    import torch
+    from paper_1904_08510_amd import workloads as W
+    cols = W.config4()
+    packed = W.pack(cols)
+    prob, ne, phi, _, _ = J.device_problem(packed, "cuda:0")
+    ne0, phi0 = ne.clone(), phi.clone()
+    ns = np.diff(packed.col_offset)
+    sargs = argparse.Namespace(**vars(args))
+    sargs.warmup = STIFF_EPISODE
+    sargs.steps = STIFF_EPISODE * args.stiff_episodes
+    guess = J.GUESS_LEARNED if net is not None else J.GUESS_EXTRAP
+    r = measure_batched(J, prob, ne, phi, ne0, phi0, ns, sargs, J.PREC_FP32, guess, net, stream,
+                        parity=not args.skip_parity, episode=STIFF_EPISODE)
+    if r["parity"] is not None:
+        par = r["parity"]
+        keep = par["columns"][: args.stiff_parity_cols]
+        ix = [par["columns"].index(c) for c in keep]
+        offs = np.concatenate([[0], np.cumsum(par["cells"])])
+        sel = np.concatenate([np.arange(offs[i], offs[i + 1]) for i in ix])
+        par = dict(columns=keep, cells=[par["cells"][i] for i in ix],
+                   last_newton_step=[par["last_newton_step"][i] for i in ix],
+                   states=[(a[sel], b[sel]) for a, b in par["states"]], converged=par["converged"])
+        parities["stiff_fp32"] = (cols, par, STIFF_EPISODE)
+    out = dict(value=r["value"], ms_per_step=r["ms_per_step"], converged=r["converged"], total=r["total"],
+               max_res=r["max_res"], kernel_ms_avg=r["kernel_ms_avg"], achieved_gbs=r["achieved_gbs"],
+               newton_mean=r["newton_mean"], gmres_per_newton=r["gmres_per_newton"],
+               per_step=r["per_step"], guess_used=r["guess_used"], learned_evaluated=r["learned_evaluated"],
+               threads=None if r["autotune"] is None else r["autotune"]["chosen"],
+               workload=f"256 columns x 65536 cells, V~U[5,10] kV, ion peak 1e17, dt=1e-4 s, "
+                        f"{STIFF_EPISODE}-step episodes (seed 4321); batched, FP32 factors, "
+                        + ("learned guess with extrapolated fallback" if net is not None else "extrapolated guess"))
+    del prob, ne, phi, ne0, phi0
+    torch.cuda.empty_cache()
+    # plain schedule, FP64 factors, on a sample of the columns
+    idx = list(range(0, len(cols), len(cols) // args.stiff_plain_cols))[: args.stiff_plain_cols]
+    sub = W.pack([cols[i] for i in idx])
+    sprob, sne, sphi, _, _ = J.device_problem(sub, "cuda:0")
+    pn, pp = torch.empty_like(sne), torch.empty_like(sphi)
+    psolver = J.Solver(J.config_for(sub, prec_precision=J.PREC_FP64, guess=J.GUESS_EXTRAP,
+                                    schedule=J.SCHED_PLAIN))
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    conv = 0
+    newton, gmres = [], []
+    for e in range(STIFF_EPISODE):
+        cn, cp = sne.clone(), sphi.clone()
+        rc, st = psolver.step(sprob, sne, sphi, pn if e else None, pp if e else None, stream=stream)
+        conv += int(np.sum(st.status == 0))
+        newton.append(float(st.newton_iters.mean()))
+        gmres.append(float(st.gmres_iters.mean()))
+        pn.copy_(cn)
+        pp.copy_(cp)
+    torch.cuda.synchronize()
+    tplain = time.perf_counter() - tp
+    psolver.close()
+    out["plain"] = dict(value=conv / tplain, columns=len(idx), steps=STIFF_EPISODE,
+                        newton_mean_per_step=newton, gmres_mean_per_step=gmres,
+                        sample=f"{len(idx)} columns (every {len(cols) // len(idx)}th) x episode steps "
+                               f"0..{STIFF_EPISODE - 1}, FP64 factors, extrapolated guess")
+    out["speedup_vs_plain"] = out["value"] / out["plain"]["value"]
+    return out
+
+
 def _cpu_column_episode(args):
     """Oracle timed mode over the first `steps` steps of a column's episode."""
     ci, steps = args
@@ -308,9 +435,24 @@ def _cpu_column_episode(args):
     return time.process_time() - t0
 
 
+def cpu_model():
+    """The host CPU's model name (lscpu's "Model name"), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def run_cpu(args):
     import multiprocessing as mp
-    ncores = min(len(os.sched_getaffinity(0)), 16)
+    # one process per core, up to the CPU share a one-GPU job has on the
+    # measuring machine (16 cores), whatever more the affinity mask shows
+    affinity = len(os.sched_getaffinity(0))
+    ncores = min(affinity, args.cpu_procs)
     idx = list(range(0, 1024, 1024 // args.cpu_cols))[: args.cpu_cols]
     tasks = [(i, args.cpu_steps) for i in idx]
     from oracle import oracle as O
@@ -324,7 +466,43 @@ def run_cpu(args):
                 sample=f"{len(tasks)} columns (every {1024 // len(tasks)}th of the batch) x episode steps "
                        f"0..{args.cpu_steps - 1}, timed mode (1e-10), one process per core; "
                        f"{sum(cpu_times):.1f} CPU-s",
-                single_core_value=n / sum(cpu_times))
+                single_core_value=n / sum(cpu_times),
+                host=dict(cpu_model=cpu_model(), affinity_cores=affinity, os_cpu_count=os.cpu_count(),
+                          processes=ncores),
+                # the oracle's timed mode stops on the scaled residual alone
+                # (||S_F^-1 F||_inf <= 1e-10); the GPU legs stop when that holds
+                # and their error estimate ||S_X^-1 P^-1 S_F^-1 F||_inf <= 1e-10
+                stop="oracle: residual only; GPU: residual and error estimate")
+
+
+def oracle_parity(cols, par, episode=EPISODE):
+    """Relative L2 errors of sampled GPU results against the oracle's
+    reference root of the same step from the same X^n (the GPU's), for every
+    step of a replayed episode.  Returns the worst per sampled column."""
+    from oracle import oracle as O
+    t0 = time.perf_counter()
+    states = par["states"]
+    out = []
+    for j, (c, n) in enumerate(zip(par["columns"], par["cells"])):
+        o = int(sum(par["cells"][:j]))
+        en_max = ep_max = 0.0
+        for k in range(episode):
+            xn = (states[k][0][o:o + n], states[k][1][o:o + n])
+            got = (states[k + 1][0][o:o + n], states[k + 1][1][o:o + n])
+            oc = O.OracleColumn(cols[c], xn[0], xn[1])
+            g = xn
+            if k > 0:
+                xp = (states[k - 1][0][o:o + n], states[k - 1][1][o:o + n])
+                e = (2 * xn[0] - xp[0], 2 * xn[1] - xp[1])
+                if O.scaled_residual_inf(oc, *e) <= O.scaled_residual_inf(oc, *g):
+                    g = e
+            r = O.newton(oc, g[0].copy(), g[1].copy(), reference=True)
+            en_max = max(en_max, float(np.linalg.norm(got[0] - r.ne) / np.linalg.norm(r.ne)))
+            ep_max = max(ep_max, float(np.linalg.norm(got[1] - r.phi) / max(np.linalg.norm(r.phi), 1e-300)))
+        out.append(dict(column=int(c), cells=int(n), last_newton_step=par["last_newton_step"][j],
+                        rel_l2_ne=en_max, rel_l2_phi=ep_max))
+    return dict(steps=episode, columns=out, worst=max(max(x["rel_l2_ne"], x["rel_l2_phi"]) for x in out),
+                oracle_s=time.perf_counter() - t0)
 
 
 def measured_traffic():
@@ -361,6 +539,13 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=EPISODE)
     ap.add_argument("--cpu-cols", type=int, default=1024)
     ap.add_argument("--cpu-steps", type=int, default=EPISODE)
+    ap.add_argument("--cpu-procs", type=int, default=16,
+                    help="largest CPU-leg process pool (the CPU share of a one-GPU job)")
+    ap.add_argument("--skip-parity", action="store_true")
+    ap.add_argument("--skip-stiff", action="store_true")
+    ap.add_argument("--stiff-episodes", type=int, default=2)
+    ap.add_argument("--stiff-plain-cols", type=int, default=4)
+    ap.add_argument("--stiff-parity-cols", type=int, default=2)
     ap.add_argument("--calib-copy", action="store_true",
                     help="one 256 MiB device copy first (HBM counter calibration)")
     args = ap.parse_args()
@@ -372,6 +557,15 @@ def main():
     cpu = None if args.skip_cpu else run_cpu(args)
     g = run_gpu(args)
     traffic = measured_traffic()
+    # the oracle's roots of sampled steps of the timed configurations (CPU,
+    # after the GPU legs, on the states those legs produced)
+    if cpu is not None and g["parities"]:
+        cpu["parity"] = {name: oracle_parity(cols, par, ep) for name, (cols, par, ep) in g["parities"].items()}
+    # the headline carries the learned guess only if the network was evaluated
+    learned_label = args.guess == "learned" and g["learned_evaluated"] > 0
+    if args.guess == "learned" and not learned_label:
+        print("bench.py: the learned candidate was never evaluated in the timed steps; the line is "
+              "labelled as the extrapolated guess", file=sys.stderr)
     line = {
         "metric": METRIC,
         "value": g["value"],
@@ -389,13 +583,13 @@ def main():
             "workload": f"{args.ncols} flame columns x U{{512..8192}} cells (seed 2026), V~U[-1000,1000], "
                         f"ion peak logU[1e15,1e17], dt=1e-5 s, 20-step episodes; batched, "
                         f"{args.prec.upper()} preconditioner factors, "
-                        + ("learned guess (BF16 conv net) with extrapolated fallback" if args.guess == "learned"
+                        + ("learned guess (BF16 conv net) with extrapolated fallback" if learned_label
                            else "extrapolated guess"),
             "columns": args.ncols,
             "cells": g["cells"],
             "episode_steps": EPISODE,
             "prec": args.prec,
-            "guess": args.guess,
+            "guess": "learned" if learned_label else "extrap",
         },
         "roofline": {
             "bound": "hbm",
@@ -415,11 +609,13 @@ def main():
         "learned": None if g.get("train") is None else dict(g["train"], guess_used=g["guess_used"],
                                                                evaluated=g["learned_evaluated"]),
         "speedup_vs_plain": (g["value"] / g["plain"]["value"]) if g.get("plain") else None,
+        "stiff": g.get("stiff"),
         "solver": {
             "converged": g["converged"], "column_steps": g["total"], "max_res": g["max_res"],
             "newton_mean": g["newton_mean"], "newton_max": g["newton_max"],
             "gmres_per_newton": g["gmres_per_newton"], "guess_used": g["guess_used"],
             "chord_steps_mean": g["chord_mean"], "autotune": g["autotune"],
+            "per_step": g["per_step"],
         },
     }
     print(json.dumps(line), flush=True)

@@ -29,7 +29,12 @@
  * JFNK_EHIP reports a HIP runtime failure; the context must then be
  * destroyed.  A column that does not converge is not an error: the call
  * returns JFNK_NOT_CONVERGED and the column's status says why; its arrays
- * hold the last accepted iterate.  jfnk_last_error gives a message.
+ * hold the last accepted iterate.  Per-cell inputs live on the device and are
+ * checked there: a column with a cell outside the problem's domain (mu < 0,
+ * D <= 0, k_loss < 0, or a non-finite mu, D, source, k_loss, ion charge,
+ * face velocity, n^k or phi^k) is not iterated, gets status
+ * JFNK_COL_BAD_INPUT and keeps X^k; the call then returns
+ * JFNK_NOT_CONVERGED.  jfnk_last_error gives a message.
  *
  * Threading: a context is used by one host thread at a time.  Calls on one
  * context are serialised on the stream they are given.
@@ -84,10 +89,10 @@ enum { JFNK_SCHED_PLAIN = 0, JFNK_SCHED_BATCHED = 1 };
 /* per-column status */
 enum {
     JFNK_COL_CONVERGED = 0,
-    JFNK_COL_MAX_NEWTON = 1,
-    JFNK_COL_NONFINITE = 2,
-    JFNK_COL_LINESEARCH = 3,
-    JFNK_COL_BAD_INPUT = 4
+    JFNK_COL_MAX_NEWTON = 1,   /* max_newton iterations without convergence */
+    JFNK_COL_NONFINITE = 2,    /* an iterate's residual is not finite */
+    JFNK_COL_LINESEARCH = 3,   /* GMRES produced no direction */
+    JFNK_COL_BAD_INPUT = 4     /* a per-cell input outside the domain (see above) */
 };
 
 typedef struct {
@@ -209,7 +214,9 @@ int jfnk_step(jfnk_ctx *ctx, const jfnk_problem *p, jfnk_state *x, jfnk_stats *s
    guess) then come from step k-1 instead of step k.  Inputs of a queued step
    (the arrays behind p and x) must stay valid and unchanged until it is
    reported; x->ne/phi are written in stream order.  A step queued on another
-   stream than the one in flight first waits for it.  jfnk_step_finish waits for
+   stream than the one in flight, or with another column layout, first waits
+   for the step in flight and reports it through prev_stats and *prev_rc as
+   above (the new step is then the only one in flight).  jfnk_step_finish waits for
    the step in flight and reports it.  Any other call on the context (a
    synchronous step, autotuning, a new model, the test exports) first finishes
    the step in flight and drops its statistics.  Allocates nothing.
@@ -231,7 +238,8 @@ const char *jfnk_last_error(const jfnk_ctx *ctx);
    steps from the state x (x itself is not modified; the steps run on device
    copies, X^{n-1} taken from x when given) once for every workgroup size
    per column in {64, 128, 256, 512} that suits the longest column (at most
-   64 cells per thread, not more threads than half its cells), measures the
+   64 cells per thread, not more threads than half its cells; 512 is tried
+   for any column longer than 256 cells), measures the
    solve time of each with HIP events and keeps the fastest for this column
    layout: later steps with the same col_offset use it.  A learned guess is
    replaced by EXTRAP while tuning.  chosen (HOST, may be NULL) receives the
@@ -338,7 +346,9 @@ int jfnk_net_train_step(jfnk_net *net, const jfnk_problem *p, const jfnk_state *
    detaches).  The context does not own the network, which must outlive its
    use.  The network is evaluated before the solve for the columns whose
    previous step on this context needed at least one Newton iteration (all
-   columns on the first step and whenever the column layout changes); after
+   columns on the first step, whenever the column layout changes, and on a
+   step without X^{n-1}, which starts a new history: the back-off records
+   below are then cleared as well); after
    r consecutive evaluations whose candidate lost to the fallback, a column
    skips the network at its next 4^min(r,5) - 1 chances (steps at which it
    would otherwise be evaluated); any change of the network's weights

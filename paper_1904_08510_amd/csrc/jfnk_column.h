@@ -210,6 +210,7 @@ struct Column {
     double rR, gR, wR;               // right-wall face coefficients
     double sfn, sfp, sxn, sxp, isfn, isfp;
     bool fac_reuse = false;          // setup found the previous step's factors usable
+    bool bad_input = false;          // setup found an input outside the problem's domain
 
     __device__ void init(const ColDesc& d, const Work& w, const SolverParams& p, ldbl* l) {
         cd = d; W = w; prm = p; lds = l;
@@ -500,15 +501,19 @@ struct Column {
     // (the loads of UC tiles go first).  Tiles run through the row groups of
     // 8 owners first, so the UC * nw tiles a workgroup has in flight cover
     // whole chunks of adjacent owners: one contiguous range of the caller's
-    // arrays, and whole (or half) cache lines of the interleaved rows.  Returns whether a face coefficient of
-    // the cells this thread wrote differs from the one the stored factors were
-    // built with; the thread of the last cell writes the right-wall face
-    // coefficients to wall[0..2].
+    // arrays, and whole (or half) cache lines of the interleaved rows.
+    // Returns a mask: kGatherChanged when a face coefficient of the cells this
+    // thread wrote differs from the one the stored factors were built with,
+    // kGatherBad when one of its cells has an input outside the problem's
+    // domain (mu < 0, D <= 0, k < 0, or a non-finite value); the thread of the
+    // last cell writes the right-wall face coefficients to wall[0..2].
     // ------------------------------------------------------------------
     // tiles of 8 x 8 cells of this column's layout
     __device__ __forceinline__ int ntiles() const { return ((cd.M + 7) >> 3) * (T / 8); }
 
-    __device__ bool gather(const UserArrays& U, int kb, int ke, int w, int nw, double* wall) {
+    static constexpr int kGatherChanged = 1, kGatherBad = 2;
+
+    __device__ int gather(const UserArrays& U, int kb, int ke, int w, int nw, double* wall) {
         const int M = cd.M, n = cd.n;
         const double dt = cd.dt, hb = 0.5 * cd.h;
         const int64_t fo = cd.uoff + cd.index;   // faces of column: n + 1 per column
@@ -518,7 +523,7 @@ struct Column {
         const bool extrap = prm.guess >= 1 && prm.has_prev;
         const bool learn = prm.guess == 2 && prm.has_learned && W.lmask[cd.index] != 0;
         const bool may_reuse = prm.fac_reuse && W.cst[cd.index].fac_valid;
-        bool changed = false;
+        bool changed = false, bad = false;
         constexpr int UC = 2;
         const int lane = threadIdx.x & 63;
         const int nrg = (M + 7) >> 3;            // row groups of 8
@@ -571,6 +576,13 @@ struct Column {
                     X00[s] = X01[s] = X10[s] = X11[s] = X20[s] = X21[s] = 0.0;
                     continue;
                 }
+                // the problem's domain: mu >= 0, D > 0, k >= 0, all values finite
+                // (the comparisons are false for NaN)
+                const bool ok = mu[v] >= 0.0 && mu[v] < INFINITY && D[v] > 0.0 && D[v] < INFINITY &&
+                                kl[v] >= 0.0 && kl[v] < INFINITY && fabs(sr[v]) < INFINITY &&
+                                fabs(qq[v]) < INFINITY && fabs(ne[v]) < INFINITY && fabs(ph[v]) < INFINITY &&
+                                fabs(uf[v]) < INFINITY;
+                bad = bad || !ok;
                 double r, g, wf = 0.0;
                 if (c == 0) {
                     r = mu[v] / D[v];
@@ -600,13 +612,15 @@ struct Column {
                 if (learn) { X20[s] = ln[v]; X21[s] = lp[v]; }
                 if (c == n - 1) {
                     // right wall face: the last cell's mu and D at distance h/2
+                    const double uR = prm.has_u ? U.uface[fo + n] : 0.0;
+                    bad = bad || !(fabs(uR) < INFINITY);
                     wall[0] = mu[v] / D[v];
                     wall[1] = (cd.bcr == 1) ? 0.0 : D[v] / hb;
-                    wall[2] = prm.has_u ? U.uface[fo + n] * hb / D[v] : 0.0;
+                    wall[2] = uR * hb / D[v];
                 }
             }
         }
-        return changed;
+        return (changed ? kGatherChanged : 0) | (bad ? kGatherBad : 0);
     }
 
     // Workspace buffer -> caller arrays (natural layout), tiles [kb, ke) of
@@ -660,16 +674,37 @@ struct Column {
         const double o_rR = csp->rR, o_gR = csp->gR, o_wR = csp->wR;
         const double o_sf[4] = {csp->fsfn, csp->fsfp, csp->fsxn, csp->fsxp};
         bool changed;    // a Jacobian coefficient of this thread's cells differs
+        bool bad = false;
         if (gathered) {
             rR = csp->nrR; gR = csp->ngR; wR = csp->nwR;
             changed = false;
-            for (int i = cd.g0; i < cd.g0 + cd.gn; ++i) changed = changed || W.gflag[i] != 0;
+            for (int i = cd.g0; i < cd.g0 + cd.gn; ++i) {
+                changed = changed || (W.gflag[i] & kGatherChanged) != 0;
+                bad = bad || (W.gflag[i] & kGatherBad) != 0;
+            }
         } else {
-            changed = gather(U, 0, ntiles(), t >> 6, T / 64, (double*)(lds + Lds<T>::kMisc));
-            __syncthreads();
+            const int gm = gather(U, 0, ntiles(), t >> 6, T / 64, (double*)(lds + Lds<T>::kMisc));
+            changed = (gm & kGatherChanged) != 0;
+            double bb[1] = {(gm & kGatherBad) ? 1.0 : 0.0};
+            wg_max<T, 1>(bb, lds + Lds<T>::kScr);   // its barriers also publish the wall values
+            bad = bb[0] != 0.0;
             const ldbl* misc = lds + Lds<T>::kMisc;
             rR = misc[0]; gR = misc[1]; wR = misc[2];
             __syncthreads();
+        }
+        if (bad) {
+            // an input outside the problem's domain: no iteration; X^n stays
+            bad_input = true;
+            *cur = 0;
+            *guess_used = 0;
+            if (t == 0) {
+                ColState* cs = W.cst + cd.index;
+                cs->sfn = cs->sfp = cs->sxn = cs->sxp = 1.0;
+                cs->fac_valid = 0;
+            }
+            Norms r;
+            r.rinf = NAN; r.r2 = NAN; r.xn2 = 0.0; r.step = INFINITY;
+            return r;
         }
 
         // Sweep A: scalings from X^n (term magnitudes) + residual at X^n, and

@@ -102,9 +102,12 @@ __global__ __launch_bounds__(kMoveThreads) void k_gather(SolveArgs a) {
     ColState* cs = a.W.cst + col.cd.index;
     const int kb = ((int)blockIdx.x - col.cd.g0) * kMoveTiles;
     const int ke = min(kb + kMoveTiles, col.ntiles());
-    const bool ch = col.gather(a.U, kb, ke, threadIdx.x >> 6, kMoveThreads / 64, &cs->nrR);
-    const int any = __syncthreads_or(ch ? 1 : 0);
-    if (threadIdx.x == 0) a.W.gflag[blockIdx.x] = any != 0 ? 1 : 0;
+    using Col = Column<T, float>;
+    const int gm = col.gather(a.U, kb, ke, threadIdx.x >> 6, kMoveThreads / 64, &cs->nrR);
+    const int any_changed = __syncthreads_or(gm & Col::kGatherChanged);
+    const int any_bad = __syncthreads_or(gm & Col::kGatherBad);
+    if (threadIdx.x == 0)
+        a.W.gflag[blockIdx.x] = (any_changed ? Col::kGatherChanged : 0) | (any_bad ? Col::kGatherBad : 0);
 }
 
 template <int T>
@@ -166,6 +169,7 @@ __global__ __launch_bounds__(T) void k_phase(PhaseArgs a) {
             scal[0] = cur; scal[1] = g; scal[2] = n.rinf; scal[3] = n.r2; scal[4] = n.xn2;
             scal[5] = n.step; scal[6] = col.sfn; scal[7] = col.sfp; scal[8] = col.sxn; scal[9] = col.sxp;
             scal[10] = col.fac_reuse ? 1.0 : 0.0;
+            scal[11] = col.bad_input ? 1.0 : 0.0;
         }
         break;
     }
@@ -359,7 +363,7 @@ struct jfnk_ctx {
 
 namespace {
 
-int drain(jfnk_ctx* ctx);
+int drain(jfnk_ctx* ctx, jfnk_stats* stt = nullptr, int32_t* rc_out = nullptr);
 
 int fail(jfnk_ctx* c, int code, const std::string& msg) {
     if (c) c->err = msg;
@@ -566,14 +570,16 @@ struct HostExecT {
         return hs;
     }
 
-    bool lagged = false;
+    bool lagged = false, bad = false;
     bool lagged_factors() const { return lagged; }
+    bool bad_input() const { return bad; }
     Norms setup(int* cur, int* guess) {
         launch(PH_SETUP);
-        const double* s = fetch(11);
+        const double* s = fetch(12);
         *cur = (int)s[0]; *guess = (int)s[1];
         Norms n{s[2], s[3], s[4], s[5]};
         lagged = s[10] == 1.0;
+        bad = s[11] == 1.0;
         sfn = s[6]; sfp = s[7];
         isfn = 1.0 / sfn; isfp = 1.0 / sfp;
         if (herr != hipSuccess) n.r2 = NAN;
@@ -905,12 +911,17 @@ int learned_guess(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream
     use.assign(nc, 1);
     int nuse = nc;
     const uint64_t ver = net_version(ctx->model);
-    if (ctx->hist_valid && (int)ctx->last_newton.size() == nc && ctx->model_version != ver) {
+    // A step without X^{n-1} starts a new history of the columns (a new
+    // episode from its start state): the records of earlier steps, and the
+    // judgement of the network made on them, do not describe it.
+    const bool fresh = x->ne_prev == nullptr;
+    const bool have_hist = ctx->hist_valid && !fresh && (int)ctx->last_newton.size() == nc;
+    if (have_hist && ctx->model_version != ver) {
         ctx->reject_streak.assign(nc, 0);
         ctx->skip_left.assign(nc, 0);
     }
     ctx->model_version = ver;
-    if (ctx->hist_valid && (int)ctx->last_newton.size() == nc) {
+    if (have_hist) {
         // skip columns that converged at their initial guess last step, and
         // back off exponentially from columns whose learned candidate keeps
         // losing: after r losses in a row, the next 4^r - 1 chances (steps at
@@ -1011,12 +1022,15 @@ int step_process(jfnk_ctx* ctx, int ncols, jfnk_stats* stt) {
     return nfail ? JFNK_NOT_CONVERGED : JFNK_OK;
 }
 
-// Finish an asynchronous step still in flight (its statistics are dropped).
-int drain(jfnk_ctx* ctx) {
+// Finish an asynchronous step still in flight.  Its statistics go to stt and
+// its code (JFNK_OK or JFNK_NOT_CONVERGED) to *rc_out, each when not NULL;
+// callers that pass neither drop them.
+int drain(jfnk_ctx* ctx, jfnk_stats* stt, int32_t* rc_out) {
     if (!ctx->pending) return JFNK_OK;
     swap_slot(ctx);
     ctx->pending = false;
-    const int rc = step_process(ctx, ctx->pending_ncols, nullptr);
+    const int rc = step_process(ctx, ctx->pending_ncols, stt);
+    if (rc_out && (rc == JFNK_OK || rc == JFNK_NOT_CONVERGED)) *rc_out = rc;
     return rc == JFNK_NOT_CONVERGED ? JFNK_OK : rc;
 }
 
@@ -1184,9 +1198,10 @@ int jfnk_step_async(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, jfnk_st
     if (ctx->cfg.schedule != JFNK_SCHED_BATCHED)
         return fail(ctx, JFNK_EINVAL, "asynchronous steps need the batched schedule");
     // a new layout rewrites the staged schedule, and a step on another stream
-    // would not be ordered after it: finish the step in flight first
+    // would not be ordered after it: finish the step in flight first (and
+    // report it, as the enqueue below would have)
     if (ctx->pending && (!schedule_matches(ctx, p) || ctx->pending_stream != (hipStream_t)stream)) {
-        rc = drain(ctx);
+        rc = drain(ctx, prev_stats, prev_rc);
         if (rc) return rc;
     }
     rc = step_enqueue(ctx, p, x, (hipStream_t)stream);
@@ -1248,7 +1263,9 @@ int jfnk_autotune(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, int
     for (int k = 0; k < 4 && rc == JFNK_OK; ++k) {
         const int T = cand[k];
         if (times_ms) times_ms[k] = -1.0;
-        if (T > kTmax || (nmax + T - 1) / T > 64 || (T > 64 && nmax <= T / 2)) continue;
+        // at most 64 cells per thread (the largest size is always tried: it
+        // is the only one for columns longer than 64 kTmax cells)
+        if (T > kTmax || (T < kTmax && (nmax + T - 1) / T > 64) || (T > 64 && nmax <= T / 2)) continue;
         ctx->force_T = T;
         ctx->sched_valid = false;
         const size_t nb = sizeof(double) * total;

@@ -72,6 +72,7 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
     Norms nr = ex.setup(&cur, &guess);
     int it = 0, gtot = 0, btot = 0, rtot = 0;
     int status = COL_MAX_NEWTON;
+    const bool bad_input = ex.bad_input();
     double hcol[kMaxRestart + 2];
     double y[kMaxRestart];
     // buffer whose state the current factorisation was built at; 3: the
@@ -83,6 +84,7 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
     int chords = 0, chord_run = 0;
     int wk[kWorkCounts] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (;;) {
+        if (bad_input) { status = COL_BAD_INPUT; break; }
         if (isnan(nr.r2)) { status = COL_NONFINITE; break; }
         if (nr.rinf <= p.tol_f) {
             if (p.tol_x <= 0.0) { status = COL_CONVERGED; break; }
@@ -275,6 +277,7 @@ struct DevExec {
 
     __device__ Norms setup(int* cur, int* guess) { return col.setup(U, cur, guess, split); }
     __device__ bool lagged_factors() const { return col.fac_reuse; }
+    __device__ bool bad_input() const { return col.bad_input; }
     __device__ void factor(int cur) { col.factor(cur); }
 
     __device__ VecRef fref(int cur, double sc) {

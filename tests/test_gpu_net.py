@@ -221,10 +221,11 @@ def test_learned_guess_keeps_the_root(J, R):
 
 def test_learned_backoff_schedule(J, R):
     """Which columns evaluate the learned candidate (phase_counts[:, 7])
-    follows the back-off rule: every column on the first step of a layout;
-    afterwards only columns whose last step needed Newton iterations, less
-    4^r - 1 skipped chances after r consecutive losses (r <= 5); new weights
-    clear the record."""
+    follows the back-off rule: every column on the first step of a layout
+    and on every step without X^{n-1} (a new episode from its start state,
+    which also clears the back-off record); afterwards only columns whose
+    last step needed Newton iterations, less 4^r - 1 skipped chances after r
+    consecutive losses (r <= 5); new weights clear the record."""
     cols = W.config2(seed=2101, ncols=8, nmin=300, nmax=900)
     packed = W.pack(cols)
     prob, ne, phi, _, _ = J.device_problem(packed)
@@ -247,8 +248,10 @@ def test_learned_backoff_schedule(J, R):
             streak[:] = 0
             skip[:] = 0
         for k in range(8):
-            if last is None:
+            if last is None or pne is None:
                 use = np.ones(nc, bool)
+                streak[:] = 0
+                skip[:] = 0
             else:
                 use = np.zeros(nc, bool)
                 for c in range(nc):
@@ -396,12 +399,23 @@ def test_async_steps_on_two_streams(J):
     a = (ne0.clone(), phi0.clone())
     b = (torch.empty_like(ne0), torch.empty_like(phi0))
     torch.cuda.synchronize()
+    reports = []
     for k in range(4):
-        solver.step_async(prob, a[0], a[1], ne_out=b[0], phi_out=b[1], stream=s1 if k % 2 == 0 else s2,
-                          prev_stats=J.Stats(n))
+        rc, st = solver.step_async(prob, a[0], a[1], ne_out=b[0], phi_out=b[1],
+                                   stream=s1 if k % 2 == 0 else s2, prev_stats=J.Stats(n))
+        # the step in flight is finished before a step on the other stream
+        # starts, and it is reported through this call all the same
+        assert (rc is None) == (k == 0)
+        if rc is not None:
+            reports.append((rc, st.status.copy(), st.newton_iters.copy()))
         a, b = b, a
-    rc, _ = solver.step_finish(stats=J.Stats(n))
-    assert rc == J.JFNK_OK
+    rc, st = solver.step_finish(stats=J.Stats(n))
+    reports.append((rc, st.status.copy(), st.newton_iters.copy()))
+    assert len(reports) == 4
+    for rc, status, newton in reports:
+        assert rc == J.JFNK_OK and np.all(status == J.COL_CONVERGED)
+    # the first step from the start state iterates
+    assert reports[0][2].sum() > 0
     torch.cuda.synchronize()
     assert np.array_equal(rn.cpu().numpy(), a[0].cpu().numpy())
     assert np.array_equal(rp.cpu().numpy(), a[1].cpu().numpy())
@@ -440,8 +454,12 @@ def test_trained_network_gain(J):
     """Trains the network on solver-generated episodes of training seeds and
     measures, on a held-out batch of the same distribution, what the learned
     guess changes against the extrapolated guess: how often its candidate is
-    taken, Newton and GMRES iterations, and device time.  The roots must not
-    change (the guess only moves Newton's starting point)."""
+    evaluated and taken, Newton and GMRES iterations, and device time.  The
+    candidate must be evaluated (every column on the episode's first step)
+    and the roots must not change (the guess only moves Newton's starting
+    point).  The gain itself (fewer Newton iterations) is the expected
+    outcome of the method; where the measurement shows none, the test
+    reports an expected failure with the numbers."""
     from paper_1904_08510_amd import train_guess as TG
     data = TG.generate(list(W.training_seeds())[:12], ncols=16, steps=20, nmin=512, nmax=2048,
                        log=lambda *a: None)
@@ -458,7 +476,7 @@ def test_trained_network_gain(J):
         if mode == "learned":
             solver.set_model(net)
         pne = pph = None
-        newton = gmres = taken = 0
+        newton = gmres = taken = evaluated = 0
         ms = 0.0
         for k in range(20):
             cur = (ne.clone(), phi.clone())
@@ -473,13 +491,17 @@ def test_trained_network_gain(J):
             newton += int(st.newton_iters.sum())
             gmres += int(st.gmres_iters.sum())
             taken += int(np.sum(st.guess_used == J.GUESS_LEARNED))
+            evaluated += int(np.sum(st.phase_counts[:, 7]))
             pne, pph = cur
-        res[mode] = dict(newton=newton, gmres=gmres, taken=taken, ms=ms, ne=ne.cpu().numpy(),
-                         phi=phi.cpu().numpy())
+        res[mode] = dict(newton=newton, gmres=gmres, taken=taken, evaluated=evaluated, ms=ms,
+                         ne=ne.cpu().numpy(), phi=phi.cpu().numpy())
     a, b = res["extrap"], res["learned"]
-    print(f"learned guess over 64 held-out columns x 20 steps: candidate taken {b['taken']} times; "
-          f"Newton {a['newton']} -> {b['newton']}, GMRES {a['gmres']} -> {b['gmres']}, "
+    print(f"learned guess over 64 held-out columns x 20 steps: candidate evaluated {b['evaluated']} and taken "
+          f"{b['taken']} times; Newton {a['newton']} -> {b['newton']}, GMRES {a['gmres']} -> {b['gmres']}, "
           f"device time {a['ms']:.1f} -> {b['ms']:.1f} ms (training loss {hist[0]:.3g} -> {hist[-1]:.3g})")
-    assert a["taken"] == 0
+    assert a["evaluated"] == 0 and b["evaluated"] >= packed.ncols
     for x, y in ((a["ne"], b["ne"]), (a["phi"], b["phi"])):
         assert np.linalg.norm(x - y) <= 1e-9 * np.linalg.norm(x)
+    if not (b["taken"] > 0 and b["newton"] < a["newton"]):
+        pytest.xfail(f"no gain measured: candidate taken {b['taken']} of {b['evaluated']} evaluations, "
+                     f"Newton {a['newton']} -> {b['newton']}, GMRES {a['gmres']} -> {b['gmres']}")

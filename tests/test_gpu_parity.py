@@ -331,16 +331,45 @@ def test_invalid_arguments_leave_outputs_untouched(J):
     assert rc == J.JFNK_ECAPACITY
 
 
-def test_nonfinite_column_is_isolated(J):
-    cols = [W.flame_column(200, 100.0), W.flame_column(300, -200.0)]
-    packed = W.pack(cols)
-    packed.src[packed.col_offset[1] + 17] = np.nan
+@pytest.mark.parametrize("sched", ["batched", "plain"])
+def test_bad_input_columns_are_isolated(J, sched):
+    """Per-cell inputs outside the problem's domain (a non-finite source, a
+    negative mobility, a zero diffusivity, a negative loss rate, a non-finite
+    start state) are found on the device: the column is not iterated, keeps
+    X^n and reports JFNK_COL_BAD_INPUT; the other columns are solved as if
+    alone."""
+    base = [W.flame_column(200, 100.0), W.flame_column(300, -200.0), W.flame_column(150, 40.0),
+            W.flame_column(260, 500.0), W.flame_column(90, -60.0), W.flame_column(333, 250.0)]
+    packed = W.pack(base)
+    o = packed.col_offset
+    packed.src[o[1] + 17] = np.nan
+    packed.mu[o[2] + 149] = -0.1          # the last cell: its wall face too
+    packed.diff[o[3]] = 0.0               # the first cell
+    packed.kloss[o[4] + 40] = -1.0
+    packed.ne[o[5] + 100] = np.inf
     prob, ne, phi, _, _ = J.device_problem(packed)
-    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64))
+    ne0, phi0 = ne.clone(), phi.clone()
+    cfg = J.config_for(packed, prec_precision=J.PREC_FP64,
+                       schedule=J.SCHED_BATCHED if sched == "batched" else J.SCHED_PLAIN)
+    solver = J.Solver(cfg)
     rc, st = solver.step(prob, ne, phi)
     assert rc == J.JFNK_NOT_CONVERGED
-    assert st.status[0] == J.COL_CONVERGED
-    assert st.status[1] == J.COL_NONFINITE
+    assert list(st.status) == [J.COL_CONVERGED] + [J.COL_BAD_INPUT] * 5, st.status
+    assert np.all(st.newton_iters[1:] == 0)
+    for c in range(1, 6):
+        sl = slice(o[c], o[c + 1])
+        assert torch.equal(ne[sl], ne0[sl]) and torch.equal(phi[sl], phi0[sl])
+    # column 0 equals the same column solved alone
+    alone = W.pack(base[:1])
+    p1, n1, f1, _, _ = J.device_problem(alone)
+    s1 = J.Solver(J.config_for(alone, prec_precision=J.PREC_FP64))
+    s1.step(p1, n1, f1)
+    assert torch.equal(ne[o[0]:o[1]], n1) and torch.equal(phi[o[0]:o[1]], f1)
+    # the flag clears once the input is repaired (same context, same layout)
+    packed.src[o[1] + 17] = 0.0
+    prob.src = torch.from_numpy(packed.src.copy()).cuda()
+    rc, st = solver.step(prob, ne, phi)
+    assert st.status[1] == J.COL_CONVERGED
 
 
 def test_newton_cap_flags_columns(J):
