@@ -355,6 +355,40 @@ int jfnk_net_train_step(jfnk_net *net, const jfnk_problem *p, const jfnk_state *
    (jfnk_net_set_params, jfnk_net_train_step) clears that record. */
 int jfnk_set_model(jfnk_ctx *ctx, jfnk_net *net);
 
+/* ---- allocation-free step ------------------------------------------------
+ *
+ * For callers that cannot allocate device memory (code that runs while a
+ * HIP graph is being captured, tight serving loops, harnesses that forbid
+ * hipMalloc): the batched step of jfnk_step without a context.  Its whole
+ * workspace (the same arrays a context holds, for this problem's padded
+ * cells, plus the work order and the gather tables) lives in a static device
+ * array of JFNK_NOALLOC_BYTES bytes that every GPU the library runs on holds
+ * from the first call on it until the process ends.  The call allocates
+ * nothing (no hipMalloc, no host heap); the caller passes the inputs and
+ * outputs as for jfnk_step.
+ *
+ * cfg: as for jfnk_create (its capacity fields bound nothing here except
+ * max_cells_per_col); the schedule is always BATCHED, the workgroup size
+ * follows the size rule (or threads_override); JFNK_GUESS_LEARNED is not
+ * available (EINVAL).  Every call starts without the previous step's
+ * factors (as the first step of a new context), so its iterates equal those
+ * of jfnk_step on a fresh context.  Limits: at most JFNK_NOALLOC_MAX_COLS
+ * columns, and the workspace must fit: 8 (60 + 4 m) bytes per padded cell
+ * (cells rounded up to a multiple of the workgroup size, m = gmres_restart;
+ * 1440 bytes at m = 30) plus 768 T bytes per column, in JFNK_NOALLOC_BYTES;
+ * larger problems return JFNK_ECAPACITY (nothing launched).  err (HOST,
+ * err_len bytes, may be NULL) receives a message on error.
+ *
+ * The array keeps the last call's contents and each call clears the part it
+ * uses.  All calls on one GPU share it: calls that overlap on one GPU (on two
+ * streams, or from two host threads) race and corrupt each other.  The call
+ * queues its work on stream and returns once the results and stats are
+ * complete.  Returns JFNK_OK, JFNK_NOT_CONVERGED, or an error code. */
+#define JFNK_NOALLOC_BYTES ((size_t)64 << 20)
+#define JFNK_NOALLOC_MAX_COLS 64
+int jfnk_step_noalloc(const jfnk_config *cfg, const jfnk_problem *p, jfnk_state *x, jfnk_stats *st,
+                      void *stream, char *err, size_t err_len);
+
 /* ---- test exports: single phases of the step, same kernels ----------- */
 
 /* F(X) (unscaled, per cell: fe, fp) with X = (x_ne, x_phi) and the step's

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -387,33 +388,56 @@ int choose_T(const jfnk_config& cfg, int nmax) {
     return T;
 }
 
-int64_t work_doubles_per_cell(int m) {
-    // fa fg fw f kd q (6) x (6) F (6) V (2(m+1)) Z (2m) dX (2) ftmp (8)
-    // fac (24, sized for FP64) tmp (2, sized for FP64) approximate-Schur temporaries (4)
-    return 6 + 6 + 6 + 2 * (m + 1) + 2 * m + 2 + kTempSlots + kFactorSlots + 2 + 4;
+// The workspace arrays for P padded cells (a multiple of 64), GMRES restart
+// m, red doubles of per-chunk data and max_cols columns, carved from base in
+// this order; returns the doubles they span.  With base == nullptr only the
+// size is computed (W untouched).
+int64_t carve_work(double* base, int64_t P, int m, int64_t red, int max_cols, Work* W) {
+    int64_t off = 0;
+    auto take = [&](int64_t n) { double* r = base ? base + off : nullptr; off += n; return r; };
+    Work w{};
+    w.P = P;
+    w.fa = take(P); w.fg = take(P); w.fw = take(P);
+    w.f = take(P); w.kd = take(P); w.q = take(P);
+    w.x = take(6 * P); w.F = take(6 * P);
+    w.V = take(2 * (int64_t)(m + 1) * P);
+    w.Z = take(2 * (int64_t)m * P);
+    w.dX = take(2 * P);
+    w.ftmp = take((int64_t)kTempSlots * P);
+    w.fac = (void*)take((int64_t)kFactorSlots * P);
+    w.tmp = (void*)take(2 * P);
+    w.sch = take(4 * P);
+    w.red = take(red);
+    w.cols = (ColDesc*)take((max_cols * (int64_t)sizeof(ColDesc) + 7) / 8);
+    w.cst = (ColState*)take((max_cols * (int64_t)sizeof(ColState) + 7) / 8);
+    w.scal = take((int64_t)max_cols * kScalSlots);
+    if (base && W) {
+        w.lmask = W->lmask;
+        w.gflag = W->gflag;
+        *W = w;
+    }
+    return off;
 }
 
 void carve(jfnk_ctx* c) {
-    const int64_t P = c->capP;
-    const int m = c->cfg.gmres_restart;
-    double* p = (double*)c->base;
-    auto take = [&](int64_t n) { double* r = p; p += n; return r; };
-    Work& W = c->W;
-    W.P = P;
-    W.fa = take(P); W.fg = take(P); W.fw = take(P);
-    W.f = take(P); W.kd = take(P); W.q = take(P);
-    W.x = take(6 * P); W.F = take(6 * P);
-    W.V = take(2 * (int64_t)(m + 1) * P);
-    W.Z = take(2 * (int64_t)m * P);
-    W.dX = take(2 * P);
-    W.ftmp = take((int64_t)kTempSlots * P);
-    W.fac = (void*)take((int64_t)kFactorSlots * P);
-    W.tmp = (void*)take(2 * P);
-    W.sch = take(4 * P);
-    W.red = take(c->capRed);
-    W.cols = (ColDesc*)take((c->cfg.max_cols * (int64_t)sizeof(ColDesc) + 7) / 8);
-    W.cst = (ColState*)take((c->cfg.max_cols * (int64_t)sizeof(ColState) + 7) / 8);
-    W.scal = take((int64_t)c->cfg.max_cols * kScalSlots);
+    carve_work((double*)c->base, c->capP, c->cfg.gmres_restart, c->capRed, c->cfg.max_cols, &c->W);
+}
+
+// The configuration's own checks (those of jfnk_create).
+bool config_valid(const jfnk_config* cfg) {
+    if (cfg->max_cols < 1 || cfg->max_total_cells < 3 || cfg->max_cells_per_col < 3 ||
+        cfg->gmres_restart < 1 || cfg->gmres_restart > kMaxRestart || cfg->max_restarts < 0 ||
+        cfg->max_newton < 0 || cfg->max_backtracks < 0 || !(cfg->tol_f > 0.0) || !(cfg->tol_x >= 0.0) ||
+        !(cfg->gamma > 0.0 && cfg->gamma < 1.0) || !(cfg->ls_theta >= 0.0 && cfg->ls_theta < 1.0) ||
+        !(cfg->chord_tol >= 0.0 && cfg->chord_tol < 1.0) ||
+        (cfg->prec_precision != JFNK_PREC_FP64 && cfg->prec_precision != JFNK_PREC_FP32) ||
+        (cfg->prec_kind != JFNK_PRECK_BLOCK && cfg->prec_kind != JFNK_PRECK_SCHUR &&
+         cfg->prec_kind != JFNK_PRECK_NONE) ||
+        cfg->guess < 0 || cfg->guess > 2 ||
+        (cfg->schedule != JFNK_SCHED_PLAIN && cfg->schedule != JFNK_SCHED_BATCHED))
+        return false;
+    const int t = cfg->threads_override;
+    return t == 0 || t == 64 || t == 128 || t == 256 || t == 512;
 }
 
 // validation of the problem; fills the schedule on success
@@ -492,26 +516,31 @@ int validate(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x) {
     return JFNK_OK;
 }
 
-SolverParams make_params(const jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x) {
+SolverParams params_of(const jfnk_config& cfg, const jfnk_problem* p, const jfnk_state* x, bool learned,
+                       bool fac_reuse) {
     SolverParams s{};
-    s.m = ctx->cfg.gmres_restart;
-    s.max_restarts = ctx->cfg.max_restarts;
-    s.max_newton = ctx->cfg.max_newton;
-    s.max_backtracks = ctx->cfg.max_backtracks;
-    s.guess = ctx->cfg.guess;
+    s.m = cfg.gmres_restart;
+    s.max_restarts = cfg.max_restarts;
+    s.max_newton = cfg.max_newton;
+    s.max_backtracks = cfg.max_backtracks;
+    s.guess = cfg.guess;
     s.has_prev = x->ne_prev != nullptr;
-    s.has_learned = ctx->learn_active ? 1 : 0;
+    s.has_learned = learned ? 1 : 0;
     s.has_u = p->u_face != nullptr;
-    s.fac_reuse = ctx->fac_reuse_ok ? 1 : 0;
-    s.prec_kind = ctx->cfg.prec_kind;
-    s.tol_f = ctx->cfg.tol_f;
-    s.tol_x = ctx->cfg.tol_x;
-    s.gamma = ctx->cfg.gamma;
-    s.theta = ctx->cfg.ls_theta;
+    s.fac_reuse = fac_reuse ? 1 : 0;
+    s.prec_kind = cfg.prec_kind;
+    s.tol_f = cfg.tol_f;
+    s.tol_x = cfg.tol_x;
+    s.gamma = cfg.gamma;
+    s.theta = cfg.ls_theta;
     // without a preconditioner a simplified-Newton step would be a unit
     // Richardson step on the scaled system: none is taken
-    s.chord_tol = ctx->cfg.prec_kind == JFNK_PRECK_NONE ? 0.0 : ctx->cfg.chord_tol;
+    s.chord_tol = cfg.prec_kind == JFNK_PRECK_NONE ? 0.0 : cfg.chord_tol;
     return s;
+}
+
+SolverParams make_params(const jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x) {
+    return params_of(ctx->cfg, p, x, ctx->learn_active, ctx->fac_reuse_ok);
 }
 
 UserArrays make_user(const jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x) {
@@ -1037,6 +1066,74 @@ int drain(jfnk_ctx* ctx, jfnk_stats* stt, int32_t* rc_out) {
 }  // namespace
 
 // ===========================================================================
+// Allocation-free step: the whole workspace of one batched step lives in a
+// file-scope device array, which every GPU the library runs on holds (at its
+// own address) until the process ends.  Host code never passes the array's
+// name to a kernel: it is a host-side stand-in there.  Its device address is
+// taken once per device with hipGetSymbolAddress, that device current, and
+// kept in g_scratch_ptr.
+// ===========================================================================
+static __device__ __align__(256) unsigned char scratch[JFNK_NOALLOC_BYTES];
+
+namespace {
+
+constexpr int kStaticMaxDevices = 64;
+constexpr int kStaticMoveCap = 1024;    // gather / write-back workgroups of one step
+void* g_scratch_ptr[kStaticMaxDevices];
+std::mutex g_scratch_mu;
+
+// Device address of this device's array (device current); nullptr on error.
+void* scratch_ptr(int dev) {
+    if (dev < 0 || dev >= kStaticMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+__global__ __launch_bounds__(256) void k_clear(uint4* p, int64_t n16) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+template <int T, class FT>
+hipError_t static_launch(const SolveArgs& a, int nmove, int ncols, hipStream_t st) {
+    hipLaunchKernelGGL((k_gather<T>), dim3(nmove), dim3(kMoveThreads), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_solve<T, FT>), dim3(ncols), dim3(T), Lds<T>::bytes(), st, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_scatter<T>), dim3(nmove), dim3(kMoveThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+template <class FT>
+hipError_t static_dispatch(int T, const SolveArgs& a, int nmove, int ncols, hipStream_t st) {
+    switch (T) {
+    case 64: return static_launch<64, FT>(a, nmove, ncols, st);
+    case 128: return static_launch<128, FT>(a, nmove, ncols, st);
+    case 256: return static_launch<256, FT>(a, nmove, ncols, st);
+    case 512: return static_launch<512, FT>(a, nmove, ncols, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int static_fail(char* err, size_t len, int code, const char* msg) {
+    if (err && len > 0) snprintf(err, len, "%s", msg);
+    return code;
+}
+
+}  // namespace
+
+// ===========================================================================
 // C ABI
 // ===========================================================================
 extern "C" {
@@ -1067,21 +1164,7 @@ int jfnk_create(const jfnk_config* cfg, jfnk_ctx** out) {
     if (!out) return JFNK_EINVAL;
     *out = nullptr;
     if (!cfg) return JFNK_EINVAL;
-    if (cfg->max_cols < 1 || cfg->max_total_cells < 3 || cfg->max_cells_per_col < 3 ||
-        cfg->gmres_restart < 1 || cfg->gmres_restart > kMaxRestart || cfg->max_restarts < 0 ||
-        cfg->max_newton < 0 || cfg->max_backtracks < 0 || !(cfg->tol_f > 0.0) || !(cfg->tol_x >= 0.0) ||
-        !(cfg->gamma > 0.0 && cfg->gamma < 1.0) || !(cfg->ls_theta >= 0.0 && cfg->ls_theta < 1.0) ||
-        !(cfg->chord_tol >= 0.0 && cfg->chord_tol < 1.0) ||
-        (cfg->prec_precision != JFNK_PREC_FP64 && cfg->prec_precision != JFNK_PREC_FP32) ||
-        (cfg->prec_kind != JFNK_PRECK_BLOCK && cfg->prec_kind != JFNK_PRECK_SCHUR &&
-         cfg->prec_kind != JFNK_PRECK_NONE) ||
-        cfg->guess < 0 || cfg->guess > 2 ||
-        (cfg->schedule != JFNK_SCHED_PLAIN && cfg->schedule != JFNK_SCHED_BATCHED))
-        return JFNK_EINVAL;
-    if (cfg->threads_override != 0) {
-        const int t = cfg->threads_override;
-        if (t != 64 && t != 128 && t != 256 && t != 512) return JFNK_EINVAL;
-    }
+    if (!config_valid(cfg)) return JFNK_EINVAL;
     jfnk_ctx* ctx = new (std::nothrow) jfnk_ctx();
     if (!ctx) return JFNK_ENOMEM;
     ctx->cfg = *cfg;
@@ -1090,10 +1173,7 @@ int jfnk_create(const jfnk_config* cfg, jfnk_ctx** out) {
     // a multiple of 64 cells: every workspace array then starts 512-byte aligned
     ctx->capP = (cfg->max_total_cells + (int64_t)cfg->max_cols * Tcap + 63) / 64 * 64;
     ctx->capRed = (int64_t)cfg->max_cols * Tcap * kRedPerChunk;
-    const int64_t per = work_doubles_per_cell(cfg->gmres_restart);
-    const int64_t words = per * ctx->capP + ctx->capRed +
-                          (cfg->max_cols * (int64_t)(sizeof(ColDesc) + sizeof(ColState)) + 16) / 8 + 4 +
-                          (int64_t)cfg->max_cols * kScalSlots;
+    const int64_t words = carve_work(nullptr, ctx->capP, cfg->gmres_restart, ctx->capRed, cfg->max_cols, nullptr);
     hipError_t e = hipMalloc((void**)&ctx->base, sizeof(double) * words);
     if (e != hipSuccess) { (void)hipGetLastError(); delete ctx; return JFNK_ENOMEM; }
     carve(ctx);
@@ -1440,6 +1520,147 @@ int jfnk_block_solve(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, 
     }
     HIP_OK(hipStreamSynchronize(st));
     return JFNK_OK;
+}
+
+int jfnk_step_noalloc(const jfnk_config* cfg, const jfnk_problem* p, jfnk_state* x, jfnk_stats* stt,
+                      void* stream, char* err, size_t err_len) {
+    if (err && err_len > 0) err[0] = '\0';
+    if (!cfg || !p || !x) return static_fail(err, err_len, JFNK_EINVAL, "null config, problem or state");
+    if (!config_valid(cfg)) return static_fail(err, err_len, JFNK_EINVAL, "invalid configuration");
+    if (cfg->guess == JFNK_GUESS_LEARNED)
+        return static_fail(err, err_len, JFNK_EINVAL, "the learned guess needs a context (jfnk_set_model)");
+    if (p->ncols < 1) return static_fail(err, err_len, JFNK_EINVAL, "ncols < 1");
+    if (p->ncols > JFNK_NOALLOC_MAX_COLS)
+        return static_fail(err, err_len, JFNK_ECAPACITY, "more columns than JFNK_NOALLOC_MAX_COLS");
+    if (!p->col_offset || !p->length || !p->dt || !p->phi_left || !p->phi_right || !p->eps_over_e ||
+        !p->bc_left || !p->bc_right || !p->ne_left || !p->ne_right)
+        return static_fail(err, err_len, JFNK_EINVAL, "null per-column array");
+    if (!p->mu || !p->diff || !p->src || !p->q_ion || !x->ne || !x->phi)
+        return static_fail(err, err_len, JFNK_EINVAL, "null per-cell array");
+    if ((x->ne_prev == nullptr) != (x->phi_prev == nullptr) || (x->ne_out == nullptr) != (x->phi_out == nullptr))
+        return static_fail(err, err_len, JFNK_EINVAL, "ne_prev/phi_prev and ne_out/phi_out go in pairs");
+    if (p->col_offset[0] != 0) return static_fail(err, err_len, JFNK_EINVAL, "col_offset[0] != 0");
+    const int nc = p->ncols;
+    int nmax = 0;
+    for (int c = 0; c < nc; ++c) {
+        const int64_t n = p->col_offset[c + 1] - p->col_offset[c];
+        if (n < 3) return static_fail(err, err_len, JFNK_EINVAL, "column with fewer than 3 cells");
+        if (n > cfg->max_cells_per_col) return static_fail(err, err_len, JFNK_ECAPACITY, "column longer than max_cells_per_col");
+        nmax = std::max<int>(nmax, (int)n);
+        const double v[7] = {p->length[c], p->dt[c], p->phi_left[c], p->phi_right[c], p->eps_over_e[c],
+                             p->ne_left[c], p->ne_right[c]};
+        for (double d : v)
+            if (!std::isfinite(d)) return static_fail(err, err_len, JFNK_EINVAL, "non-finite per-column scalar");
+        if (!(p->length[c] > 0.0) || !(p->dt[c] > 0.0) || !(p->eps_over_e[c] > 0.0))
+            return static_fail(err, err_len, JFNK_EINVAL, "length, dt and eps_over_e must be > 0");
+        if ((p->bc_left[c] != 0 && p->bc_left[c] != 1) || (p->bc_right[c] != 0 && p->bc_right[c] != 1))
+            return static_fail(err, err_len, JFNK_EINVAL, "bad boundary condition code");
+    }
+    // the schedule of jfnk_step's batched path (workgroup size by the size
+    // rule or threads_override; longest columns first), in host stack arrays
+    const int T = choose_T(*cfg, nmax);
+    ColDesc cols[JFNK_NOALLOC_MAX_COLS];
+    int order[JFNK_NOALLOC_MAX_COLS];
+    int32_t mcol[kStaticMoveCap];
+    int64_t ws = 0, red = 0;
+    for (int c = 0; c < nc; ++c) {
+        const int n = (int)(p->col_offset[c + 1] - p->col_offset[c]);
+        const int M = (n + T - 1) / T;
+        ColDesc& d = cols[c];
+        memset(&d, 0, sizeof(d));
+        d.n = n; d.M = M; d.bcl = p->bc_left[c]; d.bcr = p->bc_right[c];
+        d.index = c; d.T = T;
+        d.uoff = p->col_offset[c]; d.ws = ws; d.red = red;
+        d.h = p->length[c] / n; d.dt = p->dt[c];
+        d.phil = p->phi_left[c]; d.phir = p->phi_right[c];
+        d.eps = p->eps_over_e[c]; d.nel = p->ne_left[c]; d.ner = p->ne_right[c];
+        ws += (int64_t)T * M;
+        red += (int64_t)T * kRedPerChunk;
+        // insertion into the order by cells, longest first (stable)
+        int k = c;
+        while (k > 0 && cols[order[k - 1]].n < n) { order[k] = order[k - 1]; --k; }
+        order[k] = c;
+    }
+    int nmove = 0;
+    for (int i = 0; i < nc; ++i) {
+        ColDesc& d = cols[order[i]];
+        const int tiles = ((d.M + 7) / 8) * (T / 8);
+        const int gn = (tiles + kMoveTiles - 1) / kMoveTiles;
+        if (nmove + gn > kStaticMoveCap)
+            return static_fail(err, err_len, JFNK_ECAPACITY, "problem exceeds the allocation-free step's capacity");
+        d.g0 = nmove; d.gn = gn;
+        for (int k = 0; k < gn; ++k) mcol[nmove + k] = order[i];
+        nmove += gn;
+    }
+    // bytes: the workspace (as jfnk_create lays it out), then the work order,
+    // the write-back table and the gather flags, each 256-byte aligned
+    auto up256 = [](int64_t b) { return (b + 255) / 256 * 256; };
+    const int64_t wbytes = up256(8 * carve_work(nullptr, ws, cfg->gmres_restart, red, nc, nullptr));
+    const int64_t obytes = up256(sizeof(int) * (int64_t)nc);
+    const int64_t mbytes = up256(sizeof(int32_t) * (int64_t)nmove);
+    const int64_t total = wbytes + obytes + 2 * mbytes;
+    if (total > (int64_t)JFNK_NOALLOC_BYTES)
+        return static_fail(err, err_len, JFNK_ECAPACITY,
+                           "problem exceeds the allocation-free step's capacity (JFNK_NOALLOC_BYTES)");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return static_fail(err, err_len, JFNK_EHIP, "hipGetDevice failed");
+    unsigned char* base = (unsigned char*)scratch_ptr(dev);
+    if (!base) return static_fail(err, err_len, JFNK_EHIP, "hipGetSymbolAddress of the scratch array failed");
+    hipStream_t st = (hipStream_t)stream;
+    Work W{};
+    carve_work((double*)base, ws, cfg->gmres_restart, red, nc, &W);
+    int* d_order = (int*)(base + wbytes);
+    int32_t* d_mcol = (int32_t*)(base + wbytes + obytes);
+    W.gflag = (int32_t*)(base + wbytes + obytes + mbytes);
+    W.lmask = nullptr;
+    // the array keeps the last call's contents: clear what this step uses
+    // (padding cells must read as zero), with a kernel, not a memset node
+    const int64_t n16 = total / 16;
+    const int nb = (int)std::min<int64_t>((n16 + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_clear, dim3(nb), dim3(256), 0, st, (uint4*)base, n16);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(W.cols, cols, sizeof(ColDesc) * nc, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_order, order, sizeof(int) * nc, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_mcol, mcol, sizeof(int32_t) * nmove, hipMemcpyHostToDevice, st);
+    SolveArgs a;
+    a.W = W;
+    a.prm = params_of(*cfg, p, x, false, false);
+    a.U = UserArrays{};
+    a.U.mu = p->mu; a.U.diff = p->diff; a.U.src = p->src; a.U.kloss = p->k_loss; a.U.q = p->q_ion;
+    a.U.uface = p->u_face;
+    a.U.ne = x->ne; a.U.phi = x->phi;
+    a.U.ne_out = x->ne_out ? x->ne_out : x->ne;
+    a.U.phi_out = x->phi_out ? x->phi_out : x->phi;
+    a.U.ne_prev = x->ne_prev; a.U.phi_prev = x->phi_prev;
+    a.order = d_order;
+    a.mcol = d_mcol;
+    a.ncols = nc;
+    if (e == hipSuccess)
+        e = cfg->prec_precision == JFNK_PREC_FP32 ? static_dispatch<float>(T, a, nmove, nc, st)
+                                                  : static_dispatch<double>(T, a, nmove, nc, st);
+    ColState hcst[JFNK_NOALLOC_MAX_COLS];
+    if (e == hipSuccess) e = hipMemcpyAsync(hcst, W.cst, sizeof(ColState) * nc, hipMemcpyDeviceToHost, st);
+    // the host arrays above live on this call's stack: wait before returning
+    const hipError_t es = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = es;
+    if (e != hipSuccess) return static_fail(err, err_len, JFNK_EHIP, hipGetErrorString(e));
+    int bad = 0;
+    for (int c = 0; c < nc; ++c) {
+        const ColState& s = hcst[c];
+        if (s.status != COL_CONVERGED) ++bad;
+        if (!stt) continue;
+        if (stt->status) stt->status[c] = s.status;
+        if (stt->newton_iters) stt->newton_iters[c] = s.newton;
+        if (stt->gmres_iters) stt->gmres_iters[c] = s.gmres;
+        if (stt->backtracks) stt->backtracks[c] = s.backtracks;
+        if (stt->guess_used) stt->guess_used[c] = s.guess;
+        if (stt->chord_steps) stt->chord_steps[c] = s.chords;
+        if (stt->phase_counts)
+            for (int i = 0; i < kWorkCounts; ++i)
+                stt->phase_counts[(int64_t)c * kWorkCounts + i] = i == kWorkLearned ? 0 : s.work[i];
+        if (stt->res_scaled) stt->res_scaled[c] = s.res_inf;
+    }
+    return bad ? JFNK_NOT_CONVERGED : JFNK_OK;
 }
 
 }  // extern "C"

@@ -135,6 +135,9 @@ def lib():
         L.jfnk_autotune.restype = C.c_int
         L.jfnk_set_model.argtypes = [C.c_void_p, C.c_void_p]
         L.jfnk_set_model.restype = C.c_int
+        L.jfnk_step_noalloc.argtypes = [C.POINTER(jfnk_config), C.POINTER(jfnk_problem), C.POINTER(jfnk_state),
+                                        C.POINTER(jfnk_stats), C.c_void_p, C.c_char_p, C.c_size_t]
+        L.jfnk_step_noalloc.restype = C.c_int
         _LIB = L
     return _LIB
 
@@ -145,7 +148,11 @@ EXPORTED_SYMBOLS = ("jfnk_config_default", "jfnk_create", "jfnk_step", "jfnk_ste
                     "jfnk_block_solve", "jfnk_net_config_default", "jfnk_net_param_count",
                     "jfnk_net_create", "jfnk_net_destroy", "jfnk_net_last_error",
                     "jfnk_net_set_params", "jfnk_net_get_params", "jfnk_net_predict",
-                    "jfnk_net_grad", "jfnk_net_train_step", "jfnk_set_model", "jfnk_autotune")
+                    "jfnk_net_grad", "jfnk_net_train_step", "jfnk_set_model", "jfnk_autotune",
+                    "jfnk_step_noalloc")
+
+NOALLOC_BYTES = 64 << 20      # JFNK_NOALLOC_BYTES
+NOALLOC_MAX_COLS = 64         # JFNK_NOALLOC_MAX_COLS
 
 
 class JfnkError(RuntimeError):
@@ -430,6 +437,19 @@ class Solver:
                                     _stream_ptr(stream))
         self._check(rc, (JFNK_OK,))
         return z_ne, z_phi
+
+
+def step_noalloc(config: jfnk_config, prob: DeviceProblem, ne, phi, ne_prev=None, phi_prev=None, stream=None,
+                 stats: Optional[Stats] = None, ne_out=None, phi_out=None):
+    """One batched step without a context (jfnk_step_noalloc: the workspace
+    is the library's static device array).  Returns (rc, stats, message)."""
+    p = prob.cstruct()
+    s = Solver._state(ne, phi, ne_prev, phi_prev, ne_out, phi_out)
+    st = stats if stats is not None else Stats(prob.ncols)
+    msg = C.create_string_buffer(256)
+    rc = lib().jfnk_step_noalloc(C.byref(config), C.byref(p), C.byref(s), C.byref(st.cstruct()),
+                                 _stream_ptr(stream), msg, len(msg))
+    return rc, st, msg.value.decode()
 
 
 def config_for(packed, **kw) -> jfnk_config:
