@@ -80,8 +80,23 @@ enum { JFNK_PREC_FP64 = 0, JFNK_PREC_FP32 = 1 };
    variables, GMRES on S_F^-1 J S_X itself), the baseline of the paper's
    comparison of preconditioned and unpreconditioned iteration counts
    (Section 3.2); the error estimate then equals the scaled residual, and
-   simplified-Newton steps are not taken (chord_tol is ignored). */
-enum { JFNK_PRECK_BLOCK = 0, JFNK_PRECK_SCHUR = 1, JFNK_PRECK_NONE = 2 };
+   simplified-Newton steps are not taken (chord_tol is ignored).
+   SCHUR_MG: SCHUR with the two scalar tridiagonal blocks (dt D_f - I and S~)
+   solved by multigrid V-cycles to the tolerance mg_tol, as the paper does
+   (Section 3.2): vertex-centred coarsening by two, Galerkin coarse
+   operators P^T A P with restriction P^T, two red-black Gauss-Seidel sweeps
+   before and after the coarse correction on every level, a direct solve on
+   levels of at most 7 points; V-cycles repeat until ||b - A x||_2 <=
+   mg_tol ||b||_2 (at most 200).  mg_blocks selects the blocks solved this
+   way (bit 0: the electron block dt D_f - I, bit 1: S~); the others are
+   solved exactly.  mg_transfer selects the interpolation P per block (bit
+   set: matrix-dependent, the weights -a_i/b_i, -c_i/b_i of the operator's
+   own row at the odd point; clear: linear, 1/2 and 1/2).  With linear
+   interpolation the V-cycle diverges on the electron block wherever the
+   cell Peclet number is large (its Galerkin coarse operators lose diagonal
+   dominance); with matrix-dependent interpolation one V-cycle is an exact
+   solve in 1D. */
+enum { JFNK_PRECK_BLOCK = 0, JFNK_PRECK_SCHUR = 1, JFNK_PRECK_NONE = 2, JFNK_PRECK_SCHUR_MG = 3 };
 /* PLAIN: one column at a time, every phase a launch, control on the host.
    BATCHED: three launches per step (gather, solve, write-back); the solve
    launch runs the whole step of every column, control on the GPU. */
@@ -124,6 +139,9 @@ typedef struct {
     int32_t schedule;            /* JFNK_SCHED_* */
     int32_t threads_override;    /* 0: autotuned; else workgroup size per column */
     int32_t prec_kind;           /* JFNK_PRECK_* */
+    double mg_tol;               /* SCHUR_MG: V-cycle tolerance gamma_MG (0 < mg_tol < 1) */
+    int32_t mg_blocks;           /* SCHUR_MG: 1, 2 or 3 (blocks solved by multigrid) */
+    int32_t mg_transfer;         /* SCHUR_MG: 0..3 (blocks with matrix-dependent interpolation) */
 } jfnk_config;
 
 /* One step's problem: ncols columns packed back to back. */
@@ -185,11 +203,15 @@ typedef struct {
                                     re-read of w), every basis vector a CGS pass
                                     projects out (plus a re-read of w past the
                                     eighth), every vector summed into a direction. */
+    int32_t *mg_cycles;          /* multigrid V-cycles of the step (SCHUR_MG; else 0) */
 } jfnk_stats;
 
 /* Fill cfg with the defaults: restart 30, 5 restarts, 50 Newton iterations,
    10 backtracks, tol_f 1e-10, tol_x 1e-10, gamma 1e-4, ls_theta 0.25,
-   chord_tol 1e-3, FP32 preconditioner, extrapolated guess, batched schedule. */
+   chord_tol 1e-3, FP32 preconditioner, extrapolated guess, batched schedule,
+   BLOCK preconditioner; mg_tol 1e-4 (the paper's gamma_MG, Table 2), both
+   blocks by multigrid when SCHUR_MG is chosen, the electron block with
+   matrix-dependent and S~ with linear interpolation (mg_transfer 1). */
 void jfnk_config_default(jfnk_config *cfg);
 
 /* Allocate a context and its workspace on the current HIP device for the

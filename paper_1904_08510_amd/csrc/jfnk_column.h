@@ -701,6 +701,7 @@ struct Column {
                 ColState* cs = W.cst + cd.index;
                 cs->sfn = cs->sfp = cs->sxn = cs->sxp = 1.0;
                 cs->fac_valid = 0;
+                cs->mg_cycles = 0;
             }
             Norms r;
             r.rinf = NAN; r.r2 = NAN; r.xn2 = 0.0; r.step = INFINITY;
@@ -835,6 +836,7 @@ struct Column {
             ColState* cs = W.cst + cd.index;
             cs->sfn = sfn; cs->sfp = sfp; cs->sxn = sxn; cs->sxp = sxp;
             cs->rR = rR; cs->gR = gR; cs->wR = wR;
+            cs->mg_cycles = 0;
         }
         return best;
     }
@@ -949,7 +951,7 @@ struct Column {
                 } else {
                     C = bzero();
                 }
-                if (prm.prec_kind == 1) {
+                if (prm.prec_kind == 1 || prm.prec_kind == 3) {
                     // eq:prec_recast: keep the couplings dt D_r (row of F_e in phi)
                     // and I_e (F_phi in n, diagonal) for the apply, and factor
                     // diag(dt D_f - I, S~) with S~ = L + I_e dt D_r, the Schur
@@ -960,12 +962,17 @@ struct Column {
                     A = Blk<double>{A.a, 0.0, 0.0, A.d + kap * A.b};
                     C = Blk<double>{C.a, 0.0, 0.0, C.d + kap * C.b};
                     B = Blk<double>{B.a, 0.0, 0.0, B.d + kap * B.b};
+                    if (prm.prec_kind == 3) {
+                        // the two scalar tridiagonal blocks on the multigrid's finest level
+                        mgf(0)[c] = A.a; mgf(1)[c] = B.a; mgf(2)[c] = C.a;
+                        mgf(3)[c] = A.d; mgf(4)[c] = B.d; mgf(5)[c] = C.d;
+                    }
                 }
                 rowproc(j, s, A, B, C);
             },
             [&](int64_t s) {
                 const int j = (int)((s - cd.ws) / T);
-                if (prm.prec_kind == 1) {
+                if (prm.prec_kind == 1 || prm.prec_kind == 3) {
                     *(V4<FT>*)facp(20, s) = V4<FT>{FT(0), FT(0), FT(0), FT(0)};
                 }
                 rowproc(j, s, bzero(), beye(), bzero());
@@ -1081,6 +1088,225 @@ struct Column {
             cs->fac_valid = 1;
             cs->fsfn = sfn; cs->fsfp = sfp; cs->fsxn = sxn; cs->fsxp = sxp;
         }
+        if (prm.prec_kind == 3) mg_build();
+        __syncthreads();
+    }
+
+    // ------------------------------------------------------------------
+    // Multigrid V-cycles for the two scalar tridiagonal blocks of the
+    // approximate Schur preconditioner (eq:prec_recast), as the paper solves
+    // them (Section 3.2): vertex-centred coarsening by two (coarse point I is
+    // fine point 2I), linear interpolation P, Galerkin coarse operators
+    // P^T A P (tridiagonal again in 1D), restriction P^T, two red-black
+    // Gauss-Seidel sweeps before and after each coarse correction, a direct
+    // solve on a level of at most kMgCoarse points.  Natural-layout arrays of
+    // this column (level l + 1 follows level l), field k of mgf(k): 0-2 the
+    // electron block's sub-, main and super-diagonal, 3-5 those of S~, 6 the
+    // iterate, 7 the right-hand side, 8 the residual.
+    // ------------------------------------------------------------------
+    static constexpr int kMgMaxLevels = 32;   // ceil(n / 2^31) <= kMgCoarse for any int n
+
+    __device__ __forceinline__ double* mgf(int k) const {
+        return W.mg + (int64_t)k * W.mgP + 2 * cd.ws + 64 * (int64_t)cd.index;
+    }
+    // level sizes and offsets; returns the number of levels
+    __device__ int mg_shape(int* len, int* off) const {
+        int L = 0, n = cd.n, o = 0;
+        for (;;) {
+            len[L] = n; off[L] = o; ++L;
+            if (n <= kMgCoarse || L == kMgMaxLevels) break;
+            o += n;
+            n = (n + 1) >> 1;
+        }
+        return L;
+    }
+    // Interpolation weights of odd fine point i (between coarse points i/2
+    // and i/2 + 1) on a level with rows (a, b, c) and nc coarse points:
+    // linear (1/2, 1/2), or matrix-dependent (-a_i/b_i, -c_i/b_i: the value
+    // row i of the operator gives from its two neighbours, de Zeeuw's
+    // black-box transfer).  The right weight is 0 past the last coarse point.
+    __device__ static __forceinline__ void mg_w(const double* a, const double* b, const double* c, int i, int nc,
+                                                bool md, double& wl, double& wr) {
+        if (md) { wl = -a[i] / b[i]; wr = -c[i] / b[i]; }
+        else { wl = 0.5; wr = 0.5; }
+        if ((i >> 1) + 1 >= nc) wr = 0.0;
+    }
+    // weight of coarse point J in the interpolated value at fine point k
+    __device__ static __forceinline__ double mg_p(const double* a, const double* b, const double* c, int k, int J,
+                                                  int nf, int nc, bool md) {
+        if (k < 0 || k >= nf) return 0.0;
+        if ((k & 1) == 0) return k == 2 * J ? 1.0 : 0.0;
+        double wl, wr;
+        mg_w(a, b, c, k, nc, md, wl, wr);
+        return (k >> 1) == J ? wl : ((k >> 1) + 1 == J ? wr : 0.0);
+    }
+    __device__ void mg_build() {
+        int len[kMgMaxLevels], off[kMgMaxLevels];
+        const int L = mg_shape(len, off);
+        for (int l = 0; l + 1 < L; ++l) {
+            const int nf = len[l], nc = len[l + 1];
+            __syncthreads();
+            for (int blk = 0; blk < 2; ++blk) {
+                const bool md = (prm.mg_transfer >> blk) & 1;
+                const double* fa = mgf(3 * blk) + off[l];
+                const double* fb = mgf(3 * blk + 1) + off[l];
+                const double* fc = mgf(3 * blk + 2) + off[l];
+                double* ca = mgf(3 * blk) + off[l + 1];
+                double* cb = mgf(3 * blk + 1) + off[l + 1];
+                double* cc = mgf(3 * blk + 2) + off[l + 1];
+                // Galerkin: A_c[I][J] = sum_i P[i][I] (A P e_J)[i], rows i = 2I - 1 .. 2I + 1
+                for (int I = t; I < nc; I += T) {
+                    double e[3];
+                    for (int d = -1; d <= 1; ++d) {
+                        const int J = I + d;
+                        double acc = 0.0;
+                        if (J >= 0 && J < nc) {
+                            for (int k = -1; k <= 1; ++k) {
+                                const int i = 2 * I + k;
+                                if (i < 0 || i >= nf) continue;
+                                const double ap = (i > 0 ? fa[i] * mg_p(fa, fb, fc, i - 1, J, nf, nc, md) : 0.0) +
+                                                  fb[i] * mg_p(fa, fb, fc, i, J, nf, nc, md) +
+                                                  (i + 1 < nf ? fc[i] * mg_p(fa, fb, fc, i + 1, J, nf, nc, md) : 0.0);
+                                acc += mg_p(fa, fb, fc, i, I, nf, nc, md) * ap;
+                            }
+                        }
+                        e[d + 1] = acc;
+                    }
+                    ca[I] = e[0]; cb[I] = e[1]; cc[I] = e[2];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // nu red-black Gauss-Seidel sweeps on one level
+    __device__ void mg_smooth(const double* a, const double* b, const double* c, double* x, const double* f,
+                              int n, int nu) {
+        for (int sw = 0; sw < nu; ++sw)
+            for (int color = 0; color < 2; ++color) {
+                for (int i = 2 * t + color; i < n; i += 2 * T) {
+                    double r = f[i];
+                    if (i > 0) r -= a[i] * x[i - 1];
+                    if (i + 1 < n) r -= c[i] * x[i + 1];
+                    x[i] = r / b[i];
+                }
+                __syncthreads();
+            }
+    }
+    // one V-cycle for block blk from the iterate on level 0
+    __device__ void mg_vcycle(int blk, const int* len, const int* off, int L) {
+        double* X = mgf(6);
+        double* Fr = mgf(7);
+        double* R = mgf(8);
+        const double* A = mgf(3 * blk);
+        const double* B = mgf(3 * blk + 1);
+        const double* C = mgf(3 * blk + 2);
+        const bool md = (prm.mg_transfer >> blk) & 1;
+        for (int l = 0; l + 1 < L; ++l) {
+            const int n = len[l], o = off[l], nc = len[l + 1], oc = off[l + 1];
+            mg_smooth(A + o, B + o, C + o, X + o, Fr + o, n, 2);
+            for (int i = t; i < n; i += T) {
+                double r = Fr[o + i] - B[o + i] * X[o + i];
+                if (i > 0) r -= A[o + i] * X[o + i - 1];
+                if (i + 1 < n) r -= C[o + i] * X[o + i + 1];
+                R[o + i] = r;
+            }
+            __syncthreads();
+            // restriction P^T: the coarse point and the odd neighbours' weights on it
+            for (int I = t; I < nc; I += T) {
+                double fcI = R[o + 2 * I];
+                double wl, wr;
+                if (2 * I - 1 >= 0) {
+                    mg_w(A + o, B + o, C + o, 2 * I - 1, nc, md, wl, wr);
+                    fcI += wr * R[o + 2 * I - 1];
+                }
+                if (2 * I + 1 < n) {
+                    mg_w(A + o, B + o, C + o, 2 * I + 1, nc, md, wl, wr);
+                    fcI += wl * R[o + 2 * I + 1];
+                }
+                Fr[oc + I] = fcI;
+                X[oc + I] = 0.0;
+            }
+            __syncthreads();
+        }
+        {
+            // direct solve on the coarsest level (Thomas; the blocks are
+            // diagonally dominant M-matrices, no pivoting needed)
+            const int n = len[L - 1], o = off[L - 1];
+            if (t == 0) {
+                double cp[kMgCoarse + 1], dp[kMgCoarse + 1];
+                cp[0] = C[o] / B[o];
+                dp[0] = Fr[o] / B[o];
+                for (int i = 1; i < n; ++i) {
+                    const double m = B[o + i] - A[o + i] * cp[i - 1];
+                    cp[i] = C[o + i] / m;
+                    dp[i] = (Fr[o + i] - A[o + i] * dp[i - 1]) / m;
+                }
+                X[o + n - 1] = dp[n - 1];
+                for (int i = n - 2; i >= 0; --i) X[o + i] = dp[i] - cp[i] * X[o + i + 1];
+            }
+            __syncthreads();
+        }
+        for (int l = L - 2; l >= 0; --l) {
+            const int n = len[l], o = off[l], nc = len[l + 1], oc = off[l + 1];
+            for (int i = t; i < n; i += T) {
+                double e;
+                if ((i & 1) == 0) {
+                    e = X[oc + (i >> 1)];
+                } else {
+                    double wl, wr;
+                    mg_w(A + o, B + o, C + o, i, nc, md, wl, wr);
+                    e = wl * X[oc + (i >> 1)] + (wr != 0.0 ? wr * X[oc + (i >> 1) + 1] : 0.0);
+                }
+                X[o + i] += e;
+            }
+            __syncthreads();
+            mg_smooth(A + o, B + o, C + o, X + o, Fr + o, n, 2);
+        }
+    }
+    // out = A_blk^-1 (rs * rhs) by V-cycles to ||b - A x||_2 <= mg_tol ||b||_2
+    // (rhs and out: chunk layout; they may alias)
+    __device__ void mg_solve(int blk, CP rhs, double rs, CP out) {
+        int len[kMgMaxLevels], off[kMgMaxLevels];
+        const int L = mg_shape(len, off);
+        const int M = cd.M, n = cd.n;
+        double* X = mgf(6);
+        double* Fr = mgf(7);
+        const double* A = mgf(3 * blk);
+        const double* B = mgf(3 * blk + 1);
+        const double* C = mgf(3 * blk + 2);
+        double bb[1] = {0.0};
+        for (int j = 0; j < M; ++j) {
+            const int c = t * M + j;
+            if (c >= n) break;
+            const double v = rhs[sidx(t, j)] * rs;
+            Fr[c] = v;
+            X[c] = 0.0;
+            bb[0] += v * v;
+        }
+        wg_sum<T, 1>(bb, lds + Lds<T>::kScr);
+        int cyc = 0;
+        if (bb[0] > 0.0) {
+            const double lim = prm.mg_tol * prm.mg_tol * bb[0];
+            while (cyc < kMgMaxCycles) {
+                mg_vcycle(blk, len, off, L);
+                ++cyc;
+                double rr[1] = {0.0};
+                for (int i = t; i < n; i += T) {
+                    double r = Fr[i] - B[i] * X[i];
+                    if (i > 0) r -= A[i] * X[i - 1];
+                    if (i + 1 < n) r -= C[i] * X[i + 1];
+                    rr[0] += r * r;
+                }
+                wg_sum<T, 1>(rr, lds + Lds<T>::kScr);
+                if (rr[0] <= lim) break;
+                if (!(rr[0] <= 1e20 * bb[0])) break;   // diverged (or not finite): stop cycling
+            }
+        }
+        for (int j = 0; j < M; ++j) {
+            const int c = t * M + j;
+            out[sidx(t, j)] = (c < n && cyc > 0) ? X[c] : 0.0;
+        }
+        if (t == 0) W.cst[cd.index].mg_cycles += cyc;
         __syncthreads();
     }
 
@@ -1090,7 +1316,7 @@ struct Column {
     // ------------------------------------------------------------------
     __device__ Vec2<double> apply(const VecRef& v, CP z0, CP z1) {
         if (prm.prec_kind == 2) return apply_identity(v, z0, z1);
-        return prm.prec_kind == 1 ? apply_schur(v, z0, z1) : block_apply(v, z0, z1);
+        return (prm.prec_kind == 1 || prm.prec_kind == 3) ? apply_schur(v, z0, z1) : block_apply(v, z0, z1);
     }
 
     // No preconditioner: z = v (with v's component scales), every row of the
@@ -1121,12 +1347,18 @@ struct Column {
     __device__ Vec2<double> apply_schur(const VecRef& v, CP z0, CP z1) {
         const int M = cd.M, n = cd.n;
         const CP Y0 = schb(0), Y1 = schb(1), Y2 = schb(2), Y3 = schb(3);
-        block_apply(VecRef{v.p0, v.p1, v.s0, 0.0}, Y0, Y1);            // Y0 = z_e'
+        // each block solve: exact (the block factorisation with the other
+        // component of the right-hand side zero) or by multigrid V-cycles
+        const bool mg_n = prm.prec_kind == 3 && (prm.mg_blocks & 1);
+        const bool mg_p = prm.prec_kind == 3 && (prm.mg_blocks & 2);
+        if (mg_n) mg_solve(0, v.p0, v.s0, Y0);
+        else block_apply(VecRef{v.p0, v.p1, v.s0, 0.0}, Y0, Y1);       // Y0 = z_e'
         for (int j = 0; j < M; ++j) {
             const int64_t s = sidx(t, j);
             Y2[s] = v.p1[s] * v.s1 - (double)*facp(23, s) * Y0[s];        // v_phi - I_e z_e'
         }
-        block_apply(VecRef{Y2, Y2, 0.0, 1.0}, Y3, z1);                  // z1 = z_phi
+        if (mg_p) mg_solve(1, Y2, 1.0, z1);
+        else block_apply(VecRef{Y2, Y2, 0.0, 1.0}, Y3, z1);             // z1 = z_phi
         // dt D_r z_phi (tridiagonal; neighbours across chunks are visible after
         // the solve's closing barriers)
         for (int j = 0; j < M; ++j) {
@@ -1140,7 +1372,8 @@ struct Column {
             }
             Y2[s] = w;
         }
-        block_apply(VecRef{Y2, Y2, 1.0, 0.0}, Y3, Y1);                  // Y3 = (dt D_f - I)^-1 dt D_r z_phi
+        if (mg_n) mg_solve(0, Y2, 1.0, Y3);
+        else block_apply(VecRef{Y2, Y2, 1.0, 0.0}, Y3, Y1);             // Y3 = (dt D_f - I)^-1 dt D_r z_phi
         double zz = 0.0, zm = 0.0;
         for (int j = 0; j < M; ++j) {
             const int64_t s = sidx(t, j);

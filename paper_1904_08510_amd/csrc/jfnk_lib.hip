@@ -389,10 +389,10 @@ int choose_T(const jfnk_config& cfg, int nmax) {
 }
 
 // The workspace arrays for P padded cells (a multiple of 64), GMRES restart
-// m, red doubles of per-chunk data and max_cols columns, carved from base in
-// this order; returns the doubles they span.  With base == nullptr only the
-// size is computed (W untouched).
-int64_t carve_work(double* base, int64_t P, int m, int64_t red, int max_cols, Work* W) {
+// m, red doubles of per-chunk data and max_cols columns (and the multigrid
+// arrays when mg), carved from base in this order; returns the doubles they
+// span.  With base == nullptr only the size is computed (W untouched).
+int64_t carve_work(double* base, int64_t P, int m, int64_t red, int max_cols, Work* W, bool mg) {
     int64_t off = 0;
     auto take = [&](int64_t n) { double* r = base ? base + off : nullptr; off += n; return r; };
     Work w{};
@@ -411,6 +411,8 @@ int64_t carve_work(double* base, int64_t P, int m, int64_t red, int max_cols, Wo
     w.cols = (ColDesc*)take((max_cols * (int64_t)sizeof(ColDesc) + 7) / 8);
     w.cst = (ColState*)take((max_cols * (int64_t)sizeof(ColState) + 7) / 8);
     w.scal = take((int64_t)max_cols * kScalSlots);
+    w.mgP = mg ? 2 * P + 64 * (int64_t)max_cols : 0;
+    w.mg = mg ? take(kMgFields * w.mgP) : nullptr;
     if (base && W) {
         w.lmask = W->lmask;
         w.gflag = W->gflag;
@@ -420,7 +422,8 @@ int64_t carve_work(double* base, int64_t P, int m, int64_t red, int max_cols, Wo
 }
 
 void carve(jfnk_ctx* c) {
-    carve_work((double*)c->base, c->capP, c->cfg.gmres_restart, c->capRed, c->cfg.max_cols, &c->W);
+    carve_work((double*)c->base, c->capP, c->cfg.gmres_restart, c->capRed, c->cfg.max_cols, &c->W,
+               c->cfg.prec_kind == JFNK_PRECK_SCHUR_MG);
 }
 
 // The configuration's own checks (those of jfnk_create).
@@ -432,7 +435,10 @@ bool config_valid(const jfnk_config* cfg) {
         !(cfg->chord_tol >= 0.0 && cfg->chord_tol < 1.0) ||
         (cfg->prec_precision != JFNK_PREC_FP64 && cfg->prec_precision != JFNK_PREC_FP32) ||
         (cfg->prec_kind != JFNK_PRECK_BLOCK && cfg->prec_kind != JFNK_PRECK_SCHUR &&
-         cfg->prec_kind != JFNK_PRECK_NONE) ||
+         cfg->prec_kind != JFNK_PRECK_NONE && cfg->prec_kind != JFNK_PRECK_SCHUR_MG) ||
+        (cfg->prec_kind == JFNK_PRECK_SCHUR_MG &&
+         (!(cfg->mg_tol > 0.0 && cfg->mg_tol < 1.0) || cfg->mg_blocks < 1 || cfg->mg_blocks > 3 ||
+          cfg->mg_transfer < 0 || cfg->mg_transfer > 3)) ||
         cfg->guess < 0 || cfg->guess > 2 ||
         (cfg->schedule != JFNK_SCHED_PLAIN && cfg->schedule != JFNK_SCHED_BATCHED))
         return false;
@@ -536,6 +542,9 @@ SolverParams params_of(const jfnk_config& cfg, const jfnk_problem* p, const jfnk
     // without a preconditioner a simplified-Newton step would be a unit
     // Richardson step on the scaled system: none is taken
     s.chord_tol = cfg.prec_kind == JFNK_PRECK_NONE ? 0.0 : cfg.chord_tol;
+    s.mg_tol = cfg.mg_tol;
+    s.mg_blocks = cfg.mg_blocks;
+    s.mg_transfer = cfg.mg_transfer;
     return s;
 }
 
@@ -885,6 +894,7 @@ int gather_stats(jfnk_ctx* ctx, int ncols, jfnk_stats* stt, int* nfail) {
             if (stt->phase_counts)
                 for (int i = 0; i < kWorkCounts; ++i) stt->phase_counts[(int64_t)c * kWorkCounts + i] = s.work[i];
             if (stt->res_scaled) stt->res_scaled[c] = s.res_inf;
+            if (stt->mg_cycles) stt->mg_cycles[c] = s.mg_cycles;
         }
     }
     *nfail = bad;
@@ -1158,6 +1168,9 @@ void jfnk_config_default(jfnk_config* cfg) {
     cfg->schedule = JFNK_SCHED_BATCHED;
     cfg->threads_override = 0;
     cfg->prec_kind = JFNK_PRECK_BLOCK;
+    cfg->mg_tol = 1e-4;
+    cfg->mg_blocks = 3;
+    cfg->mg_transfer = 1;
 }
 
 int jfnk_create(const jfnk_config* cfg, jfnk_ctx** out) {
@@ -1173,7 +1186,8 @@ int jfnk_create(const jfnk_config* cfg, jfnk_ctx** out) {
     // a multiple of 64 cells: every workspace array then starts 512-byte aligned
     ctx->capP = (cfg->max_total_cells + (int64_t)cfg->max_cols * Tcap + 63) / 64 * 64;
     ctx->capRed = (int64_t)cfg->max_cols * Tcap * kRedPerChunk;
-    const int64_t words = carve_work(nullptr, ctx->capP, cfg->gmres_restart, ctx->capRed, cfg->max_cols, nullptr);
+    const int64_t words = carve_work(nullptr, ctx->capP, cfg->gmres_restart, ctx->capRed, cfg->max_cols, nullptr,
+                                     cfg->prec_kind == JFNK_PRECK_SCHUR_MG);
     hipError_t e = hipMalloc((void**)&ctx->base, sizeof(double) * words);
     if (e != hipSuccess) { (void)hipGetLastError(); delete ctx; return JFNK_ENOMEM; }
     carve(ctx);
@@ -1595,7 +1609,8 @@ int jfnk_step_noalloc(const jfnk_config* cfg, const jfnk_problem* p, jfnk_state*
     // bytes: the workspace (as jfnk_create lays it out), then the work order,
     // the write-back table and the gather flags, each 256-byte aligned
     auto up256 = [](int64_t b) { return (b + 255) / 256 * 256; };
-    const int64_t wbytes = up256(8 * carve_work(nullptr, ws, cfg->gmres_restart, red, nc, nullptr));
+    const bool mg = cfg->prec_kind == JFNK_PRECK_SCHUR_MG;
+    const int64_t wbytes = up256(8 * carve_work(nullptr, ws, cfg->gmres_restart, red, nc, nullptr, mg));
     const int64_t obytes = up256(sizeof(int) * (int64_t)nc);
     const int64_t mbytes = up256(sizeof(int32_t) * (int64_t)nmove);
     const int64_t total = wbytes + obytes + 2 * mbytes;
@@ -1608,7 +1623,7 @@ int jfnk_step_noalloc(const jfnk_config* cfg, const jfnk_problem* p, jfnk_state*
     if (!base) return static_fail(err, err_len, JFNK_EHIP, "hipGetSymbolAddress of the scratch array failed");
     hipStream_t st = (hipStream_t)stream;
     Work W{};
-    carve_work((double*)base, ws, cfg->gmres_restart, red, nc, &W);
+    carve_work((double*)base, ws, cfg->gmres_restart, red, nc, &W, mg);
     int* d_order = (int*)(base + wbytes);
     int32_t* d_mcol = (int32_t*)(base + wbytes + obytes);
     W.gflag = (int32_t*)(base + wbytes + obytes + mbytes);
@@ -1659,6 +1674,7 @@ int jfnk_step_noalloc(const jfnk_config* cfg, const jfnk_problem* p, jfnk_state*
             for (int i = 0; i < kWorkCounts; ++i)
                 stt->phase_counts[(int64_t)c * kWorkCounts + i] = i == kWorkLearned ? 0 : s.work[i];
         if (stt->res_scaled) stt->res_scaled[c] = s.res_inf;
+        if (stt->mg_cycles) stt->mg_cycles[c] = s.mg_cycles;
     }
     return bad ? JFNK_NOT_CONVERGED : JFNK_OK;
 }

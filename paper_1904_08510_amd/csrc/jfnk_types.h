@@ -25,6 +25,9 @@ constexpr int kFactorSlots = 24;     // FT values per cell stored by the factori
                                      // (20 block factors + 4 coupling entries of the
                                      // approximate-Schur preconditioner)
 constexpr int kTempSlots = 8;        // FP64 values per cell kept between factor sweeps
+constexpr int kMgFields = 9;         // multigrid arrays per column (see Column::mgf)
+constexpr int kMgCoarse = 7;         // multigrid levels of at most this many points are solved directly
+constexpr int kMgMaxCycles = 200;    // V-cycles per multigrid solve at most
 
 // Per-column counts of the phases a step executed (order of jfnk_stats.phase_counts).
 // kWorkVecReads counts the FP64 vector pairs (16 bytes per cell each) that the
@@ -66,6 +69,7 @@ struct ColState {
     double nrR, ngR, nwR;           // right-wall face coefficients of the coming step (gather launch)
     int32_t nchanged;               // gather launch: a face coefficient differs from the stored factors'
     int32_t cur;                    // workspace buffer holding the column's X^{n+1} after the step
+    int32_t mg_cycles;              // multigrid V-cycles of the step (approximate Schur + MG)
 };
 
 struct SolverParams {
@@ -78,9 +82,13 @@ struct SolverParams {
     int32_t has_learned;    // learned candidate supplied
     int32_t has_u;          // advective face velocities supplied
     int32_t fac_reuse;      // factors left by the previous step may serve this step
-    int32_t prec_kind;      // 0 exact block factorisation, 1 approximate Schur (eq:prec_recast), 2 none
+    int32_t prec_kind;      // 0 exact block factorisation, 1 approximate Schur (eq:prec_recast), 2 none,
+                            // 3 approximate Schur with multigrid block solves
+    int32_t mg_blocks;      // kind 3: bit 0 the electron block, bit 1 the S~ block by multigrid
+    int32_t mg_transfer;    // kind 3: bit k set: block k uses matrix-dependent transfers, else linear
     double tol_f, tol_x, gamma, theta;
     double chord_tol;       // simplified-Newton steps while the error estimate is below this (0: off)
+    double mg_tol;          // kind 3: V-cycles until ||b - A x||_2 <= mg_tol ||b||_2
 };
 
 // Caller arrays (natural layout, device pointers).
@@ -107,6 +115,8 @@ struct Work {
     double *ftmp;                    // kTempSlots x P doubles (factorisation)
     double *red;                     // per-chunk reduced-system data
     double *sch;                     // 4 x P doubles: approximate-Schur apply temporaries
+    double *mg;                      // kMgFields x mgP doubles: multigrid arrays (kind 3 only)
+    int64_t mgP;                     // doubles per multigrid field: 2 P + 64 max_cols
     ColDesc *cols;
     ColState *cst;
     double *scal;                    // per-column scalar exchange (host-driven mode)

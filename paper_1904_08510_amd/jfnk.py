@@ -21,7 +21,7 @@ JFNK_EINVAL, JFNK_ENOMEM, JFNK_EHIP, JFNK_ECAPACITY, JFNK_EMODEL = -1, -2, -3, -
 BC_DIRICHLET, BC_ZERO_FLUX = 0, 1
 GUESS_PREV, GUESS_EXTRAP, GUESS_LEARNED = 0, 1, 2
 PREC_FP64, PREC_FP32 = 0, 1
-PRECK_BLOCK, PRECK_SCHUR, PRECK_NONE = 0, 1, 2
+PRECK_BLOCK, PRECK_SCHUR, PRECK_NONE, PRECK_SCHUR_MG = 0, 1, 2, 3
 SCHED_PLAIN, SCHED_BATCHED = 0, 1
 COL_CONVERGED, COL_MAX_NEWTON, COL_NONFINITE, COL_LINESEARCH, COL_BAD_INPUT = 0, 1, 2, 3, 4
 
@@ -37,7 +37,8 @@ class jfnk_config(C.Structure):
                 ("max_backtracks", C.c_int32), ("tol_f", C.c_double), ("tol_x", C.c_double),
                 ("gamma", C.c_double), ("ls_theta", C.c_double), ("chord_tol", C.c_double),
                 ("prec_precision", C.c_int32), ("guess", C.c_int32), ("schedule", C.c_int32),
-                ("threads_override", C.c_int32), ("prec_kind", C.c_int32)]
+                ("threads_override", C.c_int32), ("prec_kind", C.c_int32), ("mg_tol", C.c_double),
+                ("mg_blocks", C.c_int32), ("mg_transfer", C.c_int32)]
 
 
 class jfnk_problem(C.Structure):
@@ -63,7 +64,7 @@ class jfnk_net_config(C.Structure):
 class jfnk_stats(C.Structure):
     _fields_ = [("status", _ip), ("newton_iters", _ip), ("gmres_iters", _ip),
                 ("backtracks", _ip), ("guess_used", _ip), ("res_scaled", _dp), ("chord_steps", _ip),
-                ("phase_counts", _ip)]
+                ("phase_counts", _ip), ("mg_cycles", _ip)]
 
 
 _LIB = None
@@ -263,6 +264,7 @@ class Stats:
         self.res_scaled = np.zeros(n, np.float64)
         self.chord_steps = np.zeros(n, np.int32)
         self.phase_counts = np.zeros((n, 8), np.int32)
+        self.mg_cycles = np.zeros(n, np.int32)
 
     def __setattr__(self, name, value):
         # an array bound to another object invalidates the cached argument struct
@@ -276,7 +278,7 @@ class Stats:
             return cached
         s = jfnk_stats()
         for name in ("status", "newton_iters", "gmres_iters", "backtracks", "guess_used", "chord_steps",
-                     "phase_counts"):
+                     "phase_counts", "mg_cycles"):
             a = getattr(self, name)
             assert a.dtype == np.int32 and a.flags.c_contiguous
             setattr(s, name, a.ctypes.data_as(_ip))
