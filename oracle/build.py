@@ -13,14 +13,22 @@ SRC = os.path.join(HERE, "jfnk_oracle.c")
 OUT = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose: bool = False) -> str:
+# AddressSanitizer + UndefinedBehaviorSanitizer build of the same source (a
+# host-only library: the oracle has no GPU code), for the sanitizer run of
+# the oracle's pins
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                  "-fno-omit-frame-pointer", "-g"]
+
+
+def build(verbose: bool = False, out: str = OUT, sanitize: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math",
-           "-ffp-contract=off", "-Wall", "-o", OUT + ".tmp", SRC, "-lm"]
+           "-ffp-contract=off", "-Wall", *(SANITIZE_FLAGS if sanitize else []),
+           "-o", out + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(OUT + ".tmp", OUT)
-    return OUT
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

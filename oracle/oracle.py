@@ -45,7 +45,8 @@ class _Stats(C.Structure):
 def lib():
     global _LIB
     if _LIB is None:
-        path = os.path.join(HERE, "liboracle.so")
+        # JFNK_ORACLE_LIB: another build of the same source (the sanitizer run)
+        path = os.environ.get("JFNK_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
         if not os.path.exists(path):
             from . import build as _b  # noqa: F401  (package-relative when imported as oracle.oracle)
             _b.build()
