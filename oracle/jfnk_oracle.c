@@ -26,6 +26,13 @@
  *   P_i = -n_i + q_i + (eps/e)(G_{i+1} - G_i)/h,
  *         G_j = potential difference across face j / face distance
  *                                                       (eq:nls, second row)
+ * With a transport table (Section 2.2: electron mobility and diffusivity as
+ * functions of the progress variable c and the reduced field |E|/N), mu_f and
+ * D_f of face j come from the table at the face's mean c and mean N (the
+ * adjacent cell's at a wall) and |E| = |G_j|, the field the face carries in
+ * the state at hand; the residual then depends on phi through them too, and
+ * Newton uses a finite-difference band Jacobian (central differences, six
+ * colours of the three-cell stencil).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -56,33 +63,38 @@ double orc_bernoulli_deriv(double x)
 }
 
 /* ---------------------------------------------------------------------- */
-/* Face quantities                                                        */
+/* Transport table (Section 2.2)                                          */
 /* ---------------------------------------------------------------------- */
 
-/* Electron flux through face j at state (ne, phi). */
-static double face_flux(const orc_column *c, const double *ne, const double *phi, int j)
+/* Bilinear interpolation of one table at (c, x), both clamped to the grid. */
+static double table_interp(const orc_table *t, const double *v, double cv, double x)
 {
-    const int N = c->n;
-    const double h = c->length / N;
-    double u = c->uface ? c->uface[j] : 0.0;
-    if (j == 0) {
-        if (c->bc_left == ORC_BC_ZERO_FLUX) return 0.0;
-        double hb = 0.5 * h;
-        double pe = (u * hb + c->mu[0] * (phi[0] - c->phi_left)) / c->diff[0];
-        return (c->diff[0] / hb) * (orc_bernoulli(-pe) * c->ne_left - orc_bernoulli(pe) * ne[0]);
-    }
-    if (j == N) {
-        if (c->bc_right == ORC_BC_ZERO_FLUX) return 0.0;
-        double hb = 0.5 * h;
-        double pe = (u * hb + c->mu[N - 1] * (c->phi_right - phi[N - 1])) / c->diff[N - 1];
-        return (c->diff[N - 1] / hb) *
-               (orc_bernoulli(-pe) * ne[N - 1] - orc_bernoulli(pe) * c->ne_right);
-    }
-    double muf = 0.5 * (c->mu[j - 1] + c->mu[j]);
-    double df = 0.5 * (c->diff[j - 1] + c->diff[j]);
-    double pe = (u * h + muf * (phi[j] - phi[j - 1])) / df;
-    return (df / h) * (orc_bernoulli(-pe) * ne[j - 1] - orc_bernoulli(pe) * ne[j]);
+    if (cv < t->c_min) cv = t->c_min;
+    if (cv > t->c_max) cv = t->c_max;
+    if (x < t->x_min) x = t->x_min;
+    if (x > t->x_max) x = t->x_max;
+    double fc = (cv - t->c_min) / (t->c_max - t->c_min) * (t->nc - 1);
+    double fx = (x - t->x_min) / (t->x_max - t->x_min) * (t->nx - 1);
+    int i = (int)floor(fc), k = (int)floor(fx);
+    if (i > t->nc - 2) i = t->nc - 2;
+    if (k > t->nx - 2) k = t->nx - 2;
+    double wc = fc - i, wx = fx - k;
+    const double *r0 = v + (size_t)i * t->nx, *r1 = r0 + t->nx;
+    return (1.0 - wc) * ((1.0 - wx) * r0[k] + wx * r0[k + 1]) + wc * ((1.0 - wx) * r1[k] + wx * r1[k + 1]);
 }
+
+/* mu and D at progress variable c and reduced field en_td (in Townsend,
+   1 Td = 1e-21 V m^2); a zero field takes the table's lowest column. */
+void orc_table_lookup(const orc_table *t, double c, double en_td, double *mu, double *diff)
+{
+    double x = en_td > 0.0 ? log10(en_td) : t->x_min;
+    *mu = table_interp(t, t->mu, c, x);
+    *diff = table_interp(t, t->diff, c, x);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Face quantities                                                        */
+/* ---------------------------------------------------------------------- */
 
 /* Potential gradient across face j. */
 static double face_grad(const orc_column *c, const double *phi, int j)
@@ -92,6 +104,52 @@ static double face_grad(const orc_column *c, const double *phi, int j)
     if (j == 0) return (phi[0] - c->phi_left) / (0.5 * h);
     if (j == N) return (c->phi_right - phi[N - 1]) / (0.5 * h);
     return (phi[j] - phi[j - 1]) / h;
+}
+
+/* Mobility and diffusivity of face j in state phi: the arithmetic means of
+   the two cells' values (a wall face: the adjacent cell's), or the table at
+   the face's progress variable and reduced field |E| / N. */
+static void face_mu_d(const orc_column *c, const double *phi, int j, double *mu, double *d)
+{
+    const int N = c->n;
+    int a = j == 0 ? 0 : j - 1, b = j == N ? N - 1 : j;
+    if (!c->table) {
+        *mu = 0.5 * (c->mu[a] + c->mu[b]);
+        *d = 0.5 * (c->diff[a] + c->diff[b]);
+        return;
+    }
+    double cf = 0.5 * (c->prog[a] + c->prog[b]);
+    double nf = 0.5 * (c->gas_n[a] + c->gas_n[b]);
+    double e = fabs(face_grad(c, phi, j));
+    orc_table_lookup(c->table, cf, e / nf / 1e-21, mu, d);
+}
+
+void orc_face_coeffs(const orc_column *c, const double *phi, double *mu, double *diff)
+{
+    for (int j = 0; j <= c->n; ++j) face_mu_d(c, phi, j, mu + j, diff + j);
+}
+
+/* Electron flux through face j at state (ne, phi). */
+static double face_flux(const orc_column *c, const double *ne, const double *phi, int j)
+{
+    const int N = c->n;
+    const double h = c->length / N;
+    double u = c->uface ? c->uface[j] : 0.0;
+    double muf, df;
+    if ((j == 0 && c->bc_left == ORC_BC_ZERO_FLUX) || (j == N && c->bc_right == ORC_BC_ZERO_FLUX)) return 0.0;
+    face_mu_d(c, phi, j, &muf, &df);
+    if (j == 0) {
+        double hb = 0.5 * h;
+        double pe = (u * hb + muf * (phi[0] - c->phi_left)) / df;
+        return (df / hb) * (orc_bernoulli(-pe) * c->ne_left - orc_bernoulli(pe) * ne[0]);
+    }
+    if (j == N) {
+        double hb = 0.5 * h;
+        double pe = (u * hb + muf * (c->phi_right - phi[N - 1])) / df;
+        return (df / hb) * (orc_bernoulli(-pe) * ne[N - 1] - orc_bernoulli(pe) * c->ne_right);
+    }
+    double pe = (u * h + muf * (phi[j] - phi[j - 1])) / df;
+    return (df / h) * (orc_bernoulli(-pe) * ne[j - 1] - orc_bernoulli(pe) * ne[j]);
 }
 
 void orc_face_fluxes(const orc_column *c, const double *ne, const double *phi, double *gamma)
@@ -146,22 +204,23 @@ void orc_scalings(const orc_column *c, double s[4])
     double *mag = (double *)malloc(sizeof(double) * (N + 1));
     for (int j = 0; j <= N; ++j) {
         double u = c->uface ? c->uface[j] : 0.0;
-        double dfac, pe, na, nb;
+        double dfac, pe, na, nb, muf, df;
+        if ((j == 0 && c->bc_left == ORC_BC_ZERO_FLUX) || (j == N && c->bc_right == ORC_BC_ZERO_FLUX)) {
+            mag[j] = 0.0;
+            continue;
+        }
+        face_mu_d(c, phi, j, &muf, &df);
         if (j == 0) {
-            if (c->bc_left == ORC_BC_ZERO_FLUX) { mag[j] = 0.0; continue; }
             double hb = 0.5 * h;
-            pe = (u * hb + c->mu[0] * (phi[0] - c->phi_left)) / c->diff[0];
-            dfac = c->diff[0] / hb;
+            pe = (u * hb + muf * (phi[0] - c->phi_left)) / df;
+            dfac = df / hb;
             na = c->ne_left; nb = ne[0];
         } else if (j == N) {
-            if (c->bc_right == ORC_BC_ZERO_FLUX) { mag[j] = 0.0; continue; }
             double hb = 0.5 * h;
-            pe = (u * hb + c->mu[N - 1] * (c->phi_right - phi[N - 1])) / c->diff[N - 1];
-            dfac = c->diff[N - 1] / hb;
+            pe = (u * hb + muf * (c->phi_right - phi[N - 1])) / df;
+            dfac = df / hb;
             na = ne[N - 1]; nb = c->ne_right;
         } else {
-            double muf = 0.5 * (c->mu[j - 1] + c->mu[j]);
-            double df = 0.5 * (c->diff[j - 1] + c->diff[j]);
             pe = (u * h + muf * (phi[j] - phi[j - 1])) / df;
             dfac = df / h;
             na = ne[j - 1]; nb = ne[j];
@@ -271,6 +330,49 @@ static void jacobian_generic(const orc_column *c, const double *ne, const double
     }
 }
 
+/* Table mode: the Jacobian by central differences of the residual.  The
+   residual of cell i depends on cells i-1, i, i+1 only, so perturbing every
+   third cell in one component at once (six colours) gives every column of
+   the band without overlap.  Step: 1e-6 of the component's magnitude at the
+   cell (its scale s_X at least). */
+static void jacobian_fd(const orc_column *c, const double *ne, const double *phi, setter_fn set, void *ctx)
+{
+    const int N = c->n;
+    double s[4];
+    orc_scalings(c, s);
+    double *f = (double *)malloc(sizeof(double) * N);
+    double *xn = (double *)malloc(sizeof(double) * N);
+    double *xp = (double *)malloc(sizeof(double) * N);
+    double *ep = (double *)malloc(sizeof(double) * 2 * N);
+    double *em = (double *)malloc(sizeof(double) * 2 * N);
+    double *del = (double *)malloc(sizeof(double) * N);
+    orc_source_term(c, f);
+    for (int comp = 0; comp < 2; ++comp) {
+        for (int col = 0; col < 3; ++col) {
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                memcpy(xn, ne, sizeof(double) * N);
+                memcpy(xp, phi, sizeof(double) * N);
+                for (int p = col; p < N; p += 3) {
+                    double *x = comp == 0 ? xn : xp;
+                    double scale = comp == 0 ? s[2] : s[3];
+                    del[p] = 1e-6 * (fabs(x[p]) > scale ? fabs(x[p]) : scale);
+                    x[p] += sgn == 0 ? del[p] : -del[p];
+                }
+                orc_residual(c, f, xn, xp, sgn == 0 ? ep : ep + N, sgn == 0 ? em : em + N);
+            }
+            /* ep[0..N): F_e(+), ep[N..2N): F_e(-); em likewise for F_phi */
+            for (int p = col; p < N; p += 3) {
+                for (int i = p - 1; i <= p + 1; ++i) {
+                    if (i < 0 || i >= N) continue;
+                    set(ctx, 2 * i, 2 * p + comp, (ep[i] - ep[N + i]) / (2.0 * del[p]));
+                    set(ctx, 2 * i + 1, 2 * p + comp, (em[i] - em[N + i]) / (2.0 * del[p]));
+                }
+            }
+        }
+    }
+    free(f); free(xn); free(xp); free(ep); free(em); free(del);
+}
+
 typedef struct { double *a; int n; } dense_ctx;
 static void set_dense(void *p, int r, int col, double v)
 {
@@ -283,7 +385,8 @@ void orc_jacobian_dense(const orc_column *c, const double *ne, const double *phi
     int n2 = 2 * c->n;
     memset(a, 0, sizeof(double) * (size_t)n2 * n2);
     dense_ctx d = { a, n2 };
-    jacobian_generic(c, ne, phi, set_dense, &d);
+    if (c->table) jacobian_fd(c, ne, phi, set_dense, &d);
+    else jacobian_generic(c, ne, phi, set_dense, &d);
 }
 
 /* Band storage by rows: A(i, j) at ab[i * ORC_BAND_W + (j - i + ORC_KL)],
@@ -300,7 +403,8 @@ void orc_jacobian_band(const orc_column *c, const double *ne, const double *phi,
 {
     memset(ab, 0, sizeof(double) * (size_t)2 * c->n * ORC_BAND_W);
     band_ctx b = { ab };
-    jacobian_generic(c, ne, phi, set_band, &b);
+    if (c->table) jacobian_fd(c, ne, phi, set_band, &b);
+    else jacobian_generic(c, ne, phi, set_band, &b);
 }
 
 /* ---------------------------------------------------------------------- */

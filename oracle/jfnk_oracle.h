@@ -18,6 +18,16 @@
 
 enum { ORC_CONVERGED = 0, ORC_MAX_ITERS = 1, ORC_NONFINITE = 2, ORC_SINGULAR = 3 };
 
+/* Electron transport table (Section 2.2): mobility and diffusivity on a
+   uniform grid of the progress variable c (nc points on [c_min, c_max]) and
+   of x = log10(|E|/N / 1 Td) (nx points on [x_min, x_max]), row-major
+   [nc][nx]; bilinear interpolation, both arguments clamped to the grid. */
+typedef struct {
+    int nc, nx;
+    double c_min, c_max, x_min, x_max;
+    const double *mu, *diff;
+} orc_table;
+
 typedef struct {
     int n;                       /* cells */
     double length;               /* m */
@@ -34,6 +44,9 @@ typedef struct {
     const double *uface;         /* [n+1] advective velocity at faces (NULL = 0) */
     const double *ne_old;        /* [n] n^n */
     const double *phi_old;       /* [n] phi^n */
+    const orc_table *table;      /* NULL: per-cell mu, diff; else face mu, D from the table */
+    const double *prog;          /* [n] progress variable (table only) */
+    const double *gas_n;         /* [n] background gas number density, m^-3 (table only) */
 } orc_column;
 
 typedef struct {
@@ -54,6 +67,8 @@ typedef struct {
 } orc_newton_stats;
 
 double orc_bernoulli(double x);
+void orc_table_lookup(const orc_table *t, double c, double en_td, double *mu, double *diff);
+void orc_face_coeffs(const orc_column *c, const double *phi, double *mu, double *diff);
 double orc_bernoulli_deriv(double x);
 void orc_source_term(const orc_column *c, double *f);
 void orc_face_fluxes(const orc_column *c, const double *ne, const double *phi, double *gamma);

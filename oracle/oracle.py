@@ -22,13 +22,19 @@ CONVERGED, MAX_ITERS, NONFINITE, SINGULAR = 0, 1, 2, 3
 _dp = C.POINTER(C.c_double)
 
 
+class _Table(C.Structure):
+    _fields_ = [("nc", C.c_int), ("nx", C.c_int), ("c_min", C.c_double), ("c_max", C.c_double),
+                ("x_min", C.c_double), ("x_max", C.c_double), ("mu", _dp), ("diff", _dp)]
+
+
 class _Column(C.Structure):
     _fields_ = [("n", C.c_int), ("length", C.c_double), ("dt", C.c_double),
                 ("phi_left", C.c_double), ("phi_right", C.c_double),
                 ("eps_over_e", C.c_double), ("bc_left", C.c_int), ("bc_right", C.c_int),
                 ("ne_left", C.c_double), ("ne_right", C.c_double),
                 ("mu", _dp), ("diff", _dp), ("src", _dp), ("kloss", _dp), ("q", _dp),
-                ("uface", _dp), ("ne_old", _dp), ("phi_old", _dp)]
+                ("uface", _dp), ("ne_old", _dp), ("phi_old", _dp), ("table", C.POINTER(_Table)),
+                ("prog", _dp), ("gas_n", _dp)]
 
 
 class _Opts(C.Structure):
@@ -66,6 +72,10 @@ def lib():
         L.orc_band_solve.argtypes = [C.c_int, _dp, _dp]
         L.orc_dense_solve.restype = C.c_int
         L.orc_dense_solve.argtypes = [C.c_int, _dp, _dp]
+        L.orc_table_lookup.argtypes = [C.POINTER(_Table), C.c_double, C.c_double, _dp, _dp]
+        L.orc_table_lookup.restype = None
+        L.orc_face_coeffs.argtypes = [C.POINTER(_Column), _dp, _dp, _dp]
+        L.orc_face_coeffs.restype = None
         L.orc_newton.restype = C.c_int
         L.orc_newton.argtypes = [C.POINTER(_Column), C.POINTER(_Opts), _dp, _dp,
                                  C.POINTER(_Stats)]
@@ -102,15 +112,47 @@ class OracleColumn:
         self.uface = arr(getattr(col, "uface", None))
         self.ne_old = arr(col.ne if ne_old is None else ne_old)
         self.phi_old = arr(col.phi if phi_old is None else phi_old)
+        tab = getattr(col, "table", None)
+        self.table = None if tab is None else table_struct(tab, self._keep)
+        self.prog = arr(getattr(col, "prog", None))
+        self.gas_n = arr(getattr(col, "gas_n", None))
         self.s = _Column(col.n, col.length, col.dt, col.phi_left, col.phi_right,
                          col.eps_over_e, col.bc_left, col.bc_right, col.ne_left,
                          col.ne_right, _p(self.mu), _p(self.diff), _p(self.src),
                          _p(self.kloss), _p(self.q), _p(self.uface), _p(self.ne_old),
-                         _p(self.phi_old))
+                         _p(self.phi_old),
+                         C.pointer(self.table) if self.table is not None else C.cast(None, C.POINTER(_Table)),
+                         _p(self.prog), _p(self.gas_n))
 
     @property
     def n(self):
         return self.col.n
+
+
+def table_struct(tab, keep) -> _Table:
+    """The C struct of a transport table (arrays kept alive in keep)."""
+    mu = np.ascontiguousarray(tab.mu, dtype=np.float64)
+    d = np.ascontiguousarray(tab.diff, dtype=np.float64)
+    keep += [mu, d]
+    return _Table(mu.shape[0], mu.shape[1], tab.c_min, tab.c_max, tab.x_min, tab.x_max, _p(mu), _p(d))
+
+
+def table_lookup(tab, c: float, en_td: float):
+    """(mu, D) of the table at progress variable c and reduced field en_td (Td)."""
+    keep = []
+    t = table_struct(tab, keep)
+    mu, d = C.c_double(), C.c_double()
+    lib().orc_table_lookup(C.byref(t), float(c), float(en_td), C.byref(mu), C.byref(d))
+    return mu.value, d.value
+
+
+def face_coeffs(oc: OracleColumn, phi):
+    """(mu_f, D_f) of every face (n + 1) in state phi."""
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    mu = np.empty(oc.n + 1)
+    d = np.empty(oc.n + 1)
+    lib().orc_face_coeffs(C.byref(oc.s), _p(phi), _p(mu), _p(d))
+    return mu, d
 
 
 def bernoulli(x: float) -> float:

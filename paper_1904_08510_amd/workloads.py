@@ -63,6 +63,11 @@ class Column:
     ne_right: float = 0.0
     ne_prev: Optional[np.ndarray] = None
     phi_prev: Optional[np.ndarray] = None
+    # field-dependent electron transport (see TransportTable): with a table,
+    # mu and D of every face come from it and mu, diff above are not used
+    table: Optional["TransportTable"] = None
+    prog: Optional[np.ndarray] = None      # progress variable per cell
+    gas_n: Optional[np.ndarray] = None     # background gas number density, m^-3
     meta: dict = field(default_factory=dict)
 
     def copy(self) -> "Column":
@@ -70,6 +75,59 @@ class Column:
                       for k, v in self.__dict__.items() if k != "meta"})
         c.meta = dict(self.meta)
         return c
+
+
+@dataclass
+class TransportTable:
+    """Electron mobility and diffusivity tabulated against the progress
+    variable c (nc points on [c_min, c_max]) and x = log10(|E|/N / 1 Td)
+    (nx points on [x_min, x_max]); arrays [nc, nx] (the shape of the paper's
+    BOLSIG+ tables, Section 2.2, whose data are not available here)."""
+    c_min: float
+    c_max: float
+    x_min: float
+    x_max: float
+    mu: np.ndarray
+    diff: np.ndarray
+
+    @property
+    def nc(self) -> int:
+        return int(self.mu.shape[0])
+
+    @property
+    def nx(self) -> int:
+        return int(self.mu.shape[1])
+
+
+T_IN, T_MAX, PRESSURE = 300.0, 2000.0, 101325.0
+
+
+def synthetic_transport_table(nc: int = 17, nx: int = 41) -> TransportTable:
+    """A smooth stand-in for the paper's non-thermal electron transport
+    tables: at low reduced field the thermal values of the workloads
+    (mu = 0.4 T/300, D = mu k_B T/e at T = T_in + c (T_max - T_in)); above
+    ~3 Td the electrons heat up: mobility falls by up to 60 % and the
+    electron temperature in D = mu k_B T_e / e rises by up to 2e4 K, with a
+    logistic switch in log10(|E|/N) centred at 0.5."""
+    c = np.linspace(0.0, 1.0, nc)
+    x = np.linspace(-2.0, 3.0, nx)
+    temp = T_IN + c[:, None] * (T_MAX - T_IN)
+    w = 1.0 / (1.0 + np.exp(-3.0 * (x[None, :] - 0.5)))
+    mu = 0.4 * temp / 300.0 * (1.0 - 0.6 * w)
+    te = temp + 2e4 * w
+    diff = mu * K_BOLTZMANN * te / E_CHARGE
+    return TransportTable(0.0, 1.0, -2.0, 3.0, np.ascontiguousarray(mu), np.ascontiguousarray(diff))
+
+
+def with_transport_table(col: "Column", table: TransportTable) -> "Column":
+    """The column with table transport: progress variable from its gas
+    temperature, c = (T - T_in)/(T_max - T_in) (Section 2.2), and the ideal-gas
+    number density N = p / (k_B T) at atmospheric pressure."""
+    c = col.copy()
+    c.table = table
+    c.prog = np.clip((col.temp - T_IN) / (T_MAX - T_IN), 0.0, 1.0)
+    c.gas_n = PRESSURE / (K_BOLTZMANN * col.temp)
+    return c
 
 
 def cell_centres(n: int, length: float) -> np.ndarray:
