@@ -32,7 +32,8 @@
  * hold the last accepted iterate.  Per-cell inputs live on the device and are
  * checked there: a column with a cell outside the problem's domain (mu < 0,
  * D <= 0, k_loss < 0, or a non-finite mu, D, source, k_loss, ion charge,
- * face velocity, n^k or phi^k) is not iterated, gets status
+ * face velocity, n^k or phi^k; with a transport table a non-finite c or a
+ * gas density N <= 0 in place of mu and D) is not iterated, gets status
  * JFNK_COL_BAD_INPUT and keeps X^k; the call then returns
  * JFNK_NOT_CONVERGED.  jfnk_last_error gives a message.
  *
@@ -144,6 +145,27 @@ typedef struct {
     int32_t mg_transfer;         /* SCHUR_MG: 0..3 (blocks with matrix-dependent interpolation) */
 } jfnk_config;
 
+/* Electron transport table (Section 2.2: electron mobility and diffusivity
+   as functions of the progress variable c and of the reduced field |E|/N,
+   the paper's BOLSIG+ tables).  Values on uniform grids: nc points of c on
+   [c_min, c_max] and nx points of x = log10(|E|/N / 1 Td) on [x_min, x_max]
+   (1 Td = 1e-21 V m^2); nc, nx >= 2, c_max > c_min, x_max > x_min.  mu and
+   diff: DEVICE [nc][nx] row-major (m^2/(V s), m^2/s), mu >= 0, diff > 0.
+   With a table, mu_f and D_f of every face are read from it (bilinear,
+   both arguments clamped to the grid, a zero field reading the x_min column)
+   at the face's mean c and mean gas density N (the adjacent cell's at a wall)
+   and at the field the face carries in the state being evaluated, |E| = the
+   potential difference over the face distance (h, h/2 at a wall); the
+   residual then depends on phi through them as well.  The finite-difference
+   J.v products see that dependence; the preconditioner's Jacobian holds the
+   coefficients at the state's field (their derivative is left out), and
+   factors are not kept from one step to the next. */
+typedef struct {
+    int32_t nc, nx;
+    double c_min, c_max, x_min, x_max;
+    const double *mu, *diff;
+} jfnk_table;
+
 /* One step's problem: ncols columns packed back to back. */
 typedef struct {
     int32_t ncols;
@@ -167,6 +189,11 @@ typedef struct {
                                     n+1 faces start at col_offset[c] + c), m/s
                                     (NULL: 0) */
     const double *temp;          /* [total] gas temperature, K (learned guess) */
+    const jfnk_table *table;     /* HOST struct; NULL: mu and diff per cell (above);
+                                    else face mu, D from the table and mu, diff
+                                    are not read (may be NULL) */
+    const double *prog;          /* [total] progress variable c (table only) */
+    const double *gas_n;         /* [total] gas number density N > 0, m^-3 (table only) */
 } jfnk_problem;
 
 typedef struct {

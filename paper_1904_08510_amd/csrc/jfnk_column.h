@@ -89,6 +89,46 @@ __device__ __forceinline__ void bernoulli_dpair(double x, double bx, double bmx,
 }
 
 // ---------------------------------------------------------------------------
+// Face coefficients.  A face record holds (a, b, c); the Scharfetter-Gummel
+// flux needs r = mu_f/D_f, g = D_f/h_f and w = u_f h_f/D_f.  Per-cell
+// transport: the record is (r, g, w) itself.  Table transport (Section 2.2):
+// the record is (mean progress variable, mean gas number density N (0 at a
+// zero-flux wall), u_f h_f), and mu_f, D_f are read from the table at the
+// face's reduced field |E|/N = |dphi| / (h_f N) (bilinear, clamped to the
+// grid; a zero field reads the lowest column) in the state at hand.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double tab_interp(const TabRef& t, const double* v, int i, int k, double wc,
+                                             double wx) {
+    const double* r0 = v + (int64_t)i * t.nx;
+    const double* r1 = r0 + t.nx;
+    return (1.0 - wc) * ((1.0 - wx) * r0[k] + wx * r0[k + 1]) + wc * ((1.0 - wx) * r1[k] + wx * r1[k + 1]);
+}
+
+template <bool TAB>
+__device__ __forceinline__ void face_rgw(const TabRef& t, double a, double b, double c, double ihf, double dphi,
+                                         double& r, double& g, double& w) {
+    if constexpr (!TAB) {
+        r = a; g = b; w = c;
+    } else {
+        if (!(b > 0.0)) { r = 0.0; g = 0.0; w = 0.0; return; }
+        const double en = fabs(dphi) * ihf / b * 1e21;          // reduced field in Td
+        double x = en > 0.0 ? log10(en) : t.x_min;
+        x = fmin(fmax(x, t.x_min), t.x_max);
+        const double cv = fmin(fmax(a, t.c_min), t.c_max);
+        const double fc = (cv - t.c_min) / (t.c_max - t.c_min) * (t.nc - 1);
+        const double fx = (x - t.x_min) / (t.x_max - t.x_min) * (t.nx - 1);
+        const int i = min((int)floor(fc), t.nc - 2);
+        const int k = min((int)floor(fx), t.nx - 2);
+        const double wc = fc - i, wx = fx - k;
+        const double mu = tab_interp(t, t.mu, i, k, wc, wx);
+        const double d = tab_interp(t, t.diff, i, k, wc, wx);
+        r = mu / d;
+        g = d * ihf;
+        w = c / d;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Workgroup reductions (wave64 butterflies + LDS across waves).  Fixed order:
 // bitwise reproducible from run to run.
 // ---------------------------------------------------------------------------
@@ -199,7 +239,7 @@ struct Lds {
 // ---------------------------------------------------------------------------
 // The column object: phases over the column owned by this workgroup.
 // ---------------------------------------------------------------------------
-template <int T, class FT>
+template <int T, class FT, bool TAB = false>
 struct Column {
     ColDesc cd;
     Work W;
@@ -416,8 +456,11 @@ struct Column {
 
     // electron flux and potential gradient of one face
     struct FluxFace {
-        __device__ __forceinline__ FluxRec operator()(double r, double g, double w, double ihf,
+        TabRef tb;
+        __device__ __forceinline__ FluxRec operator()(double fa, double fb, double fc, double ihf,
                                                       double nA, double pA, double nB, double pB) const {
+            double r, g, w;
+            face_rgw<TAB>(tb, fa, fb, fc, ihf, pB - pA, r, g, w);
             const double pe = w + r * (pB - pA);
             double bx, bmx;
             bernoulli_pair(pe, bx, bmx);
@@ -444,7 +487,7 @@ struct Column {
         const CP dp0 = wantstep ? stepdir.p0 : xb(0, 0);
         const CP dp1 = wantstep ? stepdir.p1 : xb(0, 1);
         struct Own { double f, k, q, d0, d1; };
-        sweep<2, FluxRec>(getx, FluxFace{},
+        sweep<2, FluxRec>(getx, FluxFace{prm.tab},
             [&](int64_t s) {
                 Own o;
                 o.f = fv[s]; o.k = kv[s]; o.q = qv[s];
@@ -551,8 +594,11 @@ struct Column {
                 }
                 if (k < ke && j < M && c < n) {
                     const int64_t u = cd.uoff + c;
-                    mu[v] = U.mu[u]; D[v] = U.diff[u];
-                    if (c > 0) { mum[v] = U.mu[u - 1]; Dm[v] = U.diff[u - 1]; }
+                    // table transport: (mu, D) slots carry (progress variable, gas density)
+                    const double* A0 = TAB ? U.prog : U.mu;
+                    const double* A1 = TAB ? U.gasn : U.diff;
+                    mu[v] = A0[u]; D[v] = A1[u];
+                    if (c > 0) { mum[v] = A0[u - 1]; Dm[v] = A1[u - 1]; }
                     ne[v] = U.ne[u]; ph[v] = U.phi[u]; sr[v] = U.src[u];
                     if (U.kloss) kl[v] = U.kloss[u];
                     qq[v] = U.q[u];
@@ -576,15 +622,27 @@ struct Column {
                     X00[s] = X01[s] = X10[s] = X11[s] = X20[s] = X21[s] = 0.0;
                     continue;
                 }
-                // the problem's domain: mu >= 0, D > 0, k >= 0, all values finite
-                // (the comparisons are false for NaN)
-                const bool ok = mu[v] >= 0.0 && mu[v] < INFINITY && D[v] > 0.0 && D[v] < INFINITY &&
+                // the problem's domain: mu >= 0, D > 0 (table: c finite, N > 0),
+                // k >= 0, all values finite (the comparisons are false for NaN)
+                const bool ok = (TAB ? fabs(mu[v]) < INFINITY : mu[v] >= 0.0 && mu[v] < INFINITY) &&
+                                D[v] > 0.0 && D[v] < INFINITY &&
                                 kl[v] >= 0.0 && kl[v] < INFINITY && fabs(sr[v]) < INFINITY &&
                                 fabs(qq[v]) < INFINITY && fabs(ne[v]) < INFINITY && fabs(ph[v]) < INFINITY &&
                                 fabs(uf[v]) < INFINITY;
                 bad = bad || !ok;
                 double r, g, wf = 0.0;
-                if (c == 0) {
+                if constexpr (TAB) {
+                    // the face record (mean c, mean N (0: zero-flux wall), u_f h_f)
+                    if (c == 0) {
+                        r = mu[v];
+                        g = (cd.bcl == 1) ? 0.0 : D[v];
+                        if (prm.has_u) wf = uf[v] * hb;
+                    } else {
+                        r = 0.5 * (mum[v] + mu[v]);
+                        g = 0.5 * (Dm[v] + D[v]);
+                        if (prm.has_u) wf = uf[v] * cd.h;
+                    }
+                } else if (c == 0) {
                     r = mu[v] / D[v];
                     g = (cd.bcl == 1) ? 0.0 : D[v] / hb;
                     if (prm.has_u) wf = uf[v] * hb / D[v];
@@ -614,9 +672,15 @@ struct Column {
                     // right wall face: the last cell's mu and D at distance h/2
                     const double uR = prm.has_u ? U.uface[fo + n] : 0.0;
                     bad = bad || !(fabs(uR) < INFINITY);
-                    wall[0] = mu[v] / D[v];
-                    wall[1] = (cd.bcr == 1) ? 0.0 : D[v] / hb;
-                    wall[2] = uR * hb / D[v];
+                    if constexpr (TAB) {
+                        wall[0] = mu[v];
+                        wall[1] = (cd.bcr == 1) ? 0.0 : D[v];
+                        wall[2] = uR * hb;
+                    } else {
+                        wall[0] = mu[v] / D[v];
+                        wall[1] = (cd.bcr == 1) ? 0.0 : D[v] / hb;
+                        wall[2] = uR * hb / D[v];
+                    }
                 }
             }
         }
@@ -720,8 +784,11 @@ struct Column {
             const CP F0 = Fb(0, 0); const CP F1 = Fb(0, 1);
             const CP E0 = Fb(1, 0); const CP E1 = Fb(1, 1);
             struct Own { double f, k, q; };
-            const auto scface = [](double r, double g, double w, double ihf, double nA, double pA, double nB,
-                                   double pB) {
+            const TabRef tb = prm.tab;
+            const auto scface = [tb](double fa, double fb, double fc, double ihf, double nA, double pA, double nB,
+                                     double pB) {
+                double r, g, w;
+                face_rgw<TAB>(tb, fa, fb, fc, ihf, pB - pA, r, g, w);
                 const double pe = w + r * (pB - pA);
                 double bx, bmx;
                 bernoulli_pair(pe, bx, bmx);
@@ -753,7 +820,7 @@ struct Column {
                 sweep2<4, ScRec, FluxRec>(
                     [&](int64_t s, double& a, double& b) { a = X00[s]; b = X01[s]; },
                     [&](int64_t s, double& a, double& b) { a = X10[s]; b = X11[s]; },
-                    scface, FluxFace{}, own,
+                    scface, FluxFace{prm.tab}, own,
                     [&](int64_t s, int c, double nC, double pC, double nE, double pE, const ScRec& L,
                         const ScRec& R, const FluxRec& LE, const FluxRec& RE, const Own& o) {
                         cellA(s, nC, pC, L, R, o);
@@ -858,9 +925,14 @@ struct Column {
     struct JacRec { double dnA, dnB, dpB, ihf; };
 
     // derivatives of the face flux w.r.t. the left (A) and right (B) states
+    // (with table transport the coefficients are held at the state's field:
+    // their own derivative with respect to the field is left out)
     struct JacFace {
-        __device__ __forceinline__ JacRec operator()(double r, double g, double w, double ihf,
+        TabRef tb;
+        __device__ __forceinline__ JacRec operator()(double fa, double fb, double fc, double ihf,
                                                      double nA, double pA, double nB, double pB) const {
+            double r, g, w;
+            face_rgw<TAB>(tb, fa, fb, fc, ihf, pB - pA, r, g, w);
             const double pe = w + r * (pB - pA);
             double bx, bmx, dbx, dbmx;
             bernoulli_pair(pe, bx, bmx);
@@ -926,7 +998,7 @@ struct Column {
 
         sweep<2, JacRec>(
             [&](int64_t s, double& a, double& b) { a = X0[s]; b = X1[s]; },
-            JacFace{},
+            JacFace{prm.tab},
             [&](int64_t s) { return W.kd[s]; },
             [&](int64_t s, int c, double nC, double pC, const JacRec& L, const JacRec& R, const double& kv) {
                 const int j = c - c0;
@@ -1580,7 +1652,7 @@ struct Column {
         struct Own { double f, k, q, F0, F1, v00, v01, v10, v11; };
         sweep<2, FluxRec>(
             [&](int64_t s, double& a, double& b) { a = X0[s] + e0 * z.p0[s]; b = X1[s] + e1 * z.p1[s]; },
-            FluxFace{},
+            FluxFace{prm.tab},
             [&](int64_t s) {
                 Own o;
                 o.f = W.f[s]; o.k = W.kd[s]; o.q = W.q[s]; o.F0 = F0[s]; o.F1 = F1[s];

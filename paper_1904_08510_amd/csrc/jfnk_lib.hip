@@ -35,12 +35,12 @@ struct SolveArgs {
     int ncols;
 };
 
-template <int T, class FT>
+template <int T, class FT, bool TAB>
 __global__ __launch_bounds__(T) void k_solve(SolveArgs a) {
     extern __shared__ double lds[];
     const int ci = a.order[blockIdx.x];
     if (ci < 0 || ci >= a.ncols) return;   // the order is a permutation; never taken
-    DevExec<T, FT> ex;
+    DevExec<T, FT, TAB> ex;
     ex.col.init(a.W.cols[ci], a.W, a.prm, (ldbl*)lds);
     ex.U = a.U;
     ColOutcome o;
@@ -95,15 +95,15 @@ __global__ __launch_bounds__(kOrderThreads) void k_order(const ColState* cst, co
 // tail.  Workgroup g serves column mcol[g], tiles [(g - g0) kMoveTiles, ...).
 constexpr int kMoveThreads = 256;
 
-template <int T>
+template <int T, bool TAB>
 __global__ __launch_bounds__(kMoveThreads) void k_gather(SolveArgs a) {
     const int ci = a.mcol[blockIdx.x];
-    Column<T, float> col;
+    using Col = Column<T, float, TAB>;
+    Col col;
     col.init(a.W.cols[ci], a.W, a.prm, nullptr);
     ColState* cs = a.W.cst + col.cd.index;
     const int kb = ((int)blockIdx.x - col.cd.g0) * kMoveTiles;
     const int ke = min(kb + kMoveTiles, col.ntiles());
-    using Col = Column<T, float>;
     const int gm = col.gather(a.U, kb, ke, threadIdx.x >> 6, kMoveThreads / 64, &cs->nrR);
     const int any_changed = __syncthreads_or(gm & Col::kGatherChanged);
     const int any_bad = __syncthreads_or(gm & Col::kGatherBad);
@@ -149,10 +149,10 @@ struct PhaseArgs {
     double* out1;
 };
 
-template <int T, class FT>
+template <int T, class FT, bool TAB>
 __global__ __launch_bounds__(T) void k_phase(PhaseArgs a) {
     extern __shared__ double lds[];
-    Column<T, FT> col;
+    Column<T, FT, TAB> col;
     col.init(a.W.cols[a.ci], a.W, a.prm, (ldbl*)lds);
     double* scal = a.W.scal + (int64_t)a.ci * kScalSlots;
     VecRef* bl = (VecRef*)(lds + Lds<T>::kBasis);
@@ -446,6 +446,37 @@ bool config_valid(const jfnk_config* cfg) {
     return t == 0 || t == 64 || t == 128 || t == 256 || t == 512;
 }
 
+// The per-cell arrays and the transport table: nullptr when usable, else why not.
+const char* check_cells(const jfnk_problem* p, const jfnk_state* x) {
+    if (!p->src || !p->q_ion || !x->ne || !x->phi) return "null per-cell array";
+    if (p->table) {
+        const jfnk_table* t = p->table;
+        if (!p->prog || !p->gas_n) return "table transport needs prog and gas_n";
+        if (t->nc < 2 || t->nx < 2 || !t->mu || !t->diff) return "transport table: bad size or null array";
+        if (!(t->c_max > t->c_min) || !(t->x_max > t->x_min) || !std::isfinite(t->c_min) ||
+            !std::isfinite(t->c_max) || !std::isfinite(t->x_min) || !std::isfinite(t->x_max))
+            return "transport table: bad grid range";
+    } else if (!p->mu || !p->diff) {
+        return "null per-cell array";
+    }
+    if ((x->ne_prev == nullptr) != (x->phi_prev == nullptr))
+        return "ne_prev and phi_prev must both be given or both NULL";
+    if ((x->ne_out == nullptr) != (x->phi_out == nullptr))
+        return "ne_out and phi_out must both be given or both NULL";
+    return nullptr;
+}
+
+TabRef tab_of(const jfnk_problem* p) {
+    TabRef t{};
+    if (p->table) {
+        t.mu = p->table->mu; t.diff = p->table->diff;
+        t.nc = p->table->nc; t.nx = p->table->nx;
+        t.c_min = p->table->c_min; t.c_max = p->table->c_max;
+        t.x_min = p->table->x_min; t.x_max = p->table->x_max;
+    }
+    return t;
+}
+
 // validation of the problem; fills the schedule on success
 int validate(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x) {
     if (!p || !x) return fail(ctx, JFNK_EINVAL, "null problem or state");
@@ -454,12 +485,7 @@ int validate(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x) {
     if (!p->col_offset || !p->length || !p->dt || !p->phi_left || !p->phi_right || !p->eps_over_e ||
         !p->bc_left || !p->bc_right || !p->ne_left || !p->ne_right)
         return fail(ctx, JFNK_EINVAL, "null per-column array");
-    if (!p->mu || !p->diff || !p->src || !p->q_ion || !x->ne || !x->phi)
-        return fail(ctx, JFNK_EINVAL, "null per-cell array");
-    if ((x->ne_prev == nullptr) != (x->phi_prev == nullptr))
-        return fail(ctx, JFNK_EINVAL, "ne_prev and phi_prev must both be given or both NULL");
-    if ((x->ne_out == nullptr) != (x->phi_out == nullptr))
-        return fail(ctx, JFNK_EINVAL, "ne_out and phi_out must both be given or both NULL");
+    if (const char* why = check_cells(p, x)) return fail(ctx, JFNK_EINVAL, why);
     if (p->col_offset[0] != 0) return fail(ctx, JFNK_EINVAL, "col_offset[0] != 0");
     int nmax = 0;
     for (int c = 0; c < p->ncols; ++c) {
@@ -545,6 +571,10 @@ SolverParams params_of(const jfnk_config& cfg, const jfnk_problem* p, const jfnk
     s.mg_tol = cfg.mg_tol;
     s.mg_blocks = cfg.mg_blocks;
     s.mg_transfer = cfg.mg_transfer;
+    s.tab = tab_of(p);
+    // with table transport the Jacobian changes with the field even when the
+    // face records do not: no factors are kept from the step before
+    if (p->table) s.fac_reuse = 0;
     return s;
 }
 
@@ -561,6 +591,7 @@ UserArrays make_user(const jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x) 
     U.phi_out = x->phi_out ? x->phi_out : x->phi;
     U.ne_prev = x->ne_prev; U.phi_prev = x->phi_prev;
     U.ne_learn = nullptr; U.phi_learn = nullptr;
+    U.prog = p->prog; U.gasn = p->gas_n;
     if (ctx->learn_active) {
         U.ne_learn = ctx->d_learn;
         U.phi_learn = ctx->d_learn + ctx->cfg.max_total_cells;
@@ -571,7 +602,7 @@ UserArrays make_user(const jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x) 
 // ---------------------------------------------------------------------------
 // Host-driven executor of the control logic (plain schedule).
 // ---------------------------------------------------------------------------
-template <int T, class FT>
+template <int T, class FT, bool TAB>
 struct HostExecT {
     jfnk_ctx* ctx;
     hipStream_t st;
@@ -595,7 +626,7 @@ struct HostExecT {
     void launch(int phase) {
         a.phase = phase;
         if (herr != hipSuccess) return;
-        hipLaunchKernelGGL((k_phase<T, FT>), dim3(1), dim3(T), Lds<T>::bytes(), st, a);
+        hipLaunchKernelGGL((k_phase<T, FT, TAB>), dim3(1), dim3(T), Lds<T>::bytes(), st, a);
         herr = hipGetLastError();
     }
     const double* fetch(int n) {
@@ -715,13 +746,13 @@ struct HostExecT {
     }
 };
 
-template <int T, class FT>
+template <int T, class FT, bool TAB>
 int run_plain(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t st) {
     const SolverParams prm = make_params(ctx, p, x);
     const UserArrays U = make_user(ctx, p, x);
     HIP_OK(hipEventRecord(ctx->ev0, st));
     for (int c = 0; c < p->ncols; ++c) {
-        HostExecT<T, FT> ex;
+        HostExecT<T, FT, TAB> ex;
         ex.ctx = ctx;
         ex.st = st;
         memset(&ex.a, 0, sizeof(ex.a));
@@ -742,7 +773,7 @@ int run_plain(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t s
     return JFNK_OK;
 }
 
-template <int T, class FT>
+template <int T, class FT, bool TAB>
 int run_batched(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t st) {
     SolveArgs a;
     a.W = ctx->W;
@@ -752,10 +783,10 @@ int run_batched(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t
     a.mcol = ctx->d_mcol;
     a.ncols = p->ncols;
     HIP_OK(hipEventRecord(ctx->ev0, st));
-    hipLaunchKernelGGL((k_gather<T>), dim3(ctx->nmove), dim3(kMoveThreads), 0, st, a);
+    hipLaunchKernelGGL((k_gather<T, TAB>), dim3(ctx->nmove), dim3(kMoveThreads), 0, st, a);
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(ctx->evg, st));
-    hipLaunchKernelGGL((k_solve<T, FT>), dim3(p->ncols), dim3(T), Lds<T>::bytes(), st, a);
+    hipLaunchKernelGGL((k_solve<T, FT, TAB>), dim3(p->ncols), dim3(T), Lds<T>::bytes(), st, a);
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(ctx->evs, st));
     hipLaunchKernelGGL((k_scatter<T>), dim3(ctx->nmove), dim3(kMoveThreads), 0, st, a);
@@ -771,12 +802,12 @@ int run_batched(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t
     return JFNK_OK;
 }
 
-template <class FT>
-int dispatch_run(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t st) {
+template <class FT, bool TAB>
+int dispatch_run_t(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t st) {
     const bool plain = ctx->cfg.schedule == JFNK_SCHED_PLAIN;
     switch (ctx->Tsel) {
 #define CASE_T(TT) \
-    case TT: return plain ? run_plain<TT, FT>(ctx, p, x, st) : run_batched<TT, FT>(ctx, p, x, st);
+    case TT: return plain ? run_plain<TT, FT, TAB>(ctx, p, x, st) : run_batched<TT, FT, TAB>(ctx, p, x, st);
         CASE_T(64) CASE_T(128) CASE_T(256) CASE_T(512)
 #undef CASE_T
     default:
@@ -784,12 +815,17 @@ int dispatch_run(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_
     }
 }
 
+template <class FT>
+int dispatch_run(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t st) {
+    return p->table ? dispatch_run_t<FT, true>(ctx, p, x, st) : dispatch_run_t<FT, false>(ctx, p, x, st);
+}
+
 // single-column phase runner for the test exports
-template <int T, class FT>
+template <int T, class FT, bool TAB>
 int run_phases(jfnk_ctx* ctx, hipStream_t st, PhaseArgs& a, const std::vector<int>& phases) {
     for (int ph : phases) {
         a.phase = ph;
-        hipLaunchKernelGGL((k_phase<T, FT>), dim3(1), dim3(T), Lds<T>::bytes(), st, a);
+        hipLaunchKernelGGL((k_phase<T, FT, TAB>), dim3(1), dim3(T), Lds<T>::bytes(), st, a);
         HIP_OK(hipGetLastError());
     }
     return JFNK_OK;
@@ -797,8 +833,10 @@ int run_phases(jfnk_ctx* ctx, hipStream_t st, PhaseArgs& a, const std::vector<in
 
 template <class FT>
 int dispatch_phases(jfnk_ctx* ctx, hipStream_t st, PhaseArgs& a, const std::vector<int>& ph) {
+    const bool tab = a.prm.tab.mu != nullptr;
     switch (ctx->Tsel) {
-#define CASE_T(TT) case TT: return run_phases<TT, FT>(ctx, st, a, ph);
+#define CASE_T(TT) \
+    case TT: return tab ? run_phases<TT, FT, true>(ctx, st, a, ph) : run_phases<TT, FT, false>(ctx, st, a, ph);
         CASE_T(64) CASE_T(128) CASE_T(256) CASE_T(512)
 #undef CASE_T
     default:
@@ -835,12 +873,7 @@ int schedule_cached(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, h
     if (!p || !x) return fail(ctx, JFNK_EINVAL, "null problem or state");
     {
         if (schedule_matches(ctx, p)) {
-            if (!p->mu || !p->diff || !p->src || !p->q_ion || !x->ne || !x->phi)
-                return fail(ctx, JFNK_EINVAL, "null per-cell array");
-            if ((x->ne_prev == nullptr) != (x->phi_prev == nullptr))
-                return fail(ctx, JFNK_EINVAL, "ne_prev and phi_prev must both be given or both NULL");
-            if ((x->ne_out == nullptr) != (x->phi_out == nullptr))
-                return fail(ctx, JFNK_EINVAL, "ne_out and phi_out must both be given or both NULL");
+            if (const char* why = check_cells(p, x)) return fail(ctx, JFNK_EINVAL, why);
             return JFNK_OK;
         }
     }
@@ -1113,27 +1146,33 @@ __global__ __launch_bounds__(256) void k_clear(uint4* p, int64_t n16) {
         p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-template <int T, class FT>
+template <int T, class FT, bool TAB>
 hipError_t static_launch(const SolveArgs& a, int nmove, int ncols, hipStream_t st) {
-    hipLaunchKernelGGL((k_gather<T>), dim3(nmove), dim3(kMoveThreads), 0, st, a);
+    hipLaunchKernelGGL((k_gather<T, TAB>), dim3(nmove), dim3(kMoveThreads), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_solve<T, FT>), dim3(ncols), dim3(T), Lds<T>::bytes(), st, a);
+    hipLaunchKernelGGL((k_solve<T, FT, TAB>), dim3(ncols), dim3(T), Lds<T>::bytes(), st, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_scatter<T>), dim3(nmove), dim3(kMoveThreads), 0, st, a);
     return hipGetLastError();
 }
 
-template <class FT>
-hipError_t static_dispatch(int T, const SolveArgs& a, int nmove, int ncols, hipStream_t st) {
+template <class FT, bool TAB>
+hipError_t static_dispatch_t(int T, const SolveArgs& a, int nmove, int ncols, hipStream_t st) {
     switch (T) {
-    case 64: return static_launch<64, FT>(a, nmove, ncols, st);
-    case 128: return static_launch<128, FT>(a, nmove, ncols, st);
-    case 256: return static_launch<256, FT>(a, nmove, ncols, st);
-    case 512: return static_launch<512, FT>(a, nmove, ncols, st);
+    case 64: return static_launch<64, FT, TAB>(a, nmove, ncols, st);
+    case 128: return static_launch<128, FT, TAB>(a, nmove, ncols, st);
+    case 256: return static_launch<256, FT, TAB>(a, nmove, ncols, st);
+    case 512: return static_launch<512, FT, TAB>(a, nmove, ncols, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <class FT>
+hipError_t static_dispatch(int T, const SolveArgs& a, int nmove, int ncols, hipStream_t st) {
+    return a.prm.tab.mu ? static_dispatch_t<FT, true>(T, a, nmove, ncols, st)
+                        : static_dispatch_t<FT, false>(T, a, nmove, ncols, st);
 }
 
 int static_fail(char* err, size_t len, int code, const char* msg) {
@@ -1549,10 +1588,7 @@ int jfnk_step_noalloc(const jfnk_config* cfg, const jfnk_problem* p, jfnk_state*
     if (!p->col_offset || !p->length || !p->dt || !p->phi_left || !p->phi_right || !p->eps_over_e ||
         !p->bc_left || !p->bc_right || !p->ne_left || !p->ne_right)
         return static_fail(err, err_len, JFNK_EINVAL, "null per-column array");
-    if (!p->mu || !p->diff || !p->src || !p->q_ion || !x->ne || !x->phi)
-        return static_fail(err, err_len, JFNK_EINVAL, "null per-cell array");
-    if ((x->ne_prev == nullptr) != (x->phi_prev == nullptr) || (x->ne_out == nullptr) != (x->phi_out == nullptr))
-        return static_fail(err, err_len, JFNK_EINVAL, "ne_prev/phi_prev and ne_out/phi_out go in pairs");
+    if (const char* why = check_cells(p, x)) return static_fail(err, err_len, JFNK_EINVAL, why);
     if (p->col_offset[0] != 0) return static_fail(err, err_len, JFNK_EINVAL, "col_offset[0] != 0");
     const int nc = p->ncols;
     int nmax = 0;
@@ -1647,6 +1683,7 @@ int jfnk_step_noalloc(const jfnk_config* cfg, const jfnk_problem* p, jfnk_state*
     a.U.ne_out = x->ne_out ? x->ne_out : x->ne;
     a.U.phi_out = x->phi_out ? x->phi_out : x->phi;
     a.U.ne_prev = x->ne_prev; a.U.phi_prev = x->phi_prev;
+    a.U.prog = p->prog; a.U.gasn = p->gas_n;
     a.order = d_order;
     a.mcol = d_mcol;
     a.ncols = nc;

@@ -262,9 +262,9 @@ __host__ __device__ void jfnk_solve(Ex& ex, const SolverParams& p, ColOutcome& o
 // every thread; the small dense GMRES state lives in LDS and is written by
 // thread 0 between barriers.
 // ---------------------------------------------------------------------------
-template <int T, class FT>
+template <int T, class FT, bool TAB = false>
 struct DevExec {
-    Column<T, FT> col;
+    Column<T, FT, TAB> col;
     UserArrays U;
 
     __device__ VecRef* basis_lds() { return (VecRef*)(double*)(col.lds + Lds<T>::kBasis); }

@@ -72,6 +72,16 @@ struct ColState {
     int32_t mg_cycles;              // multigrid V-cycles of the step (approximate Schur + MG)
 };
 
+// Electron transport table (device arrays [nc][nx] row-major) on uniform
+// grids of the progress variable c and of x = log10(|E|/N / 1 Td); mu ==
+// nullptr: per-cell coefficients instead.
+struct TabRef {
+    const double* mu;
+    const double* diff;
+    int32_t nc, nx;
+    double c_min, c_max, x_min, x_max;
+};
+
 struct SolverParams {
     int32_t m;              // GMRES restart length
     int32_t max_restarts;
@@ -89,6 +99,7 @@ struct SolverParams {
     double tol_f, tol_x, gamma, theta;
     double chord_tol;       // simplified-Newton steps while the error estimate is below this (0: off)
     double mg_tol;          // kind 3: V-cycles until ||b - A x||_2 <= mg_tol ||b||_2
+    TabRef tab;             // transport table (tab.mu == nullptr: none)
 };
 
 // Caller arrays (natural layout, device pointers).
@@ -98,6 +109,7 @@ struct UserArrays {
     const double *ne_prev, *phi_prev;
     double *ne_out, *phi_out;     // where X^{n+1} goes (ne, phi for an in-place step)
     const double *ne_learn, *phi_learn;
+    const double *prog, *gasn;    // table transport: progress variable, gas number density
 };
 
 // Workspace (device pointers).

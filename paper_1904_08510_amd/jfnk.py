@@ -41,13 +41,19 @@ class jfnk_config(C.Structure):
                 ("mg_blocks", C.c_int32), ("mg_transfer", C.c_int32)]
 
 
+class jfnk_table(C.Structure):
+    _fields_ = [("nc", C.c_int32), ("nx", C.c_int32), ("c_min", C.c_double), ("c_max", C.c_double),
+                ("x_min", C.c_double), ("x_max", C.c_double), ("mu", C.c_void_p), ("diff", C.c_void_p)]
+
+
 class jfnk_problem(C.Structure):
     _fields_ = [("ncols", C.c_int32), ("col_offset", _lp), ("length", _dp), ("dt", _dp),
                 ("phi_left", _dp), ("phi_right", _dp), ("eps_over_e", _dp),
                 ("bc_left", _ip), ("bc_right", _ip), ("ne_left", _dp), ("ne_right", _dp),
                 ("mu", C.c_void_p), ("diff", C.c_void_p), ("src", C.c_void_p),
                 ("k_loss", C.c_void_p), ("q_ion", C.c_void_p), ("u_face", C.c_void_p),
-                ("temp", C.c_void_p)]
+                ("temp", C.c_void_p), ("table", C.POINTER(jfnk_table)), ("prog", C.c_void_p),
+                ("gas_n", C.c_void_p)]
 
 
 class jfnk_state(C.Structure):
@@ -201,6 +207,9 @@ class DeviceProblem:
     q: object
     temp: object
     uface: object = None
+    table: object = None      # DeviceTable or None
+    prog: object = None
+    gas_n: object = None
 
     def __setattr__(self, name, value):
         # a field bound to another object invalidates the cached argument
@@ -235,9 +244,29 @@ class DeviceProblem:
         p.mu, p.diff, p.src = _ptr(self.mu), _ptr(self.diff), _ptr(self.src)
         p.k_loss, p.q_ion = _ptr(self.kloss), _ptr(self.q)
         p.u_face, p.temp = _ptr(self.uface), _ptr(self.temp)
+        p.prog, p.gas_n = _ptr(self.prog), _ptr(self.gas_n)
+        if self.table is not None:
+            t = self.table.cstruct()
+            keep.append(t)
+            p.table = C.pointer(t)
         object.__setattr__(self, "_keep", keep)
         object.__setattr__(self, "_cached", p if direct else None)
         return p
+
+
+@dataclass
+class DeviceTable:
+    """A transport table (workloads.TransportTable) with its arrays on the GPU."""
+    c_min: float
+    c_max: float
+    x_min: float
+    x_max: float
+    mu: object
+    diff: object
+
+    def cstruct(self) -> jfnk_table:
+        return jfnk_table(int(self.mu.shape[0]), int(self.mu.shape[1]), self.c_min, self.c_max, self.x_min,
+                          self.x_max, _ptr(self.mu), _ptr(self.diff))
 
 
 def device_problem(packed, device="cuda") -> tuple:
@@ -251,6 +280,11 @@ def device_problem(packed, device="cuda") -> tuple:
                        packed.phi_right, packed.eps_over_e, packed.bc_left, packed.bc_right,
                        packed.ne_left, packed.ne_right, dev(packed.mu), dev(packed.diff),
                        dev(packed.src), dev(packed.kloss), dev(packed.q), dev(packed.temp))
+    tab = getattr(packed, "table", None)
+    if tab is not None:
+        dp.table = DeviceTable(tab.c_min, tab.c_max, tab.x_min, tab.x_max, dev(tab.mu).contiguous(),
+                               dev(tab.diff).contiguous())
+        dp.prog, dp.gas_n = dev(packed.prog), dev(packed.gas_n)
     return dp, dev(packed.ne), dev(packed.phi), dev(packed.ne_prev), dev(packed.phi_prev)
 
 

@@ -224,6 +224,9 @@ class Packed:
     phi: np.ndarray
     ne_prev: Optional[np.ndarray]
     phi_prev: Optional[np.ndarray]
+    table: Optional[TransportTable] = None
+    prog: Optional[np.ndarray] = None
+    gas_n: Optional[np.ndarray] = None
 
     @property
     def total(self) -> int:
@@ -242,6 +245,10 @@ def pack(cols: List[Column]) -> Packed:
         return np.array([getattr(c, name) for c in cols], dtype=dtype)
 
     has_prev = all(c.ne_prev is not None for c in cols)
+    tabs = {id(c.table) for c in cols}
+    if len(tabs) != 1:
+        raise ValueError("the columns of a batch share one transport table (or none)")
+    table = cols[0].table
     return Packed(
         ncols=len(cols), col_offset=off,
         length=per("length"), dt=per("dt"), phi_left=per("phi_left"),
@@ -252,6 +259,9 @@ def pack(cols: List[Column]) -> Packed:
         q=cat("q"), temp=cat("temp"), ne=cat("ne"), phi=cat("phi"),
         ne_prev=cat("ne_prev") if has_prev else None,
         phi_prev=cat("phi_prev") if has_prev else None,
+        table=table,
+        prog=cat("prog") if table is not None else None,
+        gas_n=cat("gas_n") if table is not None else None,
     )
 
 
