@@ -192,6 +192,38 @@ def config4(seed: int = 4321, ncols: int = 256, n: int = 65536,
             for v, xf in zip(vs, xfs)]
 
 
+# ---------------------------------------------------------------------------
+# Time steps of the charged species (MISDC): one positive ion species
+# drifting in the field (mobility of H3O+, Table 3) and the ionisation /
+# recombination chemistry of the flame columns, electrodes at phi = 0 and
+# phi_right(t) = V + A sin(2 pi f t).
+# ---------------------------------------------------------------------------
+ION_MOBILITY = 4e-3        # m^2/(V s), H3O+ (Table 3)
+
+
+@dataclass
+class IonData:
+    mu_i: np.ndarray           # per cell, m^2/(V s)
+    k_rec: np.ndarray          # per cell, m^3/s
+    ac_amp: float = 0.0        # V
+    ac_freq: float = 0.0       # Hz
+
+
+def misdc_column(n: int, volts: float, *, ac_amp: float = 0.0, ac_freq: float = 0.0, cfl: float = 0.5,
+                 length: float = 0.02, x_f: float = 0.01, a_ion: float = 1e16, krec: float = 1e-13):
+    """A flame column for the MISDC step and its ion data.  n_i starts as
+    the column's ion charge q and n_e = n_i with a linear potential (no space
+    charge); dt is cfl times the ion drift CFL limit at the largest
+    electrode voltage |V| + |A| (uniform field estimate)."""
+    col = flame_column(n, volts, a_ion=a_ion, x_f=x_f, length=length, krec=krec)
+    h = length / n
+    vmax = ION_MOBILITY * (abs(volts) + abs(ac_amp)) / length
+    col.dt = cfl * h / max(vmax, 1e-30)
+    col.kloss = np.zeros(n)
+    ions = IonData(np.full(n, ION_MOBILITY), np.full(n, krec), ac_amp, ac_freq)
+    return col, ions
+
+
 def training_seeds() -> range:
     """Seeds of the learned-guess training batches (disjoint from 2026)."""
     return range(1000, 1100)
