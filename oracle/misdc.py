@@ -79,7 +79,8 @@ def reaction(col, ions: Ions, ne, ni) -> np.ndarray:
 
 def ion_face_velocity(col, ions, t, phi) -> np.ndarray:
     """Ion drift velocity at the n + 1 faces: v = u + mu_i,f (phi_a - phi_b) / h_f
-    (h/2 and the electrode potential at the walls; u = 0 in these columns)."""
+    (h/2 and the electrode potential at the walls; u: the column's face
+    velocities, when it has them)."""
     n, h = col.n, col.length / col.n
     pr = phi_right_at(col, ions, t)
     v = np.empty(n + 1)
@@ -87,7 +88,8 @@ def ion_face_velocity(col, ions, t, phi) -> np.ndarray:
     v[1:-1] = muf * (phi[:-1] - phi[1:]) / h
     v[0] = ions.mu_i[0] * (col.phi_left - phi[0]) / (0.5 * h)
     v[-1] = ions.mu_i[-1] * (phi[-1] - pr) / (0.5 * h)
-    return v
+    u = getattr(col, "uface", None)
+    return v if u is None else u + v
 
 
 def mc_slopes(ni) -> np.ndarray:

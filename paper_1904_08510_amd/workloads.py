@@ -68,6 +68,7 @@ class Column:
     table: Optional["TransportTable"] = None
     prog: Optional[np.ndarray] = None      # progress variable per cell
     gas_n: Optional[np.ndarray] = None     # background gas number density, m^-3
+    uface: Optional[np.ndarray] = None     # flow velocity at the n + 1 faces, m/s (None: 0)
     meta: dict = field(default_factory=dict)
 
     def copy(self) -> "Column":
@@ -224,6 +225,30 @@ def misdc_column(n: int, volts: float, *, ac_amp: float = 0.0, ac_freq: float = 
     return col, ions
 
 
+AC_FREQS = (1e3, 2.5e3, 5e3, 1e4, 2.5e4, 5e4, 1e5)     # Hz, the forcing frequencies of Table 4
+
+
+def config_ac(seed: int = 77, ncols: int = 1024, n: int = 1024, amp: float = 1000.0, cfl: float = 0.5):
+    """AC-forced batch for the MISDC step (Section 4.5): right electrode
+    A sin(2 pi f t) with A = 1000 V and f cycling through Table 4's seven
+    frequencies, each column at its own phase (start time uniform over its
+    period), ion peak log-uniform in [1e15, 1e17] m^-3, flame position
+    U[0.8, 1.2] cm, one dt for every column (cfl times the ion drift limit
+    at 1000 V).  Returns (columns, ion data, start times)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    peaks = 10.0 ** rng.uniform(15.0, 17.0, size=ncols)
+    xfs = rng.uniform(0.008, 0.012, size=ncols)
+    phase = rng.uniform(0.0, 1.0, size=ncols)
+    cols, ions, t0 = [], [], np.empty(ncols)
+    for i in range(ncols):
+        f = AC_FREQS[i % len(AC_FREQS)]
+        c, ion = misdc_column(n, 0.0, ac_amp=amp, ac_freq=f, cfl=cfl, a_ion=float(peaks[i]), x_f=float(xfs[i]))
+        cols.append(c)
+        ions.append(ion)
+        t0[i] = phase[i] / f
+    return cols, ions, t0
+
+
 def training_seeds() -> range:
     """Seeds of the learned-guess training batches (disjoint from 2026)."""
     return range(1000, 1100)
@@ -259,6 +284,7 @@ class Packed:
     table: Optional[TransportTable] = None
     prog: Optional[np.ndarray] = None
     gas_n: Optional[np.ndarray] = None
+    uface: Optional[np.ndarray] = None          # [total + ncols]: column c's faces from col_offset[c] + c
 
     @property
     def total(self) -> int:
@@ -281,6 +307,9 @@ def pack(cols: List[Column]) -> Packed:
     if len(tabs) != 1:
         raise ValueError("the columns of a batch share one transport table (or none)")
     table = cols[0].table
+    nu = sum(c.uface is not None for c in cols)
+    if nu not in (0, len(cols)):
+        raise ValueError("face velocities for every column of a batch or for none")
     return Packed(
         ncols=len(cols), col_offset=off,
         length=per("length"), dt=per("dt"), phi_left=per("phi_left"),
@@ -294,6 +323,7 @@ def pack(cols: List[Column]) -> Packed:
         table=table,
         prog=cat("prog") if table is not None else None,
         gas_n=cat("gas_n") if table is not None else None,
+        uface=cat("uface") if nu else None,
     )
 
 

@@ -134,3 +134,25 @@ def test_limited_ion_update_stays_within_bounds():
         flat = np.full(n, 2e15)
         a = M.ion_advection(col, flat, v, dt, np.zeros(n))
         assert np.max(np.abs(a[1:-1])) == 0.0
+
+
+def test_ion_drift_velocity_closed_form():
+    """v = u + mu_i E at every face: the flow alone with no mobility, and
+    the drift down a linear potential (uniform field V/L, the walls at half
+    a cell from their centres) added to it."""
+    n = 16
+    col, _ = W.misdc_column(n, 120.0)
+    col.uface = np.linspace(-3.0, 5.0, n + 1)
+    x = W.cell_centres(n, col.length)
+    phi = 120.0 * x / col.length
+    assert np.array_equal(M.ion_face_velocity(col, _ions(col, mu=0.0), 0.0, phi), col.uface)
+    v = M.ion_face_velocity(col, _ions(col), 0.0, phi)
+    e = -120.0 / col.length
+    assert np.allclose(v - col.uface, W.ION_MOBILITY * e, rtol=1e-12, atol=0)
+    # AC: the right electrode at t, V + A sin(2 pi f t), moves the last face's field only
+    ac = _ions(col, amp=50.0, freq=1e3)
+    t = 2.5e-4
+    va = M.ion_face_velocity(col, ac, t, phi)
+    assert np.array_equal(va[:-1], v[:-1])
+    h = col.length / n
+    assert va[-1] - col.uface[-1] == pytest.approx(W.ION_MOBILITY * (phi[-1] - 170.0) / (0.5 * h), rel=1e-12)
