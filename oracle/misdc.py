@@ -2,15 +2,14 @@
 
 TEST INFRASTRUCTURE ONLY: imported by the tests (never by the product
 library).  Plain numpy plus the oracle's Newton root (oracle.newton), one
-column at a time, written from the paper's Algorithm 1 (algo:misdc) and the
-SDC update equation of Section 3.1, restricted to the charged species:
+column at a time, written from the paper's Algorithm 1 (algo:misdc), the
+update of the provisional charged species of Section 3.1 and the
+electron/Poisson system eq:nls of Section 3.2, restricted to the charged
+species:
 
   state         n_e, phi (implicit, JFNK in the product) and one positive
                 ion species n_i (explicit advection in the drift velocity)
-  operators     T_e(n_e, phi)  electron transport -div Gamma (the residual's
-                               Scharfetter-Gummel fluxes, potentials at the
-                               state's time)
-                R(n_e, n_i)    chemistry: ionisation S - recombination
+  operators     R(n_e, n_i)    chemistry: ionisation S - recombination
                                k_r n_e n_i, the same for both species
                 A(n_i; v, F)   ion advection -div(n_i v): second-order
                                Godunov fluxes (MUSCL, monotonised-central
@@ -19,18 +18,27 @@ SDC update equation of Section 3.1, restricted to the charged species:
                                upwind cell), v = u + mu_i E (ions drift down
                                the potential gradient), electrodes absorbing
   SDC iteration k = 0 .. k_max - 1 (predictor: X^(0) = X^n):
+    I_R^(k)    = (R^n + R^(k)) / 2      integral of the chemistry over the
+                                        step, per unit time, from the last
+                                        evaluation (trapezoidal)
     v^(k)      = (v(phi^n, t^n) + v(phi^(k), t^n+1)) / 2
-    n_i~       = n_i^n + dt [A(n_i^n; v^(k), R^n) + (R^n + R^(k)) / 2]
-    s^(k)      = (T_e^n - T_e^(k)) / 2 + (R^n + R^(k)) / 2
-    X^(k+1)    = root of the backward-Euler system with f = n_e^n + dt s^(k),
-                 no implicit loss, ion charge n_i~ and the electrode
-                 potentials at t^n+1 (the provisional charged-species
-                 fields of Algorithm 1, then the electron/Poisson solve)
+    n_i~       = n_i^n + dt [A(n_i^n; v^(k), R^n) + I_R^(k)]
+    X^(k+1)    = root of eq:nls, the backward-Euler electron/Poisson system,
+                 with f_e = n_e^n + dt I_R^(k), no implicit loss, ion charge
+                 n_i~ and the electrode potentials at t^n+1
     n_i^(k+1)  = n_i~
-  At the fixed point the electrons follow the trapezoidal rule
-  n_e = n_e^n + dt (T_e^n + T_e^n+1)/2 + dt (R^n + R^n+1)/2 and the ions the
-  time-centred Godunov update: second order in time (Section 4.3).
+  At the fixed point the ions follow the time-centred Godunov update with
+  trapezoidal chemistry and the electrons backward Euler in their transport
+  (L-stable: the electrons relax on time scales far below dt, Section 4.1)
+  with trapezoidal chemistry; the potential is then first order in time.
+  electron_sdc: the electrons' transport gets the SDC correction the other
+  species' diffusion gets in Section 3.1, f_e = n_e^n + dt [(T_e^n -
+  T_e^(k)) / 2 + I_R^(k)] with T_e = -div Gamma: the fixed point is then the
+  trapezoidal rule for the electrons (second order, A- but not L-stable:
+  modes with dt |lambda| >> 1 contract by 1/2 per iteration and flip sign
+  from step to step instead of decaying).
 
+Time step: the column's dt, or a constant ion-drift CFL number (cfl_dt).
 Electrode potentials: phi_left = 0 and phi_right(t) = V + A sin(2 pi f t)
 (DC when A = 0; AC forcing of Section 4.5, Table 4).
 """
@@ -66,7 +74,8 @@ def _at_time(col, ions, t):
 
 
 def electron_transport(col, ions, t, ne, phi) -> np.ndarray:
-    """T_e = -(Gamma_{i+1/2} - Gamma_{i-1/2}) / h with the potentials at t."""
+    """T_e = -(Gamma_{i+1/2} - Gamma_{i-1/2}) / h with the potentials at t
+    (the electron transport of eq:nls; used to state the fixed point)."""
     c = _at_time(col, ions, t)
     gam = O.face_fluxes(O.OracleColumn(c), ne, phi)
     return -(gam[1:] - gam[:-1]) / (col.length / col.n)
@@ -90,6 +99,16 @@ def ion_face_velocity(col, ions, t, phi) -> np.ndarray:
     v[-1] = ions.mu_i[-1] * (phi[-1] - pr) / (0.5 * h)
     u = getattr(col, "uface", None)
     return v if u is None else u + v
+
+
+def cfl_dt(col, ions, t, phi, cfl: float) -> float:
+    """Time step at a constant ion-drift CFL number (Section 4.1: the
+    explicit advection of the charged species limits the step):
+    min(col.dt, cfl h / max_f |v_f|) with the face velocities of the state
+    (phi at t); col.dt when no face moves."""
+    vmax = float(np.max(np.abs(ion_face_velocity(col, ions, t, phi))))
+    h = col.length / col.n
+    return col.dt if vmax == 0.0 else min(col.dt, cfl * h / vmax)
 
 
 def mc_slopes(ni) -> np.ndarray:
@@ -138,26 +157,30 @@ class StepResult:
 
 
 def misdc_step(col, ions: Ions, t: float, ne, phi, ni, k_max: int = 4, keep_iterates: bool = False,
-               tol_floor: float = 1e-15) -> StepResult:
-    """One MISDC step t -> t + dt of one column (dt = col.dt)."""
+               tol_floor: float = 1e-15, dt: Optional[float] = None, electron_sdc: bool = False) -> StepResult:
+    """One MISDC step t -> t + dt of one column (dt: col.dt unless given)."""
+    if dt is not None:
+        col = col.copy()
+        col.dt = dt
     dt = col.dt
-    Tn = electron_transport(col, ions, t, ne, phi)
     Rn = reaction(col, ions, ne, ni)
+    Tn = electron_transport(col, ions, t, ne, phi) if electron_sdc else None
     vn = ion_face_velocity(col, ions, t, phi)
     k_ne, k_phi, k_ni = ne.copy(), phi.copy(), ni.copy()
     newton = 0
     its = []
     for k in range(k_max):
-        Tk = electron_transport(col, ions, t + dt, k_ne, k_phi)
         Rk = reaction(col, ions, k_ne, k_ni)
+        i_r = 0.5 * (Rn + Rk)
         vk = ion_face_velocity(col, ions, t + dt, k_phi)
         v = 0.5 * (vn + vk)
-        ni_t = ni + dt * (ion_advection(col, ni, v, dt, Rn) + 0.5 * (Rn + Rk))
-        s = 0.5 * (Tn - Tk) + 0.5 * (Rn + Rk)
+        ni_t = ni + dt * (ion_advection(col, ni, v, dt, Rn) + i_r)
         c = _at_time(col, ions, t + dt)
-        c.src = s
+        c.src = i_r
+        if electron_sdc:
+            c.src = 0.5 * (Tn - electron_transport(col, ions, t + dt, k_ne, k_phi)) + i_r
         c.q = ni_t
-        oc = O.OracleColumn(c, ne, phi)           # f = n_e^n + dt s
+        oc = O.OracleColumn(c, ne, phi)           # f_e = n_e^n + dt src
         r = O.newton(oc, k_ne.copy(), k_phi.copy(), reference=True, floor_tol=tol_floor)
         if r.status != O.CONVERGED:
             raise RuntimeError(f"oracle Newton did not converge in SDC iteration {k}")
@@ -168,15 +191,18 @@ def misdc_step(col, ions: Ions, t: float, ne, phi, ni, k_max: int = 4, keep_iter
     return StepResult(k_ne, k_phi, k_ni, newton, its)
 
 
-def march(col, ions: Ions, steps: int, t0: float = 0.0, k_max: int = 4, ne=None, phi=None, ni=None):
+def march(col, ions: Ions, steps: int, t0: float = 0.0, k_max: int = 4, ne=None, phi=None, ni=None,
+          cfl: Optional[float] = None, electron_sdc: bool = False):
     """steps MISDC steps from (ne, phi, ni) (default: the column's start
-    state with n_i = its ion charge); returns the final state and time."""
+    state with n_i = its ion charge), each of col.dt or, with cfl, of
+    cfl_dt at the step's start; returns the final state and time."""
     ne = col.ne.copy() if ne is None else ne.copy()
     phi = col.phi.copy() if phi is None else phi.copy()
     ni = col.q.copy() if ni is None else ni.copy()
     t = t0
     for _ in range(steps):
-        r = misdc_step(col, ions, t, ne, phi, ni, k_max=k_max)
+        dt = col.dt if cfl is None else cfl_dt(col, ions, t, phi, cfl)
+        r = misdc_step(col, ions, t, ne, phi, ni, k_max=k_max, dt=dt, electron_sdc=electron_sdc)
         ne, phi, ni = r.ne, r.phi, r.ni
-        t += col.dt
+        t += dt
     return ne, phi, ni, t

@@ -1,8 +1,10 @@
-"""Pins of the oracle's MISDC step (Algorithm 1, Section 3.1) against what
-the scheme must satisfy: its fixed point is the trapezoidal rule for the
-electrons, corrections raise the order in time from one to two, particles
-are conserved in closed columns, and the limited Godunov ion update stays
-within the initial bounds.  No GPU is involved."""
+"""Pins of the oracle's MISDC step (Algorithm 1, Section 3.1, with the
+electron/Poisson system eq:nls) against what the scheme must satisfy: its
+fixed point (backward Euler for the electrons' transport, or the trapezoidal
+rule with their SDC correction), the orders in time the corrections reach,
+particles conserved in closed columns, the limited Godunov ion update within
+the initial bounds, the drift velocity and the constant-CFL step in closed
+form.  No GPU is involved."""
 import math
 
 import numpy as np
@@ -16,30 +18,16 @@ def _ions(col, k_rec=1e-13, mu=W.ION_MOBILITY, amp=0.0, freq=0.0):
     return M.Ions(np.full(col.n, mu), np.full(col.n, k_rec), amp, freq)
 
 
-def test_fixed_point_is_the_trapezoidal_rule(orc):
-    """With many SDC iterations the step converges to the trapezoidal rule
-    for the electrons, n_e = n_e^n + dt (T_e^n + T_e^n+1)/2 + dt (R^n + R^n+1)/2,
-    to the time-centred ion update, and Poisson holds with the new ions.
-    Stiff modes (dt D/h^2 >> 1) contract by a factor 1/2 per iteration with
-    the backward-Euler corrector, (dt |lambda|/2)/(1 + dt |lambda|): 40
-    iterations reach the fixed point to rounding."""
+def _fixed_point(orc, electron_sdc, k_max):
     col, ions = W.misdc_column(96, 200.0, ac_amp=300.0, ac_freq=2e4, a_ion=3e15)
     ions = _ions(col, amp=300.0, freq=2e4)
     t = 1.7e-5
     ne, phi, ni = col.ne.copy(), col.phi.copy(), col.q.copy()
-    r = M.misdc_step(col, ions, t, ne, phi, ni, k_max=40, keep_iterates=True)
+    r = M.misdc_step(col, ions, t, ne, phi, ni, k_max=k_max, keep_iterates=True, electron_sdc=electron_sdc)
     dt = col.dt
     Tn = M.electron_transport(col, ions, t, ne, phi)
     Tp = M.electron_transport(col, ions, t + dt, r.ne, r.phi)
     Rn, Rp = M.reaction(col, ions, ne, ni), M.reaction(col, ions, r.ne, r.ni)
-    trap = r.ne - ne - 0.5 * dt * (Tn + Tp) - 0.5 * dt * (Rn + Rp)
-    scale = np.abs(ne) + dt * (np.abs(Tn) + np.abs(Tp) + np.abs(Rn) + np.abs(Rp))
-    assert np.max(np.abs(trap) / scale.max()) < 1e-11
-    # the iterates contract towards it
-    d = [np.max(np.abs(a[0] - b[0])) for a, b in zip(r.iterates[:-1], r.iterates[1:])]
-    assert d[-1] < 1e-9 * d[0]
-    rates = [b / a for a, b in zip(d[:-1], d[1:])]
-    assert max(rates) < 0.7 and 0.4 < np.mean(rates[-10:]) < 0.52, rates
     # ions: the time-centred update with the end-of-step state
     v = 0.5 * (M.ion_face_velocity(col, ions, t, phi) + M.ion_face_velocity(col, ions, t + dt, r.phi))
     ni_ref = ni + dt * (M.ion_advection(col, ni, v, dt, Rn) + 0.5 * (Rn + Rp))
@@ -49,14 +37,66 @@ def test_fixed_point_is_the_trapezoidal_rule(orc):
     c.q = r.ni
     _, fp = orc.residual(orc.OracleColumn(c), r.ne, r.phi)
     assert np.max(np.abs(fp)) < 1e-10 * np.max(np.abs(r.ni))
+    d = [np.max(np.abs(a[0] - b[0])) for a, b in zip(r.iterates[:-1], r.iterates[1:])]
+    scale = np.abs(ne) + dt * (np.abs(Tn) + np.abs(Tp) + np.abs(Rn) + np.abs(Rp))
+    return r, ne, dt, Tn, Tp, Rn, Rp, d, scale.max()
 
 
-def _orders(col, ions, t_end, k_max, start, ms=(4, 8, 16, 32, 64)):
+def test_fixed_point_backward_euler_electrons(orc):
+    """Default reading (eq:nls): many SDC iterations converge to backward
+    Euler for the electrons' transport with trapezoidal chemistry,
+    n_e = n_e^n + dt T_e^n+1 + dt (R^n + R^n+1)/2, to the time-centred ion
+    update, and Poisson holds with the new ions.  The iteration only feeds
+    the chemistry and the ions back: it contracts quickly."""
+    r, ne, dt, Tn, Tp, Rn, Rp, d, scale = _fixed_point(orc, False, 20)
+    be = r.ne - ne - dt * Tp - 0.5 * dt * (Rn + Rp)
+    assert np.max(np.abs(be)) / scale < 1e-11
+    trap = r.ne - ne - 0.5 * dt * (Tn + Tp) - 0.5 * dt * (Rn + Rp)
+    assert np.max(np.abs(trap)) / scale > 1e-4          # not the trapezoidal rule
+    assert d[12] < 1e-12 * d[0]
+
+
+def test_fixed_point_trapezoidal_with_electron_sdc(orc):
+    """With the SDC correction of the electron transport the fixed point is
+    the trapezoidal rule for the electrons,
+    n_e = n_e^n + dt (T_e^n + T_e^n+1)/2 + dt (R^n + R^n+1)/2.  Stiff modes
+    (dt D/h^2 >> 1) contract by a factor 1/2 per iteration with the
+    backward-Euler corrector, (dt |lambda|/2)/(1 + dt |lambda|): 40
+    iterations reach the fixed point to rounding."""
+    r, ne, dt, Tn, Tp, Rn, Rp, d, scale = _fixed_point(orc, True, 40)
+    trap = r.ne - ne - 0.5 * dt * (Tn + Tp) - 0.5 * dt * (Rn + Rp)
+    assert np.max(np.abs(trap)) / scale < 1e-11
+    assert d[-1] < 1e-9 * d[0]
+    rates = [b / a for a, b in zip(d[:-1], d[1:])]
+    assert max(rates) < 0.7 and 0.4 < np.mean(rates[-10:]) < 0.52, rates
+
+
+def test_cfl_time_step_closed_form():
+    """The constant-CFL step: cfl h / max |u + mu_i E| in a uniform field
+    (linear potential, the walls at half a cell), capped by the column's dt;
+    the column's dt when nothing moves."""
+    n = 40
+    col, _ = W.misdc_column(n, 300.0)
+    col.dt = 1.0
+    h = col.length / n
+    phi = 300.0 * W.cell_centres(n, col.length) / col.length
+    v = W.ION_MOBILITY * 300.0 / col.length
+    assert M.cfl_dt(col, _ions(col), 0.0, phi, 0.5) == pytest.approx(0.5 * h / v, rel=1e-12)
+    col.uface = np.full(n + 1, 3.0 * v)             # ions drift to -x; a flow of 3 v against it
+    assert M.cfl_dt(col, _ions(col), 0.0, phi, 0.5) == pytest.approx(0.5 * h / (2 * v), rel=1e-12)
+    col.uface = None
+    col.dt = 1e-9
+    assert M.cfl_dt(col, _ions(col), 0.0, phi, 0.5) == 1e-9
+    assert M.cfl_dt(col, _ions(col, mu=0.0), 0.0, phi, 0.5) == 1e-9
+
+
+def _orders(col, ions, t_end, k_max, start, ms=(4, 8, 16, 32, 64), electron_sdc=False):
     res = []
     for m in ms:
         c = col.copy()
         c.dt = t_end / m
-        ne, phi, ni, _ = M.march(c, ions, m, k_max=k_max, ne=start[0], phi=start[1], ni=start[2])
+        ne, phi, ni, _ = M.march(c, ions, m, k_max=k_max, ne=start[0], phi=start[1], ni=start[2],
+                                 electron_sdc=electron_sdc)
         res.append((ne, phi, ni))
     out = []
     for fld in range(3):
@@ -66,40 +106,63 @@ def _orders(col, ions, t_end, k_max, start, ms=(4, 8, 16, 32, 64)):
 
 
 def _relaxed(col, ions, steps):
-    """A state whose stiff electron modes have relaxed (a few large steps):
-    the trapezoidal rule does not damp them, so a study started far from
-    them would mix their undamped transients into the differences."""
+    """A state whose stiff electron modes have relaxed (a few large
+    backward-Euler steps): the trapezoidal rule does not damp them, so a
+    study started far from them would mix their undamped transients into the
+    differences."""
     c = col.copy()
     c.dt = 2e-6
     ne, phi, ni, _ = M.march(c, ions, steps, k_max=2)
     return ne, phi, ni
 
 
-def test_second_order_in_time(orc):
-    """Self-convergence in dt of the MISDC step (Section 4.3: second order in
-    time), 64 cells at 10 V, from a relaxed state.  With the ions held in
-    place (mobility 0: chemistry only) every field converges at second order
-    with k_max = 4 and at first order with the predictor alone (k_max = 1:
-    backward Euler for the electrons, lagged chemistry).  With ions drifting
-    in the middle of the column the orders stay near two (the limited
-    Godunov fluxes clip at the profile's extrema)."""
+def _study_columns():
     n = 64
     col, _ = W.misdc_column(n, 10.0, a_ion=1e15)
     frozen = M.Ions(np.zeros(n), np.full(n, 1e-12))
-    start = _relaxed(col, frozen, 30)
-    for k_max, lo, hi in ((4, 1.9, 2.1), (1, 0.9, 1.1)):
-        for fld, orders in enumerate(_orders(col, frozen, 4e-6, k_max, start)):
-            assert all(lo <= o <= hi for o in orders), (k_max, fld, orders)
     mid = col.copy()
     x = W.cell_centres(n, col.length)
     g = np.exp(-((x - 0.01) / 0.002) ** 2)
     mid.q, mid.ne, mid.src = 1e15 * g, 1e15 * g, 1e21 * g
-    drift = _ions(mid, k_rec=1e-12)
+    return col, frozen, mid, _ions(mid, k_rec=1e-12)
+
+
+def test_time_orders_backward_euler_electrons(orc):
+    """Self-convergence in dt, 64 cells at 10 V, from a relaxed state, in
+    the default reading: with the ions held in place (mobility 0) the ions
+    converge at second order with k_max = 4 (trapezoidal chemistry), the
+    electrons near it (they follow the ions' quasi-equilibrium) and the
+    potential at first order (the backward-Euler transport); the predictor
+    alone (k_max = 1, lagged chemistry) is first order in every field."""
+    col, frozen, mid, drift = _study_columns()
+    start = _relaxed(col, frozen, 30)
+    ne_o, phi_o, ni_o = _orders(col, frozen, 4e-6, 4, start)
+    assert all(o > 1.8 for o in ne_o) and all(1.9 <= o <= 2.1 for o in ni_o), (ne_o, ni_o)
+    assert all(0.9 <= o <= 1.1 for o in phi_o), phi_o
+    for fld, orders in enumerate(_orders(col, frozen, 4e-6, 1, start)):
+        assert all(0.9 <= o <= 1.1 for o in orders), (fld, orders)
+    # drifting ions: the potential's first-order error reaches them through v
     out = _orders(mid, drift, 4e-6, 4, _relaxed(mid, drift, 5))
+    assert np.mean(out[2]) > 1.5 and all(0.85 <= o <= 1.1 for o in out[1]), out
+
+
+def test_time_orders_with_electron_sdc(orc):
+    """Section 4.3's second order in time with the electrons' SDC
+    correction: with frozen ions every field converges at second order with
+    k_max = 4 and at first order with the predictor alone; with ions
+    drifting in the middle of the column the orders stay near two (the
+    limited Godunov fluxes clip at the profile's extrema)."""
+    col, frozen, mid, drift = _study_columns()
+    start = _relaxed(col, frozen, 30)
+    for k_max, lo, hi in ((4, 1.9, 2.1), (1, 0.9, 1.1)):
+        for fld, orders in enumerate(_orders(col, frozen, 4e-6, k_max, start, electron_sdc=True)):
+            assert all(lo <= o <= hi for o in orders), (k_max, fld, orders)
+    out = _orders(mid, drift, 4e-6, 4, _relaxed(mid, drift, 5), electron_sdc=True)
     assert np.mean(out[0]) > 1.6 and np.mean(out[2]) > 1.5, out
 
 
-def test_closed_columns_conserve_particles(orc):
+@pytest.mark.parametrize("electron_sdc", [False, True])
+def test_closed_columns_conserve_particles(orc, electron_sdc):
     """Zero-flux electron walls, ions far from the electrodes and no
     chemistry: every SDC iterate keeps the number of electrons and of ions
     (the transport operators are in flux form)."""
@@ -111,7 +174,7 @@ def test_closed_columns_conserve_particles(orc):
     bump = 1e15 * np.exp(-((x - 0.01) / 0.001) ** 2)
     ions = _ions(col, k_rec=0.0)
     ne, phi, ni = bump.copy(), col.phi.copy(), bump.copy()
-    r = M.misdc_step(col, ions, 0.0, ne, phi, ni, k_max=4, keep_iterates=True)
+    r = M.misdc_step(col, ions, 0.0, ne, phi, ni, k_max=4, keep_iterates=True, electron_sdc=electron_sdc)
     for k, (a, _, b) in enumerate(r.iterates):
         assert abs(a.sum() - ne.sum()) <= 1e-11 * ne.sum(), k
         assert abs(b.sum() - ni.sum()) <= 1e-13 * ni.sum(), k
