@@ -312,6 +312,9 @@ def run_gpu(args):
     del prob, ne, phi, ne0, phi0
     if not args.skip_stiff:
         out["stiff"] = run_stiff(J, args, net, stream, parities)
+    if not args.skip_misdc:
+        out["misdc"] = run_misdc(J, args, stream)
+        torch.cuda.empty_cache()
     out["parities"] = parities
     if net is not None:
         net.close()
@@ -411,6 +414,98 @@ def run_stiff(J, args, net, stream, parities):
                                f"0..{STIFF_EPISODE - 1}, FP64 factors, extrapolated guess")
     out["speedup_vs_plain"] = out["value"] / out["plain"]["value"]
     return out
+
+
+MISDC_CFL = 0.5
+MISDC_DT_CAP = 1e-6
+
+
+def run_misdc(J, args, stream):
+    """MISDC steps (k_max = 4 SDC iterations, each a batched JFNK solve) of
+    the AC-forced batch: 1000 V at Table 4's frequencies, every column at its
+    own phase, each step at ion-drift CFL 0.5 (Section 4.1).  The warm-up
+    steps are backward-Euler predictor steps (k_max = 1) that relax the
+    electrons from the columns' initial n_e = n_i.  Timed over whole MISDC
+    steps; the last timed step's start and result on sampled columns go to
+    the oracle afterwards."""
+    import torch
+    from paper_1904_08510_amd import workloads as W
+    cols, ions, t0 = W.config_ac(ncols=args.misdc_cols, n=args.misdc_cells)
+    for c in cols:
+        c.dt = MISDC_DT_CAP
+    packed = W.pack(cols)
+    prob, ne, phi, _, _ = J.device_problem(packed, "cuda:0")
+    prob.kloss = None
+    di = J.device_ions(np.concatenate([i.mu_i for i in ions]), np.concatenate([i.k_rec for i in ions]), packed.q,
+                       np.array([i.ac_amp for i in ions]), np.array([i.ac_freq for i in ions]))
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP32, guess=J.GUESS_EXTRAP))
+    t = t0.copy()
+    dt = np.zeros(len(cols))
+    k_max = 4
+    st = J.Stats(len(cols))
+    for _ in range(args.misdc_warmup):
+        solver.misdc_step(prob, di, t, 1, ne, phi, stream=stream, stats=st, cfl=MISDC_CFL, dt_out=dt)
+        t += dt
+    steps = args.misdc_steps
+    sample = list(range(0, len(cols), max(1, len(cols) // 2)))[:2]
+    off = packed.col_offset
+    newton = gmres = conv = 0
+    dts = []
+    t_snap = 0.0
+    torch.cuda.synchronize()
+    tic = time.perf_counter()
+    for k in range(steps):
+        if k == steps - 1:
+            # start of the last step on the sampled columns (this copy is not timed)
+            t_snap = time.perf_counter()
+            snap = [(ne[off[c]:off[c + 1]].cpu().numpy().copy(), phi[off[c]:off[c + 1]].cpu().numpy().copy(),
+                     di.n_ion[off[c]:off[c + 1]].cpu().numpy().copy(), float(t[c])) for c in sample]
+            t_snap = time.perf_counter() - t_snap
+        rc, _ = solver.misdc_step(prob, di, t, k_max, ne, phi, stream=stream, stats=st, cfl=MISDC_CFL, dt_out=dt)
+        t += dt
+        dts.append(dt.copy())
+        newton += int(st.newton_iters.sum())
+        gmres += int(st.gmres_iters.sum())
+        conv += int(np.sum(st.status == 0))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - tic - t_snap
+    got = [(ne[off[c]:off[c + 1]].cpu().numpy(), phi[off[c]:off[c + 1]].cpu().numpy(),
+            di.n_ion[off[c]:off[c + 1]].cpu().numpy(), float(dts[-1][c])) for c in sample]
+    solver.close()
+    total = len(cols) * steps
+    dts = np.array(dts)
+    return dict(value=conv / elapsed, unit="column-steps/s", converged=conv, total=total,
+                ms_per_step=1e3 * elapsed / steps, k_max=k_max,
+                newton_per_sdc_iteration=newton / (total * k_max), gmres_per_newton=gmres / max(newton, 1),
+                dt_s=dict(min=float(dts.min()), median=float(np.median(dts)), max=float(dts.max())),
+                workload=f"{len(cols)} columns x {args.misdc_cells} cells, right electrode 1000 V sin(2 pi f t), "
+                         f"f cycling through Table 4 (1k..100k Hz), random phase, ion peak logU[1e15,1e17], "
+                         f"dt at ion-drift CFL {MISDC_CFL} (cap {MISDC_DT_CAP:g} s), k_max=4, backward-Euler "
+                         f"electrons (eq:nls), FP32 factors, extrapolated predictor guess (seed 77); "
+                         f"{args.misdc_warmup} backward-Euler warm-up steps",
+                parity_sample=dict(columns=sample, start=snap, got=got, cols=[cols[c] for c in sample],
+                                   ions=[ions[c] for c in sample]))
+
+
+def misdc_oracle_parity(rec):
+    """Relative L2 differences of the sampled columns' last timed MISDC step
+    against the oracle's step from the same start, at the oracle's own CFL
+    step (checked against the step the GPU took)."""
+    from oracle import misdc as M
+    t0 = time.perf_counter()
+    out = []
+    for c, col, ion, (ne, phi, ni, t), (gn, gp, gi, gdt) in zip(rec["columns"], rec["cols"], rec["ions"],
+                                                                rec["start"], rec["got"]):
+        oi = M.Ions(ion.mu_i, ion.k_rec, ion.ac_amp, ion.ac_freq)
+        dt = M.cfl_dt(col, oi, t, phi, MISDC_CFL)
+        r = M.misdc_step(col, oi, t, ne, phi, ni, k_max=4, dt=dt)
+        out.append(dict(column=int(c), cells=int(col.n), dt_rel_diff=abs(gdt - dt) / dt,
+                        rel_l2_ne=float(np.linalg.norm(gn - r.ne) / np.linalg.norm(r.ne)),
+                        rel_l2_phi=float(np.linalg.norm(gp - r.phi) / max(np.linalg.norm(r.phi), 1e-300)),
+                        rel_l2_ni=float(np.linalg.norm(gi - r.ni) / np.linalg.norm(r.ni))))
+    return dict(steps=1, columns=out,
+                worst=max(max(x["rel_l2_ne"], x["rel_l2_phi"], x["rel_l2_ni"], x["dt_rel_diff"]) for x in out),
+                oracle_s=time.perf_counter() - t0)
 
 
 def _cpu_column_episode(args):
@@ -546,6 +641,11 @@ def main():
     ap.add_argument("--stiff-episodes", type=int, default=2)
     ap.add_argument("--stiff-plain-cols", type=int, default=4)
     ap.add_argument("--stiff-parity-cols", type=int, default=2)
+    ap.add_argument("--skip-misdc", action="store_true")
+    ap.add_argument("--misdc-cols", type=int, default=1024)
+    ap.add_argument("--misdc-cells", type=int, default=1024)
+    ap.add_argument("--misdc-steps", type=int, default=10)
+    ap.add_argument("--misdc-warmup", type=int, default=3)
     ap.add_argument("--calib-copy", action="store_true",
                     help="one 256 MiB device copy first (HBM counter calibration)")
     args = ap.parse_args()
@@ -561,6 +661,11 @@ def main():
     # after the GPU legs, on the states those legs produced)
     if cpu is not None and g["parities"]:
         cpu["parity"] = {name: oracle_parity(cols, par, ep) for name, (cols, par, ep) in g["parities"].items()}
+    misdc = g.get("misdc")
+    if misdc is not None:
+        rec = misdc.pop("parity_sample")
+        if cpu is not None and not args.skip_parity:
+            cpu.setdefault("parity", {})["misdc_fp32"] = misdc_oracle_parity(rec)
     # the headline carries the learned guess only if the network was evaluated
     learned_label = args.guess == "learned" and g["learned_evaluated"] > 0
     if args.guess == "learned" and not learned_label:
@@ -610,6 +715,7 @@ def main():
                                                                evaluated=g["learned_evaluated"]),
         "speedup_vs_plain": (g["value"] / g["plain"]["value"]) if g.get("plain") else None,
         "stiff": g.get("stiff"),
+        "misdc": misdc,
         "solver": {
             "converged": g["converged"], "column_steps": g["total"], "max_res": g["max_res"],
             "newton_mean": g["newton_mean"], "newton_max": g["newton_max"],

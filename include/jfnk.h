@@ -277,6 +277,72 @@ int jfnk_step_async(jfnk_ctx *ctx, const jfnk_problem *p, jfnk_state *x, jfnk_st
    JFNK_NOT_CONVERGED for it; JFNK_EINVAL when no step is in flight. */
 int jfnk_step_finish(jfnk_ctx *ctx, jfnk_stats *st);
 
+/* MISDC time step (the paper's Algorithm 1 with the provisional charged
+ * species of Section 3.1 and the electron/Poisson system eq:nls of Section
+ * 3.2, restricted to the charged species): electrons and the potential
+ * implicit, one positive ion species explicit, chemistry
+ * R = S - k_rec n_e n_i shared by both (S: the problem's src).  With A the
+ * ion advection -div(n_i v) (second-order Godunov: monotonised-central
+ * limited slopes, face values extrapolated to the half step with the upwind
+ * cell's forcing R^n - n_i div v; electrodes absorb ions; v = u + mu_ion E
+ * with the potential's face gradient, h/2 and the electrode potential at a
+ * wall), iteration k = 0 .. k_max-1 from X^(0) = X^n, n_i^(0) = n_i^n forms
+ *   I_R    = (R^n + R^(k)) / 2                 (chemistry over the step / dt)
+ *   v      = (v(phi^n, t^n) + v(phi^(k), t^n+1)) / 2
+ *   n_i~   = n_i^n + dt [A(n_i^n; v) + I_R]
+ *   s      = I_R  (electron_sdc = 0: eq:nls, backward Euler for the
+ *            electrons' transport), or
+ *   s      = (T_e^n - T_e^(k)) / 2 + I_R  (electron_sdc = 1: the SDC
+ *            correction of the other species' diffusion applied to the
+ *            electrons, T_e = -div Gamma with the solve's Scharfetter-Gummel
+ *            fluxes and the electrode potential of the state's time; its
+ *            fixed point is the trapezoidal rule, second order in time but
+ *            not L-stable)
+ * and solves the backward-Euler system of jfnk_step with f = n_e^n + dt s,
+ * no implicit loss, ion charge n_i~ and phi_right(t^n+1) for X^(k+1) (its
+ * Newton iteration starting from X^(k)); n_i^(k+1) = n_i~.  The right
+ * electrode potential is phi_right + A sin(2 pi f t) (Section 4.5's AC
+ * forcing; DC when A = 0); phi_left is constant.  With cfl > 0 the step is
+ * dt = min(p->dt, cfl h / max_f |v_f(phi^n, t^n)|) per column (Section
+ * 4.1: the explicit ion advection limits the step), else p->dt.
+ *
+ * p: as for jfnk_step, with src the ionisation source S, k_loss NULL
+ *    (losses come from the recombination term), q_ion not read (may be NULL)
+ *    and phi_right the DC part of the right electrode potential.
+ * m: k_max, electron_sdc, cfl (HOST scalars), t, ac_amp, ac_freq (HOST
+ *    [ncols]; ac_amp and ac_freq both or neither), mu_ion >= 0 and
+ *    k_rec >= 0 (DEVICE [total]; a cell outside that domain, or a non-finite
+ *    n_ion, makes its column JFNK_COL_BAD_INPUT: it keeps X^n and n_i^n),
+ *    n_ion (DEVICE [total], in: n_i^n, out: n_i^n+1), dt_used (HOST [ncols],
+ *    may be NULL: the step each column took).
+ * x: ne/phi in: X^n, out: X^n+1 (or in ne_out/phi_out when given);
+ *    ne_prev/phi_prev, when given, serve the predictor's guess (k = 0) as in
+ *    jfnk_step; later iterations start from X^(k).
+ * st: per column, status = the first non-converged status of the k_max
+ *    solves (else converged); newton_iters, gmres_iters, backtracks,
+ *    chord_steps, phase_counts and mg_cycles summed over them; guess_used
+ *    of the predictor; res_scaled of the last solve.
+ * The first call allocates 11 x capacity cells doubles of device workspace
+ * (kept until jfnk_destroy); the call synchronises the stream after each
+ * iteration's solve.  Returns JFNK_OK, JFNK_NOT_CONVERGED, or an error code
+ * (JFNK_EINVAL also for k_max outside 1..64, a k_loss array, electron_sdc
+ * not 0 or 1, or cfl negative or not finite). */
+typedef struct {
+    int32_t k_max;               /* SDC iterations, 1..64 (1: the predictor, first order) */
+    int32_t electron_sdc;        /* 0: eq:nls (backward Euler); 1: SDC-corrected transport */
+    double cfl;                  /* > 0: constant ion-drift CFL step (capped by p->dt); 0: p->dt */
+    const double *t;             /* HOST [ncols] time at the start of the step, s (NULL: 0) */
+    const double *ac_amp;        /* HOST [ncols] AC amplitude A, V (NULL: DC) */
+    const double *ac_freq;       /* HOST [ncols] AC frequency f, Hz */
+    const double *mu_ion;        /* [total] ion mobility, m^2/(V s) */
+    const double *k_rec;         /* [total] recombination coefficient, m^3/s */
+    double *n_ion;               /* [total] in: n_i^n, out: n_i^n+1, m^-3 */
+    double *dt_used;             /* HOST [ncols] out: the step taken, s (NULL: not reported) */
+} jfnk_misdc;
+
+int jfnk_misdc_step(jfnk_ctx *ctx, const jfnk_problem *p, const jfnk_misdc *m, jfnk_state *x,
+                    jfnk_stats *st, void *stream);
+
 /* Release the context and its workspace.  NULL-safe. */
 void jfnk_destroy(jfnk_ctx *ctx);
 

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "jfnk.h"
+#include "jfnk_misdc.h"
 #include "jfnk_net.h"
 #include "jfnk_solver.h"
 
@@ -22,6 +23,8 @@ constexpr int kTmax = 512;          // largest workgroup that owns a column
 constexpr int kScalSlots = 64;      // doubles of scalar exchange per column
 constexpr int kMaxBackoff = 5;      // a losing learned guess is skipped at up to 4^5 - 1 chances
 constexpr int kMoveTiles = 32;      // 8 x 8-cell tiles per gather / write-back workgroup
+constexpr int kMisdcArrays = 11;    // T_e^n, R^n, s, n_i~ (2), 2X^n - X^(k) (2), X^(k) (2 x 2)
+constexpr int kMisdcMaxK = 64;      // SDC iterations per step
 
 // ---------------------------------------------------------------------------
 // Batched schedule: one workgroup per column, whole step in one launch.
@@ -360,6 +363,12 @@ struct jfnk_ctx {
     bool pending = false;          // an asynchronous step is in flight (its resources in alt)
     int pending_ncols = 0;
     hipStream_t pending_stream = nullptr;
+    // MISDC step: workspace allocated by its first call
+    double* mis = nullptr;         // [kMisdcArrays][capP]
+    MisdcCol* d_mis = nullptr;     // [max_cols]
+    MisdcCol* h_mis = nullptr;     // pinned
+    double* d_vmax = nullptr;      // [max_cols] largest ion drift speed per column
+    double* h_vmax = nullptr;      // pinned
 };
 
 namespace {
@@ -1182,6 +1191,84 @@ int static_fail(char* err, size_t len, int code, const char* msg) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// MISDC step (Algorithm 1 and the SDC update of Section 3.1 around the
+// electron/potential solve): one launch of the SDC terms per iteration, then
+// the batched (or plain) JFNK step on the corrected problem.  Iteration k
+// solves from X^n with f = n_e^n + dt s^(k) and ion charge n_i~; its Newton
+// iteration starts from X^(k) by way of the extrapolated guess with
+// X^{n-1} := 2 X^n - X^(k).
+// ---------------------------------------------------------------------------
+namespace {
+
+template <bool TAB>
+int misdc_launch(jfnk_ctx* ctx, const MisdcArgs& a, int ncols, int nmax, int k, hipStream_t st) {
+    const dim3 grid(ncols, (nmax + 255) / 256);
+    if (k < 0)
+        hipLaunchKernelGGL(k_misdc_start<TAB>, grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_misdc_iter<TAB>, grid, dim3(256), 0, st, a, k == 0 ? 1 : 0);
+    HIP_OK(hipGetLastError());
+    return JFNK_OK;
+}
+
+int misdc_alloc(jfnk_ctx* ctx) {
+    if (ctx->mis) return JFNK_OK;
+    hipError_t e = hipMalloc((void**)&ctx->mis, sizeof(double) * kMisdcArrays * ctx->capP);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_mis, sizeof(MisdcCol) * ctx->cfg.max_cols);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_mis, sizeof(MisdcCol) * ctx->cfg.max_cols, 0);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_vmax, sizeof(double) * ctx->cfg.max_cols);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_vmax, sizeof(double) * ctx->cfg.max_cols, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (ctx->mis) (void)hipFree(ctx->mis);
+        if (ctx->d_mis) (void)hipFree(ctx->d_mis);
+        if (ctx->h_mis) (void)hipHostFree(ctx->h_mis);
+        if (ctx->d_vmax) (void)hipFree(ctx->d_vmax);
+        ctx->mis = nullptr;
+        ctx->d_mis = nullptr;
+        ctx->h_mis = nullptr;
+        ctx->d_vmax = nullptr;
+        return fail(ctx, JFNK_ENOMEM, "MISDC workspace allocation failed");
+    }
+    return JFNK_OK;
+}
+
+// per-column statistics of one SDC iteration, summed into the step's
+struct IterStats {
+    std::vector<int32_t> status, newton, gmres, backtracks, guess, chords, phases, mg;
+    std::vector<double> res;
+    jfnk_stats view{};
+    explicit IterStats(int n)
+        : status(n), newton(n), gmres(n), backtracks(n), guess(n), chords(n), phases((size_t)n * kWorkCounts), mg(n),
+          res(n) {
+        view = {status.data(), newton.data(), gmres.data(), backtracks.data(), guess.data(), res.data(),
+                chords.data(), phases.data(), mg.data()};
+    }
+};
+
+void misdc_accumulate(const IterStats& it, int ncols, bool first, jfnk_stats* st) {
+    if (!st) return;
+    for (int c = 0; c < ncols; ++c) {
+        if (st->status && (first || st->status[c] == JFNK_COL_CONVERGED)) st->status[c] = it.status[c];
+        auto add = [&](int32_t* dst, int32_t v) { if (dst) dst[c] = first ? v : dst[c] + v; };
+        add(st->newton_iters, it.newton[c]);
+        add(st->gmres_iters, it.gmres[c]);
+        add(st->backtracks, it.backtracks[c]);
+        add(st->chord_steps, it.chords[c]);
+        add(st->mg_cycles, it.mg[c]);
+        if (st->phase_counts)
+            for (int i = 0; i < kWorkCounts; ++i) {
+                int32_t& d = st->phase_counts[(int64_t)c * kWorkCounts + i];
+                d = (first ? 0 : d) + it.phases[(size_t)c * kWorkCounts + i];
+            }
+        if (st->guess_used && first) st->guess_used[c] = it.guess[c];
+        if (st->res_scaled) st->res_scaled[c] = it.res[c];
+    }
+}
+
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1282,6 +1369,11 @@ void jfnk_destroy(jfnk_ctx* ctx) {
     if (ctx->d_lmask) (void)hipFree(ctx->d_lmask);
     if (ctx->h_lmask) (void)hipHostFree(ctx->h_lmask);
     if (ctx->evdone) (void)hipEventDestroy(ctx->evdone);
+    if (ctx->mis) (void)hipFree(ctx->mis);
+    if (ctx->d_mis) (void)hipFree(ctx->d_mis);
+    if (ctx->h_mis) (void)hipHostFree(ctx->h_mis);
+    if (ctx->d_vmax) (void)hipFree(ctx->d_vmax);
+    if (ctx->h_vmax) (void)hipHostFree(ctx->h_vmax);
     jfnk_ctx::Slot& a = ctx->alt;
     if (a.h_cst) (void)hipHostFree(a.h_cst);
     if (a.h_order) (void)hipHostFree(a.h_order);
@@ -1366,6 +1458,157 @@ int jfnk_step_finish(jfnk_ctx* ctx, jfnk_stats* stt) {
     swap_slot(ctx);
     ctx->pending = false;
     return step_process(ctx, ctx->pending_ncols, stt);
+}
+
+int jfnk_misdc_step(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_misdc* m, jfnk_state* x, jfnk_stats* stt,
+                    void* stream) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!p || !m || !x) return fail(ctx, JFNK_EINVAL, "null problem, MISDC data or state");
+    if (m->k_max < 1 || m->k_max > kMisdcMaxK) return fail(ctx, JFNK_EINVAL, "k_max must be in 1..64");
+    if (!m->mu_ion || !m->k_rec || !m->n_ion) return fail(ctx, JFNK_EINVAL, "null ion array");
+    if ((m->ac_amp == nullptr) != (m->ac_freq == nullptr))
+        return fail(ctx, JFNK_EINVAL, "ac_amp and ac_freq must both be given or both NULL");
+    if (p->k_loss) return fail(ctx, JFNK_EINVAL, "the MISDC step takes losses from its chemistry: k_loss must be NULL");
+    if (m->electron_sdc != 0 && m->electron_sdc != 1) return fail(ctx, JFNK_EINVAL, "electron_sdc must be 0 or 1");
+    if (!(m->cfl >= 0.0) || !std::isfinite(m->cfl)) return fail(ctx, JFNK_EINVAL, "cfl must be finite and >= 0");
+    if (ctx->cfg.guess == JFNK_GUESS_LEARNED && !ctx->model)
+        return fail(ctx, JFNK_EMODEL, "learned guess requested but no model is loaded");
+    rc = drain(ctx);
+    if (rc) return rc;
+    rc = misdc_alloc(ctx);
+    if (rc) return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    const int64_t P = ctx->capP;
+    double* A = ctx->mis;
+    double *Tn = A, *Rn = A + P, *S = A + 2 * P, *Q[2] = {A + 3 * P, A + 4 * P}, *PN = A + 5 * P, *PP = A + 6 * P;
+    double *BN[2] = {A + 7 * P, A + 9 * P}, *BP[2] = {A + 8 * P, A + 10 * P};
+    if (p->ncols < 1) return fail(ctx, JFNK_EINVAL, "ncols < 1");
+    if (p->ncols > ctx->cfg.max_cols) return fail(ctx, JFNK_ECAPACITY, "ncols exceeds capacity");
+    if (!p->src || !p->phi_right) return fail(ctx, JFNK_EINVAL, "null per-cell or per-column array");
+    const int ncols = p->ncols;
+    // the problem as every iteration passes it to the solve: validated before
+    // the first launch unless it is the one the resident schedule was built from
+    std::vector<double> phir1(p->phi_right, p->phi_right + ncols);
+    jfnk_problem p2 = *p;
+    p2.src = S;
+    p2.q_ion = Q[0];
+    p2.k_loss = nullptr;
+    p2.phi_right = phir1.data();
+    {
+        jfnk_state xv = *x;
+        if (schedule_matches(ctx, &p2)) {
+            if (const char* why = check_cells(&p2, &xv)) return fail(ctx, JFNK_EINVAL, why);
+        } else {
+            ctx->sched_valid = false;
+            rc = validate(ctx, &p2, &xv);
+            if (rc) return rc;
+        }
+    }
+    int nmax = 0;
+    std::vector<double> dtv(p->dt, p->dt + ncols);
+    for (int c = 0; c < ncols; ++c) {
+        MisdcCol& mc = ctx->h_mis[c];
+        mc.off = p->col_offset[c];
+        mc.foff = p->col_offset[c] + c;
+        mc.n = (int32_t)(p->col_offset[c + 1] - p->col_offset[c]);
+        mc.bcl = p->bc_left[c];
+        mc.bcr = p->bc_right[c];
+        mc.pad = 0;
+        mc.h = p->length[c] / mc.n;
+        mc.dt = p->dt[c];
+        mc.nel = p->ne_left[c];
+        mc.ner = p->ne_right[c];
+        mc.phil = p->phi_left[c];
+        const double amp = m->ac_amp ? m->ac_amp[c] : 0.0, fr = m->ac_freq ? m->ac_freq[c] : 0.0;
+        const double t0 = m->t ? m->t[c] : 0.0;
+        if (!std::isfinite(amp) || !std::isfinite(fr) || !std::isfinite(t0))
+            return fail(ctx, JFNK_EINVAL, "non-finite start time, AC amplitude or frequency");
+        mc.phir_n = p->phi_right[c] + amp * std::sin(2.0 * M_PI * fr * t0);
+        nmax = std::max(nmax, mc.n);
+    }
+    if ((nmax + 255) / 256 > 65535) return fail(ctx, JFNK_ECAPACITY, "column too long for the MISDC launch");
+    MisdcArgs a{};
+    a.cols = ctx->d_mis;
+    a.mu = p->mu; a.diff = p->diff; a.src = p->src; a.mu_i = m->mu_ion; a.k_rec = m->k_rec;
+    a.uface = p->u_face; a.prog = p->prog; a.gasn = p->gas_n; a.tab = tab_of(p);
+    a.ne0 = x->ne; a.phi0 = x->phi; a.ni0 = m->n_ion;
+    a.Tn = Tn; a.Rn = Rn; a.s = S; a.pn = PN; a.pp = PP;
+    a.vmax = ctx->d_vmax;
+    a.esdc = m->electron_sdc;
+    if (m->cfl > 0.0) {
+        // the step from the start-of-step drift speeds (NaN speeds keep p->dt;
+        // the solve then flags the column's non-finite inputs)
+        HIP_OK(hipMemcpyAsync(ctx->d_mis, ctx->h_mis, sizeof(MisdcCol) * ncols, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_misdc_vmax, dim3(ncols), dim3(256), 0, st, a);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpyAsync(ctx->h_vmax, ctx->d_vmax, sizeof(double) * ncols, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        for (int c = 0; c < ncols; ++c) {
+            const double h = p->length[c] / (double)(p->col_offset[c + 1] - p->col_offset[c]);
+            const double vm = ctx->h_vmax[c];
+            if (vm > 0.0 && std::isfinite(vm)) dtv[c] = std::min(p->dt[c], m->cfl * h / vm);
+        }
+    }
+    for (int c = 0; c < ncols; ++c) {
+        MisdcCol& mc = ctx->h_mis[c];
+        const double amp = m->ac_amp ? m->ac_amp[c] : 0.0, fr = m->ac_freq ? m->ac_freq[c] : 0.0;
+        const double t0 = m->t ? m->t[c] : 0.0;
+        mc.dt = dtv[c];
+        mc.phir_1 = p->phi_right[c] + amp * std::sin(2.0 * M_PI * fr * (t0 + mc.dt));
+        phir1[c] = mc.phir_1;
+        if (m->dt_used) m->dt_used[c] = dtv[c];
+    }
+    p2.dt = dtv.data();
+    // (h_mis is not rewritten before the call's final synchronisation)
+    HIP_OK(hipMemcpyAsync(ctx->d_mis, ctx->h_mis, sizeof(MisdcCol) * ncols, hipMemcpyHostToDevice, st));
+    const bool tab = p->table != nullptr;
+    rc = tab ? misdc_launch<true>(ctx, a, ncols, nmax, -1, st) : misdc_launch<false>(ctx, a, ncols, nmax, -1, st);
+    if (rc) return rc;
+    const int32_t guess0 = ctx->cfg.guess;
+    IterStats it(ncols);
+    std::vector<uint8_t> bad(ncols, 0);    // flagged bad input by some iteration's solve
+    int worst = JFNK_OK;
+    for (int k = 0; k < m->k_max; ++k) {
+        const int cur = k & 1, nxt = (k + 1) & 1;
+        a.nek = k == 0 ? x->ne : BN[cur];
+        a.phik = k == 0 ? x->phi : BP[cur];
+        a.nik = k == 0 ? m->n_ion : Q[nxt];
+        a.q = Q[cur];
+        rc = tab ? misdc_launch<true>(ctx, a, ncols, nmax, k, st) : misdc_launch<false>(ctx, a, ncols, nmax, k, st);
+        if (rc) return rc;
+        p2.q_ion = Q[cur];
+        jfnk_state x2{};
+        x2.ne = x->ne;
+        x2.phi = x->phi;
+        x2.ne_prev = k == 0 ? x->ne_prev : PN;
+        x2.phi_prev = k == 0 ? x->phi_prev : PP;
+        const bool last = k == m->k_max - 1;
+        x2.ne_out = last ? x->ne_out : BN[nxt];
+        x2.phi_out = last ? x->phi_out : BP[nxt];
+        ctx->cfg.guess = k == 0 ? guess0 : JFNK_GUESS_EXTRAP;
+        rc = step_enqueue(ctx, &p2, &x2, st);
+        if (rc == JFNK_OK) rc = step_process(ctx, ncols, &it.view);
+        ctx->cfg.guess = guess0;
+        if (rc < 0) return rc;
+        if (rc == JFNK_NOT_CONVERGED) worst = JFNK_NOT_CONVERGED;
+        for (int c = 0; c < ncols; ++c) bad[c] |= it.status[c] == JFNK_COL_BAD_INPUT;
+        misdc_accumulate(it, ncols, k == 0, stt);
+    }
+    // n_i^n+1 = the last n_i~, except in columns flagged bad input (runs of
+    // the other columns copied at once)
+    const double* qf = Q[(m->k_max - 1) & 1];
+    for (int c = 0; c < ncols;) {
+        const bool keep = bad[c] != 0;
+        int e = c + 1;
+        while (e < ncols && (bad[e] != 0) == keep) ++e;
+        if (!keep)
+            HIP_OK(hipMemcpyAsync(m->n_ion + p->col_offset[c], qf + p->col_offset[c],
+                                  sizeof(double) * (p->col_offset[e] - p->col_offset[c]), hipMemcpyDeviceToDevice, st));
+        c = e;
+    }
+    HIP_OK(hipStreamSynchronize(st));
+    return worst;
 }
 
 int jfnk_autotune(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, int32_t steps,

@@ -56,6 +56,12 @@ class jfnk_problem(C.Structure):
                 ("gas_n", C.c_void_p)]
 
 
+class jfnk_misdc(C.Structure):
+    _fields_ = [("k_max", C.c_int32), ("electron_sdc", C.c_int32), ("cfl", C.c_double), ("t", _dp),
+                ("ac_amp", _dp), ("ac_freq", _dp), ("mu_ion", C.c_void_p), ("k_rec", C.c_void_p),
+                ("n_ion", C.c_void_p), ("dt_used", _dp)]
+
+
 class jfnk_state(C.Structure):
     _fields_ = [("ne", C.c_void_p), ("phi", C.c_void_p), ("ne_prev", C.c_void_p),
                 ("phi_prev", C.c_void_p), ("ne_out", C.c_void_p), ("phi_out", C.c_void_p)]
@@ -145,6 +151,9 @@ def lib():
         L.jfnk_step_noalloc.argtypes = [C.POINTER(jfnk_config), C.POINTER(jfnk_problem), C.POINTER(jfnk_state),
                                         C.POINTER(jfnk_stats), C.c_void_p, C.c_char_p, C.c_size_t]
         L.jfnk_step_noalloc.restype = C.c_int
+        L.jfnk_misdc_step.argtypes = [C.c_void_p, C.POINTER(jfnk_problem), C.POINTER(jfnk_misdc),
+                                      C.POINTER(jfnk_state), C.POINTER(jfnk_stats), C.c_void_p]
+        L.jfnk_misdc_step.restype = C.c_int
         _LIB = L
     return _LIB
 
@@ -156,7 +165,7 @@ EXPORTED_SYMBOLS = ("jfnk_config_default", "jfnk_create", "jfnk_step", "jfnk_ste
                     "jfnk_net_create", "jfnk_net_destroy", "jfnk_net_last_error",
                     "jfnk_net_set_params", "jfnk_net_get_params", "jfnk_net_predict",
                     "jfnk_net_grad", "jfnk_net_train_step", "jfnk_set_model", "jfnk_autotune",
-                    "jfnk_step_noalloc")
+                    "jfnk_step_noalloc", "jfnk_misdc_step")
 
 NOALLOC_BYTES = 64 << 20      # JFNK_NOALLOC_BYTES
 NOALLOC_MAX_COLS = 64         # JFNK_NOALLOC_MAX_COLS
@@ -269,6 +278,49 @@ class DeviceTable:
                           self.x_max, _ptr(self.mu), _ptr(self.diff))
 
 
+@dataclass
+class DeviceIons:
+    """Ion species and chemistry of a batch for the MISDC step: per-cell
+    mobility, recombination coefficient and density on the GPU, per-column AC
+    amplitude and frequency of the right electrode on the host."""
+    mu_ion: object
+    k_rec: object
+    n_ion: object
+    ac_amp: Optional[np.ndarray] = None
+    ac_freq: Optional[np.ndarray] = None
+
+    def cstruct(self, t, k_max: int, ncols: int, electron_sdc: bool = False, cfl: float = 0.0,
+                dt_out: Optional[np.ndarray] = None) -> jfnk_misdc:
+        """t: the start time of every column (a scalar) or per column;
+        dt_out: float64 [ncols] receiving the step each column took."""
+        m = jfnk_misdc()
+        m.k_max = int(k_max)
+        m.electron_sdc = 1 if electron_sdc else 0
+        m.cfl = float(cfl)
+        if dt_out is not None:
+            assert dt_out.dtype == np.float64 and dt_out.flags.c_contiguous and dt_out.shape == (ncols,)
+            m.dt_used = dt_out.ctypes.data_as(_dp)
+        keep = [np.ascontiguousarray(np.broadcast_to(np.asarray(t, dtype=np.float64), (ncols,)))]
+        m.t = keep[0].ctypes.data_as(_dp)
+        for name in ("ac_amp", "ac_freq"):
+            v = getattr(self, name)
+            if v is not None:
+                keep.append(np.ascontiguousarray(v, dtype=np.float64))
+                setattr(m, name, keep[-1].ctypes.data_as(_dp))
+        object.__setattr__(self, "_keep", keep)
+        m.mu_ion, m.k_rec, m.n_ion = _ptr(self.mu_ion), _ptr(self.k_rec), _ptr(self.n_ion)
+        return m
+
+
+def device_ions(mu_ion, k_rec, n_ion, ac_amp=None, ac_freq=None, device="cuda") -> DeviceIons:
+    import torch
+
+    def dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+
+    return DeviceIons(dev(mu_ion), dev(k_rec), dev(n_ion), ac_amp, ac_freq)
+
+
 def device_problem(packed, device="cuda") -> tuple:
     """(DeviceProblem, ne, phi, ne_prev, phi_prev) on the GPU from a workloads.Packed."""
     import torch
@@ -280,6 +332,8 @@ def device_problem(packed, device="cuda") -> tuple:
                        packed.phi_right, packed.eps_over_e, packed.bc_left, packed.bc_right,
                        packed.ne_left, packed.ne_right, dev(packed.mu), dev(packed.diff),
                        dev(packed.src), dev(packed.kloss), dev(packed.q), dev(packed.temp))
+    if getattr(packed, "uface", None) is not None:
+        dp.uface = dev(packed.uface)
     tab = getattr(packed, "table", None)
     if tab is not None:
         dp.table = DeviceTable(tab.c_min, tab.c_max, tab.x_min, tab.x_max, dev(tab.mu).contiguous(),
@@ -391,6 +445,25 @@ class Solver:
         s = self._state(ne, phi, ne_prev, phi_prev, ne_out, phi_out)
         st = stats if stats is not None else Stats(prob.ncols)
         rc = lib().jfnk_step(self.h, C.byref(p), C.byref(s), C.byref(st.cstruct()), _stream_ptr(stream))
+        if raw:
+            return rc, st
+        self._check(rc)
+        return rc, st
+
+    def misdc_step(self, prob: DeviceProblem, ions: "DeviceIons", t, k_max: int, ne, phi, ne_prev=None,
+                   phi_prev=None, stream=None, stats: Optional[Stats] = None, raw: bool = False, ne_out=None,
+                   phi_out=None, electron_sdc: bool = False, cfl: float = 0.0, dt_out=None):
+        """One MISDC step t -> t + dt of all columns (jfnk_misdc_step): X in
+        place on ne/phi (or into ne_out/phi_out), the ions in place on
+        ions.n_ion.  The problem's kloss must be None; its q is not read.
+        cfl > 0: the step at that ion-drift CFL number (capped by the
+        problem's dt), reported in dt_out when given."""
+        p = prob.cstruct()
+        m = ions.cstruct(t, k_max, prob.ncols, electron_sdc, cfl, dt_out)
+        s = self._state(ne, phi, ne_prev, phi_prev, ne_out, phi_out)
+        st = stats if stats is not None else Stats(prob.ncols)
+        rc = lib().jfnk_misdc_step(self.h, C.byref(p), C.byref(m), C.byref(s), C.byref(st.cstruct()),
+                                   _stream_ptr(stream))
         if raw:
             return rc, st
         self._check(rc)
