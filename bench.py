@@ -601,8 +601,9 @@ def oracle_parity(cols, par, episode=EPISODE):
 
 
 def measured_traffic():
-    """HBM bytes per solve launch from the committed FETCH_SIZE/WRITE_SIZE
-    counter runs, if they were taken with the current kernel sources."""
+    """HBM bytes per solve launch from the committed counter run (the L2's
+    DRAM-sector counters, 32 B each), if it was taken with the current
+    sources of the step kernels."""
     from paper_1904_08510_amd.profiling import source_hash
     path = os.path.join(ROOT, "profiles", "k_solve_c2_traffic.json")
     if not os.path.exists(path):

@@ -2,6 +2,14 @@
 
     python -m paper_1904_08510_amd.profiling stats <dir>            # --kernel-trace --stats run
     python -m paper_1904_08510_amd.profiling pmc <fetch_dir> <write_dir> <out.json>
+    python -m paper_1904_08510_amd.profiling dram <dir> <out.json>  # one --pmc run of DRAM_COUNTERS
+
+`dram` reads HBM bytes directly from the L2's DRAM-sector counters of gfx950
+(TCC_EA0_RDREQ_DRAM_32B and TCC_EA0_WRREQ_WRITE_DRAM_32B count 32-byte
+sectors, a 64-byte request as 2 and a 128-byte one as 4), with the
+calibration copy as a check rather than a scale, and records the 128-byte
+read requests two ways (TCC_BUBBLE, which the FETCH_SIZE expression prices
+at 128 bytes, and TCC_EA0_RDREQ_128B).
 
 `stats` prints the per-kernel time table of a kernel-trace run.  `pmc`
 combines a FETCH_SIZE run and a WRITE_SIZE run (counters in KiB per
@@ -28,9 +36,15 @@ COPY_KERNEL = "copyBuffer"
 CALIB_BYTES = 256 * 1024 * 1024   # bench.py --calib-copy: one copy of this many bytes
 
 
+# the sources the step kernels (gather, solve, write-back) are compiled from
+STEP_SOURCES = ("jfnk_types.h", "jfnk_column.h", "jfnk_solver.h", "jfnk_lib.hip")
+
+
 def source_hash() -> str:
+    """Hash of the step kernels' sources: counters taken with other sources
+    no longer describe the kernels."""
     h = hashlib.sha256()
-    for path in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+    for path in [os.path.join(HERE, "csrc", f) for f in STEP_SOURCES]:
         with open(path, "rb") as fh:
             h.update(os.path.basename(path).encode())
             h.update(fh.read())
@@ -101,6 +115,41 @@ def pmc(fetch_dir: str, write_dir: str, out_path: str) -> dict:
     return res
 
 
+DRAM_COUNTERS = ("TCC_EA0_RDREQ_DRAM_32B_sum", "TCC_EA0_WRREQ_WRITE_DRAM_32B_sum", "TCC_BUBBLE_sum",
+                 "TCC_EA0_RDREQ_128B_sum")
+
+
+def dram(d: str, out_path: str) -> dict:
+    per = {c: _counter_per_dispatch(d, c) for c in DRAM_COUNTERS}
+    rd, rdc = per["TCC_EA0_RDREQ_DRAM_32B_sum"]
+    wr, wrc = per["TCC_EA0_WRREQ_WRITE_DRAM_32B_sum"]
+    if not rd[SOLVE_KERNEL] or not wr[SOLVE_KERNEL]:
+        raise RuntimeError("no solve dispatches in the counter run")
+
+    def mean(v):
+        return sum(v) / len(v) if v else 0.0
+
+    kernels = {}
+    for k in STEP_KERNELS:
+        if not rd[k]:
+            continue
+        r, w = 32.0 * mean(rd[k]), 32.0 * mean(wr[k])
+        kernels[k] = dict(dispatches=len(rd[k]), read_bytes=r, write_bytes=w, traffic_bytes_per_launch=r + w,
+                          bubble_per_dispatch=mean(per["TCC_BUBBLE_sum"][0][k]),
+                          rdreq_128b_per_dispatch=mean(per["TCC_EA0_RDREQ_128B_sum"][0][k]))
+    copy = None
+    if rdc and wrc:
+        i = max(range(len(rdc)), key=lambda j: rdc[j])
+        copy = dict(read_over_bytes=32.0 * rdc[i] / CALIB_BYTES, write_over_bytes=32.0 * wrc[i] / CALIB_BYTES,
+                    bubble=per["TCC_BUBBLE_sum"][1][i] if per["TCC_BUBBLE_sum"][1] else None,
+                    rdreq_128b=per["TCC_EA0_RDREQ_128B_sum"][1][i] if per["TCC_EA0_RDREQ_128B_sum"][1] else None)
+    res = dict(source_hash=source_hash(), kernel=SOLVE_KERNEL, method="DRAM sector counters x 32 B", copy_check=copy,
+               kernels=kernels, traffic_bytes_per_launch=kernels[SOLVE_KERNEL]["traffic_bytes_per_launch"])
+    with open(out_path, "w") as fh:
+        json.dump(res, fh, indent=1)
+    return res
+
+
 if __name__ == "__main__":
     if len(sys.argv) == 1:
         print(source_hash())
@@ -108,5 +157,7 @@ if __name__ == "__main__":
         print(stats(sys.argv[2]))
     elif sys.argv[1] == "pmc":
         print(json.dumps(pmc(sys.argv[2], sys.argv[3], sys.argv[4]), indent=1))
+    elif sys.argv[1] == "dram":
+        print(json.dumps(dram(sys.argv[2], sys.argv[3]), indent=1))
     else:
         raise SystemExit(__doc__)
