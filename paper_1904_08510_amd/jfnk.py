@@ -14,7 +14,8 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libjfnk.so")
+# the in-tree build; JFNK_LIB names another build of the same sources
+LIB_PATH = os.environ.get("JFNK_LIB", os.path.join(HERE, "libjfnk.so"))
 
 JFNK_OK, JFNK_NOT_CONVERGED = 0, 1
 JFNK_EINVAL, JFNK_ENOMEM, JFNK_EHIP, JFNK_ECAPACITY, JFNK_EMODEL = -1, -2, -3, -4, -5
