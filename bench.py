@@ -30,6 +30,12 @@ if ROOT not in sys.path:
 METRIC = "column-steps/s at ||F||<1e-10, plain vs batched+learned JFNK, 1 MI355X"
 EPISODE = 20
 HBM_PEAK_GBS = 8000.0
+_T0 = time.perf_counter()
+
+
+def note(msg):
+    """A progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"bench.py [{time.perf_counter() - _T0:6.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def gather_bytes_per_cell(has_prev):
@@ -278,6 +284,7 @@ def run_gpu(args):
     net, train_info = (None, None)
     if args.guess == "learned":
         net, train_info = train_guess_net(J, args)
+        note("learned guess trained")
     cols = W.config2(seed=2026, ncols=args.ncols)
     packed = W.pack(cols)
     prob, ne, phi, _, _ = J.device_problem(packed, dev)
@@ -289,6 +296,7 @@ def run_gpu(args):
     out = measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net, stream,
                           parity=not args.skip_parity)
     out["cells"] = int(packed.col_offset[-1])
+    note(f"headline leg: {out['value']:.3e} column-steps/s")
     out["train"] = train_info
     parities = {}
     if out["parity"] is not None:
@@ -302,6 +310,7 @@ def run_gpu(args):
                 continue
             want = pr == J.PREC_FP64 and not args.skip_parity and args.prec == "fp32"
             r = measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, pr, gs, None, stream, ch, parity=want)
+            note(f"ablation {name}: {r['value']:.3e} column-steps/s")
             abl[name] = dict(value=r["value"], ms_per_step=r["ms_per_step"], converged=r["converged"],
                              max_res=r["max_res"], kernel_ms_avg=r["kernel_ms_avg"],
                              newton_mean=r["newton_mean"], chord_mean=r["chord_mean"],
@@ -312,8 +321,10 @@ def run_gpu(args):
     del prob, ne, phi, ne0, phi0
     if not args.skip_stiff:
         out["stiff"] = run_stiff(J, args, net, stream, parities)
+        note(f"stiff leg: {out['stiff']['value']:.3e} column-steps/s")
     if not args.skip_misdc:
         out["misdc"] = run_misdc(J, args, stream)
+        note(f"MISDC leg: {out['misdc']['value']:.3e} column-steps/s")
         torch.cuda.empty_cache()
     out["parities"] = parities
     if net is not None:
@@ -342,6 +353,7 @@ def run_gpu(args):
                             sample=f"{len(idx)} columns (every {args.ncols // len(idx)}th) x "
                                    f"episode steps 0..{args.plain_steps - 1}, FP64 factors, extrapolated guess")
         psolver.close()
+        note(f"plain leg: {out['plain']['value']:.3e} column-steps/s")
     return out
 
 
@@ -656,12 +668,16 @@ def main():
         sys.exit(2)
     # the CPU leg forks its worker processes before this process touches the GPU
     cpu = None if args.skip_cpu else run_cpu(args)
+    if cpu is not None:
+        note(f"CPU oracle leg: {cpu['value']:.3e} column-steps/s on {cpu['cores']} processes")
     g = run_gpu(args)
     traffic = measured_traffic()
     # the oracle's roots of sampled steps of the timed configurations (CPU,
     # after the GPU legs, on the states those legs produced)
     if cpu is not None and g["parities"]:
         cpu["parity"] = {name: oracle_parity(cols, par, ep) for name, (cols, par, ep) in g["parities"].items()}
+    if cpu is not None and g["parities"]:
+        note("oracle parity of the sampled GPU steps done")
     misdc = g.get("misdc")
     if misdc is not None:
         rec = misdc.pop("parity_sample")
