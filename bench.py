@@ -451,6 +451,8 @@ def run_misdc(J, args, stream):
     di = J.device_ions(np.concatenate([i.mu_i for i in ions]), np.concatenate([i.k_rec for i in ions]), packed.q,
                        np.array([i.ac_amp for i in ions]), np.array([i.ac_freq for i in ions]))
     solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP32, guess=J.GUESS_EXTRAP))
+    # workgroup size for this layout, timed on backward-Euler steps of the batch
+    tuned = solver.autotune(prob, ne, phi, steps=3, stream=stream)
     t = t0.copy()
     dt = np.zeros(len(cols))
     k_max = 4
@@ -490,6 +492,7 @@ def run_misdc(J, args, stream):
                 ms_per_step=1e3 * elapsed / steps, k_max=k_max,
                 newton_per_sdc_iteration=newton / (total * k_max), gmres_per_newton=gmres / max(newton, 1),
                 dt_s=dict(min=float(dts.min()), median=float(np.median(dts)), max=float(dts.max())),
+                threads=tuned[0], autotune_ms=tuned[1],
                 workload=f"{len(cols)} columns x {args.misdc_cells} cells, right electrode 1000 V sin(2 pi f t), "
                          f"f cycling through Table 4 (1k..100k Hz), random phase, ion peak logU[1e15,1e17], "
                          f"dt at ion-drift CFL {MISDC_CFL} (cap {MISDC_DT_CAP:g} s), k_max=4, backward-Euler "
@@ -655,6 +658,8 @@ def main():
     ap.add_argument("--stiff-plain-cols", type=int, default=4)
     ap.add_argument("--stiff-parity-cols", type=int, default=2)
     ap.add_argument("--skip-misdc", action="store_true")
+    ap.add_argument("--misdc-only", action="store_true",
+                    help="run only the MISDC leg and print its record (for profiling its kernels)")
     ap.add_argument("--misdc-cols", type=int, default=1024)
     ap.add_argument("--misdc-cells", type=int, default=1024)
     ap.add_argument("--misdc-steps", type=int, default=10)
@@ -666,6 +671,14 @@ def main():
         print(f"bench.py measures one GPU only: the columns are independent and this build runs "
               f"on a single MI355X (asked for --gpus {args.gpus}).", file=sys.stderr)
         sys.exit(2)
+    if args.misdc_only:
+        import torch
+        from paper_1904_08510_amd import jfnk as J
+        torch.cuda.set_device(0)
+        rec = run_misdc(J, args, torch.cuda.current_stream())
+        rec.pop("parity_sample")
+        print(json.dumps({"misdc": rec}), flush=True)
+        return
     # the CPU leg forks its worker processes before this process touches the GPU
     cpu = None if args.skip_cpu else run_cpu(args)
     if cpu is not None:
