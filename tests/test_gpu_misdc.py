@@ -325,3 +325,47 @@ def test_misdc_argument_errors(J):
         rc, _ = solver.misdc_step(prob, di, 0.0, 4, ne, phi, raw=True, cfl=cfl)
         assert rc == J.JFNK_EINVAL and "cfl" in solver.last_error()
     assert torch.equal(ne, before)
+
+
+def test_misdc_benchmark_configuration_matches_oracle(J, M):
+    """The MISDC leg as the benchmark runs it: the AC batch (1024 columns x
+    1024 cells, Table 4's frequencies at 1000 V, each column at its own phase),
+    dt capped at 1e-6 s and set by ion-drift CFL 0.5, FP32 factors, the
+    workgroup size autotuned, three backward-Euler steps (k_max = 1) and then
+    k_max = 4 steps.  Sampled columns (the first, the last, one per forcing
+    frequency) are checked against the oracle at every step from the GPU's
+    start, the CFL step included."""
+    cols, ions, t0 = W.config_ac()
+    for c in cols:
+        c.dt = 1e-6
+    packed = W.pack(cols)
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    prob.kloss = None
+    di = device_ions(J, packed, ions)
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP32, guess=J.GUESS_EXTRAP))
+    tuned = solver.autotune(prob, ne, phi, steps=3)
+    sample = sorted({0, len(cols) - 1} | set(range(1, 8)))
+    off = packed.col_offset
+    t = t0.copy()
+    dt = np.zeros(len(cols))
+    worst = 0.0
+    for k, k_max in enumerate((1, 1, 1, 4, 4)):
+        start = [(ne[off[c]:off[c + 1]].cpu().numpy().copy(), phi[off[c]:off[c + 1]].cpu().numpy().copy(),
+                  di.n_ion[off[c]:off[c + 1]].cpu().numpy().copy()) for c in sample]
+        rc, st = solver.misdc_step(prob, di, t, k_max, ne, phi, cfl=0.5, dt_out=dt)
+        assert rc == J.JFNK_OK, (k, np.flatnonzero(st.status))
+        for (c, s0) in zip(sample, start):
+            oi = oracle_ions(M, ions[c])
+            dref = M.cfl_dt(cols[c], oi, t[c], s0[1], 0.5)
+            assert dt[c] == pytest.approx(dref, rel=1e-14, abs=0), (k, c)
+            r = M.misdc_step(cols[c], oi, t[c], *s0, k_max=k_max, dt=dref)
+            sl = slice(off[c], off[c + 1])
+            for g, ref in ((ne, r.ne), (phi, r.phi), (di.n_ion, r.ni)):
+                e = np.linalg.norm(g[sl].cpu().numpy() - ref) / np.linalg.norm(ref)
+                worst = max(worst, e)
+                assert e <= 1e-9, (k, c, e)
+        t += dt
+        print(f"benchmark MISDC configuration, step {k} (k_max {k_max}): worst rel L2 so far {worst:.1e}",
+              flush=True)
+    print(f"benchmark MISDC configuration (T = {tuned[0]}): {len(sample)} columns x 5 steps, worst rel L2 "
+          f"{worst:.1e}", flush=True)
