@@ -369,3 +369,45 @@ def test_misdc_benchmark_configuration_matches_oracle(J, M):
               flush=True)
     print(f"benchmark MISDC configuration (T = {tuned[0]}): {len(sample)} columns x 5 steps, worst rel L2 "
           f"{worst:.1e}", flush=True)
+
+
+def test_misdc_with_a_learned_guess_keeps_the_oracle_roots(J, M):
+    """A network attached for the predictor's guess (untrained weights: its
+    candidate is evaluated and, if it loses, dropped): every MISDC step still
+    ends at the oracle's result, and later SDC iterations are unaffected (they
+    start from X^(k))."""
+    from paper_1904_08510_amd import train_guess as TG
+    cols, ions = misdc_batch(seed=12, sizes=(64, 300, 777))
+    cols, t0 = relax(M, cols, ions)
+    packed = W.pack(cols)
+    net = J.Net(J.net_default_config(max_cols=packed.ncols, max_total_cells=packed.total))
+    net.set_params(TG.init_params(3))
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    prob.kloss = None
+    di = device_ions(J, packed, ions)
+    solver = J.Solver(J.config_for(packed, prec_precision=J.PREC_FP64, guess=J.GUESS_LEARNED))
+    solver.set_model(net)
+    off = packed.col_offset
+    t = np.array(t0)
+    dt = np.zeros(len(cols))
+    evaluated = 0
+    for k in range(3):
+        start = [a.cpu().numpy().copy() for a in (ne, phi, di.n_ion)]
+        pn = None if k == 0 else torch.from_numpy(prev[0]).cuda()
+        pp = None if k == 0 else torch.from_numpy(prev[1]).cuda()
+        rc, st = solver.misdc_step(prob, di, t, 4, ne, phi, pn, pp, cfl=0.5, dt_out=dt)
+        assert rc == J.JFNK_OK, (k, st.status)
+        evaluated += int(st.phase_counts[:, 7].sum())
+        for i, col in enumerate(cols):
+            sl = slice(off[i], off[i + 1])
+            dref = M.cfl_dt(col, oracle_ions(M, ions[i]), t[i], start[1][sl], 0.5)
+            r = M.misdc_step(col, oracle_ions(M, ions[i]), t[i], start[0][sl], start[1][sl], start[2][sl],
+                             k_max=4, dt=dref)
+            for g, ref in ((ne, r.ne), (phi, r.phi), (di.n_ion, r.ni)):
+                e = np.linalg.norm(g[sl].cpu().numpy() - ref) / np.linalg.norm(ref)
+                assert e <= 1e-9, (k, i, e)
+        prev = start
+        t += dt
+    net.close()
+    print(f"MISDC with a learned guess: candidate evaluated for {evaluated} predictor solves", flush=True)
+    assert evaluated > 0
