@@ -323,8 +323,10 @@ int jfnk_step_finish(jfnk_ctx *ctx, jfnk_stats *st);
  *    chord_steps, phase_counts and mg_cycles summed over them; guess_used
  *    of the predictor; res_scaled of the last solve.
  * The first call allocates 11 x capacity cells doubles of device workspace
- * (kept until jfnk_destroy); the call synchronises the stream after each
- * iteration's solve.  Returns JFNK_OK, JFNK_NOT_CONVERGED, or an error code
+ * and two per-column tables (device and pinned host, capacity columns),
+ * kept until jfnk_destroy; the call synchronises the stream after each
+ * iteration's solve (and once more for the CFL step).  Like every call on a
+ * context it first finishes an asynchronous step in flight.  Returns JFNK_OK, JFNK_NOT_CONVERGED, or an error code
  * (JFNK_EINVAL also for k_max outside 1..64, a k_loss array, electron_sdc
  * not 0 or 1, or cfl negative or not finite). */
 typedef struct {
