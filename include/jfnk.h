@@ -157,9 +157,10 @@ typedef struct {
    and at the field the face carries in the state being evaluated, |E| = the
    potential difference over the face distance (h, h/2 at a wall); the
    residual then depends on phi through them as well.  The finite-difference
-   J.v products see that dependence; the preconditioner's Jacobian holds the
-   coefficients at the state's field (their derivative is left out), and
-   factors are not kept from one step to the next. */
+   J.v products see that dependence, and so does the preconditioner's
+   analytic Jacobian (the table's slope in x, d x / d(dphi) = 1/(dphi ln 10),
+   zero where an argument is clamped); factors are not kept from one step to
+   the next. */
 typedef struct {
     int32_t nc, nx;
     double c_min, c_max, x_min, x_max;

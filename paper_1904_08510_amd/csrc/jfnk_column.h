@@ -128,6 +128,47 @@ __device__ __forceinline__ void face_rgw(const TabRef& t, double a, double b, do
     }
 }
 
+// The same face coefficients and their derivatives with respect to the
+// potential difference dphi across the face (zero without a table, where an
+// argument is clamped to the grid, and at zero field): with x = log10(|E|/N)
+// and E = |dphi| / h_f, dx/d(dphi) = 1 / (dphi ln 10), and the bilinear
+// interpolant's slope in x gives dmu/dx and dD/dx.
+template <bool TAB>
+__device__ __forceinline__ void face_rgw_d(const TabRef& t, double a, double b, double c, double ihf, double dphi,
+                                           double& r, double& g, double& w, double& dr, double& dg, double& dw) {
+    dr = 0.0; dg = 0.0; dw = 0.0;
+    if constexpr (!TAB) {
+        r = a; g = b; w = c;
+    } else {
+        if (!(b > 0.0)) { r = 0.0; g = 0.0; w = 0.0; return; }
+        const double en = fabs(dphi) * ihf / b * 1e21;
+        const double x0 = en > 0.0 ? log10(en) : t.x_min;
+        const bool inside = en > 0.0 && x0 > t.x_min && x0 < t.x_max;
+        const double x = fmin(fmax(x0, t.x_min), t.x_max);
+        const double cv = fmin(fmax(a, t.c_min), t.c_max);
+        const double fc = (cv - t.c_min) / (t.c_max - t.c_min) * (t.nc - 1);
+        const double fx = (x - t.x_min) / (t.x_max - t.x_min) * (t.nx - 1);
+        const int i = min((int)floor(fc), t.nc - 2);
+        const int k = min((int)floor(fx), t.nx - 2);
+        const double wc = fc - i, wx = fx - k;
+        const double mu = tab_interp(t, t.mu, i, k, wc, wx);
+        const double d = tab_interp(t, t.diff, i, k, wc, wx);
+        r = mu / d;
+        g = d * ihf;
+        w = c / d;
+        if (inside) {
+            const double sx = (t.nx - 1) / (t.x_max - t.x_min) / (dphi * 2.302585092994046);
+            const double* m0 = t.mu + (int64_t)i * t.nx;
+            const double* d0 = t.diff + (int64_t)i * t.nx;
+            const double dmu = ((1.0 - wc) * (m0[k + 1] - m0[k]) + wc * (m0[t.nx + k + 1] - m0[t.nx + k])) * sx;
+            const double dd = ((1.0 - wc) * (d0[k + 1] - d0[k]) + wc * (d0[t.nx + k + 1] - d0[t.nx + k])) * sx;
+            dr = (dmu * d - mu * dd) / (d * d);
+            dg = dd * ihf;
+            dw = -c * dd / (d * d);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Workgroup reductions (wave64 butterflies + LDS across waves).  Fixed order:
 // bitwise reproducible from run to run.
@@ -925,14 +966,14 @@ struct Column {
     struct JacRec { double dnA, dnB, dpB, ihf; };
 
     // derivatives of the face flux w.r.t. the left (A) and right (B) states
-    // (with table transport the coefficients are held at the state's field:
-    // their own derivative with respect to the field is left out)
+    // (with table transport including the coefficients' own dependence on
+    // the face's field)
     struct JacFace {
         TabRef tb;
         __device__ __forceinline__ JacRec operator()(double fa, double fb, double fc, double ihf,
                                                      double nA, double pA, double nB, double pB) const {
-            double r, g, w;
-            face_rgw<TAB>(tb, fa, fb, fc, ihf, pB - pA, r, g, w);
+            double r, g, w, dr, dg, dw;
+            face_rgw_d<TAB>(tb, fa, fb, fc, ihf, pB - pA, r, g, w, dr, dg, dw);
             const double pe = w + r * (pB - pA);
             double bx, bmx, dbx, dbmx;
             bernoulli_pair(pe, bx, bmx);
@@ -940,7 +981,13 @@ struct Column {
             JacRec o;
             o.dnA = g * bmx;
             o.dnB = -g * bx;
-            o.dpB = g * r * (-dbmx * nA - dbx * nB);
+            if constexpr (TAB) {
+                // the coefficients follow the face's field: d(Gamma)/d(dphi) =
+                // dGamma/dpe (r + dphi dr + dw) + dGamma/dg dg
+                o.dpB = g * (-dbmx * nA - dbx * nB) * (r + (pB - pA) * dr + dw) + (bmx * nA - bx * nB) * dg;
+            } else {
+                o.dpB = g * r * (-dbmx * nA - dbx * nB);
+            }
             o.ihf = ihf;
             return o;
         }
