@@ -65,8 +65,8 @@ def solve_bytes_per_cell(has_prev, fb, counts):
     setup = 72.0                               # F(X^n): X + 5 coefficients -> F
     if has_prev:
         setup += 32.0                          # same sweep: the extrapolation in, its residual out
-    per_phase = (40.0 + 20.0 * fb,             # factor: X + 3 coefficients -> 20 factor values
-                 32.0 + 20.0 * fb,             # apply: v + 20 factor values -> z
+    per_phase = (40.0 + 16.0 * fb,             # factor: X + 3 coefficients -> 16 factor values
+                 32.0 + 16.0 * fb,             # apply: v + 16 factor values -> z
                  104.0,                        # trial: X + direction + 5 coefficients -> X_t, F_t
                  120.0,                        # J.v: X, z, F, 5 coefficients, 2 basis vectors -> w
                  32.0,                         # CGS pass: w in and out (basis vectors: extra reads)

@@ -311,23 +311,22 @@ struct Column {
     __device__ __forceinline__ CP Zb(int k, int comp) const { return CP{W.Z + 2 * (int64_t)k * W.P + comp}; }
     __device__ __forceinline__ CP dXb(int comp) const { return CP{W.dX + comp}; }
     __device__ __forceinline__ CP schb(int k) const { return CP{W.sch + 2 * (k >> 1) * W.P + (k & 1)}; }
-    // Per-cell factor values (FT), one record per cell for each sweep that
-    // reads them, so a sweep loads whole records with vector instructions:
+    // Per-cell factor values (FT), one record per cell for each group of
+    // values a sweep reads together, so a sweep loads whole records with
+    // vector instructions:
     //   [P][8]  slots 0..7:   m and m A      (apply down sweep)
-    //   [P][4]  slots 8..11:  g = m C        (apply up sweep)
-    //   [P][8]  slots 12..19: a'' and g''    (apply final sweep)
-    //   [P][4]  slots 20..23: approximate-Schur couplings
+    //   [P][4]  slots 8..11:  g = m C        (apply down and back sweeps)
+    //   [P][4]  slots 12..15: a, the left-coupling spike recurrence (back sweep)
+    //   [P][4]  slots 16..19: approximate-Schur couplings
     __device__ __forceinline__ FT* facp(int slot, int64_t s) const {
         FT* base = (FT*)W.fac;
         if (slot < 8) return base + s * 8 + slot;
         if (slot < 12) return base + 8 * W.P + s * 4 + (slot - 8);
-        if (slot < 20) return base + 12 * W.P + s * 8 + (slot - 12);
-        return base + 20 * W.P + s * 4 + (slot - 20);
+        if (slot < 16) return base + 12 * W.P + s * 4 + (slot - 12);
+        return base + 16 * W.P + s * 4 + (slot - 16);
     }
-    // the apply's intermediate d (2 FT per cell) and the factorisation's FP64
-    // temporaries (8 per cell), one record per cell
+    // the apply's intermediate d (2 FT per cell), one record per cell
     __device__ __forceinline__ V2<FT>* tmpp(int64_t s) const { return (V2<FT>*)W.tmp + s; }
-    __device__ __forceinline__ double* ftmpp(int64_t s) const { return W.ftmp + 8 * s; }
     // this thread's chunk entry of per-chunk slot k (SoA over the chunks)
     __device__ __forceinline__ double* red(int k) const { return W.red + cd.red + (int64_t)k * T + t; }
 
@@ -961,7 +960,19 @@ struct Column {
     // Jacobian assembly + factorisation (FP64 arithmetic; per-cell factors
     // stored in FT; reduced per-chunk system kept and factored in FP64).
     // Rows of chunk t: row 0 is the chunk's interface unknown x0(t); rows
-    // j >= 1 are eliminated into  x_j = d''_j - a''_j x0(t) - g''_j x0(t+1).
+    // j >= 1 are eliminated by block LU of the chunk's interior with x0(t)
+    // and x0(t+1) as boundary values:
+    //   m_j = (B_j - A_j g_{j-1})^-1,  g_j = m_j C_j,
+    //   a_1 = m_1 A_1,  a_j = -m_j A_j a_{j-1}     (response to x0(t)),
+    //   d_j = m_j v_j - m_j A_j d_{j-1},
+    //   x_j = d_j - a_j x0(t) - g_j x_{j+1}        (x_M = x0(t+1)).
+    // The interface system needs only the chunk's end rows of the spikes
+    // x_j = d''_j - a''_j x0(t) - g''_j x0(t+1): a''_{M-1} = a_{M-1},
+    // g''_{M-1} = g_{M-1}, and at row 1, from the back substitution unrolled,
+    //   a''_1 = sum_j Q_j a_j,  g''_1 = -Q_M,  d''_1 = sum_j Q_j d_j,
+    //   Q_1 = I,  Q_{j+1} = -Q_j g_j,
+    // which the forward sweeps accumulate as they go; so the factorisation is
+    // one sweep and the apply two (down, then the back substitution).
     // ------------------------------------------------------------------
     struct JacRec { double dnA, dnB, dpB, ihf; };
 
@@ -1021,6 +1032,7 @@ struct Column {
         const double s_en = isfn * sxn, s_ep = isfn * sxp, s_pn = isfp * sxn, s_pp = isfp * sxp;
         Blk<double> A0 = bzero(), B0 = beye(), C0 = bzero();
         Blk<double> gprev = bzero(), aprev = bzero();
+        Blk<double> Q = beye(), a1 = bzero();     // Q_j and the partial sum of a''_1
 
         auto rowproc = [&](int j, int64_t s, const Blk<double>& A, const Blk<double>& B,
                            const Blk<double>& C) {
@@ -1037,9 +1049,10 @@ struct Column {
             store_blk(0, s, m);
             store_blk(4, s, bmul(m, A));
             store_blk(8, s, ga);
-            V4<double>* tr = (V4<double>*)ftmpp(s);
-            tr[0] = V4<double>{al.a, al.b, al.c, al.d};
-            tr[1] = V4<double>{ga.a, ga.b, ga.c, ga.d};
+            store_blk(12, s, al);
+            const Blk<double> qa = bmul(Q, al);
+            a1 = Blk<double>{a1.a + qa.a, a1.b + qa.b, a1.c + qa.c, a1.d + qa.d};
+            Q = bneg(bmul(Q, ga));
             gprev = ga; aprev = al;
         };
 
@@ -1076,7 +1089,7 @@ struct Column {
                     // diag(dt D_f - I, S~) with S~ = L + I_e dt D_r, the Schur
                     // complement with (dt D_f - I)^-1 replaced by -I (scaled units:
                     // -(s_Fn / s_Xn) I)
-                    *(V4<FT>*)facp(20, s) = V4<FT>{(FT)A.b, (FT)B.b, (FT)C.b, (FT)B.c};
+                    *(V4<FT>*)facp(16, s) = V4<FT>{(FT)A.b, (FT)B.b, (FT)C.b, (FT)B.c};
                     const double kap = B.c / s_en;
                     A = Blk<double>{A.a, 0.0, 0.0, A.d + kap * A.b};
                     C = Blk<double>{C.a, 0.0, 0.0, C.d + kap * C.b};
@@ -1092,49 +1105,16 @@ struct Column {
             [&](int64_t s) {
                 const int j = (int)((s - cd.ws) / T);
                 if (prm.prec_kind == 1 || prm.prec_kind == 3) {
-                    *(V4<FT>*)facp(20, s) = V4<FT>{FT(0), FT(0), FT(0), FT(0)};
+                    *(V4<FT>*)facp(16, s) = V4<FT>{FT(0), FT(0), FT(0), FT(0)};
                 }
                 rowproc(j, s, bzero(), beye(), bzero());
             });
 
-        // up sweep: spikes a''_j, g''_j (FP64 recurrences from FP64 temps)
-        Blk<double> a1 = bzero(), g1 = bneg(beye()), aL = bneg(beye()), gL = bzero();
+        // the spikes' end rows (a chunk of one row has no interior: x_1 is
+        // x0(t+1) itself)
+        Blk<double> g1 = bneg(Q), aL = bneg(beye()), gL = bzero();
         if (M >= 2) {
-            Blk<double> an = aprev, gn = gprev;   // row M-1
-            aL = an; gL = gn;
-            store_blk(12, sidx(t, M - 1), an);
-            store_blk(16, sidx(t, M - 1), gn);
-            constexpr int U = 2;
-            // double-buffered groups (unconditional loads, as in the apply)
-            struct GT { Blk<double> aa[U], gg[U]; };
-            auto load_t = [&](int j0, GT& g) {
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int64_t s = sidx(t, max(j0 - u, 1));
-                    const V4<double>* tr = (const V4<double>*)ftmpp(s);
-                    const V4<double> ra = tr[0], rg = tr[1];
-                    g.aa[u] = Blk<double>{ra.a, ra.b, ra.c, ra.d};
-                    g.gg[u] = Blk<double>{rg.a, rg.b, rg.c, rg.d};
-                }
-            };
-            GT gc, gq;
-            if (M >= 3) load_t(M - 2, gc);
-            for (int j0 = M - 2; j0 >= 1; j0 -= U) {
-                load_t(j0 - U, gq);
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int j = j0 - u;
-                    if (j >= 1) {
-                        const int64_t s = sidx(t, j);
-                        an = bsub(gc.aa[u], bmul(gc.gg[u], an));
-                        gn = bneg(bmul(gc.gg[u], gn));
-                        store_blk(12, s, an);
-                        store_blk(16, s, gn);
-                    }
-                }
-                gc = gq;
-            }
-            a1 = an; g1 = gn;
+            aL = aprev; gL = gprev;
         }
         // reduced system row of chunk t
         ldbl* P = lds + Lds<T>::kPcr;
@@ -1474,7 +1454,7 @@ struct Column {
         else block_apply(VecRef{v.p0, v.p1, v.s0, 0.0}, Y0, Y1);       // Y0 = z_e'
         for (int j = 0; j < M; ++j) {
             const int64_t s = sidx(t, j);
-            Y2[s] = v.p1[s] * v.s1 - (double)*facp(23, s) * Y0[s];        // v_phi - I_e z_e'
+            Y2[s] = v.p1[s] * v.s1 - (double)*facp(19, s) * Y0[s];        // v_phi - I_e z_e'
         }
         if (mg_p) mg_solve(1, Y2, 1.0, z1);
         else block_apply(VecRef{Y2, Y2, 0.0, 1.0}, Y3, z1);             // z1 = z_phi
@@ -1487,7 +1467,7 @@ struct Column {
             if (c < n) {
                 const double zl = c > 0 ? z1[sidx((c - 1) / M, (c - 1) % M)] : 0.0;
                 const double zr = c < n - 1 ? z1[sidx((c + 1) / M, (c + 1) % M)] : 0.0;
-                w = (double)*facp(20, s) * zl + (double)*facp(21, s) * z1[s] + (double)*facp(22, s) * zr;
+                w = (double)*facp(16, s) * zl + (double)*facp(17, s) * z1[s] + (double)*facp(18, s) * zr;
             }
             Y2[s] = w;
         }
@@ -1522,28 +1502,35 @@ struct Column {
 #pragma unroll
         for (int i = 0; i < 8 * LG + 12; ++i) pc[i] = red(i)[0];
         Vec2<double> d0{v.p0[sidx(tl, 0)] * v.s0, v.p1[sidx(tl, 0)] * v.s1};
-        // down sweep: d_j = m_j v_j - At_j d_{j-1}, loads of U rows issued first
-        // Each of the three sweeps double-buffers its U-row groups: the next
-        // group's (unconditional) loads issue before this group's stores, which
-        // would otherwise hold them up in the shared in-order memory counter.
+        // down sweep: d_j = m_j v_j - At_j d_{j-1}, and with it d''_1 = sum Q_j d_j
+        // (Q_1 = I, Q_{j+1} = -Q_j g_j); loads of U rows issued first.
+        // Both sweeps double-buffer their U-row groups: the next group's
+        // (unconditional) loads issue before this group's stores, which would
+        // otherwise hold them up in the shared in-order memory counter.
         Vec2<FT> dprev{FT(0), FT(0)};
+        Vec2<double> dLast{0.0, 0.0}, dFirst{0.0, 0.0};
         if (M >= 2) {
-            struct GD { Blk<FT> mm[U], aa[U]; Vec2<FT> vv[U]; };
+            Blk<FT> Q{FT(1), FT(0), FT(0), FT(1)};
+            Vec2<FT> sq{FT(0), FT(0)};
+            // 14 values per row: FP64 factors take groups of two rows
+            constexpr int UD = sizeof(FT) == 4 ? U : 2;
+            struct GD { Blk<FT> mm[UD], aa[UD], gg[UD]; Vec2<FT> vv[UD]; };
             auto load_d = [&](int j0, GD& g) {
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
+                for (int u = 0; u < UD; ++u) {
                     const int64_t s = sidx(tl, min(j0 + u, M - 1));
                     g.mm[u] = load_blk(0, s);
                     g.aa[u] = load_blk(4, s);
+                    g.gg[u] = load_blk(8, s);
                     g.vv[u] = Vec2<FT>{(FT)(v.p0[s] * v.s0), (FT)(v.p1[s] * v.s1)};
                 }
             };
             GD gc, gn;
             load_d(1, gc);
-            for (int j0 = 1; j0 < M; j0 += U) {
-                load_d(j0 + U, gn);
+            for (int j0 = 1; j0 < M; j0 += UD) {
+                load_d(j0 + UD, gn);
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
+                for (int u = 0; u < UD; ++u) {
                     const int j = j0 + u;
                     if (j < M) {
                         const int64_t s = sidx(tl, j);
@@ -1554,45 +1541,15 @@ struct Column {
                         }
                         *tmpp(s) = V2<FT>{de.x, de.y};
                         dprev = de;
+                        const Vec2<FT> qd = bmv(Q, de);
+                        sq.x += qd.x; sq.y += qd.y;
+                        Q = bneg(bmul(Q, gc.gg[u]));
                     }
                 }
                 gc = gn;
             }
-        }
-        // up sweep: d''_j = d_j - g_j d''_{j+1}
-        Vec2<FT> dn = dprev;      // row M-1 (d'' = d)
-        Vec2<double> dLast{0.0, 0.0}, dFirst{0.0, 0.0};
-        if (M >= 2) {
-            dLast = {(double)dn.x, (double)dn.y};
-            // the next group holds rows below the current one, which this sweep
-            // has not rewritten yet (the clamped rows of a last prefetch go unused)
-            struct GU { Blk<FT> gg[U]; Vec2<FT> dd[U]; };
-            auto load_u = [&](int j0, GU& g) {
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int64_t s = sidx(tl, max(j0 - u, 1));
-                    g.gg[u] = load_blk(8, s);
-                    const V2<FT> r = *tmpp(s);
-                    g.dd[u] = Vec2<FT>{r.x, r.y};
-                }
-            };
-            GU gc, gn;
-            if (M >= 3) load_u(M - 2, gc);
-            for (int j0 = M - 2; j0 >= 1; j0 -= U) {
-                load_u(j0 - U, gn);
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int j = j0 - u;
-                    if (j >= 1) {
-                        const int64_t s = sidx(tl, j);
-                        const Vec2<FT> q = bmv(gc.gg[u], dn);
-                        dn = {gc.dd[u].x - q.x, gc.dd[u].y - q.y};
-                        *tmpp(s) = V2<FT>{dn.x, dn.y};
-                    }
-                }
-                gc = gn;
-            }
-            dFirst = {(double)dn.x, (double)dn.y};
+            dLast = {(double)dprev.x, (double)dprev.y};
+            dFirst = {(double)sq.x, (double)sq.y};
         }
         ldbl* P = lds + Lds<T>::kPcr;
         __syncthreads();
@@ -1636,35 +1593,39 @@ struct Column {
             zz += x0.x * x0.x + x0.y * x0.y;
             zm = fmax(fabs(x0.x), fabs(x0.y));
         }
+        // back substitution x_j = d_j - a_j x0(t) - g_j x_{j+1}, rows M-1 .. 1,
+        // carried in FP64 from x_M = x0(t+1)
         if (M >= 2) {
             struct GF { Blk<FT> aa[U], gg[U]; Vec2<FT> dd[U]; };
             auto load_f = [&](int j0, GF& g) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int64_t s = sidx(tl, min(j0 + u, M - 1));
+                    const int64_t s = sidx(tl, max(j0 - u, 1));
                     g.aa[u] = load_blk(12, s);
-                    g.gg[u] = load_blk(16, s);
+                    g.gg[u] = load_blk(8, s);
                     const V2<FT> r = *tmpp(s);
                     g.dd[u] = Vec2<FT>{r.x, r.y};
                 }
             };
             GF gc, gn;
-            load_f(1, gc);
-            for (int j0 = 1; j0 < M; j0 += U) {
-                load_f(j0 + U, gn);
+            load_f(M - 1, gc);
+            Vec2<double> xr = xn;
+            for (int j0 = M - 1; j0 >= 1; j0 -= U) {
+                load_f(j0 - U, gn);
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int j = j0 + u;
-                    if (j < M) {
+                    const int j = j0 - u;
+                    if (j >= 1) {
                         const int64_t s = sidx(tl, j);
                         const Blk<FT> a = gc.aa[u], g = gc.gg[u];
                         const double zx = (double)gc.dd[u].x - ((double)a.a * x0.x + (double)a.b * x0.y) -
-                                          ((double)g.a * xn.x + (double)g.b * xn.y);
+                                          ((double)g.a * xr.x + (double)g.b * xr.y);
                         const double zy = (double)gc.dd[u].y - ((double)a.c * x0.x + (double)a.d * x0.y) -
-                                          ((double)g.c * xn.x + (double)g.d * xn.y);
+                                          ((double)g.c * xr.x + (double)g.d * xr.y);
                         z0[s] = zx; z1[s] = zy;
                         zz += zx * zx + zy * zy;
                         zm = fmax(zm, fmax(fabs(zx), fabs(zy)));
+                        xr = {zx, zy};
                     }
                 }
                 gc = gn;

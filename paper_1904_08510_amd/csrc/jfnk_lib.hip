@@ -412,7 +412,6 @@ int64_t carve_work(double* base, int64_t P, int m, int64_t red, int max_cols, Wo
     w.V = take(2 * (int64_t)(m + 1) * P);
     w.Z = take(2 * (int64_t)m * P);
     w.dX = take(2 * P);
-    w.ftmp = take((int64_t)kTempSlots * P);
     w.fac = (void*)take((int64_t)kFactorSlots * P);
     w.tmp = (void*)take(2 * P);
     w.sch = take(4 * P);

@@ -21,10 +21,9 @@ namespace jfnk {
 
 constexpr int kMaxRestart = 30;      // largest GMRES restart length supported
 constexpr int kRedPerChunk = 96;     // doubles of reduced-system data per chunk (T <= 1024)
-constexpr int kFactorSlots = 24;     // FT values per cell stored by the factorisation
-                                     // (20 block factors + 4 coupling entries of the
+constexpr int kFactorSlots = 20;     // FT values per cell stored by the factorisation
+                                     // (16 block factors + 4 coupling entries of the
                                      // approximate-Schur preconditioner)
-constexpr int kTempSlots = 8;        // FP64 values per cell kept between factor sweeps
 constexpr int kMgFields = 9;         // multigrid arrays per column (see Column::mgf)
 constexpr int kMgCoarse = 7;         // multigrid levels of at most this many points are solved directly
 constexpr int kMgMaxCycles = 200;    // V-cycles per multigrid solve at most
@@ -124,7 +123,6 @@ struct Work {
     double *dX;                      // Newton direction (scaled), 2
     void *fac;                       // kFactorSlots x P values of the factor type
     void *tmp;                       // 2 x P values of the factor type (apply)
-    double *ftmp;                    // kTempSlots x P doubles (factorisation)
     double *red;                     // per-chunk reduced-system data
     double *sch;                     // 4 x P doubles: approximate-Schur apply temporaries
     double *mg;                      // kMgFields x mgP doubles: multigrid arrays (kind 3 only)
