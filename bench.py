@@ -62,6 +62,16 @@ def solve_bytes_per_cell(has_prev, fb, counts):
     passes and direction assemblies also read a number of basis vectors that
     grows with the Krylov index: those are the extra vector reads, 16 bytes
     per cell each."""
+    setup, per_phase = solve_phase_bytes(has_prev, fb)
+    return setup + sum(c * b for c, b in zip(counts, per_phase))
+
+
+PHASE_NAMES = ("factor", "apply", "trial", "jv", "cgs", "direction", "vector_reads", "learned")
+
+
+def solve_phase_bytes(has_prev, fb):
+    """(set-up bytes per cell, bytes per cell of one execution of each phase
+    in PHASE_NAMES order) for solve_bytes_per_cell."""
     setup = 72.0                               # F(X^n): X + 5 coefficients -> F
     if has_prev:
         setup += 32.0                          # same sweep: the extrapolation in, its residual out
@@ -73,7 +83,7 @@ def solve_bytes_per_cell(has_prev, fb, counts):
                  16.0,                         # direction: dX out (summed vectors: extra reads)
                  16.0,                         # one extra FP64 vector pair read
                  72.0)                         # learned candidate: X_l + 5 coefficients -> F_l
-    return setup + sum(c * b for c, b in zip(counts, per_phase))
+    return setup, per_phase
 
 
 def pick_parity_sample(rec, ns, episode=EPISODE, nextra=2, seed=99):
@@ -205,6 +215,14 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
     converged = sum(r["conv"] for r in rec)
     kern_ms = sum(r["kms"][1] for r in rec)
     kern_bytes = sum(r["bytes"] for r in rec)
+    # the solve's algorithmic bytes per launch split by phase
+    by_phase = dict.fromkeys(("setup",) + PHASE_NAMES, 0.0)
+    for r in rec:
+        setup, per_phase = solve_phase_bytes(r["has_prev"], fb)
+        by_phase["setup"] += setup * float(np.sum(ns))
+        for k, name in enumerate(PHASE_NAMES):
+            by_phase[name] += per_phase[k] * float(np.sum(ns * r["counts"][:, k]))
+    by_phase = {k: v / len(rec) for k, v in by_phase.items()}
     g_ms = sum(r["kms"][0] for r in rec)
     w_ms = sum(r["kms"][2] for r in rec)
     step_ms = sum(r["ms"] for r in rec)
@@ -216,7 +234,7 @@ def measure_batched(J, prob, ne, phi, ne0, phi0, ns, args, prec, guess, net=None
         value=converged / wall, wall=wall, ms_per_step=1e3 * wall / args.steps,
         converged=converged, total=len(ns) * args.steps, max_res=max(r["res"] for r in rec),
         kernel_ms_avg=kern_ms / len(rec), achieved_gbs=kern_bytes / (kern_ms * 1e-3) / 1e9,
-        bytes_per_launch=kern_bytes / len(rec),
+        bytes_per_launch=kern_bytes / len(rec), bytes_by_phase=by_phase,
         launches={
             "k_gather": dict(ms_avg=g_ms / len(rec), bytes_per_launch=sum(r["gbytes"] for r in rec) / len(rec),
                              achieved_gbs=sum(r["gbytes"] for r in rec) / (g_ms * 1e-3) / 1e9),
@@ -831,6 +849,7 @@ def main():
             "kernel": "k_solve",
             "kernel_ms_avg": g["kernel_ms_avg"],
             "bytes_per_launch": g["bytes_per_launch"],
+            "bytes_by_phase": g["bytes_by_phase"],
         },
         "launches": g["launches"],
         "cpu_baseline": cpu,

@@ -55,6 +55,47 @@ __device__ __forceinline__ Blk<double> bzero() { return {0.0, 0.0, 0.0, 0.0}; }
 // LDS reduction would wait for it to reach memory; a global store does not.
 template <class R>
 __device__ __forceinline__ void gst(R* p, R v) { *(__attribute__((address_space(1))) R*)p = v; }
+// Load through the global address space.  The wait counter of vector memory
+// completes global accesses in order, so a sweep can wait for one group of
+// loads while the next group is in flight; a generic (flat) access may also
+// reach LDS, and every wait on one drains all outstanding memory operations.
+template <class R>
+__device__ __forceinline__ R gld(const R* p) { return *(const __attribute__((address_space(1))) R*)p; }
+// The records go through vector types: an aggregate load is split into
+// scalar loads that the optimiser may issue through the original generic
+// pointer.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ V4<float> gld(const V4<float>* p) {
+    const f32x4 r = *(const __attribute__((address_space(1))) f32x4*)p;
+    return {r.x, r.y, r.z, r.w};
+}
+__device__ __forceinline__ V2<float> gld(const V2<float>* p) {
+    const f32x2 r = *(const __attribute__((address_space(1))) f32x2*)p;
+    return {r.x, r.y};
+}
+__device__ __forceinline__ V4<double> gld(const V4<double>* p) {
+    const f64x4 r = *(const __attribute__((address_space(1))) f64x4*)p;
+    return {r.x, r.y, r.z, r.w};
+}
+__device__ __forceinline__ V2<double> gld(const V2<double>* p) {
+    const f64x2 r = *(const __attribute__((address_space(1))) f64x2*)p;
+    return {r.x, r.y};
+}
+__device__ __forceinline__ void gst(V4<float>* p, V4<float> v) {
+    *(__attribute__((address_space(1))) f32x4*)p = f32x4{v.a, v.b, v.c, v.d};
+}
+__device__ __forceinline__ void gst(V2<float>* p, V2<float> v) {
+    *(__attribute__((address_space(1))) f32x2*)p = f32x2{v.x, v.y};
+}
+__device__ __forceinline__ void gst(V4<double>* p, V4<double> v) {
+    *(__attribute__((address_space(1))) f64x4*)p = f64x4{v.a, v.b, v.c, v.d};
+}
+__device__ __forceinline__ void gst(V2<double>* p, V2<double> v) {
+    *(__attribute__((address_space(1))) f64x2*)p = f64x2{v.x, v.y};
+}
 __device__ __forceinline__ Blk<double> beye() { return {1.0, 0.0, 0.0, 1.0}; }
 
 // ---------------------------------------------------------------------------
@@ -101,7 +142,8 @@ __device__ __forceinline__ double tab_interp(const TabRef& t, const double* v, i
                                              double wx) {
     const double* r0 = v + (int64_t)i * t.nx;
     const double* r1 = r0 + t.nx;
-    return (1.0 - wc) * ((1.0 - wx) * r0[k] + wx * r0[k + 1]) + wc * ((1.0 - wx) * r1[k] + wx * r1[k + 1]);
+    return (1.0 - wc) * ((1.0 - wx) * gld(r0 + k) + wx * gld(r0 + k + 1)) +
+           wc * ((1.0 - wx) * gld(r1 + k) + wx * gld(r1 + k + 1));
 }
 
 template <bool TAB>
@@ -160,8 +202,10 @@ __device__ __forceinline__ void face_rgw_d(const TabRef& t, double a, double b, 
             const double sx = (t.nx - 1) / (t.x_max - t.x_min) / (dphi * 2.302585092994046);
             const double* m0 = t.mu + (int64_t)i * t.nx;
             const double* d0 = t.diff + (int64_t)i * t.nx;
-            const double dmu = ((1.0 - wc) * (m0[k + 1] - m0[k]) + wc * (m0[t.nx + k + 1] - m0[t.nx + k])) * sx;
-            const double dd = ((1.0 - wc) * (d0[k + 1] - d0[k]) + wc * (d0[t.nx + k + 1] - d0[t.nx + k])) * sx;
+            const double dmu = ((1.0 - wc) * (gld(m0 + k + 1) - gld(m0 + k)) +
+                                wc * (gld(m0 + t.nx + k + 1) - gld(m0 + t.nx + k))) * sx;
+            const double dd = ((1.0 - wc) * (gld(d0 + k + 1) - gld(d0 + k)) +
+                               wc * (gld(d0 + t.nx + k + 1) - gld(d0 + t.nx + k))) * sx;
             dr = (dmu * d - mu * dd) / (d * d);
             dg = dd * ihf;
             dw = -c * dd / (d * d);
@@ -233,7 +277,10 @@ __device__ __forceinline__ void wg_max(double (&v)[K], SP scr) {
 // reads both issues one vector load for them.
 struct CP {
     double* p;
-    __host__ __device__ __forceinline__ double& operator[](int64_t s) const { return p[2 * s]; }
+    // device memory, accessed through the global address space
+    __device__ __forceinline__ __attribute__((address_space(1))) double& operator[](int64_t s) const {
+        return ((__attribute__((address_space(1))) double*)p)[2 * s];
+    }
 };
 
 struct VecRef {
@@ -246,7 +293,7 @@ struct VecRef {
 // of one pair array (p1 = p0 + 1: every Krylov vector, preconditioned
 // vector, residual and direction), with one 16-byte load.
 __device__ __forceinline__ Vec2<double> ld_pair(const VecRef& v, int64_t s) {
-    const V2<double> r = *(const V2<double>*)(v.p0.p + 2 * s);
+    const V2<double> r = gld((const V2<double>*)(v.p0.p + 2 * s));
     return {r.x, r.y};
 }
 
@@ -356,7 +403,7 @@ struct Column {
         getx(s0, nC, pC);
         if (c0 == 0) { nL = cd.nel; pL = cd.phil; ihL = 2.0 * ih; }
         else { getx(sidx(t - 1, M - 1), nL, pL); ihL = ih; }
-        FaceRec FL = face(W.fa[s0], W.fg[s0], prm.has_u ? W.fw[s0] : 0.0, ihL, nL, pL, nC, pC);
+        FaceRec FL = face(gld(W.fa + s0), gld(W.fg + s0), prm.has_u ? gld(W.fw + s0) : 0.0, ihL, nL, pL, nC, pC);
         // Group of U rows' operands.  Loads carry no conditions, so a group's
         // loads issue back to back: rows past the chunk's end reload its last
         // real row, and the last cell of the column reloads itself in place of
@@ -373,9 +420,9 @@ struct Column {
                 g.ow[u] = own(s);
                 const int64_t sn = (c0 + j >= n - 1) ? s : ((j + 1 < M) ? s + T : sidx(t + 1, 0));
                 getx(sn, g.xn[u], g.xp[u]);
-                g.fa[u] = W.fa[sn];
-                g.fg[u] = W.fg[sn];
-                g.fw[u] = W.fw[sn];
+                g.fa[u] = gld(W.fa + sn);
+                g.fg[u] = gld(W.fg + sn);
+                g.fw[u] = gld(W.fw + sn);
             }
         };
         // Double buffer: the next group's loads issue before this group's
@@ -437,9 +484,9 @@ struct Column {
             gxb(sl, nBL, pBL);
             ihL = ih;
         }
-        const double fw0 = prm.has_u ? W.fw[s0] : 0.0;
-        RecA FLA = fA(W.fa[s0], W.fg[s0], fw0, ihL, nAL, pAL, nA, pA);
-        RecB FLB = fB(W.fa[s0], W.fg[s0], fw0, ihL, nBL, pBL, nB, pB);
+        const double fw0 = prm.has_u ? gld(W.fw + s0) : 0.0;
+        RecA FLA = fA(gld(W.fa + s0), gld(W.fg + s0), fw0, ihL, nAL, pAL, nA, pA);
+        RecB FLB = fB(gld(W.fa + s0), gld(W.fg + s0), fw0, ihL, nBL, pBL, nB, pB);
         // double-buffered groups with unconditional loads, as in sweep
         struct Grp {
             double an[U], ap[U], bn[U], bp[U], fa[U], fg[U], fw[U];
@@ -454,9 +501,9 @@ struct Column {
                 const int64_t sn = (c0 + j >= n - 1) ? s : ((j + 1 < M) ? s + T : sidx(t + 1, 0));
                 gxa(sn, g.an[u], g.ap[u]);
                 gxb(sn, g.bn[u], g.bp[u]);
-                g.fa[u] = W.fa[sn];
-                g.fg[u] = W.fg[sn];
-                g.fw[u] = W.fw[sn];
+                g.fa[u] = gld(W.fa + sn);
+                g.fg[u] = gld(W.fg + sn);
+                g.fw[u] = gld(W.fw + sn);
             }
         };
         Grp gc, gn;
@@ -509,11 +556,21 @@ struct Column {
     };
 
     // ------------------------------------------------------------------
+    // The phases called out of line (the apply, the factorisation, trial and
+    // residual evaluations, J.v, Gram-Schmidt passes, linear combinations)
+    // run on a private copy of the column object.  In an out-of-line call
+    // `this` is a generic pointer that a store through any vector pointer
+    // might alias, so each field it reads would be loaded again (with a
+    // generic load, which drains every outstanding memory operation) after
+    // each store; the copy's fields stay in registers.
+    // ------------------------------------------------------------------
+
+    // ------------------------------------------------------------------
     // Residual F(X) at the state returned by getx; writes F (unscaled) and,
     // optionally, the state itself; returns the scaled norms.
     // ------------------------------------------------------------------
     template <class GetX>
-    __device__ Norms residual(GetX getx, CP oF0, CP oF1, CP oX0, CP oX1,
+    __device__ __forceinline__ Norms residual(GetX getx, CP oF0, CP oF1, CP oX0, CP oX1,
                               VecRef stepdir, double steplam) {
         double mx[3] = {0.0, 0.0, 0.0};       // max|Fe|, max|Fp|, max|step|
         double sm[4] = {0.0, 0.0, 0.0, 0.0};  // sum Fe^2, sum Fp^2, sum n^2, sum phi^2
@@ -530,7 +587,7 @@ struct Column {
         sweep<2, FluxRec>(getx, FluxFace{prm.tab},
             [&](int64_t s) {
                 Own o;
-                o.f = fv[s]; o.k = kv[s]; o.q = qv[s];
+                o.f = gld(fv + s); o.k = gld(kv + s); o.q = gld(qv + s);
                 o.d0 = dp0[s];
                 o.d1 = dp1[s];
                 return o;
@@ -589,7 +646,8 @@ struct Column {
     // thread wrote differs from the one the stored factors were built with,
     // kGatherBad when one of its cells has an input outside the problem's
     // domain (mu < 0, D <= 0, k < 0, or a non-finite value); the thread of the
-    // last cell writes the right-wall face coefficients to wall[0..2].
+    // last cell writes the right-wall face coefficients to wall[0..2]
+    // (global or LDS memory: stored through a generic pointer).
     // ------------------------------------------------------------------
     // tiles of 8 x 8 cells of this column's layout
     __device__ __forceinline__ int ntiles() const { return ((cd.M + 7) >> 3) * (T / 8); }
@@ -629,22 +687,22 @@ struct Column {
                 ofa[v] = ofg[v] = ofw[v] = okd[v] = 0.0;
                 if (may_reuse && k < ke && j < M && c < n) {
                     const int64_t s = cd.ws + (int64_t)j * T + tt;
-                    ofa[v] = W.fa[s]; ofg[v] = W.fg[s]; okd[v] = W.kd[s];
-                    if (prm.has_u) ofw[v] = W.fw[s];
+                    ofa[v] = gld(W.fa + s); ofg[v] = gld(W.fg + s); okd[v] = gld(W.kd + s);
+                    if (prm.has_u) ofw[v] = gld(W.fw + s);
                 }
                 if (k < ke && j < M && c < n) {
                     const int64_t u = cd.uoff + c;
                     // table transport: (mu, D) slots carry (progress variable, gas density)
                     const double* A0 = TAB ? U.prog : U.mu;
                     const double* A1 = TAB ? U.gasn : U.diff;
-                    mu[v] = A0[u]; D[v] = A1[u];
-                    if (c > 0) { mum[v] = A0[u - 1]; Dm[v] = A1[u - 1]; }
-                    ne[v] = U.ne[u]; ph[v] = U.phi[u]; sr[v] = U.src[u];
-                    if (U.kloss) kl[v] = U.kloss[u];
-                    qq[v] = U.q[u];
-                    if (extrap) { pn[v] = U.ne_prev[u]; pp[v] = U.phi_prev[u]; }
-                    if (learn) { ln[v] = U.ne_learn[u]; lp[v] = U.phi_learn[u]; }
-                    if (prm.has_u) uf[v] = U.uface[fo + c];
+                    mu[v] = gld(A0 + u); D[v] = gld(A1 + u);
+                    if (c > 0) { mum[v] = gld(A0 + u - 1); Dm[v] = gld(A1 + u - 1); }
+                    ne[v] = gld(U.ne + u); ph[v] = gld(U.phi + u); sr[v] = gld(U.src + u);
+                    if (U.kloss) kl[v] = gld(U.kloss + u);
+                    qq[v] = gld(U.q + u);
+                    if (extrap) { pn[v] = gld(U.ne_prev + u); pp[v] = gld(U.phi_prev + u); }
+                    if (learn) { ln[v] = gld(U.ne_learn + u); lp[v] = gld(U.phi_learn + u); }
+                    if (prm.has_u) uf[v] = gld(U.uface + fo + c);
                 }
             }
 #pragma unroll
@@ -656,9 +714,9 @@ struct Column {
                 if (k >= ke || j >= M) continue;
                 const int64_t s = cd.ws + (int64_t)j * T + tt;
                 if (c >= n) {
-                    W.fa[s] = 0.0; W.fg[s] = 0.0;
-                    if (prm.has_u) W.fw[s] = 0.0;
-                    W.f[s] = 0.0; W.kd[s] = 0.0; W.q[s] = 0.0;
+                    gst(W.fa + s, (double)(0.0)); gst(W.fg + s, (double)(0.0));
+                    if (prm.has_u) gst(W.fw + s, (double)(0.0));
+                    gst(W.f + s, (double)(0.0)); gst(W.kd + s, (double)(0.0)); gst(W.q + s, (double)(0.0));
                     X00[s] = X01[s] = X10[s] = X11[s] = X20[s] = X21[s] = 0.0;
                     continue;
                 }
@@ -699,18 +757,18 @@ struct Column {
                                   (!prm.has_u || ofw[v] == wf);
                 changed = changed || (may_reuse && !same);
                 if (!same) {
-                    W.fa[s] = r; W.fg[s] = g;
-                    if (prm.has_u) W.fw[s] = wf;
-                    W.kd[s] = dt * kl[v];
+                    gst(W.fa + s, (double)(r)); gst(W.fg + s, (double)(g));
+                    if (prm.has_u) gst(W.fw + s, (double)(wf));
+                    gst(W.kd + s, (double)(dt * kl[v]));
                 }
-                W.f[s] = ne[v] + dt * sr[v];
-                W.q[s] = qq[v];
+                gst(W.f + s, (double)(ne[v] + dt * sr[v]));
+                gst(W.q + s, (double)(qq[v]));
                 X00[s] = ne[v]; X01[s] = ph[v];
                 if (extrap) { X10[s] = 2.0 * ne[v] - pn[v]; X11[s] = 2.0 * ph[v] - pp[v]; }
                 if (learn) { X20[s] = ln[v]; X21[s] = lp[v]; }
                 if (c == n - 1) {
                     // right wall face: the last cell's mu and D at distance h/2
-                    const double uR = prm.has_u ? U.uface[fo + n] : 0.0;
+                    const double uR = prm.has_u ? gld(U.uface + fo + n) : 0.0;
                     bad = bad || !(fabs(uR) < INFINITY);
                     if constexpr (TAB) {
                         wall[0] = mu[v];
@@ -755,8 +813,8 @@ struct Column {
                 const int j = (k % nrg) * 8 + (lane & 7);
                 const int c = tt * M + j;
                 if (k < ke && j < M && c < n) {
-                    o0[cd.uoff + c] = a[v];
-                    o1[cd.uoff + c] = b[v];
+                    gst(o0 + cd.uoff + c, a[v]);
+                    gst(o1 + cd.uoff + c, b[v]);
                 }
             }
         }
@@ -838,7 +896,7 @@ struct Column {
                 o.mag = g * (bmx * fabs(nA) + bx * fabs(nB));
                 return o;
             };
-            const auto own = [&](int64_t s) { return Own{W.f[s], W.kd[s], W.q[s]}; };
+            const auto own = [&](int64_t s) { return Own{gld(W.f + s), gld(W.kd + s), gld(W.q + s)}; };
             const auto cellA = [&](int64_t s, double nC, double pC, const ScRec& L, const ScRec& R, const Own& o) {
                 const double fv = o.f, kv = o.k, qv = o.q;
                 const double fe = -nC + fv - kv * nC - dt_h * (R.gam - L.gam);
@@ -1005,10 +1063,10 @@ struct Column {
     };
 
     __device__ __forceinline__ void store_blk(int slot, int64_t s, const Blk<double>& m) {
-        *(V4<FT>*)facp(slot, s) = V4<FT>{(FT)m.a, (FT)m.b, (FT)m.c, (FT)m.d};
+        gst((V4<FT>*)facp(slot, s), V4<FT>{(FT)m.a, (FT)m.b, (FT)m.c, (FT)m.d});
     }
     __device__ __forceinline__ Blk<FT> load_blk(int slot, int64_t s) const {
-        const V4<FT> r = *(const V4<FT>*)facp(slot, s);
+        const V4<FT> r = gld((const V4<FT>*)facp(slot, s));
         return {r.a, r.b, r.c, r.d};
     }
 
@@ -1023,6 +1081,16 @@ struct Column {
             __syncthreads();
             return;
         }
+        {
+            Column self(*this);
+            self.factor_chunks(cur);
+        }
+        if (prm.prec_kind == 3) mg_build();
+        __syncthreads();
+    }
+
+    // the factorisation proper (block preconditioners)
+    __device__ __forceinline__ void factor_chunks(int cur) {
         const int M = cd.M, n = cd.n;
         const int c0 = t * M;
         const CP X0 = xb(cur, 0);
@@ -1059,7 +1127,7 @@ struct Column {
         sweep<2, JacRec>(
             [&](int64_t s, double& a, double& b) { a = X0[s]; b = X1[s]; },
             JacFace{prm.tab},
-            [&](int64_t s) { return W.kd[s]; },
+            [&](int64_t s) { return gld(W.kd + s); },
             [&](int64_t s, int c, double nC, double pC, const JacRec& L, const JacRec& R, const double& kv) {
                 const int j = c - c0;
                 Blk<double> A, B, C;
@@ -1089,15 +1157,15 @@ struct Column {
                     // diag(dt D_f - I, S~) with S~ = L + I_e dt D_r, the Schur
                     // complement with (dt D_f - I)^-1 replaced by -I (scaled units:
                     // -(s_Fn / s_Xn) I)
-                    *(V4<FT>*)facp(16, s) = V4<FT>{(FT)A.b, (FT)B.b, (FT)C.b, (FT)B.c};
+                    gst((V4<FT>*)facp(16, s), V4<FT>{(FT)A.b, (FT)B.b, (FT)C.b, (FT)B.c});
                     const double kap = B.c / s_en;
                     A = Blk<double>{A.a, 0.0, 0.0, A.d + kap * A.b};
                     C = Blk<double>{C.a, 0.0, 0.0, C.d + kap * C.b};
                     B = Blk<double>{B.a, 0.0, 0.0, B.d + kap * B.b};
                     if (prm.prec_kind == 3) {
                         // the two scalar tridiagonal blocks on the multigrid's finest level
-                        mgf(0)[c] = A.a; mgf(1)[c] = B.a; mgf(2)[c] = C.a;
-                        mgf(3)[c] = A.d; mgf(4)[c] = B.d; mgf(5)[c] = C.d;
+                        gst(mgf(0) + c, A.a); gst(mgf(1) + c, B.a); gst(mgf(2) + c, C.a);
+                        gst(mgf(3) + c, A.d); gst(mgf(4) + c, B.d); gst(mgf(5) + c, C.d);
                     }
                 }
                 rowproc(j, s, A, B, C);
@@ -1105,7 +1173,7 @@ struct Column {
             [&](int64_t s) {
                 const int j = (int)((s - cd.ws) / T);
                 if (prm.prec_kind == 1 || prm.prec_kind == 3) {
-                    *(V4<FT>*)facp(16, s) = V4<FT>{FT(0), FT(0), FT(0), FT(0)};
+                    gst((V4<FT>*)facp(16, s), V4<FT>{FT(0), FT(0), FT(0), FT(0)});
                 }
                 rowproc(j, s, bzero(), beye(), bzero());
             });
@@ -1187,8 +1255,6 @@ struct Column {
             cs->fac_valid = 1;
             cs->fsfn = sfn; cs->fsfp = sfp; cs->fsxn = sxn; cs->fsxp = sxp;
         }
-        if (prm.prec_kind == 3) mg_build();
-        __syncthreads();
     }
 
     // ------------------------------------------------------------------
@@ -1415,7 +1481,10 @@ struct Column {
     // ------------------------------------------------------------------
     __device__ Vec2<double> apply(const VecRef& v, CP z0, CP z1) {
         if (prm.prec_kind == 2) return apply_identity(v, z0, z1);
-        return (prm.prec_kind == 1 || prm.prec_kind == 3) ? apply_schur(v, z0, z1) : block_apply(v, z0, z1);
+        if (prm.prec_kind == 1 || prm.prec_kind == 3) return apply_schur(v, z0, z1);
+        Column self(*this);
+        const VecRef vl = v;    // by value: a reference would be re-read through a generic pointer
+        return self.block_apply(vl, z0, z1);
     }
 
     // No preconditioner: z = v (with v's component scales), every row of the
@@ -1454,7 +1523,7 @@ struct Column {
         else block_apply(VecRef{v.p0, v.p1, v.s0, 0.0}, Y0, Y1);       // Y0 = z_e'
         for (int j = 0; j < M; ++j) {
             const int64_t s = sidx(t, j);
-            Y2[s] = v.p1[s] * v.s1 - (double)*facp(19, s) * Y0[s];        // v_phi - I_e z_e'
+            Y2[s] = v.p1[s] * v.s1 - (double)gld(facp(19, s)) * Y0[s];        // v_phi - I_e z_e'
         }
         if (mg_p) mg_solve(1, Y2, 1.0, z1);
         else block_apply(VecRef{Y2, Y2, 0.0, 1.0}, Y3, z1);             // z1 = z_phi
@@ -1467,7 +1536,7 @@ struct Column {
             if (c < n) {
                 const double zl = c > 0 ? z1[sidx((c - 1) / M, (c - 1) % M)] : 0.0;
                 const double zr = c < n - 1 ? z1[sidx((c + 1) / M, (c + 1) % M)] : 0.0;
-                w = (double)*facp(16, s) * zl + (double)*facp(17, s) * z1[s] + (double)*facp(18, s) * zr;
+                w = (double)gld(facp(16, s)) * zl + (double)gld(facp(17, s)) * z1[s] + (double)gld(facp(18, s)) * zr;
             }
             Y2[s] = w;
         }
@@ -1490,7 +1559,7 @@ struct Column {
 
     // Block solve with the stored factors (chunk sweeps in FT, reduced
     // system in FP64).  Returns (||z||_2^2, ||z||_inf).
-    __device__ Vec2<double> block_apply(const VecRef& v, CP z0, CP z1) {
+    __device__ __forceinline__ Vec2<double> block_apply(const VecRef& v, CP z0, CP z1) {
         const int tl = t;   // a local: members are reloaded after every barrier
         constexpr int U = 4;
         constexpr int LG = ilog2(T);             // PCR stages of the interface system
@@ -1500,7 +1569,7 @@ struct Column {
         // instead of adding one memory round trip per PCR stage.
         double pc[8 * LG + 12];
 #pragma unroll
-        for (int i = 0; i < 8 * LG + 12; ++i) pc[i] = red(i)[0];
+        for (int i = 0; i < 8 * LG + 12; ++i) pc[i] = gld(red(i));
         Vec2<double> d0{v.p0[sidx(tl, 0)] * v.s0, v.p1[sidx(tl, 0)] * v.s1};
         // down sweep: d_j = m_j v_j - At_j d_{j-1}, and with it d''_1 = sum Q_j d_j
         // (Q_1 = I, Q_{j+1} = -Q_j g_j); loads of U rows issued first.
@@ -1539,7 +1608,7 @@ struct Column {
                             const Vec2<FT> q = bmv(gc.aa[u], dprev);
                             de.x -= q.x; de.y -= q.y;
                         }
-                        *tmpp(s) = V2<FT>{de.x, de.y};
+                        gst(tmpp(s), V2<FT>{de.x, de.y});
                         dprev = de;
                         const Vec2<FT> qd = bmv(Q, de);
                         sq.x += qd.x; sq.y += qd.y;
@@ -1603,7 +1672,7 @@ struct Column {
                     const int64_t s = sidx(tl, max(j0 - u, 1));
                     g.aa[u] = load_blk(12, s);
                     g.gg[u] = load_blk(8, s);
-                    const V2<FT> r = *tmpp(s);
+                    const V2<FT> r = gld(tmpp(s));
                     g.dd[u] = Vec2<FT>{r.x, r.y};
                 }
             };
@@ -1646,6 +1715,13 @@ struct Column {
     template <class BP>
     __device__ void jv(int cur, const VecRef& z, double eps, CP w0, CP w1,
                        BP basis, int nb, double* dots) {
+        Column self(*this);
+        const VecRef zl = z;
+        self.jv_body(cur, zl, eps, w0, w1, basis, nb, dots);
+    }
+    template <class BP>
+    __device__ __forceinline__ void jv_body(int cur, const VecRef& z, double eps, CP w0, CP w1,
+                                            BP basis, int nb, double* dots) {
         const CP X0 = xb(cur, 0);
         const CP X1 = xb(cur, 1);
         const CP F0 = Fb(cur, 0);
@@ -1663,7 +1739,7 @@ struct Column {
             FluxFace{prm.tab},
             [&](int64_t s) {
                 Own o;
-                o.f = W.f[s]; o.k = W.kd[s]; o.q = W.q[s]; o.F0 = F0[s]; o.F1 = F1[s];
+                o.f = gld(W.f + s); o.k = gld(W.kd + s); o.q = gld(W.q + s); o.F0 = F0[s]; o.F1 = F1[s];
                 const Vec2<double> e0 = ld_pair(b0, s), e1 = ld_pair(b1, s);
                 o.v00 = e0.x; o.v01 = e0.y;
                 o.v10 = e1.x;                // b1 is a valid array for any nb; its dot
@@ -1689,8 +1765,8 @@ struct Column {
 
     // dots[i] = basis[i] . w for i in [i0, nb)
     template <class BP>
-    __device__ void dots_more(CP w0, CP w1, BP basis, int i0, int nb,
-                              double* dots) {
+    __device__ __forceinline__ void dots_more(CP w0, CP w1, BP basis, int i0, int nb,
+                                              double* dots) {
         constexpr int U = 2;
         const int M = cd.M;
         for (int g = i0; g < nb; g += 8) {
@@ -1738,6 +1814,12 @@ struct Column {
     template <class BP>
     __device__ void cgs_pass(CP w0, CP w1, BP basis, int nb, const double* h,
                              double* dots) {
+        Column self(*this);
+        self.cgs_pass_body(w0, w1, basis, nb, h, dots);
+    }
+    template <class BP>
+    __device__ __forceinline__ void cgs_pass_body(CP w0, CP w1, BP basis, int nb, const double* h,
+                                                  double* dots) {
         if (nb <= 0) cgs_pass_any(w0, w1, basis, nb, h, dots);
         else if (nb == 1) cgs_pass_n<1>(w0, w1, basis, nb, h, dots);
         else if (nb == 2) cgs_pass_n<2>(w0, w1, basis, nb, h, dots);
@@ -1752,8 +1834,8 @@ struct Column {
     // behind the rows' loads in the in-order memory counter, one round trip
     // per vector.  Slots past nb repeat the last vector with weight 0.
     template <int NB, class BP>
-    __device__ void cgs_pass_n(CP w0, CP w1, BP basis, int nb, const double* h,
-                               double* dots) {
+    __device__ __forceinline__ void cgs_pass_n(CP w0, CP w1, BP basis, int nb, const double* h,
+                                               double* dots) {
         constexpr int U = NB <= 4 ? 4 : 2;
         const int M = cd.M;
         VecRef bv[NB];
@@ -1818,7 +1900,7 @@ struct Column {
 
     // The pass for any nb (references read per vector inside the row loop).
     template <class BP>
-    __device__ void cgs_pass_any(CP w0, CP w1, BP basis, int nb, const double* h,
+    __device__ __forceinline__ void cgs_pass_any(CP w0, CP w1, BP basis, int nb, const double* h,
                                  double* dots) {
         constexpr int U = 4;
         const int M = cd.M;
@@ -1880,6 +1962,11 @@ struct Column {
     // out = (accumulate ? out : 0) + sum_i c[i] vecs[i]
     __device__ void lincomb(CP o0, CP o1, const VecRef* vecs, const double* c, int nv,
                             bool accumulate) {
+        Column self(*this);
+        self.lincomb_body(o0, o1, vecs, c, nv, accumulate);
+    }
+    __device__ __forceinline__ void lincomb_body(CP o0, CP o1, const VecRef* vecs, const double* c, int nv,
+                                                 bool accumulate) {
         if (nv <= 0) {
             if (accumulate) lincomb_t<true>(o0, o1, vecs, c, nv);
             else lincomb_t<false>(o0, o1, vecs, c, nv);
@@ -1899,7 +1986,7 @@ struct Column {
     // nv <= NV vectors, references and weights read ahead of the row loop
     // (as in cgs_pass_n); slots past nv repeat the last vector with weight 0
     template <int NV, bool ACC>
-    __device__ void lincomb_n(CP o0, CP o1, const VecRef* vecs, const double* c, int nv) {
+    __device__ __forceinline__ void lincomb_n(CP o0, CP o1, const VecRef* vecs, const double* c, int nv) {
         constexpr int U = NV <= 4 ? 4 : 2;
         const int M = cd.M;
         VecRef vv[NV];
@@ -1941,7 +2028,7 @@ struct Column {
         }
     }
     template <bool ACC>
-    __device__ void lincomb_t(CP o0, CP o1, const VecRef* vecs, const double* c, int nv) {
+    __device__ __forceinline__ void lincomb_t(CP o0, CP o1, const VecRef* vecs, const double* c, int nv) {
         constexpr int U = 4;
         const int M = cd.M;
         for (int j0 = 0; j0 < M; j0 += U) {
@@ -1975,6 +2062,11 @@ struct Column {
 
     // Line-search trial X_t = X + lam S_X d, its residual and norms.
     __device__ Norms trial(int cur, int out, const VecRef& d, double lam) {
+        Column self(*this);
+        const VecRef dl = d;
+        return self.trial_body(cur, out, dl, lam);
+    }
+    __device__ __forceinline__ Norms trial_body(int cur, int out, const VecRef& d, double lam) {
         const CP X0 = xb(cur, 0);
         const CP X1 = xb(cur, 1);
         const double a0 = lam * sxn * d.s0, a1 = lam * sxp * d.s1;
@@ -1985,6 +2077,10 @@ struct Column {
 
     // Residual of buffer b (test export / re-evaluation)
     __device__ Norms eval(int b) {
+        Column self(*this);
+        return self.eval_body(b);
+    }
+    __device__ __forceinline__ Norms eval_body(int b) {
         const CP X0 = xb(b, 0);
         const CP X1 = xb(b, 1);
         const VecRef none{CP{nullptr}, CP{nullptr}, 0.0, 0.0};
