@@ -493,7 +493,7 @@ int jfnk_set_model(jfnk_ctx *ctx, jfnk_net *net);
  * of jfnk_step on a fresh context.  Limits: at most JFNK_NOALLOC_MAX_COLS
  * columns, and the workspace must fit: 8 (48 + 4 m) bytes per padded cell
  * (cells rounded up to a multiple of the workgroup size, m = gmres_restart;
- * 1344 bytes at m = 30) plus 768 T bytes per column, in JFNK_NOALLOC_BYTES;
+ * 1344 bytes at m = 30) plus 160 T bytes per column, in JFNK_NOALLOC_BYTES;
  * larger problems return JFNK_ECAPACITY (nothing launched).  err (HOST,
  * err_len bytes, may be NULL) receives a message on error.
  *

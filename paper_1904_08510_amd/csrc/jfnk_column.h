@@ -305,14 +305,14 @@ struct Norms {
 };
 
 // LDS layout of a column workgroup (doubles):
-//   [0, 12T)            PCR rows / exchange buffers
-//   [12T, 12T + 16*NW)  reduction scratch
+//   [0, 14T)            PCR rows / exchange buffers
+//   [14T, 14T + 16*NW)  reduction scratch
 //   then the GMRES small dense state.
 template <int T>
 struct Lds {
     static constexpr int NW = T / 64;
     static constexpr int kPcr = 0;
-    static constexpr int kScr = 12 * T;
+    static constexpr int kScr = 14 * T;
     static constexpr int kH = kScr + 16 * NW;                   // (m+1) x m, column major
     static constexpr int kCs = kH + (kMaxRestart + 1) * kMaxRestart;
     static constexpr int kSn = kCs + kMaxRestart;
@@ -1016,7 +1016,8 @@ struct Column {
 
     // ------------------------------------------------------------------
     // Jacobian assembly + factorisation (FP64 arithmetic; per-cell factors
-    // stored in FT; reduced per-chunk system kept and factored in FP64).
+    // stored in FT; the reduced per-chunk system's rows kept in FP64, and
+    // eliminated by each apply).
     // Rows of chunk t: row 0 is the chunk's interface unknown x0(t); rows
     // j >= 1 are eliminated by block LU of the chunk's interior with x0(t)
     // and x0(t+1) as boundary values:
@@ -1198,58 +1199,14 @@ struct Column {
         Blk<double> Lr = bneg(bmul(A0, aLp));
         Blk<double> Dr = bsub(bsub(B0, bmul(A0, gLp)), bmul(C0, a1));
         Blk<double> Ur = bneg(bmul(C0, g1));
-        // locals: the barriers below make the compiler reload members of an
-        // out-of-line phase function's object from memory after each of them
-        const int tl = t;
-        // parallel cyclic reduction (FP64).  The elimination factors of every
-        // stage stay in registers and are stored after the last stage: a
-        // barrier waits for the workgroup's outstanding global stores, so
-        // stores inside the loop would add one memory round trip per stage.
-        constexpr int LG = ilog2(T);
-        Blk<double> K1[LG], K2[LG];
+        // red(k) = rb + k T: A0, C0 and the chunk's row (L, D, U) of the
+        // interface system; each apply eliminates it by parallel cyclic
+        // reduction together with its right-hand side
+        double* const rb = W.red + cd.red + t;
+        const double rv[20] = {A0.a, A0.b, A0.c, A0.d, C0.a, C0.b, C0.c, C0.d, Lr.a, Lr.b, Lr.c, Lr.d,
+                               Dr.a, Dr.b, Dr.c, Dr.d, Ur.a, Ur.b, Ur.c, Ur.d};
 #pragma unroll
-        for (int lv = 0; lv < LG; ++lv) {
-            const int st = 1 << lv;
-            __syncthreads();
-            ldbl* row = P + 12 * tl;
-            row[0] = Lr.a; row[1] = Lr.b; row[2] = Lr.c; row[3] = Lr.d;
-            row[4] = Dr.a; row[5] = Dr.b; row[6] = Dr.c; row[7] = Dr.d;
-            row[8] = Ur.a; row[9] = Ur.b; row[10] = Ur.c; row[11] = Ur.d;
-            __syncthreads();
-            Blk<double> k1 = bzero(), k2 = bzero(), Lm = bzero(), Um = bzero(), Lp = bzero(), Up = bzero();
-            if (tl >= st) {
-                const ldbl* o = P + 12 * (tl - st);
-                Lm = {o[0], o[1], o[2], o[3]};
-                const Blk<double> Dm{o[4], o[5], o[6], o[7]};
-                Um = {o[8], o[9], o[10], o[11]};
-                k1 = bmul(Lr, binv(Dm));
-            }
-            if (tl + st < T) {
-                const ldbl* o = P + 12 * (tl + st);
-                Lp = {o[0], o[1], o[2], o[3]};
-                const Blk<double> Dp{o[4], o[5], o[6], o[7]};
-                Up = {o[8], o[9], o[10], o[11]};
-                k2 = bmul(Ur, binv(Dp));
-            }
-            Dr = bsub(bsub(Dr, bmul(k1, Um)), bmul(k2, Lp));
-            Lr = bneg(bmul(k1, Lm));
-            Ur = bneg(bmul(k2, Up));
-            K1[lv] = k1;
-            K2[lv] = k2;
-        }
-        const Blk<double> Di = binv(Dr);
-        // red(k) = rb + k T: A0, C0, then (k1, k2) of each stage, then D^-1
-        double* const rb = W.red + cd.red + tl;
-        gst(rb + 0 * T, A0.a); gst(rb + 1 * T, A0.b); gst(rb + 2 * T, A0.c); gst(rb + 3 * T, A0.d);
-        gst(rb + 4 * T, C0.a); gst(rb + 5 * T, C0.b); gst(rb + 6 * T, C0.c); gst(rb + 7 * T, C0.d);
-#pragma unroll
-        for (int lv = 0; lv < LG; ++lv) {
-            double* const rk = rb + (int64_t)(8 + 8 * lv) * T;
-            gst(rk + 0 * T, K1[lv].a); gst(rk + 1 * T, K1[lv].b); gst(rk + 2 * T, K1[lv].c); gst(rk + 3 * T, K1[lv].d);
-            gst(rk + 4 * T, K2[lv].a); gst(rk + 5 * T, K2[lv].b); gst(rk + 6 * T, K2[lv].c); gst(rk + 7 * T, K2[lv].d);
-        }
-        double* const rk = rb + (int64_t)(8 + 8 * LG) * T;
-        gst(rk + 0 * T, Di.a); gst(rk + 1 * T, Di.b); gst(rk + 2 * T, Di.c); gst(rk + 3 * T, Di.d);
+        for (int k = 0; k < 20; ++k) gst(rb + (int64_t)k * T, rv[k]);
         if (t == 0) {
             ColState* cs = W.cst + cd.index;
             cs->fac_valid = 1;
@@ -1564,12 +1521,11 @@ struct Column {
         constexpr int U = 4;
         constexpr int LG = ilog2(T);             // PCR stages of the interface system
         const int M = cd.M;
-        // The interface system's coefficients do not depend on v: their loads
-        // are issued first, so that their latency overlaps the chunk sweeps
-        // instead of adding one memory round trip per PCR stage.
-        double pc[8 * LG + 12];
+        // The interface system's row does not depend on v: its loads are
+        // issued first, so that their latency overlaps the chunk sweeps.
+        double pc[20];
 #pragma unroll
-        for (int i = 0; i < 8 * LG + 12; ++i) pc[i] = gld(red(i));
+        for (int i = 0; i < 20; ++i) pc[i] = gld(red(i));
         Vec2<double> d0{v.p0[sidx(tl, 0)] * v.s0, v.p1[sidx(tl, 0)] * v.s1};
         // down sweep: d_j = m_j v_j - At_j d_{j-1}, and with it d''_1 = sum Q_j d_j
         // (Q_1 = I, Q_{j+1} = -Q_j g_j); loads of U rows issued first.
@@ -1630,26 +1586,47 @@ struct Column {
         const Blk<double> C0{pc[4], pc[5], pc[6], pc[7]};
         const Vec2<double> qa = bmv(A0, dLp), qc = bmv(C0, dFirst);
         Vec2<double> r{d0.x - qa.x - qc.x, d0.y - qa.y - qc.y};
+        // Parallel cyclic reduction (FP64) of the interface system: at stage
+        // lv row t eliminates its couplings to rows t -+ 2^lv with
+        // k1 = L_t D_{t-s}^-1, k2 = U_t D_{t+s}^-1, from the rows' (L, D, U, r)
+        // exchanged through LDS (one array per value: no bank conflicts).
+        Blk<double> Lr{pc[8], pc[9], pc[10], pc[11]};
+        Blk<double> Dr{pc[12], pc[13], pc[14], pc[15]};
+        Blk<double> Ur{pc[16], pc[17], pc[18], pc[19]};
 #pragma unroll
         for (int lv = 0; lv < LG; ++lv) {
-            const int st = 1 << lv, k = 8 + 8 * lv;
+            const int st = 1 << lv;
             __syncthreads();
-            P[2 * tl] = r.x; P[2 * tl + 1] = r.y;
+            const double w[14] = {Lr.a, Lr.b, Lr.c, Lr.d, Dr.a, Dr.b, Dr.c, Dr.d, Ur.a, Ur.b, Ur.c, Ur.d, r.x, r.y};
+#pragma unroll
+            for (int k = 0; k < 14; ++k) P[k * T + tl] = w[k];
             __syncthreads();
+            Blk<double> k1 = bzero(), k2 = bzero(), Lm = bzero(), Um = bzero(), Lp = bzero(), Up = bzero();
+            Vec2<double> rm{0.0, 0.0}, rp{0.0, 0.0};
             if (tl >= st) {
-                const Blk<double> k1{pc[k], pc[k + 1], pc[k + 2], pc[k + 3]};
-                const Vec2<double> q = bmv(k1, Vec2<double>{P[2 * (tl - st)], P[2 * (tl - st) + 1]});
-                r.x -= q.x; r.y -= q.y;
+                const ldbl* o = P + (tl - st);
+                Lm = {o[0 * T], o[1 * T], o[2 * T], o[3 * T]};
+                const Blk<double> Dm{o[4 * T], o[5 * T], o[6 * T], o[7 * T]};
+                Um = {o[8 * T], o[9 * T], o[10 * T], o[11 * T]};
+                rm = {o[12 * T], o[13 * T]};
+                k1 = bmul(Lr, binv(Dm));
             }
             if (tl + st < T) {
-                const Blk<double> k2{pc[k + 4], pc[k + 5], pc[k + 6], pc[k + 7]};
-                const Vec2<double> q = bmv(k2, Vec2<double>{P[2 * (tl + st)], P[2 * (tl + st) + 1]});
-                r.x -= q.x; r.y -= q.y;
+                const ldbl* o = P + (tl + st);
+                Lp = {o[0 * T], o[1 * T], o[2 * T], o[3 * T]};
+                const Blk<double> Dp{o[4 * T], o[5 * T], o[6 * T], o[7 * T]};
+                Up = {o[8 * T], o[9 * T], o[10 * T], o[11 * T]};
+                rp = {o[12 * T], o[13 * T]};
+                k2 = bmul(Ur, binv(Dp));
             }
+            Dr = bsub(bsub(Dr, bmul(k1, Um)), bmul(k2, Lp));
+            Lr = bneg(bmul(k1, Lm));
+            Ur = bneg(bmul(k2, Up));
+            const Vec2<double> q1 = bmv(k1, rm), q2 = bmv(k2, rp);
+            r.x -= q1.x; r.y -= q1.y;
+            r.x -= q2.x; r.y -= q2.y;
         }
-        constexpr int k = 8 + 8 * LG;
-        const Blk<double> Di{pc[k], pc[k + 1], pc[k + 2], pc[k + 3]};
-        const Vec2<double> x0 = bmv(Di, r);
+        const Vec2<double> x0 = bmv(binv(Dr), r);
         __syncthreads();
         P[2 * tl] = x0.x; P[2 * tl + 1] = x0.y;
         __syncthreads();

@@ -20,7 +20,7 @@
 namespace jfnk {
 
 constexpr int kMaxRestart = 30;      // largest GMRES restart length supported
-constexpr int kRedPerChunk = 96;     // doubles of reduced-system data per chunk (T <= 1024)
+constexpr int kRedPerChunk = 20;     // doubles of reduced-system data per chunk: A0, C0, L, D, U
 constexpr int kFactorSlots = 20;     // FT values per cell stored by the factorisation
                                      // (16 block factors + 4 coupling entries of the
                                      // approximate-Schur preconditioner)
