@@ -407,7 +407,10 @@ struct Column {
         // Group of U rows' operands.  Loads carry no conditions, so a group's
         // loads issue back to back: rows past the chunk's end reload its last
         // real row, and the last cell of the column reloads itself in place of
-        // its (absent) right neighbour; neither value is used.
+        // its (absent) right neighbour; neither value is used.  Without flow
+        // the u_f h_f/D_f loads read the mu_f/D_f array instead (the same
+        // cache lines: no memory traffic) and the value is not used.
+        const double* const fwa = prm.has_u ? W.fw : W.fa;
         struct Grp {
             double xn[U], xp[U], fa[U], fg[U], fw[U];
             Own ow[U];
@@ -422,7 +425,7 @@ struct Column {
                 getx(sn, g.xn[u], g.xp[u]);
                 g.fa[u] = gld(W.fa + sn);
                 g.fg[u] = gld(W.fg + sn);
-                g.fw[u] = gld(W.fw + sn);
+                g.fw[u] = gld(fwa + sn);
             }
         };
         // Double buffer: the next group's loads issue before this group's
@@ -488,6 +491,7 @@ struct Column {
         RecA FLA = fA(gld(W.fa + s0), gld(W.fg + s0), fw0, ihL, nAL, pAL, nA, pA);
         RecB FLB = fB(gld(W.fa + s0), gld(W.fg + s0), fw0, ihL, nBL, pBL, nB, pB);
         // double-buffered groups with unconditional loads, as in sweep
+        const double* const fwa = prm.has_u ? W.fw : W.fa;
         struct Grp {
             double an[U], ap[U], bn[U], bp[U], fa[U], fg[U], fw[U];
             Own ow[U];
@@ -503,7 +507,7 @@ struct Column {
                 gxb(sn, g.bn[u], g.bp[u]);
                 g.fa[u] = gld(W.fa + sn);
                 g.fg[u] = gld(W.fg + sn);
-                g.fw[u] = gld(W.fw + sn);
+                g.fw[u] = gld(fwa + sn);
             }
         };
         Grp gc, gn;

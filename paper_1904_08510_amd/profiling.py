@@ -3,6 +3,8 @@
     python -m paper_1904_08510_amd.profiling stats <dir>            # --kernel-trace --stats run
     python -m paper_1904_08510_amd.profiling pmc <fetch_dir> <write_dir> <out.json>
     python -m paper_1904_08510_amd.profiling dram <dir> <out.json>  # one --pmc run of DRAM_COUNTERS
+    python -m paper_1904_08510_amd.profiling phase-run [n]          # the per-phase workload (GPU)
+    python -m paper_1904_08510_amd.profiling phase-traffic <dir> [n]  # its DRAM counters per phase
 
 `dram` reads HBM bytes directly from the L2's DRAM-sector counters of gfx950
 (TCC_EA0_RDREQ_DRAM_32B and TCC_EA0_WRREQ_WRITE_DRAM_32B count 32-byte
@@ -10,6 +12,11 @@ sectors, a 64-byte request as 2 and a 128-byte one as 4), with the
 calibration copy as a check rather than a scale, and records the 128-byte
 read requests two ways (TCC_BUBBLE, which the FETCH_SIZE expression prices
 at 128 bytes, and TCC_EA0_RDREQ_128B).
+
+`phase-run` runs the single-phase exports (residual, J.v, block solve) twice
+on one column of n cells (default 2^22, which streams through HBM: no cache
+holds its fields), each phase its own launch; `phase-traffic` reads a
+DRAM-counter run of it and prints the HBM bytes per cell of every phase.
 
 `stats` prints the per-kernel time table of a kernel-trace run.  `pmc`
 combines a FETCH_SIZE run and a WRITE_SIZE run (counters in KiB per
@@ -150,6 +157,59 @@ def dram(d: str, out_path: str) -> dict:
     return res
 
 
+# the launches of each single-phase export, in order (one column)
+PHASE_EXPORTS = (
+    ("residual", ("set-up", "load X", "residual", "store F")),
+    ("J.v", ("set-up", "load X", "residual", "load v", "direction copy", "direction norm", "J.v", "store w")),
+    ("block solve", ("set-up", "load X", "factorisation", "load r", "apply", "store z")),
+)
+PHASE_ROUNDS = 2
+
+
+def phase_run(n: int = 1 << 22) -> None:
+    """Single-phase exports on one flame column of n cells (FP32 factors,
+    workgroup of 256), PHASE_ROUNDS times each."""
+    import torch
+    from . import jfnk as J, workloads as W
+    packed = W.pack([W.flame_column(n, 500.0)])
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    cfg = J.config_for(packed, prec_precision=J.PREC_FP32, schedule=J.SCHED_BATCHED, threads_override=256)
+    s = J.Solver(cfg)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    r_ne = torch.randn(ne.shape, device="cuda", dtype=torch.float64, generator=g)
+    r_phi = torch.randn(phi.shape, device="cuda", dtype=torch.float64, generator=g)
+    for k in range(PHASE_ROUNDS):
+        for name, call in (("residual", lambda: s.eval_residual(prob, ne, phi, ne, phi)),
+                           ("J.v", lambda: s.eval_jv(prob, ne, phi, ne, phi, r_ne, r_phi)),
+                           ("block solve", lambda: s.block_solve(prob, ne, phi, ne, phi, r_ne, r_phi))):
+            call()
+            torch.cuda.synchronize()
+            print(f"phase-run: round {k} {name} done", flush=True)
+    s.close()
+
+
+def phase_traffic(d: str, n: int = 1 << 22) -> str:
+    """Table of HBM bytes per cell (read, write) of every single-phase launch
+    of a DRAM-counter run of phase_run, averaged over the rounds."""
+    rows = list(csv.DictReader(open(_find(d, "counter_collection.csv"))))
+    disp = {}
+    for r in rows:
+        if "k_phase" not in r.get("Kernel_Name", ""):
+            continue
+        e = disp.setdefault(int(r["Dispatch_Id"]), {})
+        e[r["Counter_Name"]] = float(r["Counter_Value"])
+    order = [disp[k] for k in sorted(disp)]
+    labels = [(e, p) for e, ps in PHASE_EXPORTS for p in ps]
+    if len(order) != PHASE_ROUNDS * len(labels):
+        raise RuntimeError(f"{len(order)} single-phase launches, expected {PHASE_ROUNDS * len(labels)}")
+    out = ["export | launch | read B/cell | write B/cell", "---|---|---|---"]
+    for i, (e, p) in enumerate(labels):
+        rd = sum(32.0 * order[k * len(labels) + i]["TCC_EA0_RDREQ_DRAM_32B_sum"] for k in range(PHASE_ROUNDS))
+        wr = sum(32.0 * order[k * len(labels) + i]["TCC_EA0_WRREQ_WRITE_DRAM_32B_sum"] for k in range(PHASE_ROUNDS))
+        out.append(f"{e} | {p} | {rd / PHASE_ROUNDS / n:.1f} | {wr / PHASE_ROUNDS / n:.1f}")
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
     if len(sys.argv) == 1:
         print(source_hash())
@@ -159,5 +219,9 @@ if __name__ == "__main__":
         print(json.dumps(pmc(sys.argv[2], sys.argv[3], sys.argv[4]), indent=1))
     elif sys.argv[1] == "dram":
         print(json.dumps(dram(sys.argv[2], sys.argv[3]), indent=1))
+    elif sys.argv[1] == "phase-run":
+        phase_run(*(int(a) for a in sys.argv[2:3]))
+    elif sys.argv[1] == "phase-traffic":
+        print(phase_traffic(sys.argv[2], *(int(a) for a in sys.argv[3:4])))
     else:
         raise SystemExit(__doc__)
