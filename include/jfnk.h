@@ -367,6 +367,35 @@ const char *jfnk_last_error(const jfnk_ctx *ctx);
 int jfnk_autotune(jfnk_ctx *ctx, const jfnk_problem *p, const jfnk_state *x, int32_t steps,
                   int32_t *chosen, double *times_ms, void *stream);
 
+/* Persisted autotuner results, so that a later process on the same kind of
+   GPU takes the tuned workgroup size without timing the candidates again.
+   A layout is keyed by its column count, total cells, table transport on or
+   off and the 64-bit FNV-1a hash of its col_offset array (a collision can
+   only select a slower workgroup size, never change a result).
+
+   jfnk_autotune_save appends one text line per layout this context tuned
+   (device architecture name, prec_precision, prec_kind, the key, the chosen
+   workgroup size and the four summed solve times) to the file at path
+   (HOST string; created if absent).  JFNK_EINVAL if the file cannot be
+   written.
+
+   jfnk_autotune_load reads such a file and keeps the lines whose device
+   architecture, prec_precision and prec_kind match this context (malformed
+   lines are skipped; for a key present more than once, the last line wins);
+   *nloaded (HOST, may be NULL) receives their count.  A later batched step
+   without threads_override whose layout matches a kept line, and that this
+   context has not tuned itself, takes that line's workgroup size if it owns
+   the longest column with at most 64 cells per thread.  JFNK_EINVAL if the
+   file cannot be opened.  Neither call touches the GPU. */
+int jfnk_autotune_save(jfnk_ctx *ctx, const char *path);
+int jfnk_autotune_load(jfnk_ctx *ctx, const char *path, int32_t *nloaded);
+
+/* The workgroup size per column that the next step of this context takes
+   for p's layout (threads_override, this context's autotuner result, a
+   loaded entry, or the size rule), into *threads (HOST).  Reads only
+   p->ncols and p->col_offset (HOST). */
+int jfnk_schedule_threads(jfnk_ctx *ctx, const jfnk_problem *p, int32_t *threads);
+
 /* Device time of the last jfnk_step's solve (ms, HIP events recorded on the
    step's stream right before and after the solve launches; for the plain
    schedule the span of all its phase launches; the learned guess, evaluated

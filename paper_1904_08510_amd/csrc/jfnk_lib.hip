@@ -341,6 +341,16 @@ struct jfnk_ctx {
     int force_T = 0;                      // set while the tuner tries a candidate
     int tuned_T = 0;
     std::vector<int64_t> tuned_off;
+    // tuned workgroup sizes by layout: this context's autotuner results and
+    // those read by jfnk_autotune_load (matched by the layout's hash)
+    struct TuneEntry {
+        uint64_t hash;
+        int32_t ncols, table, T;
+        int64_t total;
+        double ms[4];
+        bool mine;      // tuned by this context (saved by jfnk_autotune_save)
+    };
+    std::vector<TuneEntry> tune_table;
     std::vector<uint8_t> evaluated;       // network evaluated for the column this step
     std::vector<int32_t> reject_streak;   // consecutive evaluations its candidate lost
     std::vector<int32_t> skip_left;       // chances to skip before evaluating it again
@@ -388,6 +398,36 @@ int fail(jfnk_ctx* c, int code, const std::string& msg) {
             return fail(ctx, JFNK_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
         }                                                                                \
     } while (0)
+
+// 64-bit FNV-1a over the column offsets: the key of a tuned layout
+uint64_t layout_hash(const int64_t* off, int n1) {
+    uint64_t h = 1469598103934665603ull;
+    const unsigned char* b = (const unsigned char*)off;
+    for (size_t i = 0; i < sizeof(int64_t) * (size_t)n1; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// the current device's architecture name (a tuned entry's device)
+std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t pr;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&pr, dev) != hipSuccess) return "unknown";
+    std::string a = pr.gcnArchName;
+    for (char& ch : a)
+        if (ch == ' ' || ch == '\t' || ch == '\n') ch = '_';
+    return a.empty() ? "unknown" : a;
+}
+
+// A workgroup size is used for a layout when it owns its longest column with
+// at most 64 cells per thread (any size for columns beyond 64 kTmax cells,
+// which only the largest can take at 64) -- the autotuner's rule.
+bool threads_fit(int T, int nmax) {
+    if (T != 64 && T != 128 && T != 256 && T != 512) return false;
+    return T == kTmax || (nmax + T - 1) / T <= 64;
+}
 
 int choose_T(const jfnk_config& cfg, int nmax) {
     if (cfg.threads_override > 0) return cfg.threads_override;
@@ -486,6 +526,31 @@ TabRef tab_of(const jfnk_problem* p) {
 }
 
 // validation of the problem; fills the schedule on success
+// the workgroup size of a tuned entry for this layout (0: none)
+int tuned_lookup(const jfnk_ctx* ctx, const jfnk_problem* p, int nmax) {
+    if (ctx->tune_table.empty()) return 0;
+    const uint64_t h = layout_hash(p->col_offset, p->ncols + 1);
+    const int tab = p->table ? 1 : 0;
+    for (auto it = ctx->tune_table.rbegin(); it != ctx->tune_table.rend(); ++it)
+        if (it->hash == h && it->ncols == p->ncols && it->total == p->col_offset[p->ncols] && it->table == tab &&
+            threads_fit(it->T, nmax))
+            return it->T;
+    return 0;
+}
+
+// the workgroup size a step of this context takes for p's layout
+int step_threads(const jfnk_ctx* ctx, const jfnk_problem* p, int nmax) {
+    if (ctx->force_T > 0) return ctx->force_T;
+    if (ctx->cfg.threads_override == 0 && ctx->tuned_T > 0 && (int)ctx->tuned_off.size() == p->ncols + 1 &&
+        memcmp(ctx->tuned_off.data(), p->col_offset, sizeof(int64_t) * (p->ncols + 1)) == 0)
+        return ctx->tuned_T;
+    if (ctx->cfg.threads_override == 0 && ctx->cfg.schedule == JFNK_SCHED_BATCHED) {
+        const int tt = tuned_lookup(ctx, p, nmax);
+        if (tt > 0) return tt;
+    }
+    return choose_T(ctx->cfg, nmax);
+}
+
 int validate(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x) {
     if (!p || !x) return fail(ctx, JFNK_EINVAL, "null problem or state");
     if (p->ncols < 1) return fail(ctx, JFNK_EINVAL, "ncols < 1");
@@ -512,14 +577,7 @@ int validate(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x) {
     }
     if (p->col_offset[p->ncols] > ctx->cfg.max_total_cells)
         return fail(ctx, JFNK_ECAPACITY, "total cells exceed capacity");
-    int T = choose_T(ctx->cfg, nmax);
-    if (ctx->force_T > 0) {
-        T = ctx->force_T;
-    } else if (ctx->cfg.threads_override == 0 && ctx->tuned_T > 0 &&
-               (int)ctx->tuned_off.size() == p->ncols + 1 &&
-               memcmp(ctx->tuned_off.data(), p->col_offset, sizeof(int64_t) * (p->ncols + 1)) == 0) {
-        T = ctx->tuned_T;
-    }
+    const int T = step_threads(ctx, p, nmax);
     int64_t ws = 0, red = 0;
     for (int c = 0; c < p->ncols; ++c) {
         const int n = (int)(p->col_offset[c + 1] - p->col_offset[c]);
@@ -1679,7 +1737,82 @@ int jfnk_autotune(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, int
     if (rc) return rc == JFNK_EHIP ? fail(ctx, rc, "autotune: HIP copy failed") : rc;
     ctx->tuned_T = best;
     ctx->tuned_off.assign(p->col_offset, p->col_offset + p->ncols + 1);
+    jfnk_ctx::TuneEntry te{};
+    te.hash = layout_hash(p->col_offset, p->ncols + 1);
+    te.ncols = p->ncols;
+    te.table = p->table ? 1 : 0;
+    te.T = best;
+    te.total = total;
+    te.mine = true;
+    for (int k = 0; k < 4; ++k) te.ms[k] = times_ms ? times_ms[k] : -1.0;
+    ctx->tune_table.push_back(te);
     if (chosen) *chosen = best;
+    return JFNK_OK;
+}
+
+int jfnk_autotune_save(jfnk_ctx* ctx, const char* path) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!path) return fail(ctx, JFNK_EINVAL, "autotune_save: null path");
+    FILE* f = fopen(path, "a");
+    if (!f) return fail(ctx, JFNK_EINVAL, std::string("autotune_save: cannot open ") + path);
+    const std::string arch = device_arch();
+    for (const auto& e : ctx->tune_table) {
+        if (!e.mine) continue;
+        fprintf(f, "jfnk-autotune v1 %s %d %d %d %d %lld %016llx %d %.6g %.6g %.6g %.6g\n", arch.c_str(),
+                ctx->cfg.prec_precision, ctx->cfg.prec_kind, e.table, e.ncols, (long long)e.total,
+                (unsigned long long)e.hash, e.T, e.ms[0], e.ms[1], e.ms[2], e.ms[3]);
+    }
+    const bool ok = fclose(f) == 0;
+    if (!ok) return fail(ctx, JFNK_EINVAL, std::string("autotune_save: write failed: ") + path);
+    return JFNK_OK;
+}
+
+int jfnk_autotune_load(jfnk_ctx* ctx, const char* path, int32_t* nloaded) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!path) return fail(ctx, JFNK_EINVAL, "autotune_load: null path");
+    FILE* f = fopen(path, "r");
+    if (!f) return fail(ctx, JFNK_EINVAL, std::string("autotune_load: cannot open ") + path);
+    const std::string arch = device_arch();
+    char line[512];
+    int n = 0;
+    while (fgets(line, sizeof(line), f)) {
+        char a[160];
+        int prec, kind, table, ncols, T;
+        long long total;
+        unsigned long long hash;
+        double ms[4];
+        if (sscanf(line, "jfnk-autotune v1 %159s %d %d %d %d %lld %llx %d %lf %lf %lf %lf", a, &prec, &kind, &table,
+                   &ncols, &total, &hash, &T, &ms[0], &ms[1], &ms[2], &ms[3]) != 12)
+            continue;
+        if (arch != a || prec != ctx->cfg.prec_precision || kind != ctx->cfg.prec_kind) continue;
+        if (ncols < 1 || total < 1 || (table != 0 && table != 1) || (T != 64 && T != 128 && T != 256 && T != 512))
+            continue;
+        jfnk_ctx::TuneEntry e{};
+        e.hash = (uint64_t)hash;
+        e.ncols = ncols;
+        e.table = table;
+        e.T = T;
+        e.total = total;
+        e.mine = false;
+        for (int k = 0; k < 4; ++k) e.ms[k] = ms[k];
+        ctx->tune_table.push_back(e);
+        ++n;
+    }
+    fclose(f);
+    ctx->sched_valid = false;
+    if (nloaded) *nloaded = n;
+    return JFNK_OK;
+}
+
+int jfnk_schedule_threads(jfnk_ctx* ctx, const jfnk_problem* p, int32_t* threads) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!p || !p->col_offset || p->ncols < 1 || !threads) return fail(ctx, JFNK_EINVAL, "schedule_threads: bad arguments");
+    int nmax = 0;
+    for (int c = 0; c < p->ncols; ++c) nmax = std::max(nmax, (int)(p->col_offset[c + 1] - p->col_offset[c]));
+    *threads = ctx->cfg.threads_override > 0 ? ctx->cfg.threads_override : step_threads(ctx, p, nmax);
     return JFNK_OK;
 }
 

@@ -147,6 +147,12 @@ def lib():
         L.jfnk_autotune.argtypes = [C.c_void_p, C.POINTER(jfnk_problem), C.POINTER(jfnk_state), C.c_int32,
                                     _ip, _dp, C.c_void_p]
         L.jfnk_autotune.restype = C.c_int
+        L.jfnk_autotune_save.argtypes = [C.c_void_p, C.c_char_p]
+        L.jfnk_autotune_save.restype = C.c_int
+        L.jfnk_autotune_load.argtypes = [C.c_void_p, C.c_char_p, _ip]
+        L.jfnk_autotune_load.restype = C.c_int
+        L.jfnk_schedule_threads.argtypes = [C.c_void_p, C.POINTER(jfnk_problem), _ip]
+        L.jfnk_schedule_threads.restype = C.c_int
         L.jfnk_set_model.argtypes = [C.c_void_p, C.c_void_p]
         L.jfnk_set_model.restype = C.c_int
         L.jfnk_step_noalloc.argtypes = [C.POINTER(jfnk_config), C.POINTER(jfnk_problem), C.POINTER(jfnk_state),
@@ -166,7 +172,8 @@ EXPORTED_SYMBOLS = ("jfnk_config_default", "jfnk_create", "jfnk_step", "jfnk_ste
                     "jfnk_net_create", "jfnk_net_destroy", "jfnk_net_last_error",
                     "jfnk_net_set_params", "jfnk_net_get_params", "jfnk_net_predict",
                     "jfnk_net_grad", "jfnk_net_train_step", "jfnk_set_model", "jfnk_autotune",
-                    "jfnk_step_noalloc", "jfnk_misdc_step")
+                    "jfnk_step_noalloc", "jfnk_misdc_step", "jfnk_autotune_save", "jfnk_autotune_load",
+                    "jfnk_schedule_threads")
 
 NOALLOC_BYTES = 64 << 20      # JFNK_NOALLOC_BYTES
 NOALLOC_MAX_COLS = 64         # JFNK_NOALLOC_MAX_COLS
@@ -507,6 +514,24 @@ class Solver:
         self._check(lib().jfnk_autotune(self.h, C.byref(p), C.byref(s), int(steps), C.byref(ch),
                                         t.ctypes.data_as(_dp), _stream_ptr(stream)), (JFNK_OK,))
         return ch.value, {T: float(v) for T, v in zip((64, 128, 256, 512), t) if v >= 0}
+
+    def autotune_save(self, path: str):
+        """Append this context's tuned layouts to the text file at path."""
+        self._check(lib().jfnk_autotune_save(self.h, os.fsencode(path)), (JFNK_OK,))
+
+    def autotune_load(self, path: str) -> int:
+        """Read tuned layouts from path (those of this device, precision and
+        preconditioner kind); returns how many were kept."""
+        n = C.c_int32()
+        self._check(lib().jfnk_autotune_load(self.h, os.fsencode(path), C.byref(n)), (JFNK_OK,))
+        return n.value
+
+    def schedule_threads(self, prob: DeviceProblem) -> int:
+        """Workgroup size per column the next step takes for prob's layout."""
+        p = prob.cstruct()
+        t = C.c_int32()
+        self._check(lib().jfnk_schedule_threads(self.h, C.byref(p), C.byref(t)), (JFNK_OK,))
+        return t.value
 
     def set_model(self, net: Optional["Net"]):
         """Attach a learned-guess network (None detaches)."""
