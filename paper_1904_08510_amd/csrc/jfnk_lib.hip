@@ -150,22 +150,30 @@ struct PhaseArgs {
     const double* in1;
     double* out0;
     double* out1;
+    int32_t all;        // one workgroup per column (column order[blockIdx.x]) instead of column ci alone
+    int32_t ncols;      // columns of a launch over all of them
+    const int* order;   // longest columns first (the dispatcher then balances the tail)
+    int32_t eps_dev;    // PH_JV: the finite-difference step from the column's scalars (see below)
 };
 
-template <int T, class FT, bool TAB>
+// PH >= 0: a kernel holding that phase alone (its registers are that
+// phase's, not the largest over all phases); -1: the phase from the arguments.
+template <int T, class FT, bool TAB, int PH = -1>
 __global__ __launch_bounds__(T) void k_phase(PhaseArgs a) {
     extern __shared__ double lds[];
+    const int phase = PH >= 0 ? PH : a.phase;
+    const int ci = a.all ? a.order[blockIdx.x] : a.ci;
     Column<T, FT, TAB> col;
-    col.init(a.W.cols[a.ci], a.W, a.prm, (ldbl*)lds);
-    double* scal = a.W.scal + (int64_t)a.ci * kScalSlots;
+    col.init(a.W.cols[ci], a.W, a.prm, (ldbl*)lds);
+    double* scal = a.W.scal + (int64_t)ci * kScalSlots;
     VecRef* bl = (VecRef*)(lds + Lds<T>::kBasis);
-    if (a.phase != PH_SETUP) col.load_state();
-    if (a.phase == PH_JV || a.phase == PH_CGS) {
+    if (phase != PH_SETUP) col.load_state();
+    if (phase == PH_JV || phase == PH_CGS) {
         if (threadIdx.x == 0)
             for (int i = 0; i < a.nb; ++i) bl[i] = a.basis[i];
         __syncthreads();
     }
-    switch (a.phase) {
+    switch (phase) {
     case PH_SETUP: {
         int cur, g;
         const Norms n = col.setup(a.U, &cur, &g);
@@ -192,9 +200,18 @@ __global__ __launch_bounds__(T) void k_phase(PhaseArgs a) {
     }
     case PH_JV: {
         double dots[kMaxRestart + 2];
+        double eps = a.eps;
+        if (a.eps_dev) {
+            // eq:jf_dfapprox's step for z = Z[zslot] from ||S_X^-1 X||^2 (left in
+            // scal[2] by PH_EVAL) and ||z||^2 (left in scal[0] by PH_NORM_DX);
+            // every thread reads them before thread 0 overwrites scal below
+            const double xn2 = scal[2], vn2 = scal[0];
+            const double lam_fd = 6.0554544523933395e-06;
+            eps = vn2 > 0.0 ? lam_fd * (lam_fd + sqrt(xn2) / sqrt(vn2)) : 1.0;
+        }
         const VecRef z = (a.zslot >= 0) ? VecRef{col.Zb(a.zslot, 0), col.Zb(a.zslot, 1), 1.0, 1.0}
                                         : a.v;
-        col.jv(a.cur, z, a.eps, col.Vb(a.wslot, 0), col.Vb(a.wslot, 1), bl, a.nb, dots);
+        col.jv(a.cur, z, eps, col.Vb(a.wslot, 0), col.Vb(a.wslot, 1), bl, a.nb, dots);
         if (threadIdx.x == 0)
             for (int i = 0; i <= a.nb; ++i) scal[i] = dots[i];
         break;
@@ -886,12 +903,20 @@ int dispatch_run(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_
     return p->table ? dispatch_run_t<FT, true>(ctx, p, x, st) : dispatch_run_t<FT, false>(ctx, p, x, st);
 }
 
-// single-column phase runner for the test exports
+// phase runner for the test exports: column a.ci, or every column (a.all)
+// with one workgroup each; the residual and J v phases run in kernels of
+// their own
 template <int T, class FT, bool TAB>
 int run_phases(jfnk_ctx* ctx, hipStream_t st, PhaseArgs& a, const std::vector<int>& phases) {
+    const dim3 grid(a.all ? (unsigned)a.ncols : 1u);
     for (int ph : phases) {
         a.phase = ph;
-        hipLaunchKernelGGL((k_phase<T, FT, TAB>), dim3(1), dim3(T), Lds<T>::bytes(), st, a);
+        if (ph == PH_EVAL)
+            hipLaunchKernelGGL((k_phase<T, FT, TAB, PH_EVAL>), grid, dim3(T), Lds<T>::bytes(), st, a);
+        else if (ph == PH_JV)
+            hipLaunchKernelGGL((k_phase<T, FT, TAB, PH_JV>), grid, dim3(T), Lds<T>::bytes(), st, a);
+        else
+            hipLaunchKernelGGL((k_phase<T, FT, TAB>), grid, dim3(T), Lds<T>::bytes(), st, a);
         HIP_OK(hipGetLastError());
     }
     return JFNK_OK;
@@ -1028,16 +1053,10 @@ int prepare_test(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, hipS
     return JFNK_OK;
 }
 
-template <class Fn>
-int for_each_column(jfnk_ctx* ctx, const jfnk_problem* p, hipStream_t st, PhaseArgs& a, Fn fn) {
-    for (int c = 0; c < p->ncols; ++c) {
-        a.ci = c;
-        std::vector<int> ph = fn(c);
-        const int rc = ctx->cfg.prec_precision == JFNK_PREC_FP32 ? dispatch_phases<float>(ctx, st, a, ph)
-                                                                : dispatch_phases<double>(ctx, st, a, ph);
-        if (rc) return rc;
-    }
-    return JFNK_OK;
+// phases in the context's precision (over every column when a.all)
+int run_all(jfnk_ctx* ctx, hipStream_t st, PhaseArgs& a, const std::vector<int>& ph) {
+    return ctx->cfg.prec_precision == JFNK_PREC_FP32 ? dispatch_phases<float>(ctx, st, a, ph)
+                                                    : dispatch_phases<double>(ctx, st, a, ph);
 }
 
 // Learned candidate for the columns whose previous step on this layout
@@ -1852,9 +1871,8 @@ int jfnk_eval_residual(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x
     rc = prepare_test(ctx, p, x, st, a);
     if (rc) return rc;
     a.in0 = x_ne; a.in1 = x_phi; a.out0 = fe; a.out1 = fp; a.cur = 1;
-    rc = for_each_column(ctx, p, st, a, [](int) {
-        return std::vector<int>{PH_SETUP, PH_LOAD_X, PH_EVAL, PH_STORE_F};
-    });
+    a.all = 1; a.ncols = p->ncols; a.order = ctx->d_order;
+    rc = run_all(ctx, st, a, {PH_SETUP, PH_LOAD_X, PH_EVAL, PH_STORE_F});
     if (rc) return rc;
     if (scal) {
         HIP_OK(hipMemcpyAsync(ctx->h_cst, ctx->W.cst, sizeof(ColState) * p->ncols, hipMemcpyDeviceToHost, st));
@@ -1878,40 +1896,22 @@ int jfnk_eval_jv(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, cons
     PhaseArgs a;
     rc = prepare_test(ctx, p, x, st, a);
     if (rc) return rc;
-    // per column: set up, load X into buffer 1, F(X), load v into Z[0], norms
-    for (int c = 0; c < p->ncols; ++c) {
-        a.ci = c;
-        a.cur = 1; a.in0 = x_ne; a.in1 = x_phi;
-        auto run = [&](std::vector<int> ph) {
-            return ctx->cfg.prec_precision == JFNK_PREC_FP32 ? dispatch_phases<float>(ctx, st, a, ph)
-                                                            : dispatch_phases<double>(ctx, st, a, ph);
-        };
-        rc = run({PH_SETUP, PH_LOAD_X, PH_EVAL});
-        if (rc) return rc;
-        HIP_OK(hipMemcpyAsync(ctx->h_scal, ctx->W.scal + (int64_t)c * kScalSlots, sizeof(double) * 4,
-                              hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
-        const double xn2 = ctx->h_scal[2];
-        a.zslot = 0; a.in0 = v_ne; a.in1 = v_phi;
-        rc = run({PH_LOAD_V});
-        if (rc) return rc;
-        // ||v||^2 through the dX norm phase: copy v into dX via a one-term lincomb
-        a.nb = 1; a.acc = 0; a.h[0] = 1.0;
-        rc = run({PH_LINCOMB, PH_NORM_DX});
-        if (rc) return rc;
-        HIP_OK(hipMemcpyAsync(ctx->h_scal, ctx->W.scal + (int64_t)c * kScalSlots, sizeof(double),
-                              hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
-        const double vn2 = ctx->h_scal[0];
-        const double lam_fd = 6.0554544523933395e-06;
-        a.eps = (vn2 > 0.0) ? lam_fd * (lam_fd + std::sqrt(xn2) / std::sqrt(vn2)) : 1.0;
-        a.cur = 1; a.zslot = 0; a.wslot = 1; a.nb = 0;
-        a.out0 = w_ne; a.out1 = w_phi;
-        rc = run({PH_JV});
-        if (rc) return rc;
-        rc = run({PH_STORE_W});
-        if (rc) return rc;
-    }
+    // every column at once: set up, X into buffer 1 and F(X) (||S_X^-1 X||^2
+    // left in scal[2]), v into Z[0], ||v||^2 into scal[0] through the dX norm
+    // phase (v copied into dX by a one-term lincomb), then w = J v with the
+    // step formed from the two norms on the device
+    a.all = 1; a.ncols = p->ncols; a.order = ctx->d_order;
+    a.cur = 1; a.in0 = x_ne; a.in1 = x_phi;
+    rc = run_all(ctx, st, a, {PH_SETUP, PH_LOAD_X, PH_EVAL});
+    if (rc) return rc;
+    a.zslot = 0; a.in0 = v_ne; a.in1 = v_phi;
+    a.nb = 1; a.acc = 0; a.h[0] = 1.0;
+    rc = run_all(ctx, st, a, {PH_LOAD_V, PH_LINCOMB, PH_NORM_DX});
+    if (rc) return rc;
+    a.cur = 1; a.zslot = 0; a.wslot = 1; a.nb = 0; a.eps_dev = 1;
+    a.out0 = w_ne; a.out1 = w_phi;
+    rc = run_all(ctx, st, a, {PH_JV, PH_STORE_W});
+    if (rc) return rc;
     HIP_OK(hipStreamSynchronize(st));
     return JFNK_OK;
 }
@@ -1926,26 +1926,19 @@ int jfnk_block_solve(jfnk_ctx* ctx, const jfnk_problem* p, const jfnk_state* x, 
     PhaseArgs a;
     rc = prepare_test(ctx, p, x, st, a);
     if (rc) return rc;
-    for (int c = 0; c < p->ncols; ++c) {
-        a.ci = c;
-        auto run = [&](std::vector<int> ph) {
-            return ctx->cfg.prec_precision == JFNK_PREC_FP32 ? dispatch_phases<float>(ctx, st, a, ph)
-                                                            : dispatch_phases<double>(ctx, st, a, ph);
-        };
-        a.cur = 1; a.in0 = x_ne; a.in1 = x_phi;
-        rc = run({PH_SETUP, PH_LOAD_X, PH_FACTOR});
-        if (rc) return rc;
-        a.zslot = 0; a.in0 = r_ne; a.in1 = r_phi;
-        rc = run({PH_LOAD_V});
-        if (rc) return rc;
-        a.v = VecRef{CP{ctx->W.Z}, CP{ctx->W.Z + 1}, 1.0, 1.0};
-        a.zslot = 1;
-        rc = run({PH_APPLY});
-        if (rc) return rc;
-        a.out0 = z_ne; a.out1 = z_phi;
-        rc = run({PH_STORE_V});
-        if (rc) return rc;
-    }
+    // every column at once: set up, X into buffer 1, factor; r into Z[0];
+    // z = P^-1 r into Z[1]; z back to the caller
+    a.all = 1; a.ncols = p->ncols; a.order = ctx->d_order;
+    a.cur = 1; a.in0 = x_ne; a.in1 = x_phi;
+    rc = run_all(ctx, st, a, {PH_SETUP, PH_LOAD_X, PH_FACTOR});
+    if (rc) return rc;
+    a.zslot = 0; a.in0 = r_ne; a.in1 = r_phi;
+    rc = run_all(ctx, st, a, {PH_LOAD_V});
+    if (rc) return rc;
+    a.v = VecRef{CP{ctx->W.Z}, CP{ctx->W.Z + 1}, 1.0, 1.0};
+    a.zslot = 1; a.out0 = z_ne; a.out1 = z_phi;
+    rc = run_all(ctx, st, a, {PH_APPLY, PH_STORE_V});
+    if (rc) return rc;
     HIP_OK(hipStreamSynchronize(st));
     return JFNK_OK;
 }

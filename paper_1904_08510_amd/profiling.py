@@ -5,6 +5,8 @@
     python -m paper_1904_08510_amd.profiling dram <dir> <out.json>  # one --pmc run of DRAM_COUNTERS
     python -m paper_1904_08510_amd.profiling phase-run [n]          # the per-phase workload (GPU)
     python -m paper_1904_08510_amd.profiling phase-traffic <dir> [n]  # its DRAM counters per phase
+    python -m paper_1904_08510_amd.profiling batch-run [rounds] [T] # the same exports on the 1024-column batch (GPU)
+    python -m paper_1904_08510_amd.profiling batch-phases <dir>     # its kernel trace: time and GB/s per launch
 
 `dram` reads HBM bytes directly from the L2's DRAM-sector counters of gfx950
 (TCC_EA0_RDREQ_DRAM_32B and TCC_EA0_WRREQ_WRITE_DRAM_32B count 32-byte
@@ -17,6 +19,14 @@ at 128 bytes, and TCC_EA0_RDREQ_128B).
 on one column of n cells (default 2^22, which streams through HBM: no cache
 holds its fields), each phase its own launch; `phase-traffic` reads a
 DRAM-counter run of it and prints the HBM bytes per cell of every phase.
+
+`batch-run` runs the same exports on the 1024-column batch (uneven
+512..8192-cell flame columns, FP32 factors, workgroup of T = 256 unless
+given), every phase
+one launch over all columns; `batch-phases` reads a kernel-trace run of it
+and prints each launch's average duration, registers and achieved bandwidth
+by its algorithmic bytes (PHASE_BYTES per cell of the batch).  The residual
+and J.v launches are kernels holding that phase alone.
 
 `stats` prints the per-kernel time table of a kernel-trace run.  `pmc`
 combines a FETCH_SIZE run and a WRITE_SIZE run (counters in KiB per
@@ -188,6 +198,62 @@ def phase_run(n: int = 1 << 22) -> None:
     s.close()
 
 
+# algorithmic bytes per cell of the launches that stream the column
+# (FP32 factor values: 16 of 4 bytes)
+PHASE_BYTES = {
+    "residual": 72.0,          # X + 5 coefficients -> F
+    "J.v": 104.0,              # X, z, F, 5 coefficients -> w
+    "factorisation": 104.0,    # X + 3 coefficients -> 16 factor values
+    "apply": 96.0,             # r + 16 factor values -> z
+}
+BATCH_ROUNDS = 3
+
+
+def batch_run(rounds: int = BATCH_ROUNDS, threads: int = 256) -> None:
+    """Single-phase exports over the 1024-column batch from its start state,
+    rounds times each (FP32 factors, workgroups of the given size)."""
+    import torch
+    from . import jfnk as J, workloads as W
+    packed = W.pack(W.config2())
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    cfg = J.config_for(packed, prec_precision=J.PREC_FP32, schedule=J.SCHED_BATCHED, threads_override=threads)
+    s = J.Solver(cfg)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    r_ne = torch.randn(ne.shape, device="cuda", dtype=torch.float64, generator=g)
+    r_phi = torch.randn(phi.shape, device="cuda", dtype=torch.float64, generator=g)
+    for k in range(rounds):
+        for name, call in (("residual", lambda: s.eval_residual(prob, ne, phi, ne, phi)),
+                           ("J.v", lambda: s.eval_jv(prob, ne, phi, ne, phi, r_ne, r_phi)),
+                           ("block solve", lambda: s.block_solve(prob, ne, phi, ne, phi, r_ne, r_phi))):
+            call()
+            torch.cuda.synchronize()
+            print(f"batch-run: round {k} {name} done ({packed.ncols} columns, {packed.total} cells)", flush=True)
+    s.close()
+
+
+def batch_phases(d: str, rounds: int = BATCH_ROUNDS, cells: int | None = None) -> str:
+    """Per launch of a kernel-trace run of batch_run: average duration over
+    the rounds, registers, and GB/s by the algorithmic bytes."""
+    if cells is None:
+        from . import workloads as W
+        cells = W.pack(W.config2()).total
+    rows = [r for r in csv.DictReader(open(_find(d, "kernel_trace.csv"))) if "k_phase" in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    labels = [(e, p) for e, ps in PHASE_EXPORTS for p in ps]
+    if len(rows) != rounds * len(labels):
+        raise RuntimeError(f"{len(rows)} single-phase launches, expected {rounds * len(labels)}")
+    out = [f"{cells} cells; export | launch | avg ms | VGPR + AGPR | GB/s (algorithmic) | of 8 TB/s",
+           "---|---|---|---|---|---"]
+    for i, (e, p) in enumerate(labels):
+        rs = [rows[k * len(labels) + i] for k in range(rounds)]
+        ms = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rs) / rounds / 1e6
+        regs = f"{rs[0]['VGPR_Count']} + {rs[0]['Accum_VGPR_Count']}"
+        b = PHASE_BYTES.get(p)
+        bw = f"{b * cells / (ms * 1e-3) / 1e9:.0f} | {b * cells / (ms * 1e-3) / 8e12 * 100:.1f} %" if b else "— | —"
+        out.append(f"{e} | {p} | {ms:.4f} | {regs} | {bw}")
+    return "\n".join(out)
+
+
 def phase_traffic(d: str, n: int = 1 << 22) -> str:
     """Table of HBM bytes per cell (read, write) of every single-phase launch
     of a DRAM-counter run of phase_run, averaged over the rounds."""
@@ -223,5 +289,9 @@ if __name__ == "__main__":
         phase_run(*(int(a) for a in sys.argv[2:3]))
     elif sys.argv[1] == "phase-traffic":
         print(phase_traffic(sys.argv[2], *(int(a) for a in sys.argv[3:4])))
+    elif sys.argv[1] == "batch-run":
+        batch_run(*(int(a) for a in sys.argv[2:4]))
+    elif sys.argv[1] == "batch-phases":
+        print(batch_phases(sys.argv[2]))
     else:
         raise SystemExit(__doc__)

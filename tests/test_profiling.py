@@ -60,3 +60,35 @@ def test_phase_table(tmp_path):
         # read: 32 B x the mean over the rounds of (i + 1 + r) n sectors, per cell
         rd = 32.0 * sum(i + 1 + r for r in range(P.PHASE_ROUNDS)) / P.PHASE_ROUNDS
         assert table[2 + i] == f"{e} | {p} | {rd:.1f} | {16.0:.1f}"
+
+
+def test_batch_phase_table(tmp_path):
+    labels = [(e, p) for e, ps in P.PHASE_EXPORTS for p in ps]
+    cells = 10 ** 6
+    d = str(tmp_path / "prof")
+    os.makedirs(d)
+    fields = ["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp", "VGPR_Count", "Accum_VGPR_Count"]
+    with open(os.path.join(d, "run_kernel_trace.csv"), "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=fields)
+        w.writeheader()
+        di, t = 0, 0
+        for r in range(P.BATCH_ROUNDS):
+            for i in range(len(labels)):
+                # launch i lasts (i + 1) * 10 us plus r us; a copy in between is not a phase
+                w.writerow(dict(Dispatch_Id=di, Kernel_Name="k_phase<256, float, false, -1>(PhaseArgs)",
+                                Start_Timestamp=t, End_Timestamp=t + (i + 1) * 10000 + r * 1000,
+                                VGPR_Count=100 + i, Accum_VGPR_Count=0))
+                w.writerow(dict(Dispatch_Id=di + 1, Kernel_Name="__amd_rocclr_copyBuffer", Start_Timestamp=t,
+                                End_Timestamp=t + 5, VGPR_Count=8, Accum_VGPR_Count=0))
+                di, t = di + 2, t + 10 ** 6
+    table = P.batch_phases(d, cells=cells).splitlines()
+    assert len(table) == 2 + len(labels)
+    for i, (e, p) in enumerate(labels):
+        ms = ((i + 1) * 10000 + 1000 * sum(range(P.BATCH_ROUNDS)) / P.BATCH_ROUNDS) / 1e6
+        cols = [c.strip() for c in table[2 + i].split("|")]
+        assert cols[:4] == [e, p, f"{ms:.4f}", f"{100 + i} + 0"]
+        if p in P.PHASE_BYTES:
+            gbs = P.PHASE_BYTES[p] * cells / (ms * 1e-3) / 1e9
+            assert cols[4] == f"{gbs:.0f}"
+        else:
+            assert cols[4] == "—"
