@@ -7,6 +7,8 @@
     python -m paper_1904_08510_amd.profiling phase-traffic <dir> [n]  # its DRAM counters per phase
     python -m paper_1904_08510_amd.profiling batch-run [rounds] [T] # the same exports on the 1024-column batch (GPU)
     python -m paper_1904_08510_amd.profiling batch-phases <dir>     # its kernel trace: time and GB/s per launch
+    python -m paper_1904_08510_amd.profiling net-run [k]            # learned-guess inference over the batch, k times (GPU)
+    python -m paper_1904_08510_amd.profiling sq <dir> <kernel>      # mean per dispatch of each counter of a --pmc run
 
 `dram` reads HBM bytes directly from the L2's DRAM-sector counters of gfx950
 (TCC_EA0_RDREQ_DRAM_32B and TCC_EA0_WRREQ_WRITE_DRAM_32B count 32-byte
@@ -254,6 +256,46 @@ def batch_phases(d: str, rounds: int = BATCH_ROUNDS, cells: int | None = None) -
     return "\n".join(out)
 
 
+def net_run(k: int = 20) -> None:
+    """The learned guess's inference over all 4.4 M cells of the 1024-column
+    batch, k times after 3 untimed calls, with small random weights (the
+    kernel's work does not depend on their values)."""
+    import time
+    import numpy as np
+    import torch
+    from . import jfnk as J, workloads as W
+    packed = W.pack(W.config2())
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    net = J.Net(J.net_default_config(max_cols=packed.ncols, max_total_cells=packed.total))
+    rng = np.random.default_rng(0)
+    net.set_params((rng.standard_normal(net.get_params().size) * 0.05).astype(np.float32))
+    prev_n, prev_p = ne * 0.99, phi * 0.99
+    for _ in range(3):
+        net.predict(prob, ne, phi, prev_n, prev_p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(k):
+        net.predict(prob, ne, phi, prev_n, prev_p)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / k
+    print(f"net-run: full-batch inference {dt * 1e3:.3f} ms per call ({packed.total} cells, {k} calls)", flush=True)
+    net.close()
+
+
+def sq(d: str, kernel: str) -> str:
+    """Mean per dispatch of every counter of a --pmc run, over the
+    dispatches whose kernel name contains `kernel` (each counter summed over
+    its hardware instances)."""
+    tot, disp = {}, {}
+    for r in csv.DictReader(open(_find(d, "counter_collection.csv"))):
+        if kernel not in r.get("Kernel_Name", ""):
+            continue
+        c = r["Counter_Name"]
+        tot[c] = tot.get(c, 0.0) + float(r["Counter_Value"])
+        disp.setdefault(c, set()).add(r["Dispatch_Id"])
+    return "\n".join(f"{c} | {len(disp[c])} | {tot[c] / len(disp[c]):.6g}" for c in sorted(tot))
+
+
 def phase_traffic(d: str, n: int = 1 << 22) -> str:
     """Table of HBM bytes per cell (read, write) of every single-phase launch
     of a DRAM-counter run of phase_run, averaged over the rounds."""
@@ -293,5 +335,9 @@ if __name__ == "__main__":
         batch_run(*(int(a) for a in sys.argv[2:4]))
     elif sys.argv[1] == "batch-phases":
         print(batch_phases(sys.argv[2]))
+    elif sys.argv[1] == "net-run":
+        net_run(*(int(a) for a in sys.argv[2:3]))
+    elif sys.argv[1] == "sq":
+        print(sq(sys.argv[2], sys.argv[3]))
     else:
         raise SystemExit(__doc__)
