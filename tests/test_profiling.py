@@ -92,3 +92,19 @@ def test_batch_phase_table(tmp_path):
             assert cols[4] == f"{gbs:.0f}"
         else:
             assert cols[4] == "—"
+
+
+def test_sq_means_per_dispatch(tmp_path):
+    # two dispatches of the kernel, each counter reported by two hardware
+    # instances; another kernel's dispatch is left out
+    rows = []
+    for di in (1, 2):
+        for inst in (0, 1):
+            rows += [(di, "k_fused<0>(FusedArgs)", "SQ_WAVES", 10 * di + inst),
+                     (di, "k_fused<0>(FusedArgs)", "SQ_INSTS_MFMA", 100)]
+    rows += [(3, "k_solve<256, float, false>", "SQ_WAVES", 7)]
+    d = str(tmp_path / "prof")
+    write_counters(d, rows)
+    table = P.sq(d, "k_fused").splitlines()
+    # instances summed per dispatch, then the mean over dispatches
+    assert table == ["SQ_INSTS_MFMA | 2 | 200", "SQ_WAVES | 2 | 31"]
