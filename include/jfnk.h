@@ -537,6 +537,10 @@ int jfnk_step_noalloc(const jfnk_config *cfg, const jfnk_problem *p, jfnk_state 
                       void *stream, char *err, size_t err_len);
 
 /* ---- test exports: single phases of the step, same kernels ----------- */
+/* Each runs its phases one launch at a time, every launch over all columns
+   of p (one workgroup per column); the residual and J.v launches use kernels
+   that hold that phase alone.  Vectors are FP64 and in the caller's
+   natural layout.  The calls return once their results are complete. */
 
 /* F(X) (unscaled, per cell: fe, fp) with X = (x_ne, x_phi) and the step's
    X^n = (x->ne, x->phi) giving f = n^n + dt s; scal (HOST [4*ncols], may be
