@@ -341,6 +341,29 @@ def test_invalid_arguments_leave_outputs_untouched(J):
     assert rc == J.JFNK_ECAPACITY
 
 
+def test_empty_batch_and_short_columns_are_rejected(J):
+    """An empty batch (ncols = 0) and a column of fewer than 3 cells (the
+    smallest grid with an interior cell) are invalid arguments: the call
+    returns JFNK_EINVAL and leaves the state untouched; the same context
+    then steps a valid batch."""
+    packed = W.pack([W.flame_column(50, 20.0), W.flame_column(40, -20.0)])
+    prob, ne, phi, _, _ = J.device_problem(packed)
+    solver = J.Solver(J.config_for(packed))
+    before = (ne.clone(), phi.clone())
+    prob.ncols = 0
+    rc, _ = solver.step(prob, ne, phi, raw=True)
+    assert rc == J.JFNK_EINVAL
+    assert torch.equal(ne, before[0]) and torch.equal(phi, before[1])
+    prob.ncols = 2
+    prob.col_offset = np.array([0, 2, 90], dtype=packed.col_offset.dtype)    # a 2-cell column
+    rc, _ = solver.step(prob, ne, phi, raw=True)
+    assert rc == J.JFNK_EINVAL
+    assert torch.equal(ne, before[0]) and torch.equal(phi, before[1])
+    prob.col_offset = packed.col_offset.copy()
+    rc, st = solver.step(prob, ne, phi)
+    assert rc == J.JFNK_OK and np.all(st.res_scaled <= 1e-10)
+
+
 @pytest.mark.parametrize("sched", ["batched", "plain"])
 def test_bad_input_columns_are_isolated(J, sched):
     """Per-cell inputs outside the problem's domain (a non-finite source, a
