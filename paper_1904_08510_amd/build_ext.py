@@ -14,6 +14,9 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     # no packed-FP32 instructions in any generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the machine scheduler's memory-clause strategy groups the sweeps' loads:
+    # the solve launch 1.0 % shorter over five A/B pairs, the inference unchanged
+    "-mllvm", "--amdgpu-sched-strategy=max-memory-clause",
     "-Wno-unused-result",
 ]
 
