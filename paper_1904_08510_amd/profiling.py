@@ -26,8 +26,9 @@ DRAM-counter run of it and prints the HBM bytes per cell of every phase.
 512..8192-cell flame columns, FP32 factors, workgroup of T = 256 unless
 given), every phase
 one launch over all columns; `batch-phases` reads a kernel-trace run of it
-and prints each launch's average duration, registers and achieved bandwidth
-by its algorithmic bytes (PHASE_BYTES per cell of the batch).  The residual
+and prints each launch's average duration, the trace's register fields (on
+gfx950 half the compiler's VGPR + AGPR count) and achieved bandwidth by its
+algorithmic bytes (PHASE_BYTES per cell of the batch).  The residual
 and J.v launches are kernels holding that phase alone.
 
 `stats` prints the per-kernel time table of a kernel-trace run.  `pmc`
@@ -244,7 +245,7 @@ def batch_phases(d: str, rounds: int = BATCH_ROUNDS, cells: int | None = None) -
     labels = [(e, p) for e, ps in PHASE_EXPORTS for p in ps]
     if len(rows) != rounds * len(labels):
         raise RuntimeError(f"{len(rows)} single-phase launches, expected {rounds * len(labels)}")
-    out = [f"{cells} cells; export | launch | avg ms | VGPR + AGPR | GB/s (algorithmic) | of 8 TB/s",
+    out = [f"{cells} cells; export | launch | avg ms | trace VGPR_Count + Accum_VGPR_Count | GB/s (algorithmic) | of 8 TB/s",
            "---|---|---|---|---|---"]
     for i, (e, p) in enumerate(labels):
         rs = [rows[k * len(labels) + i] for k in range(rounds)]
