@@ -73,3 +73,16 @@ def test_net_create_rejects_bad_config_without_touching_a_device(libjfnk):
     assert L.jfnk_net_param_count() == 85442
     L.jfnk_net_destroy(None)
     assert L.jfnk_net_last_error(None) == b"null network"
+
+
+def test_build_targets_gfx950_without_packed_fp32():
+    """Every HIP source of the package is compiled, for gfx950 alone, with the
+    packed-FP32 instructions turned off for the device code."""
+    from paper_1904_08510_amd import build_ext
+    f = build_ext.HIPCC_FLAGS
+    assert "--offload-arch=gfx950" in f
+    assert not any(x.startswith("--offload-arch=") and x != "--offload-arch=gfx950" for x in f)
+    i = f.index("-packed-fp32-ops")
+    assert f[i - 3:i] == ["-Xclang", "-target-feature", "-Xclang"]
+    srcs = sorted(os.listdir(os.path.join(ROOT, "paper_1904_08510_amd", "csrc")))
+    assert sorted(s for s in srcs if s.endswith(".hip")) == sorted(build_ext.SOURCES)
