@@ -86,3 +86,23 @@ def test_build_targets_gfx950_without_packed_fp32():
     assert f[i - 3:i] == ["-Xclang", "-target-feature", "-Xclang"]
     srcs = sorted(os.listdir(os.path.join(ROOT, "paper_1904_08510_amd", "csrc")))
     assert sorted(s for s in srcs if s.endswith(".hip")) == sorted(build_ext.SOURCES)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built library the bindings raise: there is no other
+    implementation to fall back to.  Run in a fresh interpreter so that an
+    already loaded library does not answer."""
+    import subprocess
+    import sys
+    code = (
+        "import paper_1904_08510_amd.jfnk as J\n"
+        f"J.LIB_PATH = {str(tmp_path / 'absent.so')!r}\n"
+        "try:\n"
+        "    J.lib()\n"
+        "except RuntimeError as e:\n"
+        "    print('raised:', e)\n"
+        "else:\n"
+        "    print('loaded')\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.startswith("raised: libjfnk.so not built"), out.stdout
