@@ -9,6 +9,7 @@
     python -m paper_1904_08510_amd.profiling batch-phases <dir>     # its kernel trace: time and GB/s per launch
     python -m paper_1904_08510_amd.profiling net-run [k]            # learned-guess inference over the batch, k times (GPU)
     python -m paper_1904_08510_amd.profiling sq <dir> <kernel>      # mean per dispatch of each counter of a --pmc run
+    python -m paper_1904_08510_amd.profiling copy-bw                # a plain device copy's bandwidth (GPU)
 
 `dram` reads HBM bytes directly from the L2's DRAM-sector counters of gfx950
 (TCC_EA0_RDREQ_DRAM_32B and TCC_EA0_WRREQ_WRITE_DRAM_32B count 32-byte
@@ -283,6 +284,26 @@ def net_run(k: int = 20) -> None:
     net.close()
 
 
+def copy_bw(mib: int = 1024, k: int = 20) -> str:
+    """Bytes read plus written per second of torch's device-to-device copy of
+    mib MiB, k copies timed with events after 3 untimed ones: what a plain
+    streaming kernel reaches on this GPU, beside the 8 TB/s peak."""
+    import torch
+    src = torch.ones(mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(k):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / k
+    gbs = 2 * src.numel() * 8 / (ms * 1e-3) / 1e9
+    return f"copy-bw: {mib} MiB device copy {ms:.4f} ms, {gbs:.0f} GB/s read + write ({gbs / 8000 * 100:.1f} % of 8 TB/s)"
+
+
 def sq(d: str, kernel: str) -> str:
     """Mean per dispatch of every counter of a --pmc run, over the
     dispatches whose kernel name contains `kernel` (each counter summed over
@@ -340,5 +361,7 @@ if __name__ == "__main__":
         net_run(*(int(a) for a in sys.argv[2:3]))
     elif sys.argv[1] == "sq":
         print(sq(sys.argv[2], sys.argv[3]))
+    elif sys.argv[1] == "copy-bw":
+        print(copy_bw(), flush=True)
     else:
         raise SystemExit(__doc__)
