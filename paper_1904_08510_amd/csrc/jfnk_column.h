@@ -322,6 +322,10 @@ struct Lds {
     static constexpr int kBasis = kMisc + 16;                    // (m+1) VecRefs (4 words each)
     static constexpr int kTotal = kBasis + 4 * (kMaxRestart + 1);
     static constexpr size_t bytes() { return sizeof(double) * kTotal; }
+    // with SolverParams::dlds: the block solve's intermediate d (2 factor
+    // values per cell, rows j*T + t of up to m rows per thread) after the rest
+    static constexpr int kDTmp = (kTotal + 1) & ~1;                // 16-byte aligned
+    static constexpr size_t bytes_d(int m, size_t fts) { return sizeof(double) * kDTmp + (size_t)m * T * 2 * fts; }
 };
 
 // ---------------------------------------------------------------------------
@@ -1445,7 +1449,8 @@ struct Column {
         if (prm.prec_kind == 1 || prm.prec_kind == 3) return apply_schur(v, z0, z1);
         Column self(*this);
         const VecRef vl = v;    // by value: a reference would be re-read through a generic pointer
-        return self.block_apply(vl, z0, z1);
+        if (prm.dlds) return self.template block_apply<true>(vl, z0, z1);
+        return self.template block_apply<false>(vl, z0, z1);
     }
 
     // No preconditioner: z = v (with v's component scales), every row of the
@@ -1481,13 +1486,13 @@ struct Column {
         const bool mg_n = prm.prec_kind == 3 && (prm.mg_blocks & 1);
         const bool mg_p = prm.prec_kind == 3 && (prm.mg_blocks & 2);
         if (mg_n) mg_solve(0, v.p0, v.s0, Y0);
-        else block_apply(VecRef{v.p0, v.p1, v.s0, 0.0}, Y0, Y1);       // Y0 = z_e'
+        else block_apply<false>(VecRef{v.p0, v.p1, v.s0, 0.0}, Y0, Y1);   // Y0 = z_e'
         for (int j = 0; j < M; ++j) {
             const int64_t s = sidx(t, j);
             Y2[s] = v.p1[s] * v.s1 - (double)gld(facp(19, s)) * Y0[s];        // v_phi - I_e z_e'
         }
         if (mg_p) mg_solve(1, Y2, 1.0, z1);
-        else block_apply(VecRef{Y2, Y2, 0.0, 1.0}, Y3, z1);             // z1 = z_phi
+        else block_apply<false>(VecRef{Y2, Y2, 0.0, 1.0}, Y3, z1);         // z1 = z_phi
         // dt D_r z_phi (tridiagonal; neighbours across chunks are visible after
         // the solve's closing barriers)
         for (int j = 0; j < M; ++j) {
@@ -1502,7 +1507,7 @@ struct Column {
             Y2[s] = w;
         }
         if (mg_n) mg_solve(0, Y2, 1.0, Y3);
-        else block_apply(VecRef{Y2, Y2, 1.0, 0.0}, Y3, Y1);             // Y3 = (dt D_f - I)^-1 dt D_r z_phi
+        else block_apply<false>(VecRef{Y2, Y2, 1.0, 0.0}, Y3, Y1);         // Y3 = (dt D_f - I)^-1 dt D_r z_phi
         double zz = 0.0, zm = 0.0;
         for (int j = 0; j < M; ++j) {
             const int64_t s = sidx(t, j);
@@ -1519,8 +1524,14 @@ struct Column {
     }
 
     // Block solve with the stored factors (chunk sweeps in FT, reduced
-    // system in FP64).  Returns (||z||_2^2, ||z||_inf).
+    // system in FP64).  Returns (||z||_2^2, ||z||_inf).  DL: the intermediate
+    // d between the two sweeps lives in LDS (row j of this thread at j*T + t
+    // past the GMRES state) instead of W.tmp in HBM.
+    template <bool DL>
     __device__ __forceinline__ Vec2<double> block_apply(const VecRef& v, CP z0, CP z1) {
+        typedef FT dv2 __attribute__((ext_vector_type(2)));
+        typedef __attribute__((address_space(3))) dv2 lv2;
+        lv2* const dl = (lv2*)(lds + Lds<T>::kDTmp);
         const int tl = t;   // a local: members are reloaded after every barrier
         constexpr int U = 4;
         constexpr int LG = ilog2(T);             // PCR stages of the interface system
@@ -1568,7 +1579,8 @@ struct Column {
                             const Vec2<FT> q = bmv(gc.aa[u], dprev);
                             de.x -= q.x; de.y -= q.y;
                         }
-                        gst(tmpp(s), V2<FT>{de.x, de.y});
+                        if (DL) dl[j * T + tl] = dv2{de.x, de.y};
+                        else gst(tmpp(s), V2<FT>{de.x, de.y});
                         dprev = de;
                         const Vec2<FT> qd = bmv(Q, de);
                         sq.x += qd.x; sq.y += qd.y;
@@ -1650,11 +1662,17 @@ struct Column {
             auto load_f = [&](int j0, GF& g) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int64_t s = sidx(tl, max(j0 - u, 1));
+                    const int jj = max(j0 - u, 1);
+                    const int64_t s = sidx(tl, jj);
                     g.aa[u] = load_blk(12, s);
                     g.gg[u] = load_blk(8, s);
-                    const V2<FT> r = gld(tmpp(s));
-                    g.dd[u] = Vec2<FT>{r.x, r.y};
+                    if (DL) {
+                        const dv2 r = dl[jj * T + tl];
+                        g.dd[u] = Vec2<FT>{r.x, r.y};
+                    } else {
+                        const V2<FT> r = gld(tmpp(s));
+                        g.dd[u] = Vec2<FT>{r.x, r.y};
+                    }
                 }
             };
             GF gc, gn;

@@ -682,6 +682,20 @@ UserArrays make_user(const jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x) 
     return U;
 }
 
+// Dynamic LDS of a solve launch.  The solve runs one wave per SIMD (its
+// registers), so T / 64 waves share a CU's 160 KiB with 256 / T - 1 other
+// workgroups (one at T >= 256); when the block solve's intermediate d for the
+// longest column (mmax rows per thread) fits in that share beside the GMRES
+// state, it stays in LDS (*dlds = 1) instead of making a round trip to HBM.
+template <int T, class FT>
+size_t solve_lds(int prec_kind, int mmax, int32_t* dlds) {
+    constexpr size_t kCU = 160 * 1024;
+    constexpr size_t share = T >= 256 ? kCU : kCU * T / 256;
+    const size_t with_d = Lds<T>::bytes_d(mmax, sizeof(FT));
+    *dlds = (prec_kind == JFNK_PRECK_BLOCK && with_d <= share) ? 1 : 0;
+    return *dlds ? with_d : Lds<T>::bytes();
+}
+
 // ---------------------------------------------------------------------------
 // Host-driven executor of the control logic (plain schedule).
 // ---------------------------------------------------------------------------
@@ -691,6 +705,7 @@ struct HostExecT {
     hipStream_t st;
     PhaseArgs a;
     hipError_t herr = hipSuccess;
+    size_t lds_bytes = Lds<T>::bytes();   // the phases' dynamic LDS (solve_lds)
     double sfn = 1, sfp = 1, isfn = 1, isfp = 1;
     VecRef bas[kMaxRestart + 1];
     double H[(kMaxRestart + 1) * kMaxRestart];
@@ -709,7 +724,7 @@ struct HostExecT {
     void launch(int phase) {
         a.phase = phase;
         if (herr != hipSuccess) return;
-        hipLaunchKernelGGL((k_phase<T, FT, TAB>), dim3(1), dim3(T), Lds<T>::bytes(), st, a);
+        hipLaunchKernelGGL((k_phase<T, FT, TAB>), dim3(1), dim3(T), lds_bytes, st, a);
         herr = hipGetLastError();
     }
     const double* fetch(int n) {
@@ -831,13 +846,19 @@ struct HostExecT {
 
 template <int T, class FT, bool TAB>
 int run_plain(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t st) {
-    const SolverParams prm = make_params(ctx, p, x);
+    SolverParams prm = make_params(ctx, p, x);
+    // the batched schedule's placement of the block solve's intermediate, so
+    // that both schedules run the same arithmetic
+    int mmax = 1;
+    for (int c = 0; c < p->ncols; ++c) mmax = std::max(mmax, (int)ctx->h_cols[c].M);
+    const size_t lds_bytes = solve_lds<T, FT>(prm.prec_kind, mmax, &prm.dlds);
     const UserArrays U = make_user(ctx, p, x);
     HIP_OK(hipEventRecord(ctx->ev0, st));
     for (int c = 0; c < p->ncols; ++c) {
         HostExecT<T, FT, TAB> ex;
         ex.ctx = ctx;
         ex.st = st;
+        ex.lds_bytes = lds_bytes;
         memset(&ex.a, 0, sizeof(ex.a));
         ex.a.W = ctx->W;
         ex.a.prm = prm;
@@ -861,6 +882,9 @@ int run_batched(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t
     SolveArgs a;
     a.W = ctx->W;
     a.prm = make_params(ctx, p, x);
+    int mmax = 1;
+    for (int c = 0; c < p->ncols; ++c) mmax = std::max(mmax, (int)ctx->h_cols[c].M);
+    const size_t lds_bytes = solve_lds<T, FT>(a.prm.prec_kind, mmax, &a.prm.dlds);
     a.U = make_user(ctx, p, x);
     a.order = ctx->d_order;
     a.mcol = ctx->d_mcol;
@@ -869,7 +893,7 @@ int run_batched(jfnk_ctx* ctx, const jfnk_problem* p, jfnk_state* x, hipStream_t
     hipLaunchKernelGGL((k_gather<T, TAB>), dim3(ctx->nmove), dim3(kMoveThreads), 0, st, a);
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(ctx->evg, st));
-    hipLaunchKernelGGL((k_solve<T, FT, TAB>), dim3(p->ncols), dim3(T), Lds<T>::bytes(), st, a);
+    hipLaunchKernelGGL((k_solve<T, FT, TAB>), dim3(p->ncols), dim3(T), lds_bytes, st, a);
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(ctx->evs, st));
     hipLaunchKernelGGL((k_scatter<T>), dim3(ctx->nmove), dim3(kMoveThreads), 0, st, a);
@@ -1232,11 +1256,13 @@ __global__ __launch_bounds__(256) void k_clear(uint4* p, int64_t n16) {
 }
 
 template <int T, class FT, bool TAB>
-hipError_t static_launch(const SolveArgs& a, int nmove, int ncols, hipStream_t st) {
+hipError_t static_launch(const SolveArgs& a0, int nmove, int ncols, int mmax, hipStream_t st) {
+    SolveArgs a = a0;
+    const size_t lds_bytes = solve_lds<T, FT>(a.prm.prec_kind, mmax, &a.prm.dlds);
     hipLaunchKernelGGL((k_gather<T, TAB>), dim3(nmove), dim3(kMoveThreads), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_solve<T, FT, TAB>), dim3(ncols), dim3(T), Lds<T>::bytes(), st, a);
+    hipLaunchKernelGGL((k_solve<T, FT, TAB>), dim3(ncols), dim3(T), lds_bytes, st, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_scatter<T>), dim3(nmove), dim3(kMoveThreads), 0, st, a);
@@ -1244,20 +1270,20 @@ hipError_t static_launch(const SolveArgs& a, int nmove, int ncols, hipStream_t s
 }
 
 template <class FT, bool TAB>
-hipError_t static_dispatch_t(int T, const SolveArgs& a, int nmove, int ncols, hipStream_t st) {
+hipError_t static_dispatch_t(int T, const SolveArgs& a, int nmove, int ncols, int mmax, hipStream_t st) {
     switch (T) {
-    case 64: return static_launch<64, FT, TAB>(a, nmove, ncols, st);
-    case 128: return static_launch<128, FT, TAB>(a, nmove, ncols, st);
-    case 256: return static_launch<256, FT, TAB>(a, nmove, ncols, st);
-    case 512: return static_launch<512, FT, TAB>(a, nmove, ncols, st);
+    case 64: return static_launch<64, FT, TAB>(a, nmove, ncols, mmax, st);
+    case 128: return static_launch<128, FT, TAB>(a, nmove, ncols, mmax, st);
+    case 256: return static_launch<256, FT, TAB>(a, nmove, ncols, mmax, st);
+    case 512: return static_launch<512, FT, TAB>(a, nmove, ncols, mmax, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <class FT>
-hipError_t static_dispatch(int T, const SolveArgs& a, int nmove, int ncols, hipStream_t st) {
-    return a.prm.tab.mu ? static_dispatch_t<FT, true>(T, a, nmove, ncols, st)
-                        : static_dispatch_t<FT, false>(T, a, nmove, ncols, st);
+hipError_t static_dispatch(int T, const SolveArgs& a, int nmove, int ncols, int mmax, hipStream_t st) {
+    return a.prm.tab.mu ? static_dispatch_t<FT, true>(T, a, nmove, ncols, mmax, st)
+                        : static_dispatch_t<FT, false>(T, a, nmove, ncols, mmax, st);
 }
 
 int static_fail(char* err, size_t len, int code, const char* msg) {
@@ -2055,9 +2081,11 @@ int jfnk_step_noalloc(const jfnk_config* cfg, const jfnk_problem* p, jfnk_state*
     a.order = d_order;
     a.mcol = d_mcol;
     a.ncols = nc;
+    int mmax = 1;
+    for (int c = 0; c < nc; ++c) mmax = std::max(mmax, (int)cols[c].M);
     if (e == hipSuccess)
-        e = cfg->prec_precision == JFNK_PREC_FP32 ? static_dispatch<float>(T, a, nmove, nc, st)
-                                                  : static_dispatch<double>(T, a, nmove, nc, st);
+        e = cfg->prec_precision == JFNK_PREC_FP32 ? static_dispatch<float>(T, a, nmove, nc, mmax, st)
+                                                  : static_dispatch<double>(T, a, nmove, nc, mmax, st);
     ColState hcst[JFNK_NOALLOC_MAX_COLS];
     if (e == hipSuccess) e = hipMemcpyAsync(hcst, W.cst, sizeof(ColState) * nc, hipMemcpyDeviceToHost, st);
     // the host arrays above live on this call's stack: wait before returning

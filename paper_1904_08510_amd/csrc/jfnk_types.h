@@ -95,6 +95,8 @@ struct SolverParams {
                             // 3 approximate Schur with multigrid block solves
     int32_t mg_blocks;      // kind 3: bit 0 the electron block, bit 1 the S~ block by multigrid
     int32_t mg_transfer;    // kind 3: bit k set: block k uses matrix-dependent transfers, else linear
+    int32_t dlds;           // the block solve keeps its intermediate d in LDS (the launch's dynamic
+                            // LDS holds Lds<T>::bytes_d(M) for the longest column), else in W.tmp
     double tol_f, tol_x, gamma, theta;
     double chord_tol;       // simplified-Newton steps while the error estimate is below this (0: off)
     double mg_tol;          // kind 3: V-cycles until ||b - A x||_2 <= mg_tol ||b||_2
